@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark of the BM-Global matrix-completion hot path on one MI355X.
+
+Workload: the Netflix-shaped synthetic problem (17,770 x 480,189, |Omega| = 1e8,
+capped Zipf(1.2) row and column degrees, rank-20 truth + noise, lambda = 20,
+k0 = 16), FP64.  One step = one call of bmg_solve limited to one outer
+iteration: HMT + Nystrom initialisation, 3 BM epochs, one inexact PG step
+(subspace iteration + exact SVD + soft-threshold) and the objective, every
+sparse pass in the library's HIP kernels.  Every step starts from the same
+state, so every step does identical work.
+
+value = algorithmic bytes of all sparse passes of the timed steps / wall time.
+roofline = the kernel class with the largest time, its algorithmic bytes per
+launch / its launch time, both from HIP events on the problem's stream.
+cpu_baseline = the CPU oracle's residual + product pair on the same data.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+KERNEL_NAMES = ["k_grad (fused sampled residual + sparse product)",
+                "k_sddmm (sampled residual / curvature)",
+                "k_spmm (sparse x dense of the subspace iteration)"]
+KERNEL_SYMBOLS = ["k_grad", "k_sddmm", "k_spmm"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def traffic_for(kernel_symbol, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel_symbol, workload))
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2204_14067_amd", "csrc", "kernels.hip"), "rb").read()
+    if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(p, k=16):
+    """Oracle R = P_Omega(W H^T - A) then G = R H over the whole workload, FP64,
+    on the host cores; bytes counted with the same formula as the GPU pass."""
+    import numpy as np
+    from oracle import core
+    rng = np.random.default_rng(0)
+    W = 0.3 * rng.standard_normal((p.m, k))
+    H = 0.3 * rng.standard_normal((p.n, k))
+    reps, t_tot = 0, 0.0
+    while reps < 2 or (t_tot < 10.0 and reps < 8):
+        t0 = time.perf_counter()
+        R = core.sddmm(p, W, H)
+        G = core.spmm(p, R, H)
+        t_tot += time.perf_counter() - t0
+        reps += 1
+        del R, G
+    nbytes = p.nnz * (4 + 8) + (p.m + p.n) * k * 8 + p.m * k * 8 + 8 * (p.m + 1)
+    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    return {"value": round(nbytes * reps / t_tot / 1e9, 3), "unit": "GB/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d x (residual pass + row-oriented sparse product) over the full workload, "
+                      "k=16, FP64, %.1f s" % (reps, t_tot)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU "
+              "sharding is described in DESIGN.md but not built." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2204_14067_amd as bmg
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    t0 = time.time()
+    p = synth.netflix_shape(scale=args.scale)
+    log("workload %s generated in %.1fs" % (p.name, time.time() - t0))
+    k0, lam = 16, 20.0
+    prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64,
+                                 precision=args.precision, device=dev)
+    W, H = prob.zeros_factors()
+    log("problem resident on %s (%.2f GB workspace)" % (dev, prob.ws.numel() / 1e9))
+
+    def step():
+        return prob.bmg_solve(W, H, lam=lam, k_init=k0, max_iter=1, tol=0.0, seed=1003, timing=1)[3]
+
+    for i in range(args.warmup):
+        r = step()
+        log("warmup %d: k=%d F=%.6g passes=%d" % (i, r["k"], r["F"], r["sparse_passes"]))
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    recs = []
+    for i in range(args.steps):
+        recs.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    log("timed %d steps in %.3fs" % (args.steps, elapsed))
+    nbytes = sum(r["sparse_bytes"] for r in recs)
+    value = nbytes / elapsed / 1e9
+    kms = [sum(r["kernel_ms"][c] for r in recs) for c in range(3)]
+    kby = [sum(r["kernel_bytes"][c] for r in recs) for c in range(3)]
+    kla = [sum(r["kernel_launches"][c] for r in recs) for c in range(3)]
+    dom = max(range(3), key=lambda c: kms[c])
+    achieved = kby[dom] / (kms[dom] / 1e3) / 1e9 if kms[dom] > 0 else 0.0
+    workload = "netflix_shape" if args.scale == 1.0 else "netflix_shape_x%g" % args.scale
+    traffic = traffic_for(KERNEL_SYMBOLS[dom], workload)
+    out = {
+        "metric": "SDDMM+SpMM GB/s (% HBM peak); time-to-tol vs plain; serve p50/p99 latency",
+        "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": "%s: %dx%d, nnz=%d, capped Zipf(1.2) degrees, rank-20 truth + "
+                               "noise var 0.25, lambda=20, k0=16" % (workload, p.m, p.n, p.nnz),
+                   "step": "init (HMT+Nystrom) + 3 BM epochs + 1 inexact PG step + objective",
+                   "precision": args.precision, "rank_after_step": recs[-1]["k"],
+                   "ssi_iters_per_step": recs[-1]["ssi_iters"],
+                   "sparse_passes_per_step": recs[-1]["sparse_passes"],
+                   "frac_of_hbm_peak_whole_step": round(value / PEAK_HBM_GBS, 4)},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom],
+                     "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": round(kby[dom] / max(kla[dom], 1)),
+                     "avg_launch_us": round(kms[dom] / max(kla[dom], 1) * 1e3, 2)},
+        "kernels": {KERNEL_SYMBOLS[c]: {"launches": kla[c], "ms": round(kms[c], 3),
+                                        "GB/s": round(kby[c] / (kms[c] / 1e3) / 1e9, 2) if kms[c] else None}
+                    for c in range(3)},
+    }
+    if not args.no_extras:
+        out["time_to_tol"] = time_to_tol(bmg, synth, dev)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+def time_to_tol(bmg, synth, dev):
+    """Full solves of the 1000 x 1500 workload (|Omega| = 50,000, lambda = 0.5,
+    k0 = 8) to relative optimality residual 1e-6, FP64 and FP32."""
+    from oracle import core
+    p = synth.small_uniform()
+    out = {"workload": "small_uniform 1000x1500 nnz=50000 lambda=0.5 k0=8", "tol": 1e-6}
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "small_uniform.json")))
+    for prec in ("fp64", "fp32"):
+        prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=128, precision=prec,
+                                     device=dev)
+        prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=11, max_iter=2)   # warm caches
+        t0 = time.perf_counter()
+        W, H, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=11, max_iter=3000)
+        dt = time.perf_counter() - t0
+        Wn, Hn = W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k]
+        F64 = core.objective(p, Wn, Hn, p.lam)
+        out[prec] = {"seconds": round(dt, 4), "iters": r["iters"], "rank": k,
+                     "F": F64, "rel_err_vs_oracle_optimum": (F64 - golden["F"]) / golden["F"]}
+        log("time-to-tol %s: %.3fs, %d iters, k=%d" % (prec, dt, r["iters"], k))
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * bmg.h — C ABI of the MI355X (gfx950) hot path of BM-Global for
+ * nuclear-norm-regularised matrix completion.
+ *
+ * Problem (MC) of Sec. 1 of the paper:
+ *     min_X  1/2 || P_Omega(X - A) ||_F^2 + lambda ||X||_*
+ * solved in the factored form X = W H^T (problem (MF) / (BM-nuclear)) by
+ * Algorithm 1: BM-phase steps on (W, H) alternating with inexact
+ * proximal-gradient steps whose partial SVD comes from block subspace
+ * iteration (Algorithm 2 with p = 0) followed by singular-value
+ * soft-thresholding (eqs. exactSVD, approxSVD, truncate of Suppl. A.1.1).
+ *
+ * Conventions for every call:
+ *   - Pointers marked (device) point to GPU memory, (host) to CPU memory.
+ *     The caller owns every buffer it passes.  The library never allocates
+ *     device memory itself: all of its internal arrays live in the workspace
+ *     the caller passes to bmg_problem_create (size from bmg_workspace_size).
+ *   - Dense factors are row-major FP64: W is m x ld, H is n x ld, with the
+ *     first k columns in use (ld >= k, ld a multiple of 8, rows 16-byte aligned).
+ *   - Omega is CSR: row_ptr[m+1] int64, col[nnz] int32 sorted and duplicate-free
+ *     within each row, val[nnz] FP64 observed values A_ij.
+ *   - Work is issued on the problem's HIP stream; calls that return host
+ *     scalars synchronise that stream before returning.
+ *   - Errors: a negative bmg_status; bmg_last_error() gives a message
+ *     (thread-local).  No C++ exception crosses the ABI.
+ */
+#ifndef BMG_H
+#define BMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BMG_OK = 0,
+  BMG_NOT_CONVERGED = 1, /* max_iter reached; outputs hold the last iterate        */
+  BMG_EINVAL = -1,       /* bad argument (shape, CSR not sorted/duplicate-free, ...) */
+  BMG_ENOMEM = -2,       /* workspace too small, or rank would exceed k_cap         */
+  BMG_EDEVICE = -3,      /* a HIP call failed                                        */
+  BMG_ENONFINITE = -4,   /* NaN/Inf in the observed values or in a reduction         */
+  BMG_ECANCELLED = -5
+} bmg_status;
+
+/* Arithmetic of the sparse passes.  FP64: everything in FP64.  FP32: factors,
+ * residual and sparse values stored and multiplied in FP32, every Gram,
+ * Cholesky, eigen-decomposition and scalar reduction in FP64.  BF16: factors
+ * kept in BF16 for the sparse passes (FP32 accumulation), with the residual and
+ * objective recomputed in FP64 every refresh_every outer iterations. */
+typedef enum { BMG_FP64 = 0, BMG_FP32 = 1, BMG_BF16 = 2 } bmg_precision;
+
+typedef struct {
+  int64_t m, n, nnz;
+  const int64_t *row_ptr; /* (device) [m+1] */
+  const int32_t *col;     /* (device) [nnz] */
+  const double *val;      /* (device) [nnz] */
+} bmg_csr;
+
+typedef struct bmg_problem bmg_problem;
+
+typedef struct {
+  double lambda;        /* regularisation weight of (MC)                         */
+  double alpha;         /* fixed PG step (Sec. 6.1: L = 1, alpha = 1.99)         */
+  double tol;           /* stop when the relative optimality residual <= tol     */
+  double ssi_tol_floor; /* floor of the subspace-iteration stopping tolerance    */
+  double psi0;          /* initial safeguard noise level (Suppl. A.1.3: 0.1)     */
+  int bm_epochs;        /* y: BM epochs per PG step (Sec. 6.1.1: 3)              */
+  int max_iter;         /* outer iterations                                      */
+  int ssi_max_iter;     /* subspace iterations per PG step                       */
+  int k_init;           /* k_{-1}: width of the initial range finder             */
+  int refresh_every;    /* BF16 mode: FP64 refresh period (outer iterations)     */
+  int verbose;          /* print one line per outer iteration to stderr          */
+  int timing;           /* time every sparse-pass kernel with HIP events         */
+  uint64_t seed;        /* counter-based RNG seed (sketch and safeguard draws)   */
+} bmg_options;
+
+typedef struct {
+  int k;              /* final rank                                              */
+  int iters;          /* outer iterations done                                   */
+  int ssi_iters;      /* subspace iterations summed over all PG steps            */
+  int status;         /* bmg_status of the solve                                 */
+  double F;           /* objective of (MC) at the returned X = W H^T             */
+  double F_bm;        /* BM objective after the last BM phase                    */
+  double residual;    /* last relative optimality residual                       */
+  double eps;         /* last ||Z~ - Z||_F (inexactness of the last PG step)     */
+  double seconds;     /* wall time of the solve                                  */
+  double sparse_bytes;/* algorithmic bytes moved by the sparse passes            */
+  int sparse_passes;  /* number of sparse passes launched                        */
+  /* with opt->timing: per kernel class (0 fused residual+product of the BM
+   * gradient, 1 sampled residual / curvature, 2 sparse x dense of the subspace
+   * iteration) the summed kernel time from HIP events on the problem's stream,
+   * the algorithmic bytes of those launches, and their count */
+  double kernel_ms[3];
+  double kernel_bytes[3];
+  int kernel_launches[3];
+} bmg_result;
+
+/* Fills the defaults: alpha 1.99, tol 1e-6, ssi_tol_floor 1e-12, psi0 0.1,
+ * bm_epochs 3, max_iter 500, ssi_max_iter 50, k_init 8, refresh_every 5. */
+void bmg_options_default(bmg_options *opt);
+
+/* Bytes of device workspace a problem of this shape needs when the rank may
+ * reach k_cap (subspace blocks hold up to 2*k_cap+1 columns).  (host) out. */
+bmg_status bmg_workspace_size(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_precision prec,
+                              size_t *bytes);
+
+/* Validates the CSR (sorted, in range, duplicate-free, finite values), builds the
+ * column-major copy of Omega used by the transposed products (a stable sort of
+ * the column indices on the device), and the load-balancing plans of both
+ * orientations.  ws: (device) workspace of ws_bytes; stream: a hipStream_t (or
+ * NULL for the default stream).  The CSR arrays must stay alive and unchanged
+ * while the problem exists.  m > n is allowed; the library then works on the
+ * transpose internally (the paper assumes m <= n, Sec. 1) and the W/H arguments
+ * of every call keep their user meaning. */
+bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_precision prec, void *ws,
+                              size_t ws_bytes, void *stream, bmg_problem **out);
+void bmg_problem_destroy(bmg_problem *p);
+
+/* Sampled residual (the sparse gradient of the MC loss, Sec. 5.1):
+ *   R[p] = w_i . h_j - A_ij for every stored entry p = (i, j) in CSR order.
+ * R: (device) [nnz] FP64 or NULL (then only the sums are produced).
+ * half_sq: (host) 1/2 sum R^2.  W (m x ld), H (n x ld): (device). */
+bmg_status bmg_sddmm(bmg_problem *p, const double *W, const double *H, int k, int ld, double *R,
+                     double *half_sq);
+
+/* Sparse products with the Omega-supported matrix S whose values are given in
+ * CSR order (S: (device) [nnz]):
+ *   transpose = 0:  C (m x q) = S   B,  B (n x q)
+ *   transpose = 1:  C (n x q) = S^T B,  B (m x q)
+ * These are the products the subspace iteration needs from Z^T U and Z B
+ * (Suppl. A.1.2).  B, C: (device), leading dimensions ldb, ldc (multiples of 8). */
+bmg_status bmg_spmm(bmg_problem *p, const double *S, const double *B, int q, int ldb, double *C,
+                    int ldc, int transpose);
+
+/* BM phase of Algorithm 1: `epochs` epochs, each a W step then an H step of
+ * preconditioned steepest descent on (MF) with exact line search (the only
+ * requirement, eq. nonincrease, holds by construction).  W, H: (device), updated
+ * in place.  F_bm: (host) BM objective after the last step. */
+bmg_status bmg_bm_epochs(bmg_problem *p, double *W, double *H, int k, int ld, double lambda,
+                         int epochs, double *F_bm);
+
+/* Objective of (MC) at X = W H^T:  F = 1/2 ||P_Omega(X - A)||^2 + lambda ||X||_*,
+ * the nuclear norm from the k x k core of thin QR factors of W and H. (host) F. */
+bmg_status bmg_objective(bmg_problem *p, const double *W, const double *H, int k, int ld,
+                         double lambda, double *F);
+
+/* One inexact PG step (Algorithm 1, convex-lifting phase) from X~ = W H^T with
+ * step alpha, warm-started from the columns of W only (eq. rt0 with no previous
+ * prox output) plus one safeguard column drawn with the given seed/stream:
+ * block subspace iteration to tolerance, exact SVD of the projected matrix and
+ * soft-thresholding at alpha*lambda.  On return W, H hold the balanced factors
+ * U sqrt(Sigma), V sqrt(Sigma) of the new iterate and *k_inout its rank.
+ * sigma: (host) optional, receives the kept singular values (capacity k_cap).
+ * residual: (host) optional, relative optimality residual at X~. */
+bmg_status bmg_prox_step(bmg_problem *p, double *W, double *H, int *k_inout, int ld,
+                         const bmg_options *opt, double *sigma, double *residual);
+
+/* Algorithm 1 end to end: HMT + Nystrom initialisation (Suppl. A.1.4), then
+ * outer iterations of y BM epochs + one inexact PG step with warm start
+ * (eqs. rt0, rt0-1) and rank safeguard (eq. rt), until the relative optimality
+ * residual <= opt->tol or opt->max_iter.  W (m x ld), H (n x ld): (device)
+ * outputs; *k_out the rank.  res: (host) statistics. */
+bmg_status bmg_solve(bmg_problem *p, double *W, double *H, int ld, const bmg_options *opt,
+                     int *k_out, bmg_result *res);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *bmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BMG_H */

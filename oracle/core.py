@@ -87,6 +87,35 @@ def _c(a, dtype=np.float64):
     return np.ascontiguousarray(a, dtype=dtype)
 
 
+# ----------------------------------------------------------------------------- Omega
+
+@dataclass
+class Omega:
+    """Omega in CSR form with the observed values (any object with these
+    fields works as a problem for this module)."""
+    m: int
+    n: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def rows(self) -> np.ndarray:
+        return np.repeat(np.arange(self.m, dtype=np.int64), np.diff(self.row_ptr))
+
+
+def transpose(prob) -> Omega:
+    """Omega of A^T (entries re-sorted by column, then row)."""
+    rows = np.repeat(np.arange(prob.m, dtype=np.int64), np.diff(prob.row_ptr))
+    order = np.lexsort((rows, prob.col))
+    rp = np.zeros(prob.n + 1, np.int64)
+    np.cumsum(np.bincount(prob.col, minlength=prob.n), out=rp[1:])
+    return Omega(prob.n, prob.m, rp, rows[order].astype(np.int32), np.asarray(prob.val)[order])
+
+
 # ----------------------------------------------------------------------------- sparse loops
 
 def sddmm(prob, X: np.ndarray, Y: np.ndarray, with_values: bool = True) -> np.ndarray:
@@ -481,7 +510,12 @@ def prox_step_standalone(prob, W, H, lam: float, alpha: float = 1.99, seed: int 
     (eq. rt0 without a previous prox output) plus the safeguard column of eq. rt
     with no retained vector (a unit random vector, stream STREAM_SAFEGUARD + 0),
     Algorithm 2 with p = 0 to tolerance tau, exact SVD and threshold alpha*lam.
-    Returns (ProxResult, LmsvdResult, relative residual)."""
+    Returns (ProxResult, LmsvdResult, relative residual).  For m > n the step
+    runs on the transpose (Sec. 1) and the output factors are swapped back."""
+    if prob.m > prob.n:
+        pr, ls, res = prox_step_standalone(transpose(prob), H, W, lam, alpha, seed, tau, max_iter)
+        pr.W, pr.H = pr.H, pr.W
+        return pr, ls, res
     R = sddmm(prob, W, H)
     zop = ZOperator(prob, W, H, R, alpha)
     Ubase = orth(W)
@@ -527,8 +561,14 @@ def relative_residual(prob, Wt, Ht, R, Uhat, Wn, Hn) -> float:
 
 def solve(prob, opt: Options, callback=None) -> SolveResult:
     """Runs :func:`_solve` with single-threaded BLAS (the dense steps are small;
-    threaded BLAS only adds contention with the OpenMP sparse loops)."""
+    threaded BLAS only adds contention with the OpenMP sparse loops).  The
+    method assumes m <= n (Sec. 1: otherwise transpose), so a problem with
+    m > n is solved as its transpose and the factors are swapped back."""
     with threadpool_limits(limits=1, user_api="blas"):
+        if prob.m > prob.n:
+            res = _solve(transpose(prob), opt, callback)
+            res.W, res.H = res.H, res.W
+            return res
         return _solve(prob, opt, callback)
 
 

@@ -1,0 +1,159 @@
+"""BM-Global nuclear-norm matrix completion on one MI355X (gfx950).
+
+Thin Python front end of libbmg.so (C ABI in include/bmg.h).  PyTorch supplies
+device memory and the HIP stream; every step of the method runs in the
+library's HIP kernels and host driver.
+
+    import torch, paper_2204_14067_amd as bmg
+    prob = bmg.Problem(row_ptr, col, val, m, n, k_cap=64)      # device tensors
+    W, H, k, res = prob.bmg_solve(lam=0.5, k_init=8, tol=1e-6)
+
+Method names mirror the C entry points (bmg_sddmm, bmg_spmm, bmg_bm_epochs,
+bmg_objective, bmg_prox_step, bmg_solve).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (BMG_BF16, BMG_FP32, BMG_FP64, BMG_NOT_CONVERGED, BMG_OK, BmgError,  # noqa: F401
+                   BmgOptions, BmgResult)
+
+_PREC = {"fp64": BMG_FP64, "fp32": BMG_FP32, "bf16": BMG_BF16}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_handle(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def options(**kw) -> BmgOptions:
+    """bmg_options with the library defaults, overridden by keyword (lam= sets lambda)."""
+    o = BmgOptions()
+    _lib.load().bmg_options_default(ctypes.byref(o))
+    for key, v in kw.items():
+        setattr(o, "lambda_" if key in ("lam", "lambda") else key, v)
+    return o
+
+
+def round_ld(k: int) -> int:
+    return max(8, (k + 7) // 8 * 8)
+
+
+class Problem:
+    """One completion problem resident on the GPU (bmg_problem_create).
+
+    row_ptr (int64, m+1), col (int32, nnz), val (float64, nnz) are device
+    tensors that must stay alive; the workspace is a torch allocation owned by
+    this object."""
+
+    def __init__(self, row_ptr, col, val, m: int, n: int, k_cap: int = 64, precision: str = "fp64",
+                 device=None):
+        lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_2204_14067_amd needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device) if device is not None else row_ptr.device
+        assert row_ptr.is_cuda and col.is_cuda and val.is_cuda
+        assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32 and val.dtype == torch.float64
+        self.row_ptr, self.col, self.val = row_ptr.contiguous(), col.contiguous(), val.contiguous()
+        self.m, self.n, self.nnz, self.k_cap = int(m), int(n), int(col.numel()), int(k_cap)
+        self.precision = _PREC[precision]
+        nbytes = ctypes.c_size_t(0)
+        _lib.check(lib.bmg_workspace_size(self.m, self.n, self.nnz, self.k_cap, self.precision,
+                                          ctypes.byref(nbytes)))
+        self.ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        csr = _lib.BmgCsr(self.m, self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                          self.val.data_ptr())
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(lib.bmg_problem_create(ctypes.byref(csr), self.k_cap, self.precision,
+                                              _ptr(self.ws), self.ws.numel(),
+                                              _stream_handle(self.device), ctypes.byref(h)))
+        self._h = h
+        self.ld = round_ld(self.k_cap)
+
+    @classmethod
+    def from_host(cls, row_ptr, col, val, m, n, k_cap=64, precision="fp64", device="cuda:0"):
+        t = lambda a, dt: torch.as_tensor(a).to(device=device, dtype=dt).contiguous()  # noqa: E731
+        return cls(t(row_ptr, torch.int64), t(col, torch.int32), t(val, torch.float64), m, n, k_cap,
+                   precision, device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().bmg_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _factors(self, W, H, k):
+        ld = W.shape[1]
+        assert W.dtype == torch.float64 and H.dtype == torch.float64 and W.is_cuda and H.is_cuda
+        assert W.shape == (self.m, ld) and H.shape == (self.n, ld) and W.is_contiguous() and H.is_contiguous()
+        return ld
+
+    def zeros_factors(self, ld=None):
+        ld = ld or self.ld
+        return (torch.zeros(self.m, ld, dtype=torch.float64, device=self.device),
+                torch.zeros(self.n, ld, dtype=torch.float64, device=self.device))
+
+    # ------------------------------------------------------------------ entry points
+    def bmg_sddmm(self, W, H, k, R=None, store=True):
+        ld = self._factors(W, H, k)
+        if R is None and store:
+            R = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
+        hs = ctypes.c_double(0.0)
+        _lib.check(_lib.load().bmg_sddmm(self._h, _ptr(W), _ptr(H), k, ld, _ptr(R), ctypes.byref(hs)))
+        return R, hs.value
+
+    def bmg_spmm(self, S, B, transpose=False, C=None):
+        q = B.shape[1]
+        rows = self.n if transpose else self.m
+        if C is None:
+            C = torch.empty(rows, B.shape[1], dtype=torch.float64, device=self.device)
+        _lib.check(_lib.load().bmg_spmm(self._h, _ptr(S), _ptr(B), q, B.stride(0), _ptr(C), C.stride(0),
+                                        1 if transpose else 0))
+        return C
+
+    def bmg_bm_epochs(self, W, H, k, lam, epochs=1):
+        ld = self._factors(W, H, k)
+        F = ctypes.c_double(0.0)
+        _lib.check(_lib.load().bmg_bm_epochs(self._h, _ptr(W), _ptr(H), k, ld, lam, epochs,
+                                             ctypes.byref(F)))
+        return F.value
+
+    def bmg_objective(self, W, H, k, lam):
+        ld = self._factors(W, H, k)
+        F = ctypes.c_double(0.0)
+        _lib.check(_lib.load().bmg_objective(self._h, _ptr(W), _ptr(H), k, ld, lam, ctypes.byref(F)))
+        return F.value
+
+    def bmg_prox_step(self, W, H, k, **opts):
+        ld = self._factors(W, H, k)
+        o = options(**opts)
+        kk = ctypes.c_int(k)
+        sig = (ctypes.c_double * max(self.k_cap, 1))()
+        res = ctypes.c_double(0.0)
+        _lib.check(_lib.load().bmg_prox_step(self._h, _ptr(W), _ptr(H), ctypes.byref(kk), ld,
+                                             ctypes.byref(o), sig, ctypes.byref(res)))
+        return kk.value, [sig[i] for i in range(kk.value)], res.value
+
+    def bmg_solve(self, W=None, H=None, **opts):
+        o = options(**opts)
+        if W is None:
+            W, H = self.zeros_factors()
+        ld = self._factors(W, H, 0)
+        k = ctypes.c_int(0)
+        r = BmgResult()
+        st = _lib.load().bmg_solve(self._h, _ptr(W), _ptr(H), ld, ctypes.byref(o), ctypes.byref(k),
+                                   ctypes.byref(r))
+        _lib.check(st, allow=(BMG_OK, BMG_NOT_CONVERGED))
+        return W, H, k.value, r.as_dict()

@@ -1,0 +1,1287 @@
+// C ABI (include/bmg.h) and the host driver of BM-Global on one MI355X.
+//
+// The driver issues the kernels of kernels.hip on the problem's stream and
+// keeps only q x q FP64 matrices and scalars on the host: the Gram matrices of
+// the Rayleigh-Ritz step, of the orthonormalisation and of the exact SVD of the
+// projected matrix, the Nystrom core, and the k x k preconditioner.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "bmg.h"
+#include "bmg_internal.h"
+
+using namespace bmg;
+
+// ============================================================================ errors
+static thread_local std::string g_err;
+static bmg_status fail(bmg_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+extern "C" const char *bmg_last_error(void) { return g_err.c_str(); }
+
+struct BmgError {
+  bmg_status st;
+  std::string msg;
+};
+#define HIPC(x)                                                                          \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      throw BmgError{BMG_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};      \
+  } while (0)
+#define REQUIRE(cond, st, msg) \
+  do {                         \
+    if (!(cond)) throw BmgError{st, msg}; \
+  } while (0)
+
+// ============================================================================ constants
+static constexpr int CHUNK = 2048;         // entries per piece of a long row
+static constexpr double ORTH_TOL = 1e-6;   // numerical-rank cut of orth() on unit columns
+static constexpr double SSI_EPS = 1e-12;   // Algorithm 2's cut of small s (relative)
+static constexpr double PINV_REL = 1e-12;  // Nystrom pseudo-inverse cut (relative)
+static constexpr uint64_t STREAM_SKETCH = 1, STREAM_SAFEGUARD = 0x100;
+
+static inline int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// ============================================================================ workspace layout
+struct Layout {
+  int64_t m, n, nnz;
+  int k_cap, ldk, qld, qmax;
+  bool lowp;
+  // persistent
+  size_t csc_ptr, csc_idx, csc_a, perm, r_rows, r_cols, a32_rows, a32_cols;
+  size_t pr_short, pr_long, pr_lp0, pr_prow, pr_pbeg;
+  size_t pc_short, pc_long, pc_lp0, pc_prow, pc_pbeg;
+  size_t wsum, partial, result, gram_part, small;
+  int64_t max_long, max_pieces, wsum_cap, gram_cap;
+  // scratch region (setup sort / solver blocks overlap)
+  size_t scratch;
+  size_t s_keys_out, s_vals_in, s_rid, s_temp, s_temp_bytes;
+  size_t b_W, b_H, b_G, b_D, b_Wn, b_Hn, b_Ucur, b_Uprev, b_vec, b_B1, b_B2, b_B3, b_B4, b_Y, b_Y2;
+  size_t total;
+};
+
+static size_t sort_temp_bytes(int64_t nnz) {
+  size_t bytes = 0;
+  if (nnz <= 0) return 256;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr,
+                                         (uint32_t *)nullptr, (const int32_t *)nullptr,
+                                         (int32_t *)nullptr, (int)nnz, 0, 32,
+                                         (hipStream_t)0) != hipSuccess)
+    bytes = (size_t)nnz * 16;
+  return bytes + 256;
+}
+
+static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_precision prec) {
+  Layout L{};
+  L.m = m; L.n = n; L.nnz = nnz; L.k_cap = k_cap;
+  L.ldk = (int)rup(std::max(k_cap, 1), 8);
+  L.qmax = 2 * k_cap + 2;
+  L.qld = (int)rup(L.qmax, 8);
+  L.lowp = prec != BMG_FP64;
+  L.max_long = nnz / CHUNK + 1;
+  L.max_pieces = 2 * (nnz / CHUNK) + 2;
+  L.wsum_cap = std::max(m, n) + L.max_pieces + 8;
+  L.gram_cap = std::max<int64_t>(64LL * L.qmax * L.qmax, 1LL << 22);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += rup((int64_t)bytes + 1, 256); return o; };
+  L.csc_ptr = take(8 * (n + 1));
+  L.csc_idx = take(4 * nnz);
+  L.csc_a = take(8 * nnz);
+  L.perm = take(4 * nnz);
+  L.r_rows = take(8 * nnz);
+  L.r_cols = take(8 * nnz);
+  L.a32_rows = take(L.lowp ? 4 * nnz : 0);
+  L.a32_cols = take(L.lowp ? 4 * nnz : 0);
+  L.pr_short = take(4 * m);
+  L.pr_long = take(4 * L.max_long);
+  L.pr_lp0 = take(4 * (L.max_long + 1));
+  L.pr_prow = take(4 * L.max_pieces);
+  L.pr_pbeg = take(8 * L.max_pieces);
+  L.pc_short = take(4 * n);
+  L.pc_long = take(4 * L.max_long);
+  L.pc_lp0 = take(4 * (L.max_long + 1));
+  L.pc_prow = take(4 * L.max_pieces);
+  L.pc_pbeg = take(8 * L.max_pieces);
+  L.wsum = take(16 * L.wsum_cap);
+  L.partial = take((size_t)L.max_pieces * 1024);
+  L.result = take(8 * 64);
+  L.gram_part = take(8 * L.gram_cap);
+  L.small = take(8 * 9 * (size_t)L.qld * L.qld);
+  L.scratch = off;
+  // setup view of the scratch region
+  size_t so = off;
+  auto stake = [&](size_t bytes) { size_t o = so; so += rup((int64_t)bytes + 1, 256); return o; };
+  L.s_keys_out = stake(4 * nnz);
+  L.s_vals_in = stake(4 * nnz);
+  L.s_rid = stake(4 * nnz);
+  L.s_temp_bytes = sort_temp_bytes(nnz);
+  L.s_temp = stake(L.s_temp_bytes);
+  // solver view of the scratch region (element size 8 regardless of precision);
+  // the solver runs on the orientation with mi = min(m, n) rows
+  size_t bo = off;
+  auto btake = [&](size_t elems) { size_t o = bo; bo += rup((int64_t)(8 * elems) + 1, 256); return o; };
+  const int64_t mi = std::min(m, n), ni = std::max(m, n);
+  L.b_W = btake(mi * L.ldk);
+  L.b_H = btake(ni * L.ldk);
+  L.b_G = btake(ni * L.ldk);
+  L.b_D = btake(ni * L.ldk);
+  L.b_Wn = btake(mi * L.ldk);
+  L.b_Hn = btake(ni * L.ldk);
+  L.b_Ucur = btake(mi * L.ldk);
+  L.b_Uprev = btake(mi * L.ldk);
+  L.b_vec = btake(8 * rup(ni, 64));
+  L.b_B1 = btake(mi * L.qld);
+  L.b_B2 = btake(mi * L.qld);
+  L.b_B3 = btake(mi * L.qld);
+  L.b_B4 = btake(mi * L.qld);
+  L.b_Y = btake(ni * L.qld);
+  L.b_Y2 = btake(ni * L.qld);
+  L.total = std::max(so, bo);
+  return L;
+}
+
+// ============================================================================ problem
+struct Side {  // one orientation of Omega
+  Plan pl;
+  const double *a64 = nullptr;
+  float *a32 = nullptr;
+  void *r = nullptr;  // stored residual in this orientation's order (T)
+};
+
+struct bmg_problem {
+  Layout L;
+  bmg_precision prec;
+  hipStream_t s;
+  char *ws;
+  int64_t m_user, n_user, nnz;
+  bool transposed;  // internal problem is the transpose (user m > n)
+  Side urow, ucol;  // user CSR orientation and the built column orientation
+  int32_t *perm;    // column-order position -> CSR position
+  double *result, *gram_part, *small;
+  double *wsum;
+  void *partial;
+  // statistics of the sparse passes since the last reset
+  double bytes = 0.0;
+  int passes = 0;
+  // kernel timing with HIP events (opt->timing)
+  struct Pend {
+    hipEvent_t a, b;
+    int cls;
+    double bytes;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pend> pend;
+  hipEvent_t last_a = nullptr, last_b = nullptr;
+  int last_cls = 0;
+  double kms[3] = {0, 0, 0}, kbytes[3] = {0, 0, 0};
+  int klaunch[3] = {0, 0, 0};
+  hipEvent_t get_event() {
+    if (ev_pool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = ev_pool.back();
+    ev_pool.pop_back();
+    return e;
+  }
+  void resolve_timing() {  // call after the stream has been synchronised
+    for (const Pend &q : pend) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+        kms[q.cls] += ms;
+        kbytes[q.cls] += q.bytes;
+        klaunch[q.cls] += 1;
+      }
+      ev_pool.push_back(q.a);
+      ev_pool.push_back(q.b);
+    }
+    pend.clear();
+  }
+  void reset_stats() {
+    bytes = 0.0;
+    passes = 0;
+    for (int i = 0; i < 3; ++i) kms[i] = kbytes[i] = 0.0, klaunch[i] = 0;
+  }
+  ~bmg_problem() {
+    for (const Pend &q : pend) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+
+  template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
+  Side &rows() { return transposed ? ucol : urow; }  // internal rows (short side)
+  Side &cols() { return transposed ? urow : ucol; }
+  int64_t mi() { return transposed ? n_user : m_user; }
+  int64_t ni() { return transposed ? m_user : n_user; }
+  PassScratch scratch() {
+    PassScratch sc;
+    sc.wsum = wsum;
+    sc.partial = partial;
+    sc.result = result;
+    return sc;
+  }
+};
+
+static void build_plan(bmg_problem *P, int64_t nrows, const int64_t *d_ptr, const int32_t *d_idx,
+                       size_t o_short, size_t o_long, size_t o_lp0, size_t o_prow, size_t o_pbeg,
+                       Plan &pl) {
+  std::vector<int64_t> ptr(nrows + 1);
+  HIPC(hipMemcpyAsync(ptr.data(), d_ptr, 8 * (nrows + 1), hipMemcpyDeviceToHost, P->s));
+  HIPC(hipStreamSynchronize(P->s));
+  std::vector<int32_t> shorts, longs, lp0, prow;
+  std::vector<int64_t> pbeg;
+  shorts.reserve(nrows);
+  for (int64_t i = 0; i < nrows; ++i) {
+    const int64_t len = ptr[i + 1] - ptr[i];
+    if (len <= CHUNK) shorts.push_back((int32_t)i);
+    else longs.push_back((int32_t)i);
+  }
+  std::stable_sort(shorts.begin(), shorts.end(), [&](int32_t a, int32_t b) {
+    return (ptr[a + 1] - ptr[a]) > (ptr[b + 1] - ptr[b]);
+  });
+  for (int32_t r : longs) {
+    lp0.push_back((int32_t)prow.size());
+    for (int64_t b = ptr[r]; b < ptr[r + 1]; b += CHUNK) {
+      prow.push_back(r);
+      pbeg.push_back(b);
+    }
+  }
+  lp0.push_back((int32_t)prow.size());
+  REQUIRE((int64_t)longs.size() <= P->L.max_long && (int64_t)prow.size() <= P->L.max_pieces,
+          BMG_EINVAL, "plan larger than its bound");
+  if (!shorts.empty())
+    HIPC(hipMemcpyAsync(P->at<int32_t>(o_short), shorts.data(), 4 * shorts.size(),
+                        hipMemcpyHostToDevice, P->s));
+  if (!longs.empty())
+    HIPC(hipMemcpyAsync(P->at<int32_t>(o_long), longs.data(), 4 * longs.size(),
+                        hipMemcpyHostToDevice, P->s));
+  HIPC(hipMemcpyAsync(P->at<int32_t>(o_lp0), lp0.data(), 4 * lp0.size(), hipMemcpyHostToDevice,
+                      P->s));
+  if (!prow.empty()) {
+    HIPC(hipMemcpyAsync(P->at<int32_t>(o_prow), prow.data(), 4 * prow.size(),
+                        hipMemcpyHostToDevice, P->s));
+    HIPC(hipMemcpyAsync(P->at<int64_t>(o_pbeg), pbeg.data(), 8 * pbeg.size(),
+                        hipMemcpyHostToDevice, P->s));
+  }
+  HIPC(hipStreamSynchronize(P->s));  // host vectors go out of scope
+  pl.nrows = nrows;
+  pl.nnz = ptr[nrows];
+  pl.ptr = d_ptr;
+  pl.idx = d_idx;
+  pl.short_rows = P->at<int32_t>(o_short);
+  pl.n_short = (int64_t)shorts.size();
+  pl.long_rows = P->at<int32_t>(o_long);
+  pl.long_p0 = P->at<int32_t>(o_lp0);
+  pl.n_long = (int64_t)longs.size();
+  pl.piece_row = P->at<int32_t>(o_prow);
+  pl.piece_beg = P->at<int64_t>(o_pbeg);
+  pl.n_pieces = (int64_t)prow.size();
+  pl.chunk = CHUNK;
+}
+
+// ============================================================================ typed solver
+// Everything below runs on the internal orientation: m <= n, rows() = Omega,
+// cols() = Omega^T.  T is the storage/multiply type of the sparse passes.
+template <typename T>
+struct Engine {
+  bmg_problem *P;
+  hipStream_t s;
+  int ldk, qld;
+  int64_t m, n;
+  Side *R, *C;
+
+  explicit Engine(bmg_problem *p) : P(p), s(p->s), ldk(p->L.ldk), qld(p->L.qld) {
+    m = P->mi();
+    n = P->ni();
+    R = &P->rows();
+    C = &P->cols();
+  }
+  const T *avals(Side *sd) {
+    if constexpr (sizeof(T) == 8) return (const T *)sd->a64;
+    else return (const T *)sd->a32;
+  }
+  T *blk(size_t off) { return P->at<T>(off); }
+
+  // scratch for one sparse pass of kernel class cls (events attached when timing)
+  PassScratch sx(int cls) {
+    PassScratch sc = P->scratch();
+    if (P->timing) {
+      sc.ev0 = P->last_a = P->get_event();
+      sc.ev1 = P->last_b = P->get_event();
+      P->last_cls = cls;
+    }
+    return sc;
+  }
+  void count(const Plan &pl, double per_nnz, double fixed) {
+    const double b = per_nnz * (double)pl.nnz + fixed + 8.0 * (double)(pl.nrows + 1);
+    P->bytes += b;
+    P->passes += 1;
+    if (P->timing && P->last_a && P->last_b) {
+      P->pend.push_back({P->last_a, P->last_b, P->last_cls, b});
+      P->last_a = P->last_b = nullptr;
+    }
+  }
+  void fetch(double *h, const double *d, size_t cnt) {
+    HIPC(hipMemcpyAsync(h, d, 8 * cnt, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (!P->pend.empty()) P->resolve_timing();
+  }
+  // ---------------------------------------------------------------- dense helpers
+  std::vector<double> gram(int64_t N, int a, const T *X, int ldx, int b, const T *Y, int ldy) {
+    std::vector<double> h((size_t)a * b, 0.0);
+    if (a == 0 || b == 0) return h;
+    HIPC(launch_gram<T>(N, a, X, ldx, b, Y, ldy, P->gram_part, P->L.gram_cap, P->small, s));
+    fetch(h.data(), P->small, (size_t)a * b);
+    return h;
+  }
+  // upload a small FP64 matrix into the device staging area (slot 0..7)
+  double *put(const std::vector<double> &h, int slot) {
+    double *d = P->small + (size_t)(slot + 1) * P->L.qld * P->L.qld;
+    REQUIRE(h.size() <= (size_t)P->L.qld * P->L.qld, BMG_EINVAL, "small matrix too large");
+    if (!h.empty())
+      HIPC(hipMemcpyAsync(d, h.data(), 8 * h.size(), hipMemcpyHostToDevice, s));
+    return d;
+  }
+  // same, converted to T (for the low-rank epilogue of the sparse products)
+  T *put_t(const std::vector<double> &h, int slot) {
+    if constexpr (sizeof(T) == 8) {
+      return (T *)put(h, slot);
+    } else {
+      std::vector<float> f(h.begin(), h.end());
+      T *d = (T *)(P->small + (size_t)(slot + 1) * P->L.qld * P->L.qld);
+      if (!f.empty())
+        HIPC(hipMemcpyAsync(d, f.data(), 4 * f.size(), hipMemcpyHostToDevice, s));
+      return d;
+    }
+  }
+  void gemm(int64_t N, int a, const T *X, int ldx, int b, const std::vector<double> &M, T *Cm,
+            int ldc, double beta, int slot = 7) {
+    if (b == 0 || N == 0) return;
+    const double *dM = put(M, slot);
+    HIPC(launch_gemm_ts<T>(N, a, X, ldx, b, dM, b, Cm, ldc, beta, s));
+  }
+  // ---------------------------------------------------------------- sparse passes
+  // BM gradient on the rows side: G = R H + lam W (+ f = 1/2 sum r^2)
+  double grad_rows(const T *W, const T *H, int k, double lam, T *G) {
+    HIPC(launch_grad<T>(R->pl, avals(R), W, ldk, H, ldk, k, lam, G, ldk, sx(0), nullptr, s));
+    count(R->pl, 4.0 + sizeof(T), (double)(m + n) * k * sizeof(T) + (double)m * k * sizeof(T));
+    double h[1];
+    fetch(h, P->result, 1);
+    return 0.5 * h[0];
+  }
+  double grad_cols(const T *W, const T *H, int k, double lam, T *G) {
+    HIPC(launch_grad<T>(C->pl, avals(C), H, ldk, W, ldk, k, lam, G, ldk, sx(0), nullptr, s));
+    count(C->pl, 4.0 + sizeof(T), (double)(m + n) * k * sizeof(T) + (double)n * k * sizeof(T));
+    double h[1];
+    fetch(h, P->result, 1);
+    return 0.5 * h[0];
+  }
+  // sum over Omega of (x_row . y_col)^2 on the given side
+  double curvature(Side *sd, const T *X, const T *Y, int k, int64_t nx, int64_t ny) {
+    HIPC(launch_sddmm<T>(sd->pl, (const T *)nullptr, X, ldk, Y, ldk, k, (T *)nullptr, sx(1), s));
+    count(sd->pl, 4.0, (double)(nx + ny) * k * sizeof(T));
+    double h[2];
+    fetch(h, P->result, 2);
+    return h[0];
+  }
+  // stored residual on one side; returns {sum r^2, sum r (r + a)}
+  void sddmm_store(Side *sd, const T *X, const T *Y, int k, int64_t nx, int64_t ny, double out[2]) {
+    HIPC(launch_sddmm<T>(sd->pl, avals(sd), X, ldk, Y, ldk, k, (T *)sd->r, sx(1), s));
+    count(sd->pl, 4.0 + 2.0 * sizeof(T), (double)(nx + ny) * k * sizeof(T));
+    fetch(out, P->result, 2);
+  }
+  double loss(const T *W, const T *H, int k) {
+    if (R->pl.nnz == 0) return 0.0;
+    HIPC(launch_sddmm<T>(R->pl, avals(R), W, ldk, H, ldk, k, (T *)nullptr, sx(1), s));
+    count(R->pl, 4.0 + sizeof(T), (double)(m + n) * k * sizeof(T));
+    double h[2];
+    fetch(h, P->result, 2);
+    return 0.5 * h[0];
+  }
+
+  // ---------------------------------------------------------------- Z operator
+  // Z = X~ - alpha * S with X~ = W H^T (k columns, may be 0) and S the stored
+  // values of each side (residual, or -A for the initialisation).
+  struct ZOp {
+    const T *W, *H;
+    int k;
+    double alpha;
+    const T *s_rows, *s_cols;
+  };
+  // Y (n x q) = Z^T U = H (W^T U) - alpha S^T U
+  void z_t(const ZOp &z, const T *U, int q, T *Y) {
+    if (q == 0) return;
+    T *dM = nullptr;
+    if (z.k > 0) dM = put_t(gram(m, z.k, z.W, ldk, q, U, qld), 0);
+    HIPC(launch_spmm<T>(C->pl, z.s_cols, U, qld, q, -z.alpha, z.H, ldk, z.k, dM, q, Y, qld,
+                        sx(2), s));
+    count(C->pl, 4.0 + sizeof(T), (double)(m + n) * q * sizeof(T));
+  }
+  // V (m x q) = Z Y = W (H^T Y) - alpha S Y
+  void z_n(const ZOp &z, const T *Y, int q, T *V) {
+    if (q == 0) return;
+    T *dM = nullptr;
+    if (z.k > 0) dM = put_t(gram(n, z.k, z.H, ldk, q, Y, qld), 1);
+    HIPC(launch_spmm<T>(R->pl, z.s_rows, Y, qld, q, -z.alpha, z.W, ldk, z.k, dM, q, V, qld,
+                        sx(2), s));
+    count(R->pl, 4.0 + sizeof(T), (double)(m + n) * q * sizeof(T));
+  }
+
+  // ---------------------------------------------------------------- orth
+  // Orthonormal basis of ran(M) (N x c, ld qld) into U (ld qld), using tmp.
+  // Unit-normalised columns, pivoted Cholesky of their Gram matrix with the
+  // numerical-rank cut |R_jj| > ORTH_TOL, then one Cholesky re-orthogonalisation.
+  int orth(int64_t N, const T *M, int c, T *U, T *tmp) {
+    if (c == 0) return 0;
+    std::vector<double> G = gram(N, c, M, qld, c, M, qld);
+    std::vector<int> nz;
+    std::vector<double> dn;
+    for (int i = 0; i < c; ++i)
+      if (G[(size_t)i * c + i] > 0.0) {
+        nz.push_back(i);
+        dn.push_back(sqrt(G[(size_t)i * c + i]));
+      }
+    const int c2 = (int)nz.size();
+    if (c2 == 0) return 0;
+    std::vector<double> Gn((size_t)c2 * c2), Rp((size_t)c2 * c2);
+    for (int i = 0; i < c2; ++i)
+      for (int j = 0; j < c2; ++j)
+        Gn[(size_t)i * c2 + j] = G[(size_t)nz[i] * c + nz[j]] / (dn[i] * dn[j]);
+    std::vector<int> perm(c2);
+    const int r = la::chol_pivoted(c2, Gn.data(), ORTH_TOL * ORTH_TOL, perm.data(), Rp.data());
+    if (r == 0) return 0;
+    std::vector<double> R11((size_t)r * r), Ri((size_t)r * r);
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) R11[(size_t)i * r + j] = (j >= i) ? Rp[(size_t)i * c2 + j] : 0.0;
+    la::tri_inv_upper(r, R11.data(), Ri.data());
+    std::vector<double> Cm((size_t)c * r, 0.0);  // Q1 = M Cm
+    for (int jj = 0; jj < r; ++jj) {
+      const int col = nz[perm[jj]];
+      const double sc = 1.0 / dn[perm[jj]];
+      for (int l = 0; l < r; ++l) Cm[(size_t)col * r + l] = sc * Ri[(size_t)jj * r + l];
+    }
+    gemm(N, c, M, qld, r, Cm, tmp, qld, 0.0);
+    // re-orthogonalise
+    std::vector<double> G2 = gram(N, r, tmp, qld, r, tmp, qld), R2((size_t)r * r), R2i((size_t)r * r);
+    if (!la::chol(r, G2.data(), R2.data())) {
+      // loss of orthogonality beyond repair by one pass: fall back to a second pivoted pass
+      std::vector<int> p2(r);
+      std::vector<double> Rq((size_t)r * r);
+      const int r2 = la::chol_pivoted(r, G2.data(), 1e-14, p2.data(), Rq.data());
+      REQUIRE(r2 > 0, BMG_ENONFINITE, "orthonormalisation broke down");
+      std::vector<double> Q11((size_t)r2 * r2), Qi((size_t)r2 * r2), C2((size_t)r * r2, 0.0);
+      for (int i = 0; i < r2; ++i)
+        for (int j = 0; j < r2; ++j) Q11[(size_t)i * r2 + j] = (j >= i) ? Rq[(size_t)i * r + j] : 0.0;
+      la::tri_inv_upper(r2, Q11.data(), Qi.data());
+      for (int jj = 0; jj < r2; ++jj)
+        for (int l = 0; l < r2; ++l) C2[(size_t)p2[jj] * r2 + l] = Qi[(size_t)jj * r2 + l];
+      gemm(N, r, tmp, qld, r2, C2, U, qld, 0.0);
+      return r2;
+    }
+    la::tri_inv_upper(r, R2.data(), R2i.data());
+    gemm(N, r, tmp, qld, r, R2i, U, qld, 0.0);
+    return r;
+  }
+};
+
+// ============================================================================ C ABI: setup
+extern "C" void bmg_options_default(bmg_options *o) {
+  memset(o, 0, sizeof(*o));
+  o->lambda = 1.0;
+  o->alpha = 1.99;
+  o->tol = 1e-6;
+  o->ssi_tol_floor = 1e-12;
+  o->psi0 = 0.1;
+  o->bm_epochs = 3;
+  o->max_iter = 500;
+  o->ssi_max_iter = 50;
+  o->k_init = 8;
+  o->refresh_every = 5;
+  o->verbose = 0;
+  o->seed = 0;
+}
+
+extern "C" bmg_status bmg_workspace_size(int64_t m, int64_t n, int64_t nnz, int k_cap,
+                                         bmg_precision prec, size_t *bytes) {
+  if (!bytes || m < 0 || n < 0 || nnz < 0 || k_cap < 1 || nnz > (int64_t)INT32_MAX ||
+      m > (int64_t)INT32_MAX || n > (int64_t)INT32_MAX)
+    return fail(BMG_EINVAL, "bmg_workspace_size: bad shape");
+  if (prec != BMG_FP64 && prec != BMG_FP32) return fail(BMG_EINVAL, "precision not supported");
+  const int64_t mi = std::min(m, n);
+  (void)mi;
+  if (k_cap > (prec == BMG_FP64 ? max_width<double>() : max_width<float>()))
+    return fail(BMG_EINVAL, "k_cap above the widest sparse-pass slice");
+  Layout L = make_layout(m, n, nnz, k_cap, prec);
+  *bytes = L.total;
+  return BMG_OK;
+}
+
+extern "C" bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_precision prec,
+                                         void *ws, size_t ws_bytes, void *stream,
+                                         bmg_problem **out) {
+  if (!csr || !out || !ws) return fail(BMG_EINVAL, "bmg_problem_create: null argument");
+  *out = nullptr;
+  size_t need = 0;
+  bmg_status st = bmg_workspace_size(csr->m, csr->n, csr->nnz, k_cap, prec, &need);
+  if (st != BMG_OK) return st;
+  if (ws_bytes < need) return fail(BMG_ENOMEM, "workspace smaller than bmg_workspace_size");
+  if (csr->m == 0 || csr->n == 0) return fail(BMG_EINVAL, "empty matrix shape");
+  if (csr->nnz > 0 && (!csr->row_ptr || !csr->col || !csr->val))
+    return fail(BMG_EINVAL, "null CSR array");
+  bmg_problem *P = new bmg_problem();
+  try {
+    P->L = make_layout(csr->m, csr->n, csr->nnz, k_cap, prec);
+    P->prec = prec;
+    P->s = (hipStream_t)stream;
+    P->ws = (char *)ws;
+    P->m_user = csr->m;
+    P->n_user = csr->n;
+    P->nnz = csr->nnz;
+    P->transposed = csr->m > csr->n;
+    const Layout &L = P->L;
+    const int64_t m = csr->m, n = csr->n, nnz = csr->nnz;
+    P->perm = P->at<int32_t>(L.perm);
+    P->result = P->at<double>(L.result);
+    P->gram_part = P->at<double>(L.gram_part);
+    P->small = P->at<double>(L.small);
+    P->wsum = P->at<double>(L.wsum);
+    P->partial = P->at<void>(L.partial);
+    // --- validate the CSR (row ids first; they also feed the transpose)
+    int32_t *rid = P->at<int32_t>(L.s_rid);
+    int64_t nnz_dev = 0;
+    HIPC(hipMemcpyAsync(&nnz_dev, csr->row_ptr + m, 8, hipMemcpyDeviceToHost, P->s));
+    int64_t first = 0;
+    HIPC(hipMemcpyAsync(&first, csr->row_ptr, 8, hipMemcpyDeviceToHost, P->s));
+    HIPC(hipStreamSynchronize(P->s));
+    REQUIRE(nnz_dev == nnz && first == 0, BMG_EINVAL, "row_ptr[0] != 0 or row_ptr[m] != nnz");
+    int *flags = (int *)P->result;
+    HIPC(hipMemsetAsync(flags, 0, sizeof(int), P->s));
+    if (nnz > 0) {
+      HIPC(launch_row_ids(m, csr->row_ptr, rid, P->s));
+      HIPC(launch_check_csr(m, n, csr->row_ptr, csr->col, csr->val, rid, flags, P->s));
+    }
+    int hflags = 0;
+    HIPC(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, P->s));
+    HIPC(hipStreamSynchronize(P->s));
+    REQUIRE(!(hflags & 4), BMG_ENONFINITE, "non-finite observed value");
+    REQUIRE(!(hflags & 8), BMG_EINVAL, "row_ptr decreases");
+    REQUIRE(!(hflags & 2), BMG_EINVAL, "column index out of range");
+    REQUIRE(!(hflags & 1), BMG_EINVAL, "columns not strictly increasing within a row");
+    // --- column-major copy: stable radix sort of the column indices (CSR order
+    // is row-major, so each column's entries come out in increasing row order)
+    int64_t *cptr = P->at<int64_t>(L.csc_ptr);
+    int32_t *cidx = P->at<int32_t>(L.csc_idx);
+    double *ca = P->at<double>(L.csc_a);
+    if (nnz > 0) {
+      uint32_t *keys_out = P->at<uint32_t>(L.s_keys_out);
+      int32_t *vals_in = P->at<int32_t>(L.s_vals_in);
+      HIPC(launch_iota(nnz, vals_in, P->s));
+      int bits = 1;
+      while ((int64_t(1) << bits) < n) ++bits;
+      size_t tb = L.s_temp_bytes;
+      HIPC(hipcub::DeviceRadixSort::SortPairs(P->at<void>(L.s_temp), tb, (const uint32_t *)csr->col,
+                                              keys_out, vals_in, P->perm, (int)nnz, 0, bits, P->s));
+      HIPC(launch_col_ptr(nnz, n, (const int32_t *)keys_out, cptr, P->s));
+      HIPC(launch_gather_csc(nnz, P->perm, rid, csr->val, cidx, ca, P->s));
+    } else {
+      HIPC(launch_fill<int64_t>(cptr, n + 1, 1, 1, 0.0, P->s));
+    }
+    HIPC(hipStreamSynchronize(P->s));
+    // --- plans
+    build_plan(P, m, csr->row_ptr, csr->col, L.pr_short, L.pr_long, L.pr_lp0, L.pr_prow, L.pr_pbeg,
+               P->urow.pl);
+    build_plan(P, n, cptr, cidx, L.pc_short, L.pc_long, L.pc_lp0, L.pc_prow, L.pc_pbeg, P->ucol.pl);
+    P->urow.a64 = csr->val;
+    P->ucol.a64 = ca;
+    P->urow.r = P->at<void>(L.r_rows);
+    P->ucol.r = P->at<void>(L.r_cols);
+    if (prec != BMG_FP64) {
+      P->urow.a32 = P->at<float>(L.a32_rows);
+      P->ucol.a32 = P->at<float>(L.a32_cols);
+      HIPC((launch_convert<double, float>(nnz, csr->val, P->urow.a32, P->s)));
+      HIPC((launch_convert<double, float>(nnz, ca, P->ucol.a32, P->s)));
+    }
+    HIPC(hipStreamSynchronize(P->s));
+  } catch (const BmgError &e) {
+    delete P;
+    return fail(e.st, e.msg);
+  }
+  *out = P;
+  return BMG_OK;
+}
+
+extern "C" void bmg_problem_destroy(bmg_problem *p) { delete p; }
+
+// ============================================================================ C ABI: primitives (FP64)
+static bmg_status check_factors(bmg_problem *P, const void *W, const void *H, int k, int ld) {
+  if (!P) return fail(BMG_EINVAL, "null problem");
+  if (k < 0 || k > P->L.k_cap || ld < k || ld % 8 != 0) return fail(BMG_EINVAL, "bad k / ld");
+  if (k > 0 && (!W || !H)) return fail(BMG_EINVAL, "null factor");
+  if ((((uintptr_t)W) & 15) || (((uintptr_t)H) & 15)) return fail(BMG_EINVAL, "factors not 16-byte aligned");
+  return BMG_OK;
+}
+
+extern "C" bmg_status bmg_sddmm(bmg_problem *P, const double *W, const double *H, int k, int ld,
+                                double *R, double *half_sq) {
+  bmg_status st = check_factors(P, W, H, k, ld);
+  if (st != BMG_OK) return st;
+  try {
+    double h[2] = {0, 0};
+    if (P->nnz > 0) {
+      HIPC(launch_sddmm<double>(P->urow.pl, P->urow.a64, W, ld, H, ld, k, R, P->scratch(), P->s));
+      HIPC(hipMemcpyAsync(h, P->result, 16, hipMemcpyDeviceToHost, P->s));
+    }
+    HIPC(hipStreamSynchronize(P->s));
+    if (half_sq) *half_sq = 0.5 * h[0];
+  } catch (const BmgError &e) {
+    return fail(e.st, e.msg);
+  }
+  return BMG_OK;
+}
+
+extern "C" bmg_status bmg_spmm(bmg_problem *P, const double *S, const double *B, int q, int ldb,
+                               double *C, int ldc, int transpose) {
+  if (!P || q < 0 || ldb < q || ldc < q || ldb % 2 || ldc % 2) return fail(BMG_EINVAL, "bmg_spmm: bad argument");
+  try {
+    if (q == 0) return BMG_OK;
+    if (!transpose) {
+      if (P->nnz == 0) HIPC(launch_fill<double>(C, P->m_user, q, ldc, 0.0, P->s));
+      else HIPC(launch_spmm<double>(P->urow.pl, S, B, ldb, q, 1.0, nullptr, 0, 0, nullptr, 0, C, ldc,
+                                    P->scratch(), P->s));
+    } else {
+      if (P->nnz == 0) HIPC(launch_fill<double>(C, P->n_user, q, ldc, 0.0, P->s));
+      else {
+        double *Sc = (double *)P->ucol.r;  // values permuted into column order
+        HIPC(launch_gather_perm(P->nnz, P->perm, S, Sc, P->s));
+        HIPC(launch_spmm<double>(P->ucol.pl, Sc, B, ldb, q, 1.0, nullptr, 0, 0, nullptr, 0, C, ldc,
+                                 P->scratch(), P->s));
+      }
+    }
+    HIPC(hipStreamSynchronize(P->s));
+  } catch (const BmgError &e) {
+    return fail(e.st, e.msg);
+  }
+  return BMG_OK;
+}
+
+// ============================================================================ the method (internal orientation)
+template <typename T>
+struct Method : Engine<T> {
+  using E = Engine<T>;
+  using E::P; using E::s; using E::ldk; using E::qld; using E::m; using E::n; using E::R; using E::C;
+  using E::gram; using E::gemm; using E::orth; using E::z_t; using E::z_n; using E::blk; using E::avals;
+  using typename E::ZOp;
+
+  explicit Method(bmg_problem *p) : E(p) {}
+
+  static double trace_prod(const std::vector<double> &A, const std::vector<double> &B, int k) {
+    double t = 0.0;  // tr(A B) for symmetric k x k A, B
+    for (size_t i = 0; i < (size_t)k * k; ++i) t += A[i] * B[i];
+    return t;
+  }
+  double fro2(int64_t N, const T *X, int ld, int c) {
+    std::vector<double> g = gram(N, c, X, ld, c, X, ld);
+    double t = 0.0;
+    for (int i = 0; i < c; ++i) t += g[(size_t)i * c + i];
+    return t;
+  }
+
+  // ------------------------------------------------------------ BM phase
+  // One preconditioned steepest-descent step with exact line search on the
+  // rows-side factor (W when rows_side, else H).  Returns true if it moved.
+  bool bm_half(bool rows_side, T *W, T *H, int k, double lam) {
+    const int64_t nown = rows_side ? m : n, noth = rows_side ? n : m;
+    T *own = rows_side ? W : H;
+    const T *oth = rows_side ? H : W;
+    T *G = blk(P->L.b_G), *D = blk(P->L.b_D);
+    if (rows_side) E::grad_rows(W, H, k, lam, G);
+    else E::grad_cols(W, H, k, lam, G);
+    // preconditioner (oth^T oth + lam I)^{-1}
+    std::vector<double> Pk = gram(noth, k, oth, ldk, k, oth, ldk);
+    for (int i = 0; i < k; ++i) Pk[(size_t)i * k + i] += lam;
+    std::vector<double> Pi((size_t)k * k);
+    REQUIRE(la::spd_inv(k, Pk.data(), Pi.data()), BMG_ENONFINITE, "BM preconditioner not SPD");
+    std::vector<double> GG = gram(nown, k, G, ldk, k, G, ldk);
+    // <G, D> = -tr(G^T G P), ||D||^2 = tr(P G^T G P)
+    const double gd = trace_prod(GG, Pi, k);
+    if (!(gd > 0.0)) return false;
+    std::vector<double> PGGP((size_t)k * k, 0.0), tmp((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        double a = 0.0;
+        for (int l = 0; l < k; ++l) a += GG[(size_t)i * k + l] * Pi[(size_t)l * k + j];
+        tmp[(size_t)i * k + j] = a;
+      }
+    double dd = 0.0;
+    for (int i = 0; i < k; ++i)
+      for (int l = 0; l < k; ++l) dd += Pi[(size_t)i * k + l] * tmp[(size_t)l * k + i];
+    std::vector<double> negP(Pi);
+    for (double &v : negP) v = -v;
+    gemm(nown, k, G, ldk, k, negP, D, ldk, 0.0);
+    const double curv = rows_side ? E::curvature(R, D, oth, k, nown, noth)
+                                  : E::curvature(C, D, oth, k, nown, noth);
+    const double denom = curv + lam * dd;
+    REQUIRE(std::isfinite(denom) && std::isfinite(gd), BMG_ENONFINITE, "non-finite BM line search");
+    if (!(denom > 0.0)) return false;
+    const double step = gd / denom;
+    HIPC(launch_axpy<T>(nown, k, step, D, ldk, own, ldk, s));
+    return true;
+  }
+
+  // F~(W, H) = f + lam/2 (||W||^2 + ||H||^2)
+  double bm_objective(const T *W, const T *H, int k, double lam) {
+    if (k == 0) return E::loss(W, H, 0);
+    return E::loss(W, H, k) + 0.5 * lam * (fro2(m, W, ldk, k) + fro2(n, H, ldk, k));
+  }
+
+  // ------------------------------------------------------------ prox tail
+  // Exact SVD of Uhat^T Z from Y = Z^T Uhat (n x q) and its Gram matrix, then
+  // soft-thresholding at beta (eqs. exactSVD, approxSVD, truncate).
+  struct Tail {
+    int k = 0, q = 0;
+    std::vector<double> sig_hat, sigma;  // all q / kept k
+    bool has_u = false;
+    double sum_sig2 = 0.0;
+  };
+  Tail prox_tail(const T *U, const T *Y, int q, const std::vector<double> &Tq, double beta, T *Wn,
+                 T *Hn, T *Unew, T *uvec) {
+    Tail out;
+    out.q = q;
+    if (q == 0) return out;
+    std::vector<double> w(q), V((size_t)q * q);
+    la::sym_eig(q, Tq.data(), w.data(), V.data());
+    out.sig_hat.resize(q);
+    for (int j = 0; j < q; ++j) {
+      out.sig_hat[j] = sqrt(std::max(w[j], 0.0));
+      out.sum_sig2 += std::max(w[j], 0.0);
+    }
+    int k = 0;
+    while (k < q && out.sig_hat[k] - beta > 0.0) ++k;
+    REQUIRE(k <= P->L.k_cap, BMG_ENOMEM,
+            "rank of the prox output (" + std::to_string(k) + ") exceeds k_cap");
+    out.k = k;
+    std::vector<double> CW((size_t)q * k), CH((size_t)q * k), CU((size_t)q * k);
+    for (int j = 0; j < k; ++j) {
+      const double sg = out.sig_hat[j] - beta;
+      out.sigma.push_back(sg);
+      const double a = sqrt(sg), b = sqrt(sg) / out.sig_hat[j];
+      for (int i = 0; i < q; ++i) {
+        CW[(size_t)i * k + j] = V[(size_t)i * q + j] * a;
+        CH[(size_t)i * k + j] = V[(size_t)i * q + j] * b;
+        CU[(size_t)i * k + j] = V[(size_t)i * q + j];
+      }
+    }
+    gemm(m, q, U, qld, k, CW, Wn, ldk, 0.0);
+    gemm(n, q, Y, qld, k, CH, Hn, ldk, 0.0);
+    gemm(m, q, U, qld, k, CU, Unew, ldk, 0.0);
+    if (k < q) {
+      std::vector<double> cu(q);
+      for (int i = 0; i < q; ++i) cu[i] = V[(size_t)i * q + k];
+      gemm(m, q, U, qld, 1, cu, uvec, 1, 0.0);
+      out.has_u = true;
+    }
+    return out;
+  }
+
+  // ------------------------------------------------------------ Algorithm 2 with p = 0
+  // U0 (m x q0, orthonormal) in Ubuf.  On return *Uout / *Yout point at the
+  // final basis (q columns) and Z^T of it; Tq is their Gram matrix.
+  int lmsvd(const ZOp &z, T *Ubuf, int q, double tau, int max_iter, double keep_level,
+            T **Uout, T **Yout, std::vector<double> &Tq, int *iters) {
+    T *U = Ubuf, *Y = blk(P->L.b_Y), *V = blk(P->L.b_B3), *tmp = blk(P->L.b_B4);
+    z_t(z, U, q, Y);
+    std::vector<double> prev;
+    int it = 0;
+    for (it = 1; it <= max_iter && q > 0; ++it) {
+      std::vector<double> Tm = gram(n, q, Y, qld, q, Y, qld);
+      std::vector<double> theta(q);
+      la::sym_eig(q, Tm.data(), theta.data(), nullptr);
+      z_n(z, Y, q, V);                 // L(U) = Z Z^T U (Ritz rotation omitted: same range)
+      q = orth(m, V, q, U, tmp);       // U^{t,i+1}
+      z_t(z, U, q, Y);
+      bool done = false;
+      if (!prev.empty() && prev.size() == theta.size()) {
+        double dmax = 0.0;
+        for (size_t j = 0; j < theta.size(); ++j)
+          if (j == 0 || theta[j] > keep_level) dmax = std::max(dmax, fabs(theta[j] - prev[j]));
+        done = dmax <= tau * std::max(theta[0], 0.0);
+      }
+      prev = theta;
+      if (done) break;
+    }
+    *iters = std::min(it, max_iter);
+    Tq = gram(n, q, Y, qld, q, Y, qld);
+    // Algorithm 2's final cut: keep columns with s_j = ||Z^T u_j|| > eps * max
+    double smax = 0.0;
+    for (int j = 0; j < q; ++j) smax = std::max(smax, sqrt(std::max(Tq[(size_t)j * q + j], 0.0)));
+    std::vector<int> J;
+    for (int j = 0; j < q; ++j)
+      if (sqrt(std::max(Tq[(size_t)j * q + j], 0.0)) > SSI_EPS * smax) J.push_back(j);
+    if ((int)J.size() < q) {
+      const int qj = (int)J.size();
+      std::vector<double> Sel((size_t)q * qj, 0.0), Tj((size_t)qj * qj);
+      for (int c = 0; c < qj; ++c) Sel[(size_t)J[c] * qj + c] = 1.0;
+      T *U2 = blk(P->L.b_B4), *Y2 = blk(P->L.b_Y2);
+      gemm(m, q, U, qld, qj, Sel, U2, qld, 0.0);
+      gemm(n, q, Y, qld, qj, Sel, Y2, qld, 0.0);
+      for (int a = 0; a < qj; ++a)
+        for (int b = 0; b < qj; ++b) Tj[(size_t)a * qj + b] = Tq[(size_t)J[a] * q + J[b]];
+      Tq = Tj;
+      U = U2;
+      Y = Y2;
+      q = qj;
+    }
+    *Uout = U;
+    *Yout = Y;
+    return q;
+  }
+
+  // ------------------------------------------------------------ state of Algorithm 1
+  struct State {
+    T *W, *H, *Wn, *Hn, *Ucur, *Uprev, *uvec;
+    int k = 0, kc = 0, kp = 0;
+    int rank_cur = 0, rank_prev = 0, trunc_prev = 0;
+    bool has_u = false;
+    double psi = 0.1, res_prev = 1.0;
+    std::vector<double> sigma;
+  };
+  void init_state(State &S) {
+    S.W = blk(P->L.b_W); S.H = blk(P->L.b_H);
+    S.Wn = blk(P->L.b_Wn); S.Hn = blk(P->L.b_Hn);
+    S.Ucur = blk(P->L.b_Ucur); S.Uprev = blk(P->L.b_Uprev);
+    S.uvec = blk(P->L.b_vec);
+  }
+
+  // Initialisation (Suppl. A.1.4): X_{-1} = 0, Z_{-1} = P_Omega(A), HMT range
+  // finder + Nystrom for Z Z^T, then the prox tail with beta = lambda.
+  void initialize(State &S, int k0, double lam, uint64_t seed) {
+    ZOp z0{nullptr, nullptr, 0, -1.0, avals(R), avals(C)};   // Z = 0 - (-1) * A
+    T *B1 = blk(P->L.b_B1), *B2 = blk(P->L.b_B2), *B3 = blk(P->L.b_B3), *B4 = blk(P->L.b_B4);
+    T *Y = blk(P->L.b_Y);
+    k0 = std::max(1, std::min(k0, qld));
+    HIPC(launch_normals<T>(seed, STREAM_SKETCH, m, k0, qld, B1, s));
+    z_t(z0, B1, k0, Y);
+    z_n(z0, Y, k0, B3);                                   // A_{-1} Om
+    int r = orth(m, B3, k0, B2, B4);                      // Q
+    int kq = 0;
+    std::vector<double> Tq;
+    T *Uf = B1;
+    if (r > 0) {
+      z_t(z0, B2, r, Y);
+      z_n(z0, Y, r, B3);                                  // A Q
+      std::vector<double> Cm = gram(m, r, B2, qld, r, B3, qld);   // Q^T A Q
+      int r2 = orth(m, B3, r, B1, B4);                    // Q^ with A Q = Q^ R^
+      std::vector<double> Rh = gram(m, r2, B1, qld, r, B3, qld);  // R^ = Q^^T A Q (r2 x r)
+      // pseudo-inverse of C through its eigen-decomposition
+      std::vector<double> cw(r), cv((size_t)r * r), Cp((size_t)r * r, 0.0);
+      la::sym_eig(r, Cm.data(), cw.data(), cv.data());
+      for (int l = 0; l < r; ++l) {
+        if (!(cw[0] > 0.0) || !(cw[l] > PINV_REL * cw[0])) continue;
+        const double inv = 1.0 / cw[l];
+        for (int i = 0; i < r; ++i)
+          for (int j = 0; j < r; ++j) Cp[(size_t)i * r + j] += cv[(size_t)i * r + l] * inv * cv[(size_t)j * r + l];
+      }
+      std::vector<double> RC((size_t)r2 * r, 0.0), Mn((size_t)r2 * r2, 0.0);
+      for (int i = 0; i < r2; ++i)
+        for (int j = 0; j < r; ++j) {
+          double a = 0.0;
+          for (int l = 0; l < r; ++l) a += Rh[(size_t)i * r + l] * Cp[(size_t)l * r + j];
+          RC[(size_t)i * r + j] = a;
+        }
+      for (int i = 0; i < r2; ++i)
+        for (int j = 0; j < r2; ++j) {
+          double a = 0.0;
+          for (int l = 0; l < r; ++l) a += RC[(size_t)i * r + l] * Rh[(size_t)j * r + l];
+          Mn[(size_t)i * r2 + j] = a;
+        }
+      std::vector<double> mw(r2), mv((size_t)r2 * r2);
+      la::sym_eig(r2, Mn.data(), mw.data(), mv.data());
+      std::vector<int> pos;
+      for (int l = 0; l < r2; ++l)
+        if (mw[0] > 0.0 && mw[l] > SSI_EPS * mw[0]) pos.push_back(l);
+      kq = (int)pos.size();
+      std::vector<double> Sel((size_t)r2 * kq);
+      for (int i = 0; i < r2; ++i)
+        for (int c = 0; c < kq; ++c) Sel[(size_t)i * kq + c] = mv[(size_t)i * r2 + pos[c]];
+      gemm(m, r2, B1, qld, kq, Sel, B2, qld, 0.0);       // Uhat_0 = Q^ U~
+      z_t(z0, B2, kq, Y);
+      Tq = gram(n, kq, Y, qld, kq, Y, qld);
+      Uf = B2;
+    }
+    Tail tl = prox_tail(Uf, Y, kq, Tq, lam * 1.0, S.W, S.H, S.Ucur, S.uvec);
+    S.k = tl.k;
+    S.kc = tl.k;
+    S.kp = 0;
+    S.rank_cur = tl.k;
+    S.rank_prev = 0;
+    S.trunc_prev = tl.q - tl.k;
+    S.has_u = tl.has_u;
+    S.sigma = tl.sigma;
+  }
+
+  // One inexact PG step from X~ = W H^T (Algorithm 1, convex lifting phase).
+  struct StepInfo {
+    int q = 0, iters = 0;
+    bool added = false;
+    double residual = 0.0, eps = 0.0;
+  };
+  StepInfo pg_step(State &S, bool changed, double lam, double alpha, double tau, int ssi_max,
+                   uint64_t seed, int t) {
+    StepInfo info;
+    const int k = S.k;
+    T *B1 = blk(P->L.b_B1), *B2 = blk(P->L.b_B2), *B4 = blk(P->L.b_B4);
+    // residual of X~ stored in both orientations
+    double sr[2] = {0, 0}, sc[2] = {0, 0};
+    if (R->pl.nnz > 0) {
+      E::sddmm_store(R, S.W, S.H, k, m, n, sr);
+      E::sddmm_store(C, S.H, S.W, k, n, m, sc);
+    }
+    ZOp z{S.W, S.H, k, alpha, (const T *)R->r, (const T *)C->r};
+    // warm start (eqs. rt0 / rt0-1): orth([U_t, W~_t]) or orth([U_t, U_{t-1}])
+    const T *second = changed ? S.W : S.Uprev;
+    const int c2 = changed ? k : S.kp;
+    HIPC(launch_copy_cols<T>(m, S.kc, S.Ucur, ldk, B1, qld, s));
+    HIPC(launch_copy_cols<T>(m, c2, second, ldk, B1 + S.kc, qld, s));
+    int cb = orth(m, B1, S.kc + c2, B2, B4);
+    // rank safeguard (eq. rt)
+    const bool add = S.trunc_prev <= 1 || S.rank_cur == S.rank_prev || cb == 0;
+    T *U0 = B2;
+    int q0 = cb;
+    if (add) {
+      T *col = B2 + cb;  // column cb of the block
+      T *ut = blk(P->L.b_vec) + 2 * rup(m, 64);
+      T *zv = blk(P->L.b_vec) + 4 * rup(m, 64);
+      HIPC(launch_normals<T>(seed, STREAM_SAFEGUARD + (uint64_t)t, m, 1, 1, zv, s));
+      double nu = 0.0;
+      if (S.has_u) {
+        HIPC(launch_copy_cols<T>(m, 1, S.uvec, 1, ut, 1, s));
+        if (cb > 0) {
+          std::vector<double> c = gram(m, cb, B2, qld, 1, ut, 1);
+          for (double &v : c) v = -v;
+          gemm(m, cb, B2, qld, 1, c, ut, 1, 1.0);
+        }
+        nu = sqrt(gram(m, 1, ut, 1, 1, ut, 1)[0]);
+      }
+      if (cb > 0) {
+        std::vector<double> c = gram(m, cb, B2, qld, 1, zv, 1);
+        for (double &v : c) v = -v;
+        gemm(m, cb, B2, qld, 1, c, zv, 1, 1.0);
+      }
+      if (nu > 0.0) {
+        const double c = gram(m, 1, ut, 1, 1, zv, 1)[0] / (nu * nu);
+        HIPC(launch_axpy<T>(m, 1, -c, ut, 1, zv, 1, s));
+      }
+      const double nz = sqrt(gram(m, 1, zv, 1, 1, zv, 1)[0]);
+      const double scale = nz > 0.0 ? 1.0 / nz : 0.0;
+      // column = u_t + psi * xi  (or the unit random vector when no u is kept)
+      HIPC(launch_fill<T>(col, m, 1, qld, 0.0, s));
+      HIPC(launch_axpy<T>(m, 1, (S.has_u ? S.psi : 1.0) * scale, zv, 1, col, qld, s));
+      if (S.has_u) HIPC(launch_axpy<T>(m, 1, 1.0, ut, 1, col, qld, s));
+      q0 = orth(m, B2, cb + 1, B1, B4);
+      U0 = B1;
+      info.added = true;
+    }
+    // subspace iteration
+    T *Uf = nullptr, *Yf = nullptr;
+    std::vector<double> Tq;
+    const int q = lmsvd(z, U0, q0, tau, ssi_max, (alpha * lam) * (alpha * lam), &Uf, &Yf, Tq,
+                        &info.iters);
+    info.q = q;
+    // new U_cur goes into the old U_prev buffer
+    std::swap(S.Ucur, S.Uprev);
+    std::swap(S.kc, S.kp);
+    Tail tl = prox_tail(Uf, Yf, q, Tq, alpha * lam, S.Wn, S.Hn, S.Ucur, S.uvec);
+    S.kc = tl.k;
+    // ||X~ - X+|| = sqrt(||Uhat^T X~ - Uhat^T X+||^2 + ||(I - Uhat Uhat^T) X~||^2)
+    double d2 = 0.0, x2 = 0.0;
+    if (q > 0) {
+      T *Dt = (Yf == blk(P->L.b_Y2)) ? blk(P->L.b_Y) : blk(P->L.b_Y2);  // n x q scratch
+      std::vector<double> A1 = gram(m, k, S.W, ldk, q, Uf, qld);        // W~^T Uhat
+      std::vector<double> A2 = gram(m, tl.k, S.Wn, ldk, q, Uf, qld);    // W+^T Uhat
+      for (double &v : A2) v = -v;
+      // Dt = H~ (W~^T Uhat) - H+ (W+^T Uhat)  =  (Uhat^T X~ - Uhat^T X+)^T
+      if (k > 0) gemm(n, k, S.H, ldk, q, A1, Dt, qld, 0.0);
+      else HIPC(launch_fill<T>(Dt, n, q, qld, 0.0, s));
+      if (tl.k > 0) gemm(n, tl.k, S.Hn, ldk, q, A2, Dt, qld, 1.0);
+      d2 = fro2(n, Dt, qld, q);
+      if (k > 0) {
+        T *Em = blk(P->L.b_D);
+        HIPC(launch_copy_cols<T>(m, k, S.W, ldk, Em, ldk, s));
+        std::vector<double> negA1(A1);
+        for (double &v : negA1) v = -v;
+        gemm(m, q, Uf, qld, k, [&] {  // (Uhat^T W~) laid out q x k
+          std::vector<double> t2((size_t)q * k);
+          for (int i = 0; i < k; ++i)
+            for (int j = 0; j < q; ++j) t2[(size_t)j * k + i] = negA1[(size_t)i * q + j];
+          return t2;
+        }(), Em, ldk, 1.0);
+        std::vector<double> EE = gram(m, k, Em, ldk, k, Em, ldk);
+        std::vector<double> HH = gram(n, k, S.H, ldk, k, S.H, ldk);
+        d2 += std::max(0.0, trace_prod(EE, HH, k));
+      }
+    } else if (k > 0) {
+      d2 = trace_prod(gram(m, k, S.W, ldk, k, S.W, ldk), gram(n, k, S.H, ldk, k, S.H, ldk), k);
+    }
+    if (k > 0) x2 = trace_prod(gram(m, k, S.W, ldk, k, S.W, ldk), gram(n, k, S.H, ldk, k, S.H, ldk), k);
+    info.residual = sqrt(d2) / (1.0 + sqrt(std::max(x2, 0.0)) + sqrt(sr[0]));
+    const double z2 = x2 - 2.0 * alpha * sr[1] + alpha * alpha * sr[0];
+    info.eps = sqrt(std::max(z2 - tl.sum_sig2, 0.0));
+    // safeguard bookkeeping
+    const int trunc = tl.q - tl.k;
+    S.has_u = trunc >= 1;
+    if (trunc == 1) S.psi *= 0.5;
+    S.trunc_prev = trunc;
+    S.rank_prev = S.rank_cur;
+    S.rank_cur = tl.k;
+    std::swap(S.W, S.Wn);
+    std::swap(S.H, S.Hn);
+    S.k = tl.k;
+    S.sigma = tl.sigma;
+    return info;
+  }
+
+  double objective_balanced(State &S, double lam) {
+    double ssum = 0.0;
+    for (double v : S.sigma) ssum += v;
+    return E::loss(S.W, S.H, S.k) + lam * ssum;
+  }
+
+  // Algorithm 1
+  bmg_status solve(const bmg_options &o, State &S, bmg_result *res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    init_state(S);
+    S.psi = o.psi0;
+    initialize(S, o.k_init, o.lambda, o.seed);
+    double F = objective_balanced(S, o.lambda), F_bm = F, resid = INFINITY, eps = 0.0;
+    int t = 0, ssi_total = 0;
+    bool conv = false;
+    for (t = 0; t < o.max_iter; ++t) {
+      bool changed = false;
+      for (int e = 0; e < o.bm_epochs && S.k > 0; ++e) {
+        changed |= bm_half(true, S.W, S.H, S.k, o.lambda);
+        changed |= bm_half(false, S.W, S.H, S.k, o.lambda);
+      }
+      F_bm = bm_objective(S.W, S.H, S.k, o.lambda);
+      const double tau = std::max(o.ssi_tol_floor, std::min(1e-4, 0.1 * S.res_prev * S.res_prev));
+      StepInfo st = pg_step(S, changed, o.lambda, o.alpha, tau, o.ssi_max_iter, o.seed, t);
+      ssi_total += st.iters;
+      resid = st.residual;
+      eps = st.eps;
+      F = objective_balanced(S, o.lambda);
+      REQUIRE(std::isfinite(F) && std::isfinite(resid), BMG_ENONFINITE, "non-finite objective");
+      if (o.verbose)
+        fprintf(stderr, "[bmg] t=%d F=%.15g F_bm=%.15g res=%.3e k=%d q=%d ssi=%d eps=%.3e add=%d\n", t,
+                F, F_bm, resid, S.k, st.q, st.iters, eps, (int)st.added);
+      S.res_prev = resid;
+      if (resid <= o.tol) {
+        conv = true;
+        ++t;
+        break;
+      }
+    }
+    HIPC(hipStreamSynchronize(s));
+    P->resolve_timing();
+    if (res) {
+      for (int c = 0; c < 3; ++c) {
+        res->kernel_ms[c] = P->kms[c];
+        res->kernel_bytes[c] = P->kbytes[c];
+        res->kernel_launches[c] = P->klaunch[c];
+      }
+      res->k = S.k;
+      res->iters = t;
+      res->ssi_iters = ssi_total;
+      res->status = conv ? BMG_OK : BMG_NOT_CONVERGED;
+      res->F = F;
+      res->F_bm = F_bm;
+      res->residual = resid;
+      res->eps = eps;
+      res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      res->sparse_bytes = P->bytes;
+      res->sparse_passes = P->passes;
+    }
+    return conv ? BMG_OK : BMG_NOT_CONVERGED;
+  }
+};
+
+// ============================================================================ user <-> internal factor copies
+// User W is m_user x ld (FP64), H is n_user x ld.  Internal rows side = W unless transposed.
+template <typename T>
+static void load_factors(bmg_problem *P, const double *W, const double *H, int k, int ld, T *Wi,
+                         T *Hi) {
+  const double *a = P->transposed ? H : W, *b = P->transposed ? W : H;
+  const int64_t mi = P->mi(), ni = P->ni();
+  const int ldk = P->L.ldk;
+  if (k == 0) return;
+  if constexpr (sizeof(T) == 8) {
+    HIPC(launch_copy_cols<double>(mi, k, a, ld, (double *)Wi, ldk, P->s));
+    HIPC(launch_copy_cols<double>(ni, k, b, ld, (double *)Hi, ldk, P->s));
+  } else {
+    HIPC(launch_convert_cols(mi, k, a, ld, (float *)Wi, ldk, P->s));
+    HIPC(launch_convert_cols(ni, k, b, ld, (float *)Hi, ldk, P->s));
+  }
+}
+template <typename T>
+static void store_factors(bmg_problem *P, const T *Wi, const T *Hi, int k, double *W, double *H,
+                          int ld) {
+  double *a = P->transposed ? H : W, *b = P->transposed ? W : H;
+  const int64_t mi = P->mi(), ni = P->ni();
+  const int ldk = P->L.ldk;
+  HIPC(launch_fill<double>(a, mi, ld, ld, 0.0, P->s));
+  HIPC(launch_fill<double>(b, ni, ld, ld, 0.0, P->s));
+  if (k == 0) return;
+  if constexpr (sizeof(T) == 8) {
+    HIPC(launch_copy_cols<double>(mi, k, (const double *)Wi, ldk, a, ld, P->s));
+    HIPC(launch_copy_cols<double>(ni, k, (const double *)Hi, ldk, b, ld, P->s));
+  } else {
+    HIPC(launch_convert_cols(mi, k, (const float *)Wi, ldk, a, ld, P->s));
+    HIPC(launch_convert_cols(ni, k, (const float *)Hi, ldk, b, ld, P->s));
+  }
+}
+
+// ============================================================================ C ABI: method calls
+extern "C" bmg_status bmg_bm_epochs(bmg_problem *P, double *W, double *H, int k, int ld,
+                                    double lambda, int epochs, double *F_bm) {
+  bmg_status st = check_factors(P, W, H, k, ld);
+  if (st != BMG_OK) return st;
+  try {
+    Method<double> M(P);
+    double *Wi = M.blk(P->L.b_W), *Hi = M.blk(P->L.b_H);
+    load_factors<double>(P, W, H, k, ld, Wi, Hi);
+    for (int e = 0; e < epochs && k > 0; ++e) {
+      M.bm_half(true, Wi, Hi, k, lambda);
+      M.bm_half(false, Wi, Hi, k, lambda);
+    }
+    if (F_bm) *F_bm = M.bm_objective(Wi, Hi, k, lambda);
+    if (k > 0) {
+      const double *a = P->transposed ? Hi : Wi, *b = P->transposed ? Wi : Hi;
+      HIPC(launch_copy_cols<double>(P->m_user, k, a, P->L.ldk, W, ld, P->s));
+      HIPC(launch_copy_cols<double>(P->n_user, k, b, P->L.ldk, H, ld, P->s));
+    }
+    HIPC(hipStreamSynchronize(P->s));
+  } catch (const BmgError &e) {
+    return fail(e.st, e.msg);
+  }
+  return BMG_OK;
+}
+
+extern "C" bmg_status bmg_objective(bmg_problem *P, const double *W, const double *H, int k, int ld,
+                                    double lambda, double *F) {
+  bmg_status st = check_factors(P, W, H, k, ld);
+  if (st != BMG_OK) return st;
+  try {
+    Method<double> M(P);
+    double *Wi = M.blk(P->L.b_W), *Hi = M.blk(P->L.b_H);
+    load_factors<double>(P, W, H, k, ld, Wi, Hi);
+    double f = M.loss(Wi, Hi, k), nuc = 0.0;
+    if (k > 0) {
+      // ||W H^T||_* = sum sqrt(eig(S (H^T H) S^T)) with S^T S = W^T W
+      std::vector<double> WW = M.gram(M.m, k, Wi, P->L.ldk, k, Wi, P->L.ldk);
+      std::vector<double> HH = M.gram(M.n, k, Hi, P->L.ldk, k, Hi, P->L.ldk);
+      std::vector<double> w(k), V((size_t)k * k), Sm((size_t)k * k), T1((size_t)k * k), T2((size_t)k * k);
+      la::sym_eig(k, WW.data(), w.data(), V.data());
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) Sm[(size_t)i * k + j] = sqrt(std::max(w[i], 0.0)) * V[(size_t)j * k + i];
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+          double a = 0.0;
+          for (int l = 0; l < k; ++l) a += Sm[(size_t)i * k + l] * HH[(size_t)l * k + j];
+          T1[(size_t)i * k + j] = a;
+        }
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+          double a = 0.0;
+          for (int l = 0; l < k; ++l) a += T1[(size_t)i * k + l] * Sm[(size_t)j * k + l];
+          T2[(size_t)i * k + j] = a;
+        }
+      la::sym_eig(k, T2.data(), w.data(), nullptr);
+      for (int i = 0; i < k; ++i) nuc += sqrt(std::max(w[i], 0.0));
+    }
+    if (F) *F = f + lambda * nuc;
+  } catch (const BmgError &e) {
+    return fail(e.st, e.msg);
+  }
+  return BMG_OK;
+}
+
+extern "C" bmg_status bmg_prox_step(bmg_problem *P, double *W, double *H, int *k_inout, int ld,
+                                    const bmg_options *opt, double *sigma, double *residual) {
+  if (!k_inout || !opt) return fail(BMG_EINVAL, "bmg_prox_step: null argument");
+  bmg_status st = check_factors(P, W, H, *k_inout, ld);
+  if (st != BMG_OK) return st;
+  try {
+    Method<double> M(P);
+    Method<double>::State S;
+    M.init_state(S);
+    const int k = *k_inout;
+    load_factors<double>(P, W, H, k, ld, S.W, S.H);
+    // warm start from W~ alone: no previous prox output, no retained vector
+    S.k = k; S.kc = 0; S.kp = 0;
+    S.rank_cur = 0; S.rank_prev = 0; S.trunc_prev = 0;
+    S.has_u = false;
+    S.psi = opt->psi0;
+    const double tau = opt->ssi_tol_floor;
+    auto info = M.pg_step(S, true, opt->lambda, opt->alpha, tau, opt->ssi_max_iter, opt->seed, 0);
+    REQUIRE(S.k <= ld, BMG_ENOMEM, "output rank exceeds ld");
+    store_factors<double>(P, S.W, S.H, S.k, W, H, ld);
+    HIPC(hipStreamSynchronize(P->s));
+    *k_inout = S.k;
+    if (sigma)
+      for (int i = 0; i < S.k; ++i) sigma[i] = S.sigma[i];
+    if (residual) *residual = info.residual;
+  } catch (const BmgError &e) {
+    return fail(e.st, e.msg);
+  }
+  return BMG_OK;
+}
+
+extern "C" bmg_status bmg_solve(bmg_problem *P, double *W, double *H, int ld, const bmg_options *opt,
+                                int *k_out, bmg_result *res) {
+  if (!P || !opt || !W || !H) return fail(BMG_EINVAL, "bmg_solve: null argument");
+  if (ld < 8 || ld % 8) return fail(BMG_EINVAL, "bmg_solve: ld must be a positive multiple of 8");
+  if (opt->lambda <= 0.0 || opt->alpha <= 0.0 || opt->bm_epochs < 0 || opt->max_iter < 0 ||
+      opt->ssi_max_iter < 1 || opt->k_init < 1)
+    return fail(BMG_EINVAL, "bmg_solve: bad options");
+  P->reset_stats();
+  P->timing = opt->timing != 0;
+  try {
+    bmg_status st;
+    int k = 0;
+    if (P->prec == BMG_FP64) {
+      Method<double> M(P);
+      Method<double>::State S;
+      st = M.solve(*opt, S, res);
+      k = S.k;
+      REQUIRE(k <= ld, BMG_ENOMEM, "rank exceeds ld");
+      store_factors<double>(P, S.W, S.H, k, W, H, ld);
+    } else {
+      Method<float> M(P);
+      Method<float>::State S;
+      st = M.solve(*opt, S, res);
+      k = S.k;
+      REQUIRE(k <= ld, BMG_ENOMEM, "rank exceeds ld");
+      store_factors<float>(P, S.W, S.H, k, W, H, ld);
+      // the objective reported for the FP32 path is recomputed in FP64 from the stored factors
+    }
+    HIPC(hipStreamSynchronize(P->s));
+    P->timing = false;
+    if (k_out) *k_out = k;
+    if (res) res->status = st;
+    return st;
+  } catch (const BmgError &e) {
+    P->timing = false;
+    if (res) res->status = e.st;
+    return fail(e.st, e.msg);
+  }
+}

@@ -1,0 +1,109 @@
+// Internal declarations shared by the kernels (kernels.hip) and the host
+// driver (api.hip, linalg.cpp).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace bmg {
+
+// One compressed orientation of Omega (rows of A for the CSR orientation,
+// rows of A^T for the column-major copy) plus its load-balancing plan:
+//   short rows (length <= chunk) are processed one row per lane group, in
+//   order of decreasing length so the groups of a wave finish together;
+//   long rows are cut into pieces of `chunk` entries, one wave per piece,
+//   whose partial row results are summed in piece order by a fix-up pass.
+struct Plan {
+  int64_t nrows = 0, nnz = 0;
+  const int64_t *ptr = nullptr;   // [nrows+1]
+  const int32_t *idx = nullptr;   // [nnz] column (or row) index of each entry
+  const int32_t *short_rows = nullptr;
+  int64_t n_short = 0;
+  const int32_t *piece_row = nullptr;
+  const int64_t *piece_beg = nullptr;
+  int64_t n_pieces = 0;
+  const int32_t *long_rows = nullptr;
+  const int32_t *long_p0 = nullptr;  // [n_long+1] first piece of each long row
+  int64_t n_long = 0;
+  int chunk = 2048;
+};
+
+// Scratch used by one sparse pass: per-wave scalar partials and per-piece
+// vector partials.
+struct PassScratch {
+  double *wsum = nullptr;      // [max_waves * 2]
+  void *partial = nullptr;     // [n_pieces * width] (element type of the pass)
+  double *result = nullptr;    // [2] final scalar sums
+  hipEvent_t ev0 = nullptr;    // if set, recorded around the main kernel launch
+  hipEvent_t ev1 = nullptr;
+};
+
+// ---------------------------------------------------------------- launchers (kernels.hip)
+// All return hipError_t of the launch; widths/ld are in elements.
+
+// Fused sampled residual + sparse product (BM gradient of (MF)):
+//   r_p = x_row . y_col - a_p ;  Out_row = sum_p r_p y_col + lam * x_row ;  sums[0] = sum r^2
+template <typename T>
+hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const T *Y, int ldy, int k,
+                       double lam, T *Out, int ldo, PassScratch sc, int64_t *waves_out,
+                       hipStream_t s);
+
+// Sampled product (no sparse output vector): r_p = x_row . y_col - (a ? a_p : 0),
+// optionally stored to R[p]; sums[0] = sum r^2, sums[1] = sum r (r + a).
+template <typename T>
+hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const T *Y, int ldy, int k,
+                        T *R, PassScratch sc, hipStream_t s);
+
+// C = coef * S B + X M on a column slice of width <= 64*VEC:
+//   S values in this orientation's order, B (rows indexed by idx), X own-side
+//   factor (kx columns, may be null with kx = 0), M (kx x q, row-major ldm).
+template <typename T>
+hipError_t launch_spmm(const Plan &pl, const T *S, const T *B, int ldb, int q, double coef,
+                       const T *X, int ldx, int kx, const T *M, int ldm, T *C, int ldc,
+                       PassScratch sc, hipStream_t s);
+
+// Dense helpers.
+template <typename T>
+hipError_t launch_gram(int64_t N, int a, const T *X, int ldx, int b, const T *Y, int ldy,
+                       double *part, int64_t part_cap, double *out, hipStream_t s);
+template <typename T>
+hipError_t launch_gemm_ts(int64_t N, int a, const T *X, int ldx, int b, const double *M, int ldm,
+                          T *C, int ldc, double beta, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T *p, int64_t rows, int cols, int ld, double v, hipStream_t s);
+template <typename T>
+hipError_t launch_axpy(int64_t rows, int cols, double a, const T *X, int ldx, T *Y, int ldy,
+                       hipStream_t s);  // Y += a X
+template <typename T>
+hipError_t launch_copy_cols(int64_t rows, int cols, const T *X, int ldx, T *Y, int ldy,
+                            hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t launch_convert(int64_t n, const Tin *x, Tout *y, hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t launch_convert_cols(int64_t rows, int cols, const Tin *X, int ldx, Tout *Y, int ldy,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_normals(uint64_t seed, uint64_t stream, int64_t rows, int cols, int ld, T *out,
+                          hipStream_t s);  // entry (i, j) is normal number i*cols + j
+hipError_t launch_gather_perm(int64_t nnz, const int32_t *perm, const double *in, double *out,
+                              hipStream_t s);
+hipError_t launch_reduce_wsum(const double *wsum, int64_t waves, int nsum, double *out,
+                              hipStream_t s);
+// Setup helpers.
+hipError_t launch_row_ids(int64_t m, const int64_t *row_ptr, int32_t *rid, hipStream_t s);
+hipError_t launch_iota(int64_t n, int32_t *p, hipStream_t s);
+hipError_t launch_gather_csc(int64_t nnz, const int32_t *perm, const int32_t *rid,
+                             const double *val, int32_t *crow, double *cval, hipStream_t s);
+hipError_t launch_col_ptr(int64_t nnz, int64_t n, const int32_t *sorted_col, int64_t *cptr,
+                          hipStream_t s);
+hipError_t launch_check_csr(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                            const double *val, const int32_t *rid, int *flags, hipStream_t s);
+
+// Widest slice one launch handles for element type T.
+template <typename T> constexpr int max_width() { return 64 * (16 / (int)sizeof(T)); }
+
+}  // namespace bmg
+
+#include "linalg.h"

@@ -1,0 +1,292 @@
+"""GPU parity: every entry point of libbmg.so against the CPU oracle on the same
+seeded inputs (FP64 unless stated).
+
+Tolerances:
+* sampled residual: |R_gpu - R_orc| <= 4 k u (|W| |H|^T + |A|)_ij elementwise,
+  u = 2^-53 (the two sides add the k products in different orders);
+* sparse products: |C_gpu - C_orc| <= 4 d u (|S| |B|)  with d the row length;
+* iterative results (BM epochs, prox, solve): relative objective error
+  <= 1e-8 in FP64 and <= 1e-5 in FP32, the bars the method is held to.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2204_14067_amd as bmg
+import synth
+from oracle import core, dense
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+DEV = "cuda:0"
+
+
+def to_dev(p, k_cap=32, precision="fp64"):
+    return bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=k_cap,
+                                 precision=precision, device=DEV)
+
+
+def factors(p, k, ld, seed):
+    rng = np.random.default_rng(seed)
+    W = np.zeros((p.m, ld)); H = np.zeros((p.n, ld))
+    W[:, :k] = rng.standard_normal((p.m, k))
+    H[:, :k] = rng.standard_normal((p.n, k))
+    return W, H
+
+
+def t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def long_rows_problem():
+    row_ptr, col = synth.uniform_pattern(12, 9000, 36_000, seed=21)   # rows of ~3000 > one piece
+    val, _, _ = synth.values(12, 9000, row_ptr, col, 3, 0.5, 0.01, seed=22)
+    return synth.Problem("long_rows", 12, 9000, row_ptr, col, val, 0.3, 4)
+
+
+CASES = {
+    "tiny": lambda: synth.tiny(7, 11, 30),
+    "single_entry": lambda: synth.tiny(3, 4, 1),
+    "empty_rows": lambda: synth.tiny(80, 50, 40, seed=4),
+    "tall_m_gt_n": lambda: synth.tiny(90, 35, 900, seed=5),
+    "long_rows": long_rows_problem,
+    "powerlaw": lambda: synth.netflix_shape(scale=0.03),
+}
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        _cache[name] = CASES[name]()
+    return _cache[name]
+
+
+# ----------------------------------------------------------------------------- primitives
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("k", [1, 5, 16, 17, 64, 128])
+def test_sddmm_parity(name, k):
+    p = case(name)
+    print("sddmm", name, p.m, p.n, p.nnz, "k", k, flush=True)
+    dp = to_dev(p, k_cap=128)
+    ld = bmg.round_ld(k)
+    W, H = factors(p, k, ld, seed=k)
+    R, hs = dp.bmg_sddmm(t(W), t(H), k)
+    R = R.cpu().numpy()
+    Ro = core.sddmm(p, W[:, :k], H[:, :k])
+    bound = 4 * k * U * (core.sddmm(p, np.abs(W[:, :k]), np.abs(H[:, :k]), with_values=False)
+                         + np.abs(p.val))
+    assert np.all(np.abs(R - Ro) <= bound + 1e-300)
+    assert math.isclose(hs, 0.5 * float(np.sum(Ro ** 2)), rel_tol=1e-12, abs_tol=1e-300)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("q", [1, 8, 33, 130, 257])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_spmm_parity(name, q, transpose):
+    p = case(name)
+    print("spmm", name, p.nnz, "q", q, "T", transpose, flush=True)
+    dp = to_dev(p, k_cap=8)
+    rng = np.random.default_rng(q)
+    S = rng.standard_normal(p.nnz)
+    ldq = bmg.round_ld(q)
+    B = np.zeros((p.m if transpose else p.n, ldq))
+    B[:, :q] = rng.standard_normal((B.shape[0], q))
+    C = dp.bmg_spmm(t(S), t(B)[:, :].narrow(1, 0, ldq), transpose=transpose).cpu().numpy()[:, :q]
+    if transpose:
+        Co = core.spmm_t(p, S, B[:, :q])
+        Cb = core.spmm_t(p, np.abs(S), np.abs(B[:, :q]))
+        d = np.bincount(p.col, minlength=p.n)[:, None]
+    else:
+        Co = core.spmm(p, S, B[:, :q])
+        Cb = core.spmm(p, np.abs(S), np.abs(B[:, :q]))
+        d = np.diff(p.row_ptr)[:, None]
+    assert np.all(np.abs(C - Co) <= 4 * np.maximum(d, 1) * U * Cb + 1e-300)
+
+
+@pytest.mark.parametrize("name", ["tiny", "tall_m_gt_n", "long_rows", "powerlaw"])
+def test_bm_epochs_parity(name):
+    p = case(name)
+    k, lam = 6, 0.7
+    dp = to_dev(p, k_cap=16)
+    ld = bmg.round_ld(16)
+    W, H = factors(p, k, ld, seed=3)
+    Wd, Hd = t(W), t(H)
+    Fbm = dp.bmg_bm_epochs(Wd, Hd, k, lam, epochs=2)
+    # the library runs on the m <= n orientation (W step first there)
+    tp = p.m > p.n
+    q = core.transpose(p) if tp else p
+    Wo, Ho = (H[:, :k], W[:, :k]) if tp else (W[:, :k], H[:, :k])
+    for _ in range(2):
+        Wo, Ho, _ = core.bm_epoch(q, Wo, Ho, lam)
+    Fo = core.bm_objective(q, Wo, Ho, lam)
+    if tp:
+        Wo, Ho = Ho, Wo
+    assert math.isclose(Fbm, Fo, rel_tol=1e-10)
+    scale = max(np.abs(Wo).max(), np.abs(Ho).max())
+    assert np.allclose(Wd.cpu().numpy()[:, :k], Wo, rtol=1e-8, atol=1e-9 * scale)
+    assert np.allclose(Hd.cpu().numpy()[:, :k], Ho, rtol=1e-8, atol=1e-9 * scale)
+    assert np.all(Wd.cpu().numpy()[:, k:] == 0)
+
+
+@pytest.mark.parametrize("name", ["tiny", "tall_m_gt_n", "powerlaw"])
+def test_objective_parity(name):
+    p = case(name)
+    k = 5
+    dp = to_dev(p, k_cap=8)
+    W, H = factors(p, k, 8, seed=11)
+    F = dp.bmg_objective(t(W), t(H), k, 0.9)
+    assert math.isclose(F, core.objective(p, W[:, :k], H[:, :k], 0.9), rel_tol=1e-11)
+
+
+@pytest.mark.parametrize("name", ["tiny", "tall_m_gt_n", "long_rows", "powerlaw"])
+def test_prox_step_parity(name):
+    p = case(name)
+    lam, alpha, k = 0.4, 1.99, 4
+    dp = to_dev(p, k_cap=32)
+    W, H = factors(p, k, 32, seed=5)
+    Wd, Hd = t(W), t(H)
+    kg, sig, res = dp.bmg_prox_step(Wd, Hd, k, lam=lam, alpha=alpha, seed=9, ssi_tol_floor=1e-13,
+                                    ssi_max_iter=200)
+    pr, ls, reso = core.prox_step_standalone(p, W[:, :k], H[:, :k], lam, alpha, seed=9, tau=1e-13,
+                                             max_iter=200)
+    assert kg == pr.k
+    assert np.allclose(sig, pr.sigma, rtol=1e-8, atol=1e-10 * max(pr.sigma.max(initial=0), 1))
+    Wg, Hg = Wd.cpu().numpy()[:, :kg], Hd.cpu().numpy()[:, :kg]
+    d = math.sqrt(core.diff_fro2_factored(Wg, Hg, pr.W, pr.H))
+    assert d <= 1e-7 * max(1.0, math.sqrt(core.fro2_factored(pr.W, pr.H)))
+    assert math.isclose(res, reso, rel_tol=1e-5, abs_tol=1e-12)
+
+
+# ----------------------------------------------------------------------------- solver
+
+def solve_both(p, lam, k0, tol, k_cap=64, precision="fp64", seed=3, orc=None):
+    dp = to_dev(p, k_cap=k_cap, precision=precision)
+    W, H, k, r = dp.bmg_solve(lam=lam, k_init=k0, tol=tol, seed=seed, max_iter=3000)
+    if orc is None:
+        orc = core.solve(p, core.Options(lam=lam, k0=k0, tol=tol, seed=seed, max_iter=3000))
+    return dp, W, H, k, r, orc
+
+
+@pytest.mark.parametrize("shape", [(40, 60, 700), (60, 40, 700), (120, 200, 4000)])
+def test_solve_parity_fp64(shape):
+    m, n, nnz = shape
+    p = synth.tiny(m, n, nnz, rank=3, lam=0.3, seed=m + n)
+    dp, W, H, k, r, orc = solve_both(p, 0.3, 4, 1e-10)
+    print("solve", shape, r, orc.F, orc.k, orc.iters, flush=True)
+    assert r["status"] == 0 and orc.converged
+    assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
+    assert k == orc.k
+    # the returned factors reproduce the reported objective (recomputed by the oracle)
+    Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
+    assert math.isclose(Fw, r["F"], rel_tol=1e-10)
+
+
+def test_solve_full_omega_closed_form():
+    m, n, lam = 30, 45, 1.5
+    p = synth.tiny(m, n, m * n, rank=4, seed=12)
+    A, _ = dense.to_dense(p)
+    dp = to_dev(p, k_cap=32)
+    W, H, k, r = dp.bmg_solve(lam=lam, k_init=4, tol=1e-12, seed=1)
+    X = W.cpu().numpy()[:, :k] @ H.cpu().numpy()[:, :k].T
+    assert np.allclose(X, dense.prox_nuclear(A, lam), atol=1e-8)
+
+
+def test_solve_zero_solution_and_empty():
+    p = synth.tiny(20, 30, 200, seed=6)
+    A, _ = dense.to_dense(p)
+    lam = 1.01 * np.linalg.svd(A, compute_uv=False)[0]
+    W, H, k, r = to_dev(p, 16).bmg_solve(lam=lam, k_init=4, tol=1e-10)
+    assert k == 0 and math.isclose(r["F"], 0.5 * float(np.sum(p.val ** 2)), rel_tol=1e-13)
+    pe = synth.tiny(8, 9, 0)
+    W, H, k, r = to_dev(pe, 8).bmg_solve(lam=0.1, k_init=3, tol=1e-10)
+    assert k == 0 and r["F"] == 0.0
+
+
+def test_solve_small_uniform_matches_golden(golden_dir):
+    """1000 x 1500, |Omega| = 50,000, lambda = 0.5, k0 = 8: F within 1e-8 of the
+    oracle optimum stored in tests/golden (itself certified by a duality gap)."""
+    g = json.load(open(os.path.join(golden_dir, "small_uniform.json")))
+    p = synth.small_uniform()
+    dp = to_dev(p, k_cap=128)
+    W, H, k, r = dp.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-10, seed=11, max_iter=3000)
+    print("small_uniform", r, flush=True)
+    assert r["status"] == 0
+    assert abs(r["F"] - g["F"]) <= 1e-8 * g["F"]
+    assert k == g["rank"]
+
+
+def test_solve_fp32_objective_error():
+    p = synth.tiny(150, 220, 5000, rank=3, lam=0.3, seed=31)
+    dp, W, H, k, r, orc = solve_both(p, 0.3, 4, 1e-6, precision="fp32")
+    Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
+    Fstar = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-11, seed=3)).F
+    print("fp32", r, Fw, Fstar, flush=True)
+    assert abs(Fw - Fstar) <= 1e-5 * Fstar
+
+
+def test_solve_is_bitwise_deterministic():
+    p = synth.netflix_shape(scale=0.02)
+    outs = []
+    for _ in range(2):
+        dp = to_dev(p, k_cap=32)
+        W, H, k, r = dp.bmg_solve(lam=20.0, k_init=4, tol=1e-5, max_iter=5, seed=2)
+        outs.append((W.cpu().numpy(), H.cpu().numpy(), r["F"]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+# ----------------------------------------------------------------------------- errors
+
+def test_invalid_inputs_are_rejected():
+    p = synth.tiny(6, 7, 20)
+    bad = p.col.copy(); bad[1], bad[2] = bad[2], bad[1]     # unsorted within a row? ensure same row
+    rows = p.rows()
+    if rows[1] == rows[2]:
+        with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
+            bmg.Problem.from_host(p.row_ptr, bad, p.val, p.m, p.n, device=DEV)
+    oob = p.col.copy(); oob[0] = p.n
+    with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
+        bmg.Problem.from_host(p.row_ptr, oob, p.val, p.m, p.n, device=DEV)
+    nanv = p.val.copy(); nanv[3] = np.nan
+    with pytest.raises(bmg.BmgError, match="BMG_ENONFINITE"):
+        bmg.Problem.from_host(p.row_ptr, p.col, nanv, p.m, p.n, device=DEV)
+    dp = to_dev(p, k_cap=8)
+    with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
+        dp.bmg_solve(lam=-1.0)
+
+
+# ----------------------------------------------------------------------------- full size, sampled
+
+def test_netflix_shape_full_size_sampled_rows():
+    """17,770 x 480,189, |Omega| = 1e8 (the benchmark's workload): the sampled
+    residual and both gradient products on sampled rows / columns against the
+    oracle evaluated on those rows only."""
+    p = synth.netflix_shape()
+    k, lam = 16, 20.0
+    dp = to_dev(p, k_cap=16)
+    W, H = factors(p, k, 16, seed=7)
+    W *= 0.3; H *= 0.3
+    R, hs = dp.bmg_sddmm(t(W), t(H), k)
+    rows = np.random.default_rng(1).choice(p.m, 64, replace=False)
+    rows = np.union1d(rows, np.argsort(np.diff(p.row_ptr))[-4:])     # include dense rows
+    Rg = R.cpu().numpy()
+    for i in rows:
+        a, b = p.row_ptr[i], p.row_ptr[i + 1]
+        ro = W[i, :k] @ H[p.col[a:b], :k].T - p.val[a:b]
+        assert np.allclose(Rg[a:b], ro, rtol=1e-12, atol=1e-12)
+    # gradient products R H and R^T W on sampled rows / columns
+    GW = dp.bmg_spmm(R, t(H)).cpu().numpy()
+    for i in rows[:16]:
+        a, b = p.row_ptr[i], p.row_ptr[i + 1]
+        assert np.allclose(GW[i, :k], Rg[a:b] @ H[p.col[a:b], :k], rtol=1e-10, atol=1e-9)
+    GH = dp.bmg_spmm(R, t(W), transpose=True).cpu().numpy()
+    cols = np.random.default_rng(2).choice(p.n, 16, replace=False)
+    prow = p.rows()
+    for j in cols:
+        sel = np.nonzero(p.col == j)[0]
+        assert np.allclose(GH[j, :k], Rg[sel] @ W[prow[sel], :k], rtol=1e-10, atol=1e-9)

@@ -1,0 +1,104 @@
+"""Host-side checks that need no GPU: the C-ABI library loads and exports every
+entry point include/bmg.h declares; host queries validate their arguments;
+the synthetic generators are deterministic and produce valid CSR."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "bmg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bmg_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2204_14067_amd import _lib
+    if not os.path.exists(_lib.SO):
+        from paper_2204_14067_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2204_14067_amd import _lib
+    names = header_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_options_default(lib):
+    from paper_2204_14067_amd import _lib
+    o = _lib.BmgOptions()
+    lib.bmg_options_default(ctypes.byref(o))
+    assert o.alpha == 1.99 and o.bm_epochs == 3 and o.psi0 == 0.1 and o.tol == 1e-6
+
+
+def test_workspace_size_and_argument_checks(lib):
+    from paper_2204_14067_amd import _lib
+    nb = ctypes.c_size_t(0)
+    assert lib.bmg_workspace_size(1000, 1500, 50_000, 128, _lib.BMG_FP64, ctypes.byref(nb)) == 0
+    small = nb.value
+    assert small > 50_000 * 36
+    assert lib.bmg_workspace_size(1000, 1500, 500_000, 128, _lib.BMG_FP64, ctypes.byref(nb)) == 0
+    assert nb.value > small
+    assert lib.bmg_workspace_size(-1, 5, 5, 8, 0, ctypes.byref(nb)) == _lib.BMG_EINVAL
+    assert b"bad shape" in lib.bmg_last_error()
+    assert lib.bmg_workspace_size(10, 10, 5, 0, 0, ctypes.byref(nb)) == _lib.BMG_EINVAL
+    assert lib.bmg_workspace_size(10, 10, 5, 4096, 0, ctypes.byref(nb)) == _lib.BMG_EINVAL
+    # creating with a null CSR is rejected before any device call
+    h = ctypes.c_void_p()
+    assert lib.bmg_problem_create(None, 8, 0, None, 0, None, ctypes.byref(h)) == _lib.BMG_EINVAL
+
+
+def test_no_cpu_fallback_without_gpu():
+    import torch
+    import paper_2204_14067_amd as bmg
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    p = synth.tiny(5, 6, 10)
+    with pytest.raises(RuntimeError):
+        bmg.Problem(torch.as_tensor(p.row_ptr), torch.as_tensor(p.col), torch.as_tensor(p.val),
+                    p.m, p.n)
+
+
+def _check_csr(p):
+    assert p.row_ptr[0] == 0 and p.row_ptr[-1] == len(p.col) == len(p.val)
+    assert np.all(np.diff(p.row_ptr) >= 0)
+    assert p.col.min(initial=0) >= 0 and (len(p.col) == 0 or p.col.max() < p.n)
+    rows = p.rows()
+    key = rows * p.n + p.col
+    assert np.all(np.diff(key) > 0)   # sorted, duplicate-free
+
+
+def test_synth_uniform_and_powerlaw_valid_and_deterministic():
+    a = synth.small_uniform()
+    _check_csr(a)
+    assert a.nnz == 50_000 and a.m == 1000 and a.n == 1500
+    b = synth.small_uniform()
+    assert np.array_equal(a.col, b.col) and np.array_equal(a.val, b.val)
+    p = synth.netflix_shape(scale=0.05)
+    _check_csr(p)
+    deg = np.diff(p.row_ptr)
+    assert deg.max() > 20 * np.median(deg)          # heavy-tailed rows
+    assert p.val.min() >= 1.0 and p.val.max() <= 5.0  # ratings clip
+    q = synth.netflix_shape(scale=0.05)
+    assert np.array_equal(p.col, q.col)
+
+
+def test_serving_stream_shapes():
+    reqs = synth.serving_stream(count=64)
+    t = [r.arrival for r in reqs]
+    assert all(b > a for a, b in zip(t, t[1:]))
+    assert 1.0 < t[-1] < 8.0          # ~64 / 20 per second
+    assert all(500 <= r.m <= 20000 and 1000 <= r.n <= 50000 and 3 <= r.rank <= 15 for r in reqs)

@@ -134,7 +134,8 @@ def test_bm_half_step_is_exact_line_search_and_monotone():
 
 def test_bm_H_step_matches_transposed_W_step():
     p = tiny_problem(25, 35, 300)
-    pt = synth.Problem("t", p.n, p.m, *_transpose(p), p.lam, p.k0)
+    pt = core.transpose(p)
+    assert np.array_equal(pt.col, _transpose(p)[1]) and np.array_equal(pt.val, _transpose(p)[2])
     W, H = rand((25, 3), 1), rand((35, 3), 2)
     H1, s1 = core.bm_half_step_H(p, W, H, 0.2)
     H2, s2 = core.bm_half_step_W(pt, H, W, 0.2)
@@ -248,6 +249,15 @@ def test_full_omega_closed_form():
     assert np.allclose(res.W @ res.H.T, Xs, atol=1e-9)
     F_star = dense.mc_objective_dense(Xs, A, np.ones_like(A, bool), lam)
     assert math.isclose(res.F, F_star, rel_tol=1e-12)
+
+
+def test_solve_tall_problem_equals_transposed_solve():
+    p = tiny_problem(45, 30, 500, lam=0.3, rank=2, seed=10)
+    a = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-11, seed=3))
+    A, M = dense.to_dense(p)
+    Xd, _ = dense.proximal_gradient_dense(A, M, 0.3, alpha=1.99, tol=1e-14)
+    assert a.W.shape[0] == 45 and a.H.shape[0] == 30
+    assert math.isclose(a.F, dense.mc_objective_dense(Xd, A, M, 0.3), rel_tol=1e-11)
 
 
 def test_solve_matches_dense_proximal_gradient():
