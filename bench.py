@@ -60,7 +60,7 @@ def cpu_baseline(p, k=16):
     W = 0.3 * rng.standard_normal((p.m, k))
     H = 0.3 * rng.standard_normal((p.n, k))
     reps, t_tot = 0, 0.0
-    while reps < 2 or (t_tot < 10.0 and reps < 8):
+    while reps < 2 or (t_tot < 10.0 and reps < 200):
         t0 = time.perf_counter()
         R = core.sddmm(p, W, H)
         G = core.spmm(p, R, H)

@@ -85,14 +85,15 @@ static size_t sort_temp_bytes(int64_t nnz) {
 static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_precision prec) {
   Layout L{};
   L.m = m; L.n = n; L.nnz = nnz; L.k_cap = k_cap;
-  L.ldk = (int)rup(std::max(k_cap, 1), 8);
+  // leading dimensions in multiples of 16 elements: factor rows start on 128-byte lines
+  L.ldk = (int)rup(std::max(k_cap, 1), 16);
   L.qmax = 2 * k_cap + 2;
-  L.qld = (int)rup(L.qmax, 8);
+  L.qld = (int)rup(L.qmax, 16);
   L.lowp = prec != BMG_FP64;
   L.max_long = nnz / CHUNK + 1;
   L.max_pieces = 2 * (nnz / CHUNK) + 2;
   L.wsum_cap = std::max(m, n) + L.max_pieces + 8;
-  L.gram_cap = std::max<int64_t>(64LL * L.qmax * L.qmax, 1LL << 22);
+  L.gram_cap = std::max<int64_t>(64LL * L.qmax * L.qmax, 2048LL * 4096);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += rup((int64_t)bytes + 1, 256); return o; };
   L.csc_ptr = take(8 * (n + 1));
@@ -1074,7 +1075,9 @@ struct Method : Engine<T> {
         changed |= bm_half(false, S.W, S.H, S.k, o.lambda);
       }
       F_bm = bm_objective(S.W, S.H, S.k, o.lambda);
-      const double tau = std::max(o.ssi_tol_floor, std::min(1e-4, 0.1 * S.res_prev * S.res_prev));
+      // FP32 passes cannot resolve Ritz values below ~1e-7 of the largest
+      const double floor = std::max(o.ssi_tol_floor, sizeof(T) == 4 ? 1e-6 : 0.0);
+      const double tau = std::max(floor, std::min(1e-4, 0.1 * S.res_prev * S.res_prev));
       StepInfo st = pg_step(S, changed, o.lambda, o.alpha, tau, o.ssi_max_iter, o.seed, t);
       ssi_total += st.iters;
       resid = st.residual;

@@ -102,6 +102,7 @@ hipError_t launch_check_csr(int64_t m, int64_t n, const int64_t *row_ptr, const 
                             const double *val, const int32_t *rid, int *flags, hipStream_t s);
 
 // Widest slice one launch handles for element type T.
+// (8 lanes x 16 bytes per chunk, at most 8 chunks: 128 doubles / 256 floats)
 template <typename T> constexpr int max_width() { return 64 * (16 / (int)sizeof(T)); }
 
 }  // namespace bmg

@@ -8,8 +8,9 @@
 // (2 doubles / 4 floats) of the k-vectors, so one gathered factor row is a
 // single fully-used cache-line access, dot products need log2(G) butterfly
 // steps inside the group, and the accumulated output row never leaves
-// registers until the row ends.  Index/value streams are read with
-// non-temporal loads so they do not evict the gathered factor rows from L2.
+// registers until the row ends.  (Index/value streams use ordinary loads:
+// measured on the 1e8-entry workload, non-temporal loads were up to 30%
+// slower on the column-oriented passes and no faster elsewhere.)
 //
 // Determinism: no floating-point atomics anywhere.  Scalar sums are written
 // per wave and added in a fixed order by a one-block kernel; long rows are
@@ -24,8 +25,17 @@ template <typename T> struct VT;
 template <> struct VT<double> { static constexpr int V = 2; };
 template <> struct VT<float> { static constexpr int V = 4; };
 
+#ifndef BMG_NT_STREAMS
+#define BMG_NT_STREAMS 0
+#endif
 template <typename T>
-__device__ __forceinline__ T nt_load(const T *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ T nt_load(const T *p) {
+#if BMG_NT_STREAMS
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
 
 // Load V consecutive elements row[f0 .. f0+V) with per-element bound lim
 // (elements at or beyond lim read as 0 and are never touched).
@@ -80,7 +90,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-constexpr int UNROLL = 4;
+#ifndef BMG_UNROLL
+#define BMG_UNROLL 4
+#endif
+constexpr int UNROLL = BMG_UNROLL;  // entries in flight per lane group
 constexpr int WAVES_PER_BLOCK = 4;
 
 __host__ __device__ inline int64_t short_waves(const Plan &pl, int G) {
@@ -88,16 +101,57 @@ __host__ __device__ inline int64_t short_waves(const Plan &pl, int G) {
   return (pl.n_short + S - 1) / S;
 }
 
+// ============================================================================ lane-group row access
+// A lane group of G lanes owns one row of Omega.  A dense k-vector is split in
+// C chunks of G*V consecutive columns (one 128-byte line for G = 8 in FP64);
+// lane `sub` holds columns c*G*V + sub*V .. +V-1 of chunk c.
+template <typename T, int G, int C>
+struct Row {
+  static constexpr int V = VT<T>::V;
+  static constexpr int CW = G * V;       // columns per chunk
+  static constexpr int WB = CW * C;      // columns covered
+  T v[C][V];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < V; ++e) v[c][e] = T(0);
+  }
+  __device__ __forceinline__ void load(const T *__restrict__ row, int sub, int lim) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) ldv<T, V>(row, c * CW + sub * V, lim, v[c]);
+  }
+  __device__ __forceinline__ void store(T *__restrict__ row, int sub, int lim) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c) stv<T, V>(row, c * CW + sub * V, lim, v[c]);
+  }
+  __device__ __forceinline__ T dot(const Row &o) const {
+    T s = T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < V; ++e) s += v[c][e] * o.v[c][e];
+    return s;
+  }
+  __device__ __forceinline__ void axpy(T a, const Row &o) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < V; ++e) v[c][e] += a * o.v[c][e];
+  }
+};
+
 // ============================================================================ fused residual + product
-// For one entry range [p, p + n*step) of a row: r = x.y_j - a_p ; acc += r y_j ; ss += r^2.
-template <typename T, int G, int V>
+// For entries p, p+step, ... (n of them) of one row:
+//   r = x . y_j - a_p ;  acc += r y_j ;  ss += r^2   (ss on the group leader only)
+template <typename T, int G, int C>
 __device__ __forceinline__ void grad_block(const Plan &pl, const T *__restrict__ a,
-                                           const T *__restrict__ Y, int ldy, int k, int f0,
-                                           const T (&x)[V], T (&acc)[V], double &ss, bool leader,
-                                           int64_t p, int64_t step, int n) {
+                                           const T *__restrict__ Y, int ldy, int k, int sub,
+                                           const Row<T, G, C> &x, Row<T, G, C> &acc, double &ss,
+                                           bool leader, int64_t p, int64_t step, int n) {
   int j[UNROLL];
   T av[UNROLL];
-  T y[UNROLL][V];
+  Row<T, G, C> y[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     if (u < n) {
@@ -110,63 +164,53 @@ __device__ __forceinline__ void grad_block(const Plan &pl, const T *__restrict__
   }
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
-    if (j[u] >= 0) ldv<T, V>(Y + (int64_t)j[u] * ldy, f0, k, y[u]);
-    else {
-#pragma unroll
-      for (int e = 0; e < V; ++e) y[u][e] = T(0);
-    }
+    if (j[u] >= 0) y[u].load(Y + (int64_t)j[u] * ldy, sub, k);
+    else y[u].zero();
   }
   T d[UNROLL];
 #pragma unroll
-  for (int u = 0; u < UNROLL; ++u) {
-    T s = T(0);
-#pragma unroll
-    for (int e = 0; e < V; ++e) s += x[e] * y[u][e];
-    d[u] = s;
-  }
+  for (int u = 0; u < UNROLL; ++u) d[u] = x.dot(y[u]);
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) d[u] = group_sum<G>(d[u]);
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     if (u < n) {
       const T r = d[u] - av[u];
-#pragma unroll
-      for (int e = 0; e < V; ++e) acc[e] += r * y[u][e];
+      acc.axpy(r, y[u]);
       if (leader) ss += (double)r * (double)r;
     }
   }
 }
 
-template <typename T, int G>
+template <typename T, int G, int C>
 __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
                                               const T *__restrict__ X, int ldx,
                                               const T *__restrict__ Y, int ldy, int k, double lam,
                                               T *__restrict__ Out, int ldo,
                                               T *__restrict__ partial, double *__restrict__ wsum,
                                               int64_t total_waves) {
-  constexpr int V = VT<T>::V, S = 64 / G, WB = G * V;
-  const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G, f0 = sub * V;
+  using RowT = Row<T, G, C>;
+  constexpr int S = 64 / G, WB = RowT::WB;
+  const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
   const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
   const int64_t sw = short_waves(pl, G);
   const bool leader = (sub == 0);
   double ss = 0.0;
-  T acc[V];
-#pragma unroll
-  for (int e = 0; e < V; ++e) acc[e] = T(0);
+  RowT acc;
+  acc.zero();
   if (gw < sw) {
     const int64_t ri = gw * S + slot;
     if (ri < pl.n_short) {
       const int row = pl.short_rows[ri];
-      T x[V];
-      ldv<T, V>(X + (int64_t)row * ldx, f0, k, x);
+      RowT x;
+      x.load(X + (int64_t)row * ldx, sub, k);
       const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
       for (int64_t p = beg; p < end; p += UNROLL) {
         const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
-        grad_block<T, G, V>(pl, a, Y, ldy, k, f0, x, acc, ss, leader, p, 1, n);
+        grad_block<T, G, C>(pl, a, Y, ldy, k, sub, x, acc, ss, leader, p, 1, n);
       }
-#pragma unroll
-      for (int e = 0; e < V; ++e) acc[e] += (T)lam * x[e];
-      stv<T, V>(Out + (int64_t)row * ldo, f0, k, acc);
+      acc.axpy((T)lam, x);
+      acc.store(Out + (int64_t)row * ldo, sub, k);
     }
   } else if (gw < total_waves) {
     const int64_t pc = gw - sw;
@@ -174,57 +218,55 @@ __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
     const int64_t beg = pl.piece_beg[pc];
     int64_t end = pl.ptr[row + 1];
     if (end > beg + pl.chunk) end = beg + pl.chunk;
-    T x[V];
-    ldv<T, V>(X + (int64_t)row * ldx, f0, k, x);
+    RowT x;
+    x.load(X + (int64_t)row * ldx, sub, k);
     for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
       const int64_t rem = (end - p + S - 1) / S;
       const int n = (int)(rem < UNROLL ? rem : UNROLL);
-      grad_block<T, G, V>(pl, a, Y, ldy, k, f0, x, acc, ss, leader, p, S, n);
+      grad_block<T, G, C>(pl, a, Y, ldy, k, sub, x, acc, ss, leader, p, S, n);
     }
 #pragma unroll
-    for (int e = 0; e < V; ++e) acc[e] = slot_sum<G>(acc[e]);
-    if (slot == 0) stv<T, V>(partial + pc * WB, f0, WB, acc);
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < RowT::V; ++e) acc.v[c][e] = slot_sum<G>(acc.v[c][e]);
+    if (slot == 0) acc.store(partial + pc * WB, sub, WB);
   }
   ss = wave_sum(ss);
   if (lane == 0 && gw < total_waves) wsum[gw] = ss;
 }
 
 // Long rows: Out_row = sum of piece partials (piece order) + lam * x_row.
-template <typename T, int G>
+template <typename T, int G, int C>
 __global__ __launch_bounds__(256) void k_grad_fix(Plan pl, const T *__restrict__ partial,
                                                   const T *__restrict__ X, int ldx, int k,
                                                   double lam, T *__restrict__ Out, int ldo) {
-  constexpr int V = VT<T>::V, WB = G * V;
+  using RowT = Row<T, G, C>;
   const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const int f0 = (threadIdx.x % G) * V;
+  const int sub = threadIdx.x % G;
   if (g >= pl.n_long) return;
   const int row = pl.long_rows[g];
-  T acc[V];
-#pragma unroll
-  for (int e = 0; e < V; ++e) acc[e] = T(0);
+  RowT acc, t;
+  acc.zero();
   for (int pc = pl.long_p0[g]; pc < pl.long_p0[g + 1]; ++pc) {
-    T t[V];
-    ldv<T, V>(partial + (int64_t)pc * WB, f0, WB, t);
-#pragma unroll
-    for (int e = 0; e < V; ++e) acc[e] += t[e];
+    t.load(partial + (int64_t)pc * RowT::WB, sub, RowT::WB);
+    acc.axpy(T(1), t);
   }
-  T x[V];
-  ldv<T, V>(X + (int64_t)row * ldx, f0, k, x);
-#pragma unroll
-  for (int e = 0; e < V; ++e) acc[e] += (T)lam * x[e];
-  stv<T, V>(Out + (int64_t)row * ldo, f0, k, acc);
+  RowT x;
+  x.load(X + (int64_t)row * ldx, sub, k);
+  acc.axpy((T)lam, x);
+  acc.store(Out + (int64_t)row * ldo, sub, k);
 }
 
 // ============================================================================ sampled residual
-template <typename T, int G, int V>
+template <typename T, int G, int C>
 __device__ __forceinline__ void sddmm_block(const Plan &pl, const T *__restrict__ a,
-                                            const T *__restrict__ Y, int ldy, int k, int f0,
-                                            const T (&x)[V], T *__restrict__ R, double &ss,
+                                            const T *__restrict__ Y, int ldy, int k, int sub,
+                                            const Row<T, G, C> &x, T *__restrict__ R, double &ss,
                                             double &sx, bool leader, int64_t p, int64_t step,
                                             int n) {
   int j[UNROLL];
   T av[UNROLL];
-  T y[UNROLL][V];
+  Row<T, G, C> y[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     if (u < n) {
@@ -237,20 +279,12 @@ __device__ __forceinline__ void sddmm_block(const Plan &pl, const T *__restrict_
   }
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
-    if (j[u] >= 0) ldv<T, V>(Y + (int64_t)j[u] * ldy, f0, k, y[u]);
-    else {
-#pragma unroll
-      for (int e = 0; e < V; ++e) y[u][e] = T(0);
-    }
+    if (j[u] >= 0) y[u].load(Y + (int64_t)j[u] * ldy, sub, k);
+    else y[u].zero();
   }
   T d[UNROLL];
 #pragma unroll
-  for (int u = 0; u < UNROLL; ++u) {
-    T s = T(0);
-#pragma unroll
-    for (int e = 0; e < V; ++e) s += x[e] * y[u][e];
-    d[u] = group_sum<G>(s);
-  }
+  for (int u = 0; u < UNROLL; ++u) d[u] = group_sum<G>(x.dot(y[u]));
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     if (u < n && leader) {
@@ -262,14 +296,15 @@ __device__ __forceinline__ void sddmm_block(const Plan &pl, const T *__restrict_
   }
 }
 
-template <typename T, int G>
+template <typename T, int G, int C>
 __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
                                                const T *__restrict__ X, int ldx,
                                                const T *__restrict__ Y, int ldy, int k,
                                                T *__restrict__ R, double *__restrict__ wsum,
                                                int64_t total_waves) {
-  constexpr int V = VT<T>::V, S = 64 / G;
-  const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G, f0 = sub * V;
+  using RowT = Row<T, G, C>;
+  constexpr int S = 64 / G;
+  const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
   const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
   const int64_t sw = short_waves(pl, G);
   const bool leader = (sub == 0);
@@ -278,12 +313,12 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
     const int64_t ri = gw * S + slot;
     if (ri < pl.n_short) {
       const int row = pl.short_rows[ri];
-      T x[V];
-      ldv<T, V>(X + (int64_t)row * ldx, f0, k, x);
+      RowT x;
+      x.load(X + (int64_t)row * ldx, sub, k);
       const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
       for (int64_t p = beg; p < end; p += UNROLL) {
         const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
-        sddmm_block<T, G, V>(pl, a, Y, ldy, k, f0, x, R, ss, sx, leader, p, 1, n);
+        sddmm_block<T, G, C>(pl, a, Y, ldy, k, sub, x, R, ss, sx, leader, p, 1, n);
       }
     }
   } else if (gw < total_waves) {
@@ -292,12 +327,12 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
     const int64_t beg = pl.piece_beg[pc];
     int64_t end = pl.ptr[row + 1];
     if (end > beg + pl.chunk) end = beg + pl.chunk;
-    T x[V];
-    ldv<T, V>(X + (int64_t)row * ldx, f0, k, x);
+    RowT x;
+    x.load(X + (int64_t)row * ldx, sub, k);
     for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
       const int64_t rem = (end - p + S - 1) / S;
       const int n = (int)(rem < UNROLL ? rem : UNROLL);
-      sddmm_block<T, G, V>(pl, a, Y, ldy, k, f0, x, R, ss, sx, leader, p, S, n);
+      sddmm_block<T, G, C>(pl, a, Y, ldy, k, sub, x, R, ss, sx, leader, p, S, n);
     }
   }
   ss = wave_sum(ss);
@@ -309,13 +344,13 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
 }
 
 // ============================================================================ sparse x dense
-template <typename T, int G, int V>
+template <typename T, int G, int C>
 __device__ __forceinline__ void spmm_block(const Plan &pl, const T *__restrict__ Sv,
-                                           const T *__restrict__ B, int ldb, int wq, int f0,
-                                           T (&acc)[V], int64_t p, int64_t step, int n) {
+                                           const T *__restrict__ B, int ldb, int wq, int sub,
+                                           Row<T, G, C> &acc, int64_t p, int64_t step, int n) {
   int j[UNROLL];
   T sv[UNROLL];
-  T b[UNROLL][V];
+  Row<T, G, C> b[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     if (u < n) {
@@ -328,48 +363,45 @@ __device__ __forceinline__ void spmm_block(const Plan &pl, const T *__restrict__
   }
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
-    if (j[u] >= 0) ldv<T, V>(B + (int64_t)j[u] * ldb, f0, wq, b[u]);
-    else {
-#pragma unroll
-      for (int e = 0; e < V; ++e) b[u][e] = T(0);
-    }
+    if (j[u] >= 0) b[u].load(B + (int64_t)j[u] * ldb, sub, wq);
+    else b[u].zero();
   }
 #pragma unroll
-  for (int u = 0; u < UNROLL; ++u)
-#pragma unroll
-    for (int e = 0; e < V; ++e) acc[e] += sv[u] * b[u][e];
+  for (int u = 0; u < UNROLL; ++u) acc.axpy(sv[u], b[u]);
 }
 
-// out = coef * acc + x_row . M[:, slice]
-template <typename T, int V>
-__device__ __forceinline__ void lowrank_epilogue(T (&acc)[V], double coef, const T *__restrict__ xr,
-                                                 int kx, const T *__restrict__ M, int ldm, int wq,
-                                                 int f0) {
+// acc <- coef * acc + x_row . M[:, slice]
+template <typename T, int G, int C>
+__device__ __forceinline__ void lowrank_epilogue(Row<T, G, C> &acc, double coef,
+                                                 const T *__restrict__ xr, int kx,
+                                                 const T *__restrict__ M, int ldm, int wq,
+                                                 int sub) {
+  using RowT = Row<T, G, C>;
 #pragma unroll
-  for (int e = 0; e < V; ++e) acc[e] *= (T)coef;
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int e = 0; e < RowT::V; ++e) acc.v[c][e] *= (T)coef;
   for (int r = 0; r < kx; ++r) {
-    const T xv = xr[r];
-    T mv[V];
-    ldv<T, V>(M + (int64_t)r * ldm, f0, wq, mv);
-#pragma unroll
-    for (int e = 0; e < V; ++e) acc[e] += xv * mv[e];
+    RowT mv;
+    mv.load(M + (int64_t)r * ldm, sub, wq);
+    acc.axpy(xr[r], mv);
   }
 }
 
-template <typename T, int G>
+template <typename T, int G, int C>
 __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
                                               const T *__restrict__ B, int ldb, int wq,
                                               double coef, const T *__restrict__ X, int ldx,
                                               int kx, const T *__restrict__ M, int ldm,
-                                              T *__restrict__ C, int ldc,
+                                              T *__restrict__ Cm, int ldc,
                                               T *__restrict__ partial, int64_t total_waves) {
-  constexpr int V = VT<T>::V, S = 64 / G, WB = G * V;
-  const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G, f0 = sub * V;
+  using RowT = Row<T, G, C>;
+  constexpr int S = 64 / G, WB = RowT::WB;
+  const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
   const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
   const int64_t sw = short_waves(pl, G);
-  T acc[V];
-#pragma unroll
-  for (int e = 0; e < V; ++e) acc[e] = T(0);
+  RowT acc;
+  acc.zero();
   if (gw < sw) {
     const int64_t ri = gw * S + slot;
     if (ri < pl.n_short) {
@@ -377,10 +409,10 @@ __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
       const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
       for (int64_t p = beg; p < end; p += UNROLL) {
         const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
-        spmm_block<T, G, V>(pl, Sv, B, ldb, wq, f0, acc, p, 1, n);
+        spmm_block<T, G, C>(pl, Sv, B, ldb, wq, sub, acc, p, 1, n);
       }
-      lowrank_epilogue<T, V>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, f0);
-      stv<T, V>(C + (int64_t)row * ldc, f0, wq, acc);
+      lowrank_epilogue<T, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
+      acc.store(Cm + (int64_t)row * ldc, sub, wq);
     }
   } else if (gw < total_waves) {
     const int64_t pc = gw - sw;
@@ -391,43 +423,46 @@ __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
     for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
       const int64_t rem = (end - p + S - 1) / S;
       const int n = (int)(rem < UNROLL ? rem : UNROLL);
-      spmm_block<T, G, V>(pl, Sv, B, ldb, wq, f0, acc, p, S, n);
+      spmm_block<T, G, C>(pl, Sv, B, ldb, wq, sub, acc, p, S, n);
     }
 #pragma unroll
-    for (int e = 0; e < V; ++e) acc[e] = slot_sum<G>(acc[e]);
-    if (slot == 0) stv<T, V>(partial + pc * WB, f0, WB, acc);
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < RowT::V; ++e) acc.v[c][e] = slot_sum<G>(acc.v[c][e]);
+    if (slot == 0) acc.store(partial + pc * WB, sub, WB);
   }
 }
 
-template <typename T, int G>
+template <typename T, int G, int C>
 __global__ __launch_bounds__(256) void k_spmm_fix(Plan pl, const T *__restrict__ partial,
                                                   double coef, const T *__restrict__ X, int ldx,
                                                   int kx, const T *__restrict__ M, int ldm, int wq,
-                                                  T *__restrict__ C, int ldc) {
-  constexpr int V = VT<T>::V, WB = G * V;
+                                                  T *__restrict__ Cm, int ldc) {
+  using RowT = Row<T, G, C>;
   const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const int f0 = (threadIdx.x % G) * V;
+  const int sub = threadIdx.x % G;
   if (g >= pl.n_long) return;
   const int row = pl.long_rows[g];
-  T acc[V];
-#pragma unroll
-  for (int e = 0; e < V; ++e) acc[e] = T(0);
+  RowT acc, t;
+  acc.zero();
   for (int pc = pl.long_p0[g]; pc < pl.long_p0[g + 1]; ++pc) {
-    T t[V];
-    ldv<T, V>(partial + (int64_t)pc * WB, f0, WB, t);
-#pragma unroll
-    for (int e = 0; e < V; ++e) acc[e] += t[e];
+    t.load(partial + (int64_t)pc * RowT::WB, sub, RowT::WB);
+    acc.axpy(T(1), t);
   }
-  lowrank_epilogue<T, V>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, f0);
-  stv<T, V>(C + (int64_t)row * ldc, f0, wq, acc);
+  lowrank_epilogue<T, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
+  acc.store(Cm + (int64_t)row * ldc, sub, wq);
 }
 
 // ============================================================================ launchers
-static inline int pick_G(int width, int V) {
-  int need = (width + V - 1) / V;
-  int G = 4;
-  while (G < need && G < 64) G <<= 1;
-  return G;
+// Lane group G and chunk count C for a width w: G = 4 (one 64-byte span) for
+// narrow rows, else G = 8 with C = ceil(w / (8 V)) line-sized chunks.
+struct GC {
+  int G, C;
+};
+static inline GC pick_gc(int width, int V) {
+  if (width <= 4 * V) return {4, 1};
+  int c = (width + 8 * V - 1) / (8 * V);
+  return {8, c < 1 ? 1 : c};
 }
 
 static inline int64_t total_waves(const Plan &pl, int G) { return short_waves(pl, G) + pl.n_pieces; }
@@ -437,14 +472,20 @@ static inline dim3 wave_grid(int64_t waves) {
   return dim3((unsigned)(b > 0 ? b : 1));
 }
 
-#define BMG_DISPATCH_G(G, ...)                                   \
-  switch (G) {                                                   \
-    case 4: { constexpr int GG = 4; __VA_ARGS__; } break;        \
-    case 8: { constexpr int GG = 8; __VA_ARGS__; } break;        \
-    case 16: { constexpr int GG = 16; __VA_ARGS__; } break;      \
-    case 32: { constexpr int GG = 32; __VA_ARGS__; } break;      \
-    default: { constexpr int GG = 64; __VA_ARGS__; } break;      \
-  }
+#define BMG_DISPATCH_GC(gc, ...)                                                        \
+  do {                                                                                  \
+    if (gc.G == 4) { constexpr int GG = 4, CC = 1; __VA_ARGS__; }                       \
+    else switch (gc.C) {                                                                \
+      case 1: { constexpr int GG = 8, CC = 1; __VA_ARGS__; } break;                     \
+      case 2: { constexpr int GG = 8, CC = 2; __VA_ARGS__; } break;                     \
+      case 3: { constexpr int GG = 8, CC = 3; __VA_ARGS__; } break;                     \
+      case 4: { constexpr int GG = 8, CC = 4; __VA_ARGS__; } break;                     \
+      case 5: { constexpr int GG = 8, CC = 5; __VA_ARGS__; } break;                     \
+      case 6: { constexpr int GG = 8, CC = 6; __VA_ARGS__; } break;                     \
+      case 7: { constexpr int GG = 8, CC = 7; __VA_ARGS__; } break;                     \
+      default: { constexpr int GG = 8, CC = 8; __VA_ARGS__; } break;                    \
+    }                                                                                   \
+  } while (0)
 
 template <typename T>
 hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const T *Y, int ldy, int k,
@@ -452,18 +493,18 @@ hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const T 
                        hipStream_t s) {
   constexpr int V = VT<T>::V;
   if (k > max_width<T>()) return hipErrorInvalidValue;
-  const int G = pick_G(k, V);
-  const int64_t tw = total_waves(pl, G);
+  const GC gc = pick_gc(k, V);
+  const int64_t tw = total_waves(pl, gc.G);
   if (waves_out) *waves_out = tw;
-  BMG_DISPATCH_G(G, {
+  BMG_DISPATCH_GC(gc, {
     if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
-    hipLaunchKernelGGL((k_grad<T, GG>), wave_grid(tw), dim3(256), 0, s, pl, a, X, ldx, Y, ldy, k,
-                       lam, Out, ldo, (T *)sc.partial, sc.wsum, tw);
+    hipLaunchKernelGGL((k_grad<T, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, a, X, ldx, Y, ldy,
+                       k, lam, Out, ldo, (T *)sc.partial, sc.wsum, tw);
     if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
     if (pl.n_long > 0) {
       const int64_t thr = pl.n_long * GG;
-      hipLaunchKernelGGL((k_grad_fix<T, GG>), dim3((unsigned)((thr + 255) / 256)), dim3(256), 0, s,
-                         pl, (const T *)sc.partial, X, ldx, k, lam, Out, ldo);
+      hipLaunchKernelGGL((k_grad_fix<T, GG, CC>), dim3((unsigned)((thr + 255) / 256)), dim3(256),
+                         0, s, pl, (const T *)sc.partial, X, ldx, k, lam, Out, ldo);
     }
   });
   hipError_t e = hipGetLastError();
@@ -476,12 +517,12 @@ hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const T
                         T *R, PassScratch sc, hipStream_t s) {
   constexpr int V = VT<T>::V;
   if (k > max_width<T>()) return hipErrorInvalidValue;
-  const int G = pick_G(k, V);
-  const int64_t tw = total_waves(pl, G);
-  BMG_DISPATCH_G(G, {
+  const GC gc = pick_gc(k, V);
+  const int64_t tw = total_waves(pl, gc.G);
+  BMG_DISPATCH_GC(gc, {
     if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
-    hipLaunchKernelGGL((k_sddmm<T, GG>), wave_grid(tw), dim3(256), 0, s, pl, a, X, ldx, Y, ldy, k,
-                       R, sc.wsum, tw);
+    hipLaunchKernelGGL((k_sddmm<T, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, a, X, ldx, Y,
+                       ldy, k, R, sc.wsum, tw);
     if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
   });
   hipError_t e = hipGetLastError();
@@ -491,24 +532,25 @@ hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const T
 
 template <typename T>
 hipError_t launch_spmm(const Plan &pl, const T *Sv, const T *B, int ldb, int q, double coef,
-                       const T *X, int ldx, int kx, const T *M, int ldm, T *C, int ldc,
+                       const T *X, int ldx, int kx, const T *M, int ldm, T *Cm, int ldc,
                        PassScratch sc, hipStream_t s) {
   constexpr int V = VT<T>::V;
   const int WMAX = max_width<T>();
   for (int c0 = 0; c0 < q; c0 += WMAX) {
     const int wq = (q - c0) < WMAX ? (q - c0) : WMAX;
-    const int G = pick_G(wq, V);
-    const int64_t tw = total_waves(pl, G);
-    BMG_DISPATCH_G(G, {
+    const GC gc = pick_gc(wq, V);
+    const int64_t tw = total_waves(pl, gc.G);
+    BMG_DISPATCH_GC(gc, {
       if (sc.ev0 && c0 == 0) (void)hipEventRecord(sc.ev0, s);
-      hipLaunchKernelGGL((k_spmm<T, GG>), wave_grid(tw), dim3(256), 0, s, pl, Sv, B + c0, ldb, wq,
-                         coef, X, ldx, kx, M ? M + c0 : M, ldm, C + c0, ldc, (T *)sc.partial, tw);
+      hipLaunchKernelGGL((k_spmm<T, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, Sv, B + c0, ldb,
+                         wq, coef, X, ldx, kx, M ? M + c0 : M, ldm, Cm + c0, ldc, (T *)sc.partial,
+                         tw);
       if (sc.ev1 && c0 + WMAX >= q) (void)hipEventRecord(sc.ev1, s);
       if (pl.n_long > 0) {
         const int64_t thr = pl.n_long * GG;
-        hipLaunchKernelGGL((k_spmm_fix<T, GG>), dim3((unsigned)((thr + 255) / 256)), dim3(256), 0,
-                           s, pl, (const T *)sc.partial, coef, X, ldx, kx, M ? M + c0 : M, ldm, wq,
-                           C + c0, ldc);
+        hipLaunchKernelGGL((k_spmm_fix<T, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
+                           dim3(256), 0, s, pl, (const T *)sc.partial, coef, X, ldx, kx,
+                           M ? M + c0 : M, ldm, wq, Cm + c0, ldc);
       }
     });
     hipError_t e = hipGetLastError();
@@ -544,45 +586,48 @@ hipError_t launch_reduce_wsum(const double *wsum, int64_t waves, int nsum, doubl
 }
 
 // ============================================================================ tall-skinny Gram
-// part[chunk][a][b] = sum over the chunk's rows of X[r, :a]^T Y[r, :b]; then
-// out = sum over chunks in chunk order.  64-row x 32-column LDS tiles, FP64.
-constexpr int GR_ROWS = 64, GR_T = 32;
-
-template <typename T>
+// part[w][a][b] = sum over the rows of wave w of X[r, :a]^T Y[r, :b]; then
+// out = sum over waves in wave order.  Lane l of a wave owns output column
+// j = 64*blockIdx.z + l and up to IA output rows i0..i0+IA-1; per data row it
+// loads one element of Y (coalesced across lanes) and the IA values of X,
+// which are the same for every lane (uniform loads).  Reads X and Y once.
+template <typename T, int IA>
 __global__ __launch_bounds__(256) void k_gram(int64_t N, int a, const T *__restrict__ X, int ldx,
                                               int b, const T *__restrict__ Y, int ldy,
-                                              int64_t rows_per_chunk, double *__restrict__ part) {
-  __shared__ double xs[GR_ROWS][GR_T + 1];
-  __shared__ double ys[GR_ROWS][GR_T + 1];
-  const int ta = blockIdx.x, tb = blockIdx.y;
-  const int64_t chunk = blockIdx.z;
-  const int tx = threadIdx.x % GR_T, ty = threadIdx.x / GR_T;  // ty in 0..7
-  const int64_t r_beg = chunk * rows_per_chunk;
-  int64_t r_end = r_beg + rows_per_chunk;
-  if (r_end > N) r_end = N;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t r0 = r_beg; r0 < r_end; r0 += GR_ROWS) {
-    for (int t = threadIdx.x; t < GR_ROWS * GR_T; t += 256) {
-      const int rr = t / GR_T, cc = t % GR_T;
-      const int64_t r = r0 + rr;
-      const int ca = ta * GR_T + cc, cb = tb * GR_T + cc;
-      xs[rr][cc] = (r < r_end && ca < a) ? (double)X[r * ldx + ca] : 0.0;
-      ys[rr][cc] = (r < r_end && cb < b) ? (double)Y[r * ldy + cb] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < GR_ROWS; ++rr) {
-      const double yv = ys[rr][tx];
+                                              int64_t rows_per_wave, int64_t nwaves,
+                                              double *__restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int i0 = blockIdx.y * IA;
+  const int j = blockIdx.z * 64 + lane;
+  if (w >= nwaves) return;
+  const int64_t r0 = w * rows_per_wave;
+  const int64_t r1 = (r0 + rows_per_wave < N) ? r0 + rows_per_wave : N;
+  const int ia = (a - i0) < IA ? (a - i0) : IA;
+  const bool on = j < b;
+  double acc[IA];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] += xs[rr][ty + 8 * i] * yv;
-    }
-    __syncthreads();
-  }
+  for (int i = 0; i < IA; ++i) acc[i] = 0.0;
+  int64_t r = r0;
+  for (; r + 2 <= r1; r += 2) {
+    const double y0 = on ? (double)Y[r * ldy + j] : 0.0;
+    const double y1 = on ? (double)Y[(r + 1) * ldy + j] : 0.0;
+    const T *x0 = X + r * ldx + i0, *x1 = X + (r + 1) * ldx + i0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int ia = ta * GR_T + ty + 8 * i, ib = tb * GR_T + tx;
-    if (ia < a && ib < b) part[(chunk * a + ia) * b + ib] = acc[i];
+    for (int i = 0; i < IA; ++i)
+      if (i < ia) acc[i] += (double)x0[i] * y0 + (double)x1[i] * y1;
   }
+  if (r < r1) {
+    const double y0 = on ? (double)Y[r * ldy + j] : 0.0;
+    const T *x0 = X + r * ldx + i0;
+#pragma unroll
+    for (int i = 0; i < IA; ++i)
+      if (i < ia) acc[i] += (double)x0[i] * y0;
+  }
+  if (on)
+#pragma unroll
+    for (int i = 0; i < IA; ++i)
+      if (i < ia) part[(w * a + i0 + i) * b + j] = acc[i];
 }
 
 __global__ void k_gram_reduce(int64_t nchunks, int64_t ab, const double *__restrict__ part,
@@ -599,28 +644,25 @@ hipError_t launch_gram(int64_t N, int a, const T *X, int ldx, int b, const T *Y,
                        double *part, int64_t part_cap, double *out, hipStream_t s) {
   const int64_t ab = (int64_t)a * b;
   if (ab == 0) return hipSuccess;
-  const int tiles = ((a + GR_T - 1) / GR_T) * ((b + GR_T - 1) / GR_T);
-  int64_t nchunks = (N + 4095) / 4096;
-  // enough blocks to fill the chip, bounded by the partial buffer
-  if (nchunks * tiles < 2048) nchunks = (2048 + tiles - 1) / tiles;
-  int64_t maxc = (N + GR_ROWS - 1) / GR_ROWS;
-  if (nchunks > maxc) nchunks = maxc;
-  if (nchunks < 1) nchunks = 1;
-  if (nchunks * ab > part_cap) nchunks = part_cap / ab;
-  if (nchunks < 1) return hipErrorInvalidValue;
-  int64_t rpc = (N + nchunks - 1) / nchunks;
-  rpc = ((rpc + GR_ROWS - 1) / GR_ROWS) * GR_ROWS;
-  if (rpc < GR_ROWS) rpc = GR_ROWS;
-  nchunks = N > 0 ? (N + rpc - 1) / rpc : 1;
-  if (N == 0) {
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ab + 255) / 256)), dim3(256), 0, s,
-                       (int64_t)0, ab, part, out);
-    return hipGetLastError();
+  int64_t nwaves = (N + 255) / 256;          // >= 256 rows per wave
+  if (nwaves > 2048) nwaves = 2048;
+  if (nwaves < 1) nwaves = 1;
+  if (nwaves * ab > part_cap) nwaves = part_cap / ab;
+  if (nwaves < 1) return hipErrorInvalidValue;
+  const int64_t rpw = N > 0 ? (N + nwaves - 1) / nwaves : 1;
+  nwaves = N > 0 ? (N + rpw - 1) / rpw : 0;
+  if (nwaves > 0) {
+    const int IA = a > 16 ? 32 : (a > 8 ? 16 : 8);
+    dim3 grid((unsigned)((nwaves + 3) / 4), (unsigned)((a + IA - 1) / IA), (unsigned)((b + 63) / 64));
+    if (IA == 32)
+      hipLaunchKernelGGL((k_gram<T, 32>), grid, dim3(256), 0, s, N, a, X, ldx, b, Y, ldy, rpw, nwaves, part);
+    else if (IA == 16)
+      hipLaunchKernelGGL((k_gram<T, 16>), grid, dim3(256), 0, s, N, a, X, ldx, b, Y, ldy, rpw, nwaves, part);
+    else
+      hipLaunchKernelGGL((k_gram<T, 8>), grid, dim3(256), 0, s, N, a, X, ldx, b, Y, ldy, rpw, nwaves, part);
   }
-  dim3 grid((a + GR_T - 1) / GR_T, (b + GR_T - 1) / GR_T, (unsigned)nchunks);
-  hipLaunchKernelGGL((k_gram<T>), grid, dim3(256), 0, s, N, a, X, ldx, b, Y, ldy, rpc, part);
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ab + 255) / 256)), dim3(256), 0, s, nchunks,
-                     ab, part, out);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ab + 255) / 256)), dim3(256), 0, s, nwaves, ab,
+                     part, out);
   return hipGetLastError();
 }
 
