@@ -152,6 +152,7 @@ def main():
                     for c in range(3)},
     }
     if not args.no_extras:
+        out["precision_modes"] = precision_steps(bmg, p, dev, k0, lam)
         out["time_to_tol"] = time_to_tol(bmg, synth, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -159,23 +160,52 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def precision_steps(bmg, p, dev, k0, lam, steps=2):
+    """The same step (one outer iteration from the same start) in the lower
+    precision modes on the same workload."""
+    import torch
+    out = {}
+    for prec in ("fp32", "bf16"):
+        prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision=prec,
+                                     device=dev)
+        W, H = prob.zeros_factors()
+        run = lambda: prob.bmg_solve(W, H, lam=lam, k_init=k0, max_iter=1, tol=0.0, seed=1003,  # noqa: E731
+                                     timing=1, refresh_every=1000)[3]
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = [run() for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        kms = [sum(r["kernel_ms"][c] for r in recs) / steps for c in range(3)]
+        out[prec] = {"ms_per_step": round(dt * 1e3, 3),
+                     "GB/s": round(sum(r["sparse_bytes"] for r in recs) / steps / dt / 1e9, 2),
+                     "kernel_ms_per_step": {KERNEL_SYMBOLS[c]: round(kms[c], 3) for c in range(3)}}
+        log("step %s: %.1f ms" % (prec, dt * 1e3))
+        del prob
+    return out
+
+
 def time_to_tol(bmg, synth, dev):
     """Full solves of the 1000 x 1500 workload (|Omega| = 50,000, lambda = 0.5,
-    k0 = 8) to relative optimality residual 1e-6, FP64 and FP32."""
+    k0 = 8) to relative optimality residual 1e-6 in FP64, FP32 and BF16 (BF16:
+    FP64 refresh every 5 outer iterations, whose PG steps gather FP32)."""
     from oracle import core
     p = synth.small_uniform()
     out = {"workload": "small_uniform 1000x1500 nnz=50000 lambda=0.5 k0=8", "tol": 1e-6}
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", "small_uniform.json")))
-    for prec in ("fp64", "fp32"):
-        prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=128, precision=prec,
+    for prec, tol in (("fp64", 1e-6), ("fp32", 1e-6), ("bf16", 1e-6)):
+        prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n,
+                                     k_cap=128 if prec == "fp64" else 192, precision=prec,
                                      device=dev)
-        prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=11, max_iter=2)   # warm caches
+        prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=tol, seed=11, max_iter=2)   # warm caches
         t0 = time.perf_counter()
-        W, H, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=11, max_iter=3000)
+        W, H, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=tol, seed=11, max_iter=1000)
         dt = time.perf_counter() - t0
         Wn, Hn = W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k]
         F64 = core.objective(p, Wn, Hn, p.lam)
-        out[prec] = {"seconds": round(dt, 4), "iters": r["iters"], "rank": k,
+        out[prec] = {"seconds": round(dt, 4), "iters": r["iters"], "rank": k, "tol": tol,
+                     "converged": r["status"] == 0, "residual": r["residual"],
                      "F": F64, "rel_err_vs_oracle_optimum": (F64 - golden["F"]) / golden["F"]}
         log("time-to-tol %s: %.3fs, %d iters, k=%d" % (prec, dt, r["iters"], k))
     return out

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "bmg.h"
@@ -63,6 +64,7 @@ struct Layout {
   size_t pr_short, pr_long, pr_lp0, pr_prow, pr_pbeg;
   size_t pc_short, pc_long, pc_lp0, pc_prow, pc_pbeg;
   size_t wsum, partial, result, gram_part, small;
+  size_t g_W, g_H, g_U, g_Y, d_W64, d_H64, d_R64;  // BF16 mode: shadows and FP64 refresh
   int64_t max_long, max_pieces, wsum_cap, gram_cap;
   // scratch region (setup sort / solver blocks overlap)
   size_t scratch;
@@ -119,6 +121,17 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_prec
   L.result = take(8 * 64);
   L.gram_part = take(8 * L.gram_cap);
   L.small = take(8 * 9 * (size_t)L.qld * L.qld);
+  {
+    const bool bf = prec == BMG_BF16;
+    const int64_t mi0 = std::min(m, n), ni0 = std::max(m, n);
+    L.g_W = take(bf ? 2 * mi0 * L.ldk : 0);
+    L.g_H = take(bf ? 2 * ni0 * L.ldk : 0);
+    L.g_U = take(bf ? 2 * mi0 * L.qld : 0);
+    L.g_Y = take(bf ? 2 * ni0 * L.qld : 0);
+    L.d_W64 = take(bf ? 8 * mi0 * L.ldk : 0);
+    L.d_H64 = take(bf ? 8 * ni0 * L.ldk : 0);
+    L.d_R64 = take(bf ? 8 * nnz : 0);
+  }
   L.scratch = off;
   // setup view of the scratch region
   size_t so = off;
@@ -295,8 +308,11 @@ static void build_plan(bmg_problem *P, int64_t nrows, const int64_t *d_ptr, cons
 // ============================================================================ typed solver
 // Everything below runs on the internal orientation: m <= n, rows() = Omega,
 // cols() = Omega^T.  T is the storage/multiply type of the sparse passes.
-template <typename T>
+template <typename T, typename TG = T>
 struct Engine {
+  static constexpr bool kShadow = !std::is_same<T, TG>::value;
+  // BF16 mode: the subspace products of a refresh step gather the FP32 masters
+  bool exact_gather = false;
   bmg_problem *P;
   hipStream_t s;
   int ldk, qld;
@@ -312,6 +328,31 @@ struct Engine {
   const T *avals(Side *sd) {
     if constexpr (sizeof(T) == 8) return (const T *)sd->a64;
     else return (const T *)sd->a32;
+  }
+  // Runs f(gathered operand): the BF16 shadow of src, or src itself in the FP64 /
+  // FP32 modes and whenever exact_gather is set.
+  template <class F>
+  void with_gather(int slot, const T *src, int64_t rows, int cols, int ld, F &&f) {
+    if constexpr (kShadow) {
+      if (!exact_gather) {
+        f(gath(slot, src, rows, cols, ld));
+        return;
+      }
+    }
+    f(src);
+  }
+  // The operand a sparse pass gathers, in the gather type: src itself, or its
+  // BF16 shadow (converted just before the pass).  Slots: 0 m-side factor,
+  // 1 n-side factor, 2 m-side block, 3 n-side block.
+  const TG *gath(int slot, const T *src, int64_t rows, int cols, int ld) {
+    if constexpr (!kShadow) {
+      return src;
+    } else {
+      const size_t off = slot == 0 ? P->L.g_W : slot == 1 ? P->L.g_H : slot == 2 ? P->L.g_U : P->L.g_Y;
+      TG *dst = P->at<TG>(off);
+      if (cols > 0 && rows > 0) HIPC((launch_convert_cols<T, TG>(rows, cols, src, ld, dst, ld, s)));
+      return dst;
+    }
   }
   T *blk(size_t off) { return P->at<T>(off); }
 
@@ -376,37 +417,52 @@ struct Engine {
   // ---------------------------------------------------------------- sparse passes
   // BM gradient on the rows side: G = R H + lam W (+ f = 1/2 sum r^2)
   double grad_rows(const T *W, const T *H, int k, double lam, T *G) {
-    HIPC(launch_grad<T>(R->pl, avals(R), W, ldk, H, ldk, k, lam, G, ldk, sx(0), nullptr, s));
-    count(R->pl, 4.0 + sizeof(T), (double)(m + n) * k * sizeof(T) + (double)m * k * sizeof(T));
+    with_gather(1, H, n, k, ldk, [&](auto Yg) {
+      using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
+      HIPC((launch_grad<T, TY>(R->pl, avals(R), W, ldk, Yg, ldk, k, lam, G, ldk, sx(0), nullptr, s)));
+    });
+    count(R->pl, 4.0 + sizeof(T), (double)n * k * sizeof(TG) + 2.0 * m * k * sizeof(T));
     double h[1];
     fetch(h, P->result, 1);
     return 0.5 * h[0];
   }
   double grad_cols(const T *W, const T *H, int k, double lam, T *G) {
-    HIPC(launch_grad<T>(C->pl, avals(C), H, ldk, W, ldk, k, lam, G, ldk, sx(0), nullptr, s));
-    count(C->pl, 4.0 + sizeof(T), (double)(m + n) * k * sizeof(T) + (double)n * k * sizeof(T));
+    with_gather(0, W, m, k, ldk, [&](auto Yg) {
+      using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
+      HIPC((launch_grad<T, TY>(C->pl, avals(C), H, ldk, Yg, ldk, k, lam, G, ldk, sx(0), nullptr, s)));
+    });
+    count(C->pl, 4.0 + sizeof(T), (double)m * k * sizeof(TG) + 2.0 * n * k * sizeof(T));
     double h[1];
     fetch(h, P->result, 1);
     return 0.5 * h[0];
   }
   // sum over Omega of (x_row . y_col)^2 on the given side
   double curvature(Side *sd, const T *X, const T *Y, int k, int64_t nx, int64_t ny) {
-    HIPC(launch_sddmm<T>(sd->pl, (const T *)nullptr, X, ldk, Y, ldk, k, (T *)nullptr, sx(1), s));
-    count(sd->pl, 4.0, (double)(nx + ny) * k * sizeof(T));
+    with_gather(sd == R ? 1 : 0, Y, ny, k, ldk, [&](auto Yg) {
+      using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
+      HIPC((launch_sddmm<T, TY>(sd->pl, (const T *)nullptr, X, ldk, Yg, ldk, k, (T *)nullptr, sx(1), s)));
+    });
+    count(sd->pl, 4.0, (double)nx * k * sizeof(T) + (double)ny * k * sizeof(TG));
     double h[2];
     fetch(h, P->result, 2);
     return h[0];
   }
   // stored residual on one side; returns {sum r^2, sum r (r + a)}
   void sddmm_store(Side *sd, const T *X, const T *Y, int k, int64_t nx, int64_t ny, double out[2]) {
-    HIPC(launch_sddmm<T>(sd->pl, avals(sd), X, ldk, Y, ldk, k, (T *)sd->r, sx(1), s));
-    count(sd->pl, 4.0 + 2.0 * sizeof(T), (double)(nx + ny) * k * sizeof(T));
+    with_gather(sd == R ? 1 : 0, Y, ny, k, ldk, [&](auto Yg) {
+      using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
+      HIPC((launch_sddmm<T, TY>(sd->pl, avals(sd), X, ldk, Yg, ldk, k, (T *)sd->r, sx(1), s)));
+    });
+    count(sd->pl, 4.0 + 2.0 * sizeof(T), (double)nx * k * sizeof(T) + (double)ny * k * sizeof(TG));
     fetch(out, P->result, 2);
   }
   double loss(const T *W, const T *H, int k) {
     if (R->pl.nnz == 0) return 0.0;
-    HIPC(launch_sddmm<T>(R->pl, avals(R), W, ldk, H, ldk, k, (T *)nullptr, sx(1), s));
-    count(R->pl, 4.0 + sizeof(T), (double)(m + n) * k * sizeof(T));
+    with_gather(1, H, n, k, ldk, [&](auto Yg) {
+      using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
+      HIPC((launch_sddmm<T, TY>(R->pl, avals(R), W, ldk, Yg, ldk, k, (T *)nullptr, sx(1), s)));
+    });
+    count(R->pl, 4.0 + sizeof(T), (double)m * k * sizeof(T) + (double)n * k * sizeof(TG));
     double h[2];
     fetch(h, P->result, 2);
     return 0.5 * h[0];
@@ -426,18 +482,24 @@ struct Engine {
     if (q == 0) return;
     T *dM = nullptr;
     if (z.k > 0) dM = put_t(gram(m, z.k, z.W, ldk, q, U, qld), 0);
-    HIPC(launch_spmm<T>(C->pl, z.s_cols, U, qld, q, -z.alpha, z.H, ldk, z.k, dM, q, Y, qld,
-                        sx(2), s));
-    count(C->pl, 4.0 + sizeof(T), (double)(m + n) * q * sizeof(T));
+    with_gather(2, U, m, q, qld, [&](auto Ug) {
+      using TY = std::remove_const_t<std::remove_pointer_t<decltype(Ug)>>;
+      HIPC((launch_spmm<T, TY>(C->pl, z.s_cols, Ug, qld, q, -z.alpha, z.H, ldk, z.k, dM, q, Y, qld,
+                               sx(2), s)));
+    });
+    count(C->pl, 4.0 + sizeof(T), (double)m * q * sizeof(TG) + (double)n * q * sizeof(T));
   }
   // V (m x q) = Z Y = W (H^T Y) - alpha S Y
   void z_n(const ZOp &z, const T *Y, int q, T *V) {
     if (q == 0) return;
     T *dM = nullptr;
     if (z.k > 0) dM = put_t(gram(n, z.k, z.H, ldk, q, Y, qld), 1);
-    HIPC(launch_spmm<T>(R->pl, z.s_rows, Y, qld, q, -z.alpha, z.W, ldk, z.k, dM, q, V, qld,
-                        sx(2), s));
-    count(R->pl, 4.0 + sizeof(T), (double)(m + n) * q * sizeof(T));
+    with_gather(3, Y, n, q, qld, [&](auto Yg) {
+      using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
+      HIPC((launch_spmm<T, TY>(R->pl, z.s_rows, Yg, qld, q, -z.alpha, z.W, ldk, z.k, dM, q, V, qld,
+                               sx(2), s)));
+    });
+    count(R->pl, 4.0 + sizeof(T), (double)n * q * sizeof(TG) + (double)m * q * sizeof(T));
   }
 
   // ---------------------------------------------------------------- orth
@@ -519,7 +581,7 @@ extern "C" bmg_status bmg_workspace_size(int64_t m, int64_t n, int64_t nnz, int 
   if (!bytes || m < 0 || n < 0 || nnz < 0 || k_cap < 1 || nnz > (int64_t)INT32_MAX ||
       m > (int64_t)INT32_MAX || n > (int64_t)INT32_MAX)
     return fail(BMG_EINVAL, "bmg_workspace_size: bad shape");
-  if (prec != BMG_FP64 && prec != BMG_FP32) return fail(BMG_EINVAL, "precision not supported");
+  if (prec != BMG_FP64 && prec != BMG_FP32 && prec != BMG_BF16) return fail(BMG_EINVAL, "unknown precision");
   const int64_t mi = std::min(m, n);
   (void)mi;
   if (k_cap > (prec == BMG_FP64 ? max_width<double>() : max_width<float>()))
@@ -641,7 +703,7 @@ extern "C" bmg_status bmg_sddmm(bmg_problem *P, const double *W, const double *H
   try {
     double h[2] = {0, 0};
     if (P->nnz > 0) {
-      HIPC(launch_sddmm<double>(P->urow.pl, P->urow.a64, W, ld, H, ld, k, R, P->scratch(), P->s));
+      HIPC((launch_sddmm<double, double>(P->urow.pl, P->urow.a64, W, ld, H, ld, k, R, P->scratch(), P->s)));
       HIPC(hipMemcpyAsync(h, P->result, 16, hipMemcpyDeviceToHost, P->s));
     }
     HIPC(hipStreamSynchronize(P->s));
@@ -659,15 +721,15 @@ extern "C" bmg_status bmg_spmm(bmg_problem *P, const double *S, const double *B,
     if (q == 0) return BMG_OK;
     if (!transpose) {
       if (P->nnz == 0) HIPC(launch_fill<double>(C, P->m_user, q, ldc, 0.0, P->s));
-      else HIPC(launch_spmm<double>(P->urow.pl, S, B, ldb, q, 1.0, nullptr, 0, 0, nullptr, 0, C, ldc,
-                                    P->scratch(), P->s));
+      else HIPC((launch_spmm<double, double>(P->urow.pl, S, B, ldb, q, 1.0, nullptr, 0, 0, nullptr, 0, C, ldc,
+                                    P->scratch(), P->s)));
     } else {
       if (P->nnz == 0) HIPC(launch_fill<double>(C, P->n_user, q, ldc, 0.0, P->s));
       else {
         double *Sc = (double *)P->ucol.r;  // values permuted into column order
         HIPC(launch_gather_perm(P->nnz, P->perm, S, Sc, P->s));
-        HIPC(launch_spmm<double>(P->ucol.pl, Sc, B, ldb, q, 1.0, nullptr, 0, 0, nullptr, 0, C, ldc,
-                                 P->scratch(), P->s));
+        HIPC((launch_spmm<double, double>(P->ucol.pl, Sc, B, ldb, q, 1.0, nullptr, 0, 0, nullptr, 0, C, ldc,
+                                 P->scratch(), P->s)));
       }
     }
     HIPC(hipStreamSynchronize(P->s));
@@ -678,9 +740,10 @@ extern "C" bmg_status bmg_spmm(bmg_problem *P, const double *S, const double *B,
 }
 
 // ============================================================================ the method (internal orientation)
-template <typename T>
-struct Method : Engine<T> {
-  using E = Engine<T>;
+template <typename T, typename TG = T>
+struct Method : Engine<T, TG> {
+  using E = Engine<T, TG>;
+  using E::kShadow;
   using E::P; using E::s; using E::ldk; using E::qld; using E::m; using E::n; using E::R; using E::C;
   using E::gram; using E::gemm; using E::orth; using E::z_t; using E::z_n; using E::blk; using E::avals;
   using typename E::ZOp;
@@ -938,18 +1001,55 @@ struct Method : Engine<T> {
     bool added = false;
     double residual = 0.0, eps = 0.0;
   };
+  // FP64 sampled residual of both orientations from the FP32 masters (BF16
+  // mode refresh): R in FP64 from FP64 copies of W, H and the FP64 values,
+  // stored back in the pass type.
+  void residual_fp64(const T *W, const T *H, int k, double sr[2]) {
+    double *W64 = P->template at<double>(P->L.d_W64), *H64 = P->template at<double>(P->L.d_H64);
+    double *R64 = P->template at<double>(P->L.d_R64);
+    HIPC((launch_convert_cols<T, double>(m, k, W, ldk, W64, ldk, s)));
+    HIPC((launch_convert_cols<T, double>(n, k, H, ldk, H64, ldk, s)));
+    double sc[2];
+    HIPC((launch_sddmm<double, double>(R->pl, R->a64, W64, ldk, H64, ldk, k, R64, E::sx(1), s)));
+    E::count(R->pl, 20.0, (double)(m + n) * k * 8.0);
+    E::fetch(sr, P->result, 2);
+    HIPC((launch_convert<double, T>(R->pl.nnz, R64, (T *)R->r, s)));
+    HIPC((launch_sddmm<double, double>(C->pl, C->a64, H64, ldk, W64, ldk, k, R64, E::sx(1), s)));
+    E::count(C->pl, 20.0, (double)(m + n) * k * 8.0);
+    E::fetch(sc, P->result, 2);
+    HIPC((launch_convert<double, T>(C->pl.nnz, R64, (T *)C->r, s)));
+  }
+  double loss_fp64(const T *W, const T *H, int k) {
+    if (R->pl.nnz == 0) return 0.0;
+    double *W64 = P->template at<double>(P->L.d_W64), *H64 = P->template at<double>(P->L.d_H64);
+    HIPC((launch_convert_cols<T, double>(m, k, W, ldk, W64, ldk, s)));
+    HIPC((launch_convert_cols<T, double>(n, k, H, ldk, H64, ldk, s)));
+    HIPC((launch_sddmm<double, double>(R->pl, R->a64, W64, ldk, H64, ldk, k, (double *)nullptr,
+                                       E::sx(1), s)));
+    E::count(R->pl, 12.0, (double)(m + n) * k * 8.0);
+    double h[2];
+    E::fetch(h, P->result, 2);
+    return 0.5 * h[0];
+  }
+
   StepInfo pg_step(State &S, bool changed, double lam, double alpha, double tau, int ssi_max,
-                   uint64_t seed, int t) {
+                   uint64_t seed, int t, bool fp64_refresh = false) {
     StepInfo info;
     const int k = S.k;
     T *B1 = blk(P->L.b_B1), *B2 = blk(P->L.b_B2), *B4 = blk(P->L.b_B4);
     // residual of X~ stored in both orientations
     double sr[2] = {0, 0}, sc[2] = {0, 0};
     if (R->pl.nnz > 0) {
-      E::sddmm_store(R, S.W, S.H, k, m, n, sr);
-      E::sddmm_store(C, S.H, S.W, k, n, m, sc);
+      if (kShadow && fp64_refresh && k > 0) {
+        residual_fp64(S.W, S.H, k, sr);
+      } else {
+        E::sddmm_store(R, S.W, S.H, k, m, n, sr);
+        E::sddmm_store(C, S.H, S.W, k, n, m, sc);
+      }
     }
     ZOp z{S.W, S.H, k, alpha, (const T *)R->r, (const T *)C->r};
+    const bool hi_before = this->exact_gather;
+    this->exact_gather = kShadow && (fp64_refresh || hi_before);
     // warm start (eqs. rt0 / rt0-1): orth([U_t, W~_t]) or orth([U_t, U_{t-1}])
     const T *second = changed ? S.W : S.Uprev;
     const int c2 = changed ? k : S.kp;
@@ -1040,6 +1140,7 @@ struct Method : Engine<T> {
     const double z2 = x2 - 2.0 * alpha * sr[1] + alpha * alpha * sr[0];
     info.eps = sqrt(std::max(z2 - tl.sum_sig2, 0.0));
     // safeguard bookkeeping
+    this->exact_gather = hi_before;
     const int trunc = tl.q - tl.k;
     S.has_u = trunc >= 1;
     if (trunc == 1) S.psi *= 0.5;
@@ -1053,9 +1154,10 @@ struct Method : Engine<T> {
     return info;
   }
 
-  double objective_balanced(State &S, double lam) {
+  double objective_balanced(State &S, double lam, bool fp64 = false) {
     double ssum = 0.0;
     for (double v : S.sigma) ssum += v;
+    if (kShadow && fp64) return (S.k > 0 ? loss_fp64(S.W, S.H, S.k) : E::loss(S.W, S.H, 0)) + lam * ssum;
     return E::loss(S.W, S.H, S.k) + lam * ssum;
   }
 
@@ -1065,12 +1167,22 @@ struct Method : Engine<T> {
     init_state(S);
     S.psi = o.psi0;
     initialize(S, o.k_init, o.lambda, o.seed);
-    double F = objective_balanced(S, o.lambda), F_bm = F, resid = INFINITY, eps = 0.0;
+    double F = objective_balanced(S, o.lambda, true), F_bm = F, resid = INFINITY, eps = 0.0;
+    const int every = std::max(1, o.refresh_every);
+    bool hi = false;                    // BF16 mode switched to FP32 gathers
+    double last_refresh = INFINITY;
     int t = 0, ssi_total = 0;
     bool conv = false;
     for (t = 0; t < o.max_iter; ++t) {
+      // BF16 mode: every `every`-th iteration is a refresh: no BM phase (the
+      // paper allows skipping it), R and F in FP64 and FP32 gathers in the PG
+      // step, so only its residual certifies convergence.  Once a refreshed
+      // residual is <= 1e-3 or stops falling, BF16 noise dominates the
+      // remaining error and every later iteration runs with FP32 gathers.
+      const bool refresh = !kShadow || hi || (t + 1) % every == 0;
+      this->exact_gather = kShadow && hi;
       bool changed = false;
-      for (int e = 0; e < o.bm_epochs && S.k > 0; ++e) {
+      for (int e = 0; e < o.bm_epochs && S.k > 0 && !(kShadow && refresh && !hi); ++e) {
         changed |= bm_half(true, S.W, S.H, S.k, o.lambda);
         changed |= bm_half(false, S.W, S.H, S.k, o.lambda);
       }
@@ -1078,22 +1190,28 @@ struct Method : Engine<T> {
       // FP32 passes cannot resolve Ritz values below ~1e-7 of the largest
       const double floor = std::max(o.ssi_tol_floor, sizeof(T) == 4 ? 1e-6 : 0.0);
       const double tau = std::max(floor, std::min(1e-4, 0.1 * S.res_prev * S.res_prev));
-      StepInfo st = pg_step(S, changed, o.lambda, o.alpha, tau, o.ssi_max_iter, o.seed, t);
+      StepInfo st = pg_step(S, changed, o.lambda, o.alpha, tau, o.ssi_max_iter, o.seed, t, refresh);
       ssi_total += st.iters;
       resid = st.residual;
       eps = st.eps;
-      F = objective_balanced(S, o.lambda);
+      F = objective_balanced(S, o.lambda, refresh);
       REQUIRE(std::isfinite(F) && std::isfinite(resid), BMG_ENONFINITE, "non-finite objective");
       if (o.verbose)
         fprintf(stderr, "[bmg] t=%d F=%.15g F_bm=%.15g res=%.3e k=%d q=%d ssi=%d eps=%.3e add=%d\n", t,
                 F, F_bm, resid, S.k, st.q, st.iters, eps, (int)st.added);
       S.res_prev = resid;
-      if (resid <= o.tol) {
+      if (kShadow && refresh && !hi) {
+        if (resid <= 1e-3 || resid > 0.7 * last_refresh) hi = true;
+        last_refresh = resid;
+      }
+      if (resid <= o.tol && refresh) {
         conv = true;
         ++t;
         break;
       }
     }
+    this->exact_gather = false;
+    if (kShadow) F = objective_balanced(S, o.lambda, true);
     HIPC(hipStreamSynchronize(s));
     P->resolve_timing();
     if (res) {
@@ -1268,14 +1386,20 @@ extern "C" bmg_status bmg_solve(bmg_problem *P, double *W, double *H, int ld, co
       k = S.k;
       REQUIRE(k <= ld, BMG_ENOMEM, "rank exceeds ld");
       store_factors<double>(P, S.W, S.H, k, W, H, ld);
-    } else {
+    } else if (P->prec == BMG_FP32) {
       Method<float> M(P);
       Method<float>::State S;
       st = M.solve(*opt, S, res);
       k = S.k;
       REQUIRE(k <= ld, BMG_ENOMEM, "rank exceeds ld");
       store_factors<float>(P, S.W, S.H, k, W, H, ld);
-      // the objective reported for the FP32 path is recomputed in FP64 from the stored factors
+    } else {
+      Method<float, bf16_t> M(P);
+      Method<float, bf16_t>::State S;
+      st = M.solve(*opt, S, res);
+      k = S.k;
+      REQUIRE(k <= ld, BMG_ENOMEM, "rank exceeds ld");
+      store_factors<float>(P, S.W, S.H, k, W, H, ld);
     }
     HIPC(hipStreamSynchronize(P->s));
     P->timing = false;

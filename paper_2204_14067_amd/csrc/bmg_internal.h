@@ -9,6 +9,8 @@
 
 namespace bmg {
 
+typedef uint16_t bf16_t;  // BF16 storage: the upper 16 bits of an FP32 (RNE)
+
 // One compressed orientation of Omega (rows of A for the CSR orientation,
 // rows of A^T for the column-major copy) plus its load-balancing plan:
 //   short rows (length <= chunk) are processed one row per lane group, in
@@ -45,22 +47,23 @@ struct PassScratch {
 
 // Fused sampled residual + sparse product (BM gradient of (MF)):
 //   r_p = x_row . y_col - a_p ;  Out_row = sum_p r_p y_col + lam * x_row ;  sums[0] = sum r^2
-template <typename T>
-hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const T *Y, int ldy, int k,
+// T: registers, own rows and outputs; TG: the gathered factor rows.
+template <typename T, typename TG>
+hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const TG *Y, int ldy, int k,
                        double lam, T *Out, int ldo, PassScratch sc, int64_t *waves_out,
                        hipStream_t s);
 
 // Sampled product (no sparse output vector): r_p = x_row . y_col - (a ? a_p : 0),
 // optionally stored to R[p]; sums[0] = sum r^2, sums[1] = sum r (r + a).
-template <typename T>
-hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const T *Y, int ldy, int k,
+template <typename T, typename TG>
+hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const TG *Y, int ldy, int k,
                         T *R, PassScratch sc, hipStream_t s);
 
 // C = coef * S B + X M on a column slice of width <= 64*VEC:
 //   S values in this orientation's order, B (rows indexed by idx), X own-side
 //   factor (kx columns, may be null with kx = 0), M (kx x q, row-major ldm).
-template <typename T>
-hipError_t launch_spmm(const Plan &pl, const T *S, const T *B, int ldb, int q, double coef,
+template <typename T, typename TG>
+hipError_t launch_spmm(const Plan &pl, const T *S, const TG *B, int ldb, int q, double coef,
                        const T *X, int ldx, int kx, const T *M, int ldm, T *C, int ldc,
                        PassScratch sc, hipStream_t s);
 

@@ -21,9 +21,22 @@
 
 namespace bmg {
 
-template <typename T> struct VT;
-template <> struct VT<double> { static constexpr int V = 2; };
-template <> struct VT<float> { static constexpr int V = 4; };
+// Elements per 16-byte lane slice of the gathered type.
+template <typename TG> struct VT { static constexpr int V = 16 / (int)sizeof(TG); };
+
+// BF16 storage (upper half of an FP32), rounded to nearest even.
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+template <typename To, typename From> __device__ __forceinline__ To cvt(From x) { return (To)x; }
+template <> __device__ __forceinline__ float cvt<float, bf16_t>(bf16_t x) { return bf2f(x); }
+template <> __device__ __forceinline__ double cvt<double, bf16_t>(bf16_t x) { return (double)bf2f(x); }
+template <> __device__ __forceinline__ bf16_t cvt<bf16_t, float>(float x) { return f2bf(x); }
+template <> __device__ __forceinline__ bf16_t cvt<bf16_t, double>(double x) { return f2bf((float)x); }
 
 #ifndef BMG_NT_STREAMS
 #define BMG_NT_STREAMS 0
@@ -37,37 +50,55 @@ __device__ __forceinline__ T nt_load(const T *p) {
 #endif
 }
 
-// Load V consecutive elements row[f0 .. f0+V) with per-element bound lim
-// (elements at or beyond lim read as 0 and are never touched).
-template <typename T, int V>
-__device__ __forceinline__ void ldv(const T *__restrict__ row, int f0, int lim, T (&x)[V]) {
+// Load V consecutive elements row[f0 .. f0+V) of memory type TM into T
+// registers, with per-element bound lim (elements at or beyond lim read as 0
+// and are never touched).
+template <typename T, typename TM, int V>
+__device__ __forceinline__ void ldv(const TM *__restrict__ row, int f0, int lim, T (&x)[V]) {
   if (f0 + V <= lim) {
-    if constexpr (sizeof(T) == 8) {
+    if constexpr (sizeof(TM) == 8 && V == 2) {
       const double2 v = *reinterpret_cast<const double2 *>(row + f0);
-      x[0] = v.x; x[1] = v.y;
-    } else {
-      const float4 v = *reinterpret_cast<const float4 *>(row + f0);
-      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
-    }
-  } else {
+      x[0] = (T)v.x; x[1] = (T)v.y;
+      return;
+    } else if constexpr (sizeof(TM) == 4 && (V == 4 || V == 8)) {
 #pragma unroll
-    for (int e = 0; e < V; ++e) x[e] = (f0 + e < lim) ? row[f0 + e] : T(0);
+      for (int h = 0; h < V / 4; ++h) {
+        const float4 v = *reinterpret_cast<const float4 *>(row + f0 + 4 * h);
+        x[4 * h] = (T)v.x; x[4 * h + 1] = (T)v.y; x[4 * h + 2] = (T)v.z; x[4 * h + 3] = (T)v.w;
+      }
+      return;
+    } else if constexpr (sizeof(TM) == 2 && V == 8) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(row + f0);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        x[2 * h] = (T)__uint_as_float(w[h] << 16);
+        x[2 * h + 1] = (T)__uint_as_float(w[h] & 0xffff0000u);
+      }
+      return;
+    }
   }
+#pragma unroll
+  for (int e = 0; e < V; ++e) x[e] = (f0 + e < lim) ? cvt<T, TM>(row[f0 + e]) : T(0);
 }
 
-template <typename T, int V>
-__device__ __forceinline__ void stv(T *__restrict__ row, int f0, int lim, const T (&x)[V]) {
+template <typename T, typename TM, int V>
+__device__ __forceinline__ void stv(TM *__restrict__ row, int f0, int lim, const T (&x)[V]) {
   if (f0 + V <= lim) {
-    if constexpr (sizeof(T) == 8) {
+    if constexpr (sizeof(TM) == 8 && sizeof(T) == 8 && V == 2) {
       *reinterpret_cast<double2 *>(row + f0) = make_double2(x[0], x[1]);
-    } else {
-      *reinterpret_cast<float4 *>(row + f0) = make_float4(x[0], x[1], x[2], x[3]);
-    }
-  } else {
+      return;
+    } else if constexpr (sizeof(TM) == 4 && sizeof(T) == 4 && (V == 4 || V == 8)) {
 #pragma unroll
-    for (int e = 0; e < V; ++e)
-      if (f0 + e < lim) row[f0 + e] = x[e];
+      for (int h = 0; h < V / 4; ++h)
+        *reinterpret_cast<float4 *>(row + f0 + 4 * h) =
+            make_float4(x[4 * h], x[4 * h + 1], x[4 * h + 2], x[4 * h + 3]);
+      return;
+    }
   }
+#pragma unroll
+  for (int e = 0; e < V; ++e)
+    if (f0 + e < lim) row[f0 + e] = cvt<TM, T>(x[e]);
 }
 
 // Butterfly sum inside a lane group of G (xor offsets 1 .. G/2).
@@ -105,9 +136,9 @@ __host__ __device__ inline int64_t short_waves(const Plan &pl, int G) {
 // A lane group of G lanes owns one row of Omega.  A dense k-vector is split in
 // C chunks of G*V consecutive columns (one 128-byte line for G = 8 in FP64);
 // lane `sub` holds columns c*G*V + sub*V .. +V-1 of chunk c.
-template <typename T, int G, int C>
+template <typename T, typename TG, int G, int C>
 struct Row {
-  static constexpr int V = VT<T>::V;
+  static constexpr int V = VT<TG>::V;
   static constexpr int CW = G * V;       // columns per chunk
   static constexpr int WB = CW * C;      // columns covered
   T v[C][V];
@@ -117,13 +148,15 @@ struct Row {
 #pragma unroll
       for (int e = 0; e < V; ++e) v[c][e] = T(0);
   }
-  __device__ __forceinline__ void load(const T *__restrict__ row, int sub, int lim) {
+  template <typename TM>
+  __device__ __forceinline__ void load(const TM *__restrict__ row, int sub, int lim) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) ldv<T, V>(row, c * CW + sub * V, lim, v[c]);
+    for (int c = 0; c < C; ++c) ldv<T, TM, V>(row, c * CW + sub * V, lim, v[c]);
   }
-  __device__ __forceinline__ void store(T *__restrict__ row, int sub, int lim) const {
+  template <typename TM>
+  __device__ __forceinline__ void store(TM *__restrict__ row, int sub, int lim) const {
 #pragma unroll
-    for (int c = 0; c < C; ++c) stv<T, V>(row, c * CW + sub * V, lim, v[c]);
+    for (int c = 0; c < C; ++c) stv<T, TM, V>(row, c * CW + sub * V, lim, v[c]);
   }
   __device__ __forceinline__ T dot(const Row &o) const {
     T s = T(0);
@@ -144,14 +177,14 @@ struct Row {
 // ============================================================================ fused residual + product
 // For entries p, p+step, ... (n of them) of one row:
 //   r = x . y_j - a_p ;  acc += r y_j ;  ss += r^2   (ss on the group leader only)
-template <typename T, int G, int C>
+template <typename T, typename TG, int G, int C>
 __device__ __forceinline__ void grad_block(const Plan &pl, const T *__restrict__ a,
-                                           const T *__restrict__ Y, int ldy, int k, int sub,
-                                           const Row<T, G, C> &x, Row<T, G, C> &acc, double &ss,
+                                           const TG *__restrict__ Y, int ldy, int k, int sub,
+                                           const Row<T, TG, G, C> &x, Row<T, TG, G, C> &acc, double &ss,
                                            bool leader, int64_t p, int64_t step, int n) {
   int j[UNROLL];
   T av[UNROLL];
-  Row<T, G, C> y[UNROLL];
+  Row<T, TG, G, C> y[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     if (u < n) {
@@ -182,14 +215,14 @@ __device__ __forceinline__ void grad_block(const Plan &pl, const T *__restrict__
   }
 }
 
-template <typename T, int G, int C>
+template <typename T, typename TG, int G, int C>
 __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
                                               const T *__restrict__ X, int ldx,
-                                              const T *__restrict__ Y, int ldy, int k, double lam,
+                                              const TG *__restrict__ Y, int ldy, int k, double lam,
                                               T *__restrict__ Out, int ldo,
                                               T *__restrict__ partial, double *__restrict__ wsum,
                                               int64_t total_waves) {
-  using RowT = Row<T, G, C>;
+  using RowT = Row<T, TG, G, C>;
   constexpr int S = 64 / G, WB = RowT::WB;
   const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
   const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
@@ -207,7 +240,7 @@ __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
       const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
       for (int64_t p = beg; p < end; p += UNROLL) {
         const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
-        grad_block<T, G, C>(pl, a, Y, ldy, k, sub, x, acc, ss, leader, p, 1, n);
+        grad_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, acc, ss, leader, p, 1, n);
       }
       acc.axpy((T)lam, x);
       acc.store(Out + (int64_t)row * ldo, sub, k);
@@ -223,7 +256,7 @@ __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
     for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
       const int64_t rem = (end - p + S - 1) / S;
       const int n = (int)(rem < UNROLL ? rem : UNROLL);
-      grad_block<T, G, C>(pl, a, Y, ldy, k, sub, x, acc, ss, leader, p, S, n);
+      grad_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, acc, ss, leader, p, S, n);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c)
@@ -236,11 +269,11 @@ __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
 }
 
 // Long rows: Out_row = sum of piece partials (piece order) + lam * x_row.
-template <typename T, int G, int C>
+template <typename T, typename TG, int G, int C>
 __global__ __launch_bounds__(256) void k_grad_fix(Plan pl, const T *__restrict__ partial,
                                                   const T *__restrict__ X, int ldx, int k,
                                                   double lam, T *__restrict__ Out, int ldo) {
-  using RowT = Row<T, G, C>;
+  using RowT = Row<T, TG, G, C>;
   const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   if (g >= pl.n_long) return;
@@ -258,15 +291,15 @@ __global__ __launch_bounds__(256) void k_grad_fix(Plan pl, const T *__restrict__
 }
 
 // ============================================================================ sampled residual
-template <typename T, int G, int C>
+template <typename T, typename TG, int G, int C>
 __device__ __forceinline__ void sddmm_block(const Plan &pl, const T *__restrict__ a,
-                                            const T *__restrict__ Y, int ldy, int k, int sub,
-                                            const Row<T, G, C> &x, T *__restrict__ R, double &ss,
+                                            const TG *__restrict__ Y, int ldy, int k, int sub,
+                                            const Row<T, TG, G, C> &x, T *__restrict__ R, double &ss,
                                             double &sx, bool leader, int64_t p, int64_t step,
                                             int n) {
   int j[UNROLL];
   T av[UNROLL];
-  Row<T, G, C> y[UNROLL];
+  Row<T, TG, G, C> y[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     if (u < n) {
@@ -296,13 +329,13 @@ __device__ __forceinline__ void sddmm_block(const Plan &pl, const T *__restrict_
   }
 }
 
-template <typename T, int G, int C>
+template <typename T, typename TG, int G, int C>
 __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
                                                const T *__restrict__ X, int ldx,
-                                               const T *__restrict__ Y, int ldy, int k,
+                                               const TG *__restrict__ Y, int ldy, int k,
                                                T *__restrict__ R, double *__restrict__ wsum,
                                                int64_t total_waves) {
-  using RowT = Row<T, G, C>;
+  using RowT = Row<T, TG, G, C>;
   constexpr int S = 64 / G;
   const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
   const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
@@ -318,7 +351,7 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
       const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
       for (int64_t p = beg; p < end; p += UNROLL) {
         const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
-        sddmm_block<T, G, C>(pl, a, Y, ldy, k, sub, x, R, ss, sx, leader, p, 1, n);
+        sddmm_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, R, ss, sx, leader, p, 1, n);
       }
     }
   } else if (gw < total_waves) {
@@ -332,7 +365,7 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
     for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
       const int64_t rem = (end - p + S - 1) / S;
       const int n = (int)(rem < UNROLL ? rem : UNROLL);
-      sddmm_block<T, G, C>(pl, a, Y, ldy, k, sub, x, R, ss, sx, leader, p, S, n);
+      sddmm_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, R, ss, sx, leader, p, S, n);
     }
   }
   ss = wave_sum(ss);
@@ -344,13 +377,13 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
 }
 
 // ============================================================================ sparse x dense
-template <typename T, int G, int C>
+template <typename T, typename TG, int G, int C>
 __device__ __forceinline__ void spmm_block(const Plan &pl, const T *__restrict__ Sv,
-                                           const T *__restrict__ B, int ldb, int wq, int sub,
-                                           Row<T, G, C> &acc, int64_t p, int64_t step, int n) {
+                                           const TG *__restrict__ B, int ldb, int wq, int sub,
+                                           Row<T, TG, G, C> &acc, int64_t p, int64_t step, int n) {
   int j[UNROLL];
   T sv[UNROLL];
-  Row<T, G, C> b[UNROLL];
+  Row<T, TG, G, C> b[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     if (u < n) {
@@ -371,12 +404,12 @@ __device__ __forceinline__ void spmm_block(const Plan &pl, const T *__restrict__
 }
 
 // acc <- coef * acc + x_row . M[:, slice]
-template <typename T, int G, int C>
-__device__ __forceinline__ void lowrank_epilogue(Row<T, G, C> &acc, double coef,
+template <typename T, typename TG, int G, int C>
+__device__ __forceinline__ void lowrank_epilogue(Row<T, TG, G, C> &acc, double coef,
                                                  const T *__restrict__ xr, int kx,
                                                  const T *__restrict__ M, int ldm, int wq,
                                                  int sub) {
-  using RowT = Row<T, G, C>;
+  using RowT = Row<T, TG, G, C>;
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
@@ -388,14 +421,14 @@ __device__ __forceinline__ void lowrank_epilogue(Row<T, G, C> &acc, double coef,
   }
 }
 
-template <typename T, int G, int C>
+template <typename T, typename TG, int G, int C>
 __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
-                                              const T *__restrict__ B, int ldb, int wq,
+                                              const TG *__restrict__ B, int ldb, int wq,
                                               double coef, const T *__restrict__ X, int ldx,
                                               int kx, const T *__restrict__ M, int ldm,
                                               T *__restrict__ Cm, int ldc,
                                               T *__restrict__ partial, int64_t total_waves) {
-  using RowT = Row<T, G, C>;
+  using RowT = Row<T, TG, G, C>;
   constexpr int S = 64 / G, WB = RowT::WB;
   const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
   const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
@@ -409,9 +442,9 @@ __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
       const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
       for (int64_t p = beg; p < end; p += UNROLL) {
         const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
-        spmm_block<T, G, C>(pl, Sv, B, ldb, wq, sub, acc, p, 1, n);
+        spmm_block<T, TG, G, C>(pl, Sv, B, ldb, wq, sub, acc, p, 1, n);
       }
-      lowrank_epilogue<T, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
+      lowrank_epilogue<T, TG, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
       acc.store(Cm + (int64_t)row * ldc, sub, wq);
     }
   } else if (gw < total_waves) {
@@ -423,7 +456,7 @@ __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
     for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
       const int64_t rem = (end - p + S - 1) / S;
       const int n = (int)(rem < UNROLL ? rem : UNROLL);
-      spmm_block<T, G, C>(pl, Sv, B, ldb, wq, sub, acc, p, S, n);
+      spmm_block<T, TG, G, C>(pl, Sv, B, ldb, wq, sub, acc, p, S, n);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c)
@@ -433,12 +466,12 @@ __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
   }
 }
 
-template <typename T, int G, int C>
+template <typename T, typename TG, int G, int C>
 __global__ __launch_bounds__(256) void k_spmm_fix(Plan pl, const T *__restrict__ partial,
                                                   double coef, const T *__restrict__ X, int ldx,
                                                   int kx, const T *__restrict__ M, int ldm, int wq,
                                                   T *__restrict__ Cm, int ldc) {
-  using RowT = Row<T, G, C>;
+  using RowT = Row<T, TG, G, C>;
   const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   if (g >= pl.n_long) return;
@@ -449,17 +482,19 @@ __global__ __launch_bounds__(256) void k_spmm_fix(Plan pl, const T *__restrict__
     t.load(partial + (int64_t)pc * RowT::WB, sub, RowT::WB);
     acc.axpy(T(1), t);
   }
-  lowrank_epilogue<T, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
+  lowrank_epilogue<T, TG, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
   acc.store(Cm + (int64_t)row * ldc, sub, wq);
 }
 
 // ============================================================================ launchers
-// Lane group G and chunk count C for a width w: G = 4 (one 64-byte span) for
-// narrow rows, else G = 8 with C = ceil(w / (8 V)) line-sized chunks.
+// Lane group G and chunk count C for a width w (V elements of the gathered type
+// per lane): G = 2 or 4 for narrow rows (one partial line), else G = 8 with
+// C = ceil(w / (8 V)) line-sized chunks.
 struct GC {
   int G, C;
 };
 static inline GC pick_gc(int width, int V) {
+  if (width <= 2 * V) return {2, 1};
   if (width <= 4 * V) return {4, 1};
   int c = (width + 8 * V - 1) / (8 * V);
   return {8, c < 1 ? 1 : c};
@@ -474,7 +509,8 @@ static inline dim3 wave_grid(int64_t waves) {
 
 #define BMG_DISPATCH_GC(gc, ...)                                                        \
   do {                                                                                  \
-    if (gc.G == 4) { constexpr int GG = 4, CC = 1; __VA_ARGS__; }                       \
+    if (gc.G == 2) { constexpr int GG = 2, CC = 1; __VA_ARGS__; }                       \
+    else if (gc.G == 4) { constexpr int GG = 4, CC = 1; __VA_ARGS__; }                  \
     else switch (gc.C) {                                                                \
       case 1: { constexpr int GG = 8, CC = 1; __VA_ARGS__; } break;                     \
       case 2: { constexpr int GG = 8, CC = 2; __VA_ARGS__; } break;                     \
@@ -487,24 +523,24 @@ static inline dim3 wave_grid(int64_t waves) {
     }                                                                                   \
   } while (0)
 
-template <typename T>
-hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const T *Y, int ldy, int k,
+template <typename T, typename TG>
+hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const TG *Y, int ldy, int k,
                        double lam, T *Out, int ldo, PassScratch sc, int64_t *waves_out,
                        hipStream_t s) {
-  constexpr int V = VT<T>::V;
+  constexpr int V = VT<TG>::V;
   if (k > max_width<T>()) return hipErrorInvalidValue;
   const GC gc = pick_gc(k, V);
   const int64_t tw = total_waves(pl, gc.G);
   if (waves_out) *waves_out = tw;
   BMG_DISPATCH_GC(gc, {
     if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
-    hipLaunchKernelGGL((k_grad<T, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, a, X, ldx, Y, ldy,
-                       k, lam, Out, ldo, (T *)sc.partial, sc.wsum, tw);
+    hipLaunchKernelGGL((k_grad<T, TG, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, a, X, ldx, Y,
+                       ldy, k, lam, Out, ldo, (T *)sc.partial, sc.wsum, tw);
     if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
     if (pl.n_long > 0) {
       const int64_t thr = pl.n_long * GG;
-      hipLaunchKernelGGL((k_grad_fix<T, GG, CC>), dim3((unsigned)((thr + 255) / 256)), dim3(256),
-                         0, s, pl, (const T *)sc.partial, X, ldx, k, lam, Out, ldo);
+      hipLaunchKernelGGL((k_grad_fix<T, TG, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
+                         dim3(256), 0, s, pl, (const T *)sc.partial, X, ldx, k, lam, Out, ldo);
     }
   });
   hipError_t e = hipGetLastError();
@@ -512,16 +548,16 @@ hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const T 
   return launch_reduce_wsum(sc.wsum, tw, 1, sc.result, s);
 }
 
-template <typename T>
-hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const T *Y, int ldy, int k,
+template <typename T, typename TG>
+hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const TG *Y, int ldy, int k,
                         T *R, PassScratch sc, hipStream_t s) {
-  constexpr int V = VT<T>::V;
+  constexpr int V = VT<TG>::V;
   if (k > max_width<T>()) return hipErrorInvalidValue;
   const GC gc = pick_gc(k, V);
   const int64_t tw = total_waves(pl, gc.G);
   BMG_DISPATCH_GC(gc, {
     if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
-    hipLaunchKernelGGL((k_sddmm<T, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, a, X, ldx, Y,
+    hipLaunchKernelGGL((k_sddmm<T, TG, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, a, X, ldx, Y,
                        ldy, k, R, sc.wsum, tw);
     if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
   });
@@ -530,11 +566,11 @@ hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const T
   return launch_reduce_wsum(sc.wsum, tw, 2, sc.result, s);
 }
 
-template <typename T>
-hipError_t launch_spmm(const Plan &pl, const T *Sv, const T *B, int ldb, int q, double coef,
+template <typename T, typename TG>
+hipError_t launch_spmm(const Plan &pl, const T *Sv, const TG *B, int ldb, int q, double coef,
                        const T *X, int ldx, int kx, const T *M, int ldm, T *Cm, int ldc,
                        PassScratch sc, hipStream_t s) {
-  constexpr int V = VT<T>::V;
+  constexpr int V = VT<TG>::V;
   const int WMAX = max_width<T>();
   for (int c0 = 0; c0 < q; c0 += WMAX) {
     const int wq = (q - c0) < WMAX ? (q - c0) : WMAX;
@@ -542,13 +578,13 @@ hipError_t launch_spmm(const Plan &pl, const T *Sv, const T *B, int ldb, int q, 
     const int64_t tw = total_waves(pl, gc.G);
     BMG_DISPATCH_GC(gc, {
       if (sc.ev0 && c0 == 0) (void)hipEventRecord(sc.ev0, s);
-      hipLaunchKernelGGL((k_spmm<T, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, Sv, B + c0, ldb,
-                         wq, coef, X, ldx, kx, M ? M + c0 : M, ldm, Cm + c0, ldc, (T *)sc.partial,
-                         tw);
+      hipLaunchKernelGGL((k_spmm<T, TG, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, Sv, B + c0,
+                         ldb, wq, coef, X, ldx, kx, M ? M + c0 : M, ldm, Cm + c0, ldc,
+                         (T *)sc.partial, tw);
       if (sc.ev1 && c0 + WMAX >= q) (void)hipEventRecord(sc.ev1, s);
       if (pl.n_long > 0) {
         const int64_t thr = pl.n_long * GG;
-        hipLaunchKernelGGL((k_spmm_fix<T, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
+        hipLaunchKernelGGL((k_spmm_fix<T, TG, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
                            dim3(256), 0, s, pl, (const T *)sc.partial, coef, X, ldx, kx,
                            M ? M + c0 : M, ldm, wq, Cm + c0, ldc);
       }
@@ -644,7 +680,7 @@ hipError_t launch_gram(int64_t N, int a, const T *X, int ldx, int b, const T *Y,
                        double *part, int64_t part_cap, double *out, hipStream_t s) {
   const int64_t ab = (int64_t)a * b;
   if (ab == 0) return hipSuccess;
-  int64_t nwaves = (N + 255) / 256;          // >= 256 rows per wave
+  int64_t nwaves = (N + 63) / 64;            // >= 64 rows per wave
   if (nwaves > 2048) nwaves = 2048;
   if (nwaves < 1) nwaves = 1;
   if (nwaves * ab > part_cap) nwaves = part_cap / ab;
@@ -804,7 +840,7 @@ __global__ void k_convert_cols(int64_t rows, int cols, const Tin *X, int ldx, To
   if (i >= rows * cols) return;
   const int64_t r = i / cols;
   const int c = (int)(i % cols);
-  Y[r * ldy + c] = (Tout)X[r * ldx + c];
+  Y[r * ldy + c] = cvt<Tout, Tin>(X[r * ldx + c]);
 }
 template <typename Tin, typename Tout>
 hipError_t launch_convert_cols(int64_t rows, int cols, const Tin *X, int ldx, Tout *Y, int ldy,
@@ -819,6 +855,10 @@ template hipError_t launch_convert_cols<double, float>(int64_t, int, const doubl
                                                        hipStream_t);
 template hipError_t launch_convert_cols<float, double>(int64_t, int, const float *, int, double *, int,
                                                        hipStream_t);
+template hipError_t launch_convert_cols<float, bf16_t>(int64_t, int, const float *, int, bf16_t *, int,
+                                                       hipStream_t);
+template hipError_t launch_convert_cols<double, double>(int64_t, int, const double *, int, double *,
+                                                        int, hipStream_t);
 
 // ============================================================================ counter-based normals
 // SplitMix64 (Steele, Lea, Flood 2014): draw c of stream (seed, id) is
@@ -951,14 +991,19 @@ hipError_t launch_check_csr(int64_t m, int64_t n, const int64_t *row_ptr, const 
 }
 
 // ============================================================================ instantiations
+#define BMG_INST_PASS(T, TG)                                                                    \
+  template hipError_t launch_grad<T, TG>(const Plan &, const T *, const T *, int, const TG *, int,   \
+                                         int, double, T *, int, PassScratch, int64_t *,              \
+                                         hipStream_t);                                               \
+  template hipError_t launch_sddmm<T, TG>(const Plan &, const T *, const T *, int, const TG *, int,  \
+                                          int, T *, PassScratch, hipStream_t);                       \
+  template hipError_t launch_spmm<T, TG>(const Plan &, const T *, const TG *, int, int, double,      \
+                                         const T *, int, int, const T *, int, T *, int, PassScratch, \
+                                         hipStream_t);
+BMG_INST_PASS(double, double)
+BMG_INST_PASS(float, float)
+BMG_INST_PASS(float, bf16_t)
 #define BMG_INST(T)                                                                              \
-  template hipError_t launch_grad<T>(const Plan &, const T *, const T *, int, const T *, int, int, \
-                                     double, T *, int, PassScratch, int64_t *, hipStream_t);       \
-  template hipError_t launch_sddmm<T>(const Plan &, const T *, const T *, int, const T *, int,    \
-                                      int, T *, PassScratch, hipStream_t);                         \
-  template hipError_t launch_spmm<T>(const Plan &, const T *, const T *, int, int, double,         \
-                                     const T *, int, int, const T *, int, T *, int, PassScratch,   \
-                                     hipStream_t);                                                 \
   template hipError_t launch_gram<T>(int64_t, int, const T *, int, int, const T *, int, double *,  \
                                      int64_t, double *, hipStream_t);                              \
   template hipError_t launch_gemm_ts<T>(int64_t, int, const T *, int, int, const double *, int,   \

@@ -24,70 +24,79 @@ static inline double &at(std::vector<double> &A, int n, int i, int j) { return A
 void sym_eig(int n, const double *A0, double *w, double *Vout) {
   if (n <= 0) return;
   std::vector<double> A(A0, A0 + (size_t)n * n);
-  // symmetrise against rounding in the input
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i)  // symmetrise against rounding in the input
     for (int j = i + 1; j < n; ++j) {
       const double s = 0.5 * (at(A, n, i, j) + at(A, n, j, i));
       at(A, n, i, j) = at(A, n, j, i) = s;
     }
   const bool vec = Vout != nullptr;
-  std::vector<double> Q;
-  if (vec) {
-    Q.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) at(Q, n, i, i) = 1.0;
-  }
-  std::vector<double> v(n), p(n);
-  // --- Householder tridiagonalisation: A <- H A H, Q <- Q H with
-  // H = I - 2 v v^T / (v^T v) acting on indices k+1 .. n-1.
+  // --- Householder tridiagonalisation.  Step k reflects rows/columns k+1..n-1
+  // with H = I - tau v v^T; the trailing block gets the symmetric rank-2 update
+  // A22 <- A22 - v w^T - w v^T,  w = p - (tau/2)(p^T v) v,  p = tau A22 v.
+  std::vector<double> vs((size_t)n * n, 0.0), taus(n, 0.0), p(n), wv(n);
+  std::vector<double> d(n), e(n, 0.0);
   for (int k = 0; k + 2 < n; ++k) {
+    double *v = &vs[(size_t)k * n];
     double sig = 0.0;
     for (int i = k + 1; i < n; ++i) sig += at(A, n, i, k) * at(A, n, i, k);
-    double tail = sig - at(A, n, k + 1, k) * at(A, n, k + 1, k);
-    if (tail <= 0.0) continue;  // column already tridiagonal
-    sig = sqrt(sig);
     const double x0 = at(A, n, k + 1, k);
-    const double alpha = x0 >= 0 ? -sig : sig;
+    if (sig - x0 * x0 <= 0.0) continue;  // already tridiagonal in this column
+    const double nrm = sqrt(sig);
+    const double alpha = x0 >= 0 ? -nrm : nrm;
     for (int i = k + 1; i < n; ++i) v[i] = at(A, n, i, k);
     v[k + 1] -= alpha;
-    double beta = 0.0;
-    for (int i = k + 1; i < n; ++i) beta += v[i] * v[i];
-    if (beta == 0.0) continue;
-    const double tau = 2.0 / beta;
-    // left: rows k+1.. of A: A -= tau v (v^T A)
-    for (int j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int i = k + 1; i < n; ++i) s += v[i] * at(A, n, i, j);
-      p[j] = tau * s;
+    double vv = 0.0;
+    for (int i = k + 1; i < n; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double tau = 2.0 / vv;
+    taus[k] = tau;
+    for (int i = k + 1; i < n; ++i) {
+      double acc = 0.0;
+      const double *row = &A[(size_t)i * n];
+      for (int j = k + 1; j < n; ++j) acc += row[j] * v[j];
+      p[i] = tau * acc;
     }
-    for (int i = k + 1; i < n; ++i)
-      for (int j = 0; j < n; ++j) at(A, n, i, j) -= v[i] * p[j];
-    // right: columns k+1.. of A: A -= tau (A v) v^T
-    for (int i = 0; i < n; ++i) {
-      double s = 0.0;
-      for (int j = k + 1; j < n; ++j) s += at(A, n, i, j) * v[j];
-      p[i] = tau * s;
+    double pv = 0.0;
+    for (int i = k + 1; i < n; ++i) pv += p[i] * v[i];
+    for (int i = k + 1; i < n; ++i) wv[i] = p[i] - 0.5 * tau * pv * v[i];
+    for (int i = k + 1; i < n; ++i) {
+      double *row = &A[(size_t)i * n];
+      const double vi = v[i], wi = wv[i];
+      for (int j = k + 1; j < n; ++j) row[j] -= vi * wv[j] + wi * v[j];
     }
-    for (int i = 0; i < n; ++i)
-      for (int j = k + 1; j < n; ++j) at(A, n, i, j) -= p[i] * v[j];
-    if (vec) {
-      for (int i = 0; i < n; ++i) {
-        double s = 0.0;
-        for (int j = k + 1; j < n; ++j) s += at(Q, n, i, j) * v[j];
-        p[i] = tau * s;
+    at(A, n, k + 1, k) = at(A, n, k, k + 1) = alpha;
+    for (int i = k + 2; i < n; ++i) at(A, n, i, k) = at(A, n, k, i) = 0.0;
+  }
+  for (int i = 0; i < n; ++i) d[i] = at(A, n, i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = at(A, n, i, i + 1);
+  // Z = Q^T with Q = H_0 H_1 ... H_{n-3}, accumulated backwards on rows
+  std::vector<double> Z;
+  if (vec) {
+    Z.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+    // Q = H_0 (H_1 (... H_{n-3})); Z = Q^T = (... H_{n-3}) ... H_0 applied from the right:
+    // build Q column-block-wise: Q[k+1:, k+1:] = H_k Q[k+1:, k+1:]  (k descending),
+    // kept as Z (rows of Z are columns of Q).
+    for (int k = n - 3; k >= 0; --k) {
+      if (taus[k] == 0.0) continue;
+      const double *v = &vs[(size_t)k * n];
+      const double tau = taus[k];
+      // for each column c >= k+1 of Q (row c of Z): q_c[k+1:] -= tau v (v^T q_c[k+1:])
+      for (int c = k + 1; c < n; ++c) {
+        double *zc = &Z[(size_t)c * n];
+        double acc = 0.0;
+        for (int i = k + 1; i < n; ++i) acc += v[i] * zc[i];
+        acc *= tau;
+        for (int i = k + 1; i < n; ++i) zc[i] -= acc * v[i];
       }
-      for (int i = 0; i < n; ++i)
-        for (int j = k + 1; j < n; ++j) at(Q, n, i, j) -= p[i] * v[j];
     }
   }
-  std::vector<double> d(n), e(n, 0.0);
-  for (int i = 0; i < n; ++i) d[i] = at(A, n, i, i);
-  for (int i = 0; i + 1 < n; ++i) e[i] = 0.5 * (at(A, n, i, i + 1) + at(A, n, i + 1, i));
-  // --- implicit symmetric QR with Wilkinson shift on the tridiagonal (d, e)
+  // --- implicit symmetric QR with Wilkinson shift on the tridiagonal (d, e);
+  // rotations of columns k, k+1 of Q are rotations of rows k, k+1 of Z
   const double eps = 2.220446049250313e-16;
   int hi = n - 1;
   int guard = 0;
   while (hi > 0 && guard < 60 * n) {
-    // deflate from the bottom
     if (fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi])) || e[hi - 1] == 0.0) {
       e[hi - 1] = 0.0;
       --hi;
@@ -97,7 +106,6 @@ void sym_eig(int n, const double *A0, double *w, double *Vout) {
     while (lo > 0 && !(fabs(e[lo - 1]) <= eps * (fabs(d[lo - 1]) + fabs(d[lo])))) --lo;
     if (lo > 0) e[lo - 1] = 0.0;
     ++guard;
-    // Wilkinson shift from the trailing 2x2 of the block [lo, hi]
     const double delta = 0.5 * (d[hi - 1] - d[hi]);
     const double es = e[hi - 1] * e[hi - 1];
     const double den = delta + copysign(sqrt(delta * delta + es), delta == 0.0 ? 1.0 : delta);
@@ -118,22 +126,22 @@ void sym_eig(int n, const double *A0, double *w, double *Vout) {
         e[k + 1] = c * e[k + 1];
       }
       if (vec) {
+        double *zk = &Z[(size_t)k * n], *zk1 = &Z[(size_t)(k + 1) * n];
         for (int i = 0; i < n; ++i) {
-          const double qk = at(Q, n, i, k), qk1 = at(Q, n, i, k + 1);
-          at(Q, n, i, k) = c * qk - s * qk1;
-          at(Q, n, i, k + 1) = s * qk + c * qk1;
+          const double qk = zk[i], qk1 = zk1[i];
+          zk[i] = c * qk - s * qk1;
+          zk1[i] = s * qk + c * qk1;
         }
       }
     }
   }
-  // sort descending
   std::vector<int> ord(n);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] > d[b]; });
   for (int i = 0; i < n; ++i) w[i] = d[ord[i]];
   if (vec)
     for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) Vout[(size_t)i * n + j] = at(Q, n, i, ord[j]);
+      for (int j = 0; j < n; ++j) Vout[(size_t)i * n + j] = Z[(size_t)ord[j] * n + i];
 }
 
 int chol_pivoted(int n, const double *G, double tol, int *perm, double *R) {

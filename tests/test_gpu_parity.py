@@ -229,6 +229,25 @@ def test_solve_fp32_objective_error():
     assert abs(Fw - Fstar) <= 1e-5 * Fstar
 
 
+@pytest.mark.parametrize("refresh", [2, 5])
+def test_solve_bf16_objective_error(refresh):
+    """BF16 gathers, FP32 accumulation, FP64 residual/objective refresh every
+    `refresh` outer iterations (those skip the BM phase and gather FP32 in the
+    PG step): objective within 1e-3 of the FP64 optimum."""
+    p = synth.tiny(150, 220, 5000, rank=3, lam=0.3, seed=31)
+    dp = to_dev(p, k_cap=64, precision="bf16")
+    W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-5, seed=3, max_iter=600,
+                              refresh_every=refresh)
+    Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
+    Fstar = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-11, seed=3)).F
+    print("bf16", refresh, r["status"], r["iters"], r["residual"], Fw, Fstar, (Fw - Fstar) / Fstar,
+          flush=True)
+    assert r["status"] == 0
+    assert abs(Fw - Fstar) <= 1e-3 * Fstar
+    # the reported F is the FP64 objective of the FP32 master factors
+    assert math.isclose(r["F"], Fw, rel_tol=1e-6)
+
+
 def test_solve_is_bitwise_deterministic():
     p = synth.netflix_shape(scale=0.02)
     outs = []
