@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=48,
+                    help="requests replayed by the serving measurement (256 in the full stream)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU "
@@ -154,6 +156,7 @@ def main():
     if not args.no_extras:
         out["precision_modes"] = precision_steps(bmg, p, dev, k0, lam)
         out["time_to_tol"] = time_to_tol(bmg, synth, dev)
+        out["serve"] = serving(bmg, synth, dev, args.serve_count)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p)
@@ -183,6 +186,68 @@ def precision_steps(bmg, p, dev, k0, lam, steps=2):
                      "kernel_ms_per_step": {KERNEL_SYMBOLS[c]: round(kms[c], 3) for c in range(3)}}
         log("step %s: %.1f ms" % (prec, dt * 1e3))
         del prob
+    return out
+
+
+def serving(bmg, synth, dev, count):
+    """Serving stream: requests arrive (Poisson, 20/s) with m ~ U[500, 20000],
+    n ~ U[1000, 50000], density ~ U[0.5%, 2%], rank 3..15, noise variance 0.05,
+    lambda above the noise level on Omega; FP32 solves to residual 1e-5 through
+    the server (admission by footprint in an 8 GiB arena, 8 slots).  Latency =
+    completion - arrival.  Baseline: the same problems one after another with
+    the plain FP64 solver to the same residual."""
+    import numpy as np
+    reqs = synth.serving_stream(count=count)
+    t0 = time.time()
+    probs = [synth.request_problem(r) for r in reqs]
+    log("serving: %d requests generated in %.1fs (nnz %.1fM..%.1fM)" % (
+        count, time.time() - t0, min(p.nnz for p in probs) / 1e6, max(p.nnz for p in probs) / 1e6))
+    opts = dict(tol=1e-5, k_init=8, max_iter=3000, seed=7)
+    srv = bmg.Server(8 << 30, max_slots=8, device=dev)
+    tickets = []
+    start = time.perf_counter()
+    for r, p in zip(reqs, probs):
+        delay = r.arrival - (time.perf_counter() - start)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=128, precision="fp32",
+                                  lam=r.lam, **opts))
+    srv.drain()
+    makespan = time.perf_counter() - start
+    infos = [srv.poll(t)[0] for t in tickets]
+    st = srv.stats()
+    srv.close()
+    lat = np.array([i["total_s"] for i in infos])
+    ok = sum(1 for i in infos if i["state"] == 2 and i["status"] == 0)
+    # plain FP64 solver, one problem at a time, same tolerance
+    t1 = time.perf_counter()
+    plain = []
+    for r, p in zip(reqs, probs):
+        prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=128, precision="fp64",
+                                     device=dev)
+        tt = time.perf_counter()
+        try:
+            _, _, k, res = prob.bmg_solve(lam=r.lam, **opts)
+            plain.append((time.perf_counter() - tt, res["F"]))
+        except bmg.BmgError as e:
+            log("plain fp64 solve failed: %s" % e)
+            plain.append((time.perf_counter() - tt, float("nan")))
+        del prob
+    plain_total = time.perf_counter() - t1
+    rel = [abs(i["result"]["F"] - f) / abs(f) for i, (_, f) in zip(infos, plain)
+           if i["state"] == 2 and f == f and f != 0]
+    out = {"requests": count, "converged": ok, "p50_s": round(float(np.percentile(lat, 50)), 4),
+           "p99_s": round(float(np.percentile(lat, 99)), 4),
+           "throughput_per_s": round(count / makespan, 3), "makespan_s": round(makespan, 3),
+           "arrival_span_s": round(reqs[-1].arrival, 3), "peak_running": st["peak_running"],
+           "peak_arena_GB": round(st["peak_bytes"] / 1e9, 3),
+           "plain_fp64_sequential": {"total_s": round(plain_total, 3),
+                                     "p50_solve_s": round(float(np.median([p[0] for p in plain])), 4),
+                                     "throughput_per_s": round(count / plain_total, 3)},
+           "max_rel_F_diff_vs_fp64": float(max(rel)) if rel else None,
+           "ranks": sorted({i["k"] for i in infos})}
+    log("serving: p50 %.3fs p99 %.3fs, %.2f req/s (plain fp64 sequential %.2f req/s)" % (
+        out["p50_s"], out["p99_s"], out["throughput_per_s"], out["plain_fp64_sequential"]["throughput_per_s"]))
     return out
 
 

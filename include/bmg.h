@@ -165,6 +165,52 @@ bmg_status bmg_prox_step(bmg_problem *p, double *W, double *H, int *k_inout, int
 bmg_status bmg_solve(bmg_problem *p, double *W, double *H, int ld, const bmg_options *opt,
                      int *k_out, bmg_result *res);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop over many completion problems of different shapes on one
+ * GPU.  The caller gives the server one device arena; every admitted problem
+ * lives in a first-fit allocation inside it (its CSR copy, W, H and its
+ * workspace), so admission is by HBM footprint.  Requests are admitted in
+ * arrival order, a later request may be admitted ahead of an earlier one that
+ * does not fit yet (backfill).  Each of max_slots slots is a host worker with
+ * its own HIP stream; admitted problems run concurrently on the device and a
+ * slot and its memory are reused as soon as a problem finishes.  Every
+ * problem's computation is independent of the others (own stream, own memory,
+ * deterministic kernels): a result is the same alone and in the mix. */
+typedef struct bmg_server bmg_server;
+
+typedef struct {
+  int state;          /* 0 queued, 1 running, 2 done, 3 failed                  */
+  int status;         /* bmg_status of the solve (when done or failed)          */
+  int k;              /* rank of the result                                     */
+  double queued_s;    /* submit -> admission                                    */
+  double run_s;       /* admission -> result copied back                        */
+  double total_s;     /* submit -> result copied back                           */
+  size_t footprint;   /* arena bytes the request occupied                       */
+  bmg_result result;
+} bmg_request_info;
+
+/* Arena bytes one request needs (CSR copy + factors at ld = k_cap rounded to 8
+ * + workspace).  (host) out. */
+bmg_status bmg_server_footprint(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_precision prec,
+                                size_t *bytes);
+/* arena: (device) memory owned by the caller, kept alive until destroy. */
+bmg_status bmg_server_create(void *arena, size_t arena_bytes, int max_slots, bmg_server **out);
+/* Copies the (host) CSR and queues the request; *ticket identifies it.
+ * BMG_ENOMEM if the request could never fit in the arena. */
+bmg_status bmg_server_submit(bmg_server *s, const bmg_csr *host_csr, int k_cap, bmg_precision prec,
+                             const bmg_options *opt, uint64_t *ticket);
+/* Non-blocking.  info: (host).  When the request is done and W_host/H_host are
+ * non-null, the factors are copied out (m x ld and n x ld row-major, FP64,
+ * columns beyond k zero). */
+bmg_status bmg_server_poll(bmg_server *s, uint64_t ticket, bmg_request_info *info, double *W_host,
+                           double *H_host, int ld);
+/* Blocks until every submitted request is done or failed. */
+bmg_status bmg_server_drain(bmg_server *s);
+/* Peak number of concurrently running problems and peak arena bytes in use. */
+bmg_status bmg_server_stats(bmg_server *s, int *peak_running, size_t *peak_bytes);
+/* Waits for running requests, drops queued ones, frees host state. */
+void bmg_server_destroy(bmg_server *s);
+
 /* Thread-local message of the last failing call on this thread. */
 const char *bmg_last_error(void);
 

@@ -157,3 +157,69 @@ class Problem:
                                    ctypes.byref(r))
         _lib.check(st, allow=(BMG_OK, BMG_NOT_CONVERGED))
         return W, H, k.value, r.as_dict()
+
+
+class Server:
+    """Request loop over many problems on one GPU (bmg_server_*): admission by
+    HBM footprint inside one torch-allocated arena, max_slots problems running
+    concurrently on their own streams."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 4, device="cuda:0"):
+        lib = _lib.load()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(torch.device(device)):
+            _lib.check(lib.bmg_server_create(_ptr(self.arena), self.arena.numel(), max_slots,
+                                             ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def footprint(m, n, nnz, k_cap=64, precision="fp32"):
+        b = ctypes.c_size_t(0)
+        _lib.check(_lib.load().bmg_server_footprint(m, n, nnz, k_cap, _PREC[precision], ctypes.byref(b)))
+        return b.value
+
+    def submit(self, row_ptr, col, val, m, n, k_cap=64, precision="fp32", **opts):
+        import numpy as np
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        vl = np.ascontiguousarray(val, dtype=np.float64)
+        csr = _lib.BmgCsr(m, n, len(cl), rp.ctypes.data, cl.ctypes.data, vl.ctypes.data)
+        o = options(**opts)
+        t = ctypes.c_uint64(0)
+        _lib.check(_lib.load().bmg_server_submit(self._h, ctypes.byref(csr), k_cap, _PREC[precision],
+                                                 ctypes.byref(o), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket, m=None, n=None, ld=None):
+        import numpy as np
+        info = _lib.BmgRequestInfo()
+        W = H = None
+        wp = hp = None
+        if m is not None:
+            W = np.zeros((m, ld)); H = np.zeros((n, ld))
+            wp, hp = W.ctypes.data_as(ctypes.c_void_p), H.ctypes.data_as(ctypes.c_void_p)
+        _lib.check(_lib.load().bmg_server_poll(self._h, ticket, ctypes.byref(info), wp, hp, ld or 0))
+        out = {"state": info.state, "status": info.status, "k": info.k, "queued_s": info.queued_s,
+               "run_s": info.run_s, "total_s": info.total_s, "footprint": info.footprint,
+               "result": info.result.as_dict()}
+        return out, W, H
+
+    def drain(self):
+        _lib.check(_lib.load().bmg_server_drain(self._h))
+
+    def stats(self):
+        pr, pb = ctypes.c_int(0), ctypes.c_size_t(0)
+        _lib.check(_lib.load().bmg_server_stats(self._h, ctypes.byref(pr), ctypes.byref(pb)))
+        return {"peak_running": pr.value, "peak_bytes": pb.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().bmg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

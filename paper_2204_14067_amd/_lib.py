@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "BMG_OK", 1: "BMG_NOT_CONVERGED", -1: "BMG_EINVAL", -2: "BMG_
 # the C ABI's exported entry points (checked by the CPU tests)
 EXPORTS = ["bmg_options_default", "bmg_workspace_size", "bmg_problem_create", "bmg_problem_destroy",
            "bmg_sddmm", "bmg_spmm", "bmg_bm_epochs", "bmg_objective", "bmg_prox_step", "bmg_solve",
-           "bmg_last_error"]
+           "bmg_last_error", "bmg_server_footprint", "bmg_server_create", "bmg_server_submit",
+           "bmg_server_poll", "bmg_server_drain", "bmg_server_stats", "bmg_server_destroy"]
 
 
 class BmgCsr(ctypes.Structure):
@@ -52,6 +53,13 @@ class BmgResult(ctypes.Structure):
             v = getattr(self, f)
             out[f] = list(v) if hasattr(v, "_length_") else v
         return out
+
+
+class BmgRequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("status", ctypes.c_int), ("k", ctypes.c_int),
+                ("queued_s", ctypes.c_double), ("run_s", ctypes.c_double),
+                ("total_s", ctypes.c_double), ("footprint", ctypes.c_size_t),
+                ("result", BmgResult)]
 
 
 class BmgError(RuntimeError):
@@ -85,8 +93,18 @@ def load():
     lib.bmg_objective.argtypes = [p, p, p, i32, i32, d, P(d)]
     lib.bmg_prox_step.argtypes = [p, p, p, P(i32), i32, P(BmgOptions), P(d), P(d)]
     lib.bmg_solve.argtypes = [p, p, p, i32, P(BmgOptions), P(i32), P(BmgResult)]
+    lib.bmg_server_footprint.argtypes = [i64, i64, i64, i32, i32, P(ctypes.c_size_t)]
+    lib.bmg_server_create.argtypes = [p, ctypes.c_size_t, i32, P(p)]
+    lib.bmg_server_submit.argtypes = [p, P(BmgCsr), i32, i32, P(BmgOptions), P(ctypes.c_uint64)]
+    lib.bmg_server_poll.argtypes = [p, ctypes.c_uint64, P(BmgRequestInfo), p, p, i32]
+    lib.bmg_server_drain.argtypes = [p]
+    lib.bmg_server_stats.argtypes = [p, P(i32), P(ctypes.c_size_t)]
+    lib.bmg_server_destroy.argtypes = [p]
+    lib.bmg_server_destroy.restype = None
     for f in ["bmg_workspace_size", "bmg_problem_create", "bmg_sddmm", "bmg_spmm", "bmg_bm_epochs",
-              "bmg_objective", "bmg_prox_step", "bmg_solve"]:
+              "bmg_objective", "bmg_prox_step", "bmg_solve", "bmg_server_footprint",
+              "bmg_server_create", "bmg_server_submit", "bmg_server_poll", "bmg_server_drain",
+              "bmg_server_stats"]:
         getattr(lib, f).restype = ctypes.c_int
     lib.bmg_last_error.argtypes = []
     lib.bmg_last_error.restype = ctypes.c_char_p

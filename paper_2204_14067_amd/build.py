@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libbmg.so")
-SOURCES = ["kernels.hip", "api.hip", "linalg.cpp"]
+SOURCES = ["kernels.hip", "api.hip", "linalg.cpp", "server.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions in the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -25,9 +25,10 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         cmd = ["hipcc"] + FLAGS + ["-c", os.path.join(HERE, "csrc", src), "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = ["hipcc", "-x", "c++"] + [f for f in FLAGS if not f.startswith("--offload")
-                                            and f not in ("-Xclang", "-target-feature", "-packed-fp32-ops")] \
+        if src.endswith(".cpp"):   # host-only C++ (no device code)
+            cmd = ["hipcc", "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"] + \
+                [f for f in FLAGS if not f.startswith("--offload")
+                 and f not in ("-Xclang", "-target-feature", "-packed-fp32-ops")] \
                 + ["-c", os.path.join(HERE, "csrc", src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -37,7 +38,7 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError("compilation of %s failed" % src)
         objs.append(obj)
     tmp = SO + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stderr)

@@ -18,7 +18,7 @@ Workloads (all synthetic; no dataset records are reproduced):
   lambda = 50, k0 = 32.
 * ``serving_stream`` 256 problems, Poisson arrivals at 20/s, m ~ U[500, 20000],
   n ~ U[1000, 50000], density ~ U[0.5%, 2%], rank ~ U{3..15}, noise variance
-  0.05, lambda ~ U[0.1, 5].
+  0.05, lambda relative to the sampling/noise level (see serving_stream).
 
 The ``scale`` argument shrinks a power-law workload (m, n and |Omega| by the
 same factor) for tests that must finish in seconds on the oracle.
@@ -198,9 +198,18 @@ class Request:
 
 def serving_stream(count: int = 256, rate: float = 20.0, seed: int = 1005,
                    m_range=(500, 20_000), n_range=(1_000, 50_000), dens_range=(0.005, 0.02),
-                   rank_range=(3, 15), lam_range=(0.1, 5.0)) -> list:
+                   rank_range=(3, 15), lam_range=(0.1, 5.0), lam_over_noise=(1.0, 2.0),
+                   noise_var=0.05) -> list:
     """Request descriptors of the serving workload (problems are built lazily by
-    :func:`request_problem`)."""
+    :func:`request_problem`).
+
+    lambda: with lam_over_noise set (the default), lambda = u * L with
+    u ~ U[lam_over_noise] and L = sqrt(1 + noise_var) (sqrt(n d) + sqrt(m d)),
+    the spectral norm of what sampling leaves outside the low-rank part (the
+    sampling artefact of the unit-variance truth plus the noise on Omega); a
+    lambda drawn from lam_range = [0.1, 5] sits below that level for nearly every
+    request and the solution then fits it at ranks in the hundreds.  Pass
+    lam_over_noise=None to draw from lam_range instead."""
     u = uniforms(seed, 0x77, 6 * count).reshape(count, 6)
     t = 0.0
     out = []
@@ -210,7 +219,11 @@ def serving_stream(count: int = 256, rate: float = 20.0, seed: int = 1005,
         n = int(n_range[0] + u[i, 2] * (n_range[1] - n_range[0]))
         d = dens_range[0] + u[i, 3] * (dens_range[1] - dens_range[0])
         r = int(rank_range[0] + min(rank_range[1] - rank_range[0], int(u[i, 4] * (rank_range[1] - rank_range[0] + 1))))
-        lam = lam_range[0] + u[i, 5] * (lam_range[1] - lam_range[0])
+        if lam_over_noise is None:
+            lam = lam_range[0] + u[i, 5] * (lam_range[1] - lam_range[0])
+        else:
+            L = math.sqrt(1.0 + noise_var) * (math.sqrt(n * d) + math.sqrt(m * d))
+            lam = (lam_over_noise[0] + u[i, 5] * (lam_over_noise[1] - lam_over_noise[0])) * L
         out.append(Request(t, m, n, d, r, lam, seed * 1000 + i))
     return out
 

@@ -1,0 +1,57 @@
+"""Serving loop (bmg_server_*): continuous admission by HBM footprint, several
+problems running at once, and every result identical alone and in the mix."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2204_14067_amd as bmg
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def small_requests(count=6):
+    reqs = synth.serving_stream(count=count, seed=77, m_range=(300, 1500), n_range=(500, 3000),
+                                dens_range=(0.02, 0.05))
+    return [(r, synth.request_problem(r)) for r in reqs]
+
+
+def test_serving_alone_equals_mix_and_admission_binds():
+    items = small_requests()
+    opts = dict(tol=1e-5, k_init=8, max_iter=2000, seed=5)
+    alone = []
+    for r, p in items:
+        dp = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp32",
+                                   device=DEV)
+        W, H, k, res = dp.bmg_solve(lam=r.lam, **opts)
+        alone.append((k, res["F"], res["status"]))
+        print("alone", p.name, k, res["F"], res["iters"], flush=True)
+    fps = [bmg.Server.footprint(p.m, p.n, p.nnz, 64, "fp32") for _, p in items]
+    arena = int(2.2 * max(fps))                       # at most two of the largest fit at once
+    srv = bmg.Server(arena, max_slots=4, device=DEV)
+    tickets = [srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp32", lam=r.lam,
+                          **opts) for r, p in items]
+    srv.drain()
+    st = srv.stats()
+    print("stats", st, "arena", arena, flush=True)
+    assert st["peak_bytes"] <= arena
+    assert 1 <= st["peak_running"] <= 4
+    for (r, p), t, (k, F, status) in zip(items, tickets, alone):
+        info, W, H = srv.poll(t, p.m, p.n, 64)
+        print("mix", p.name, info["k"], info["result"]["F"], info["queued_s"], info["run_s"], flush=True)
+        assert info["state"] == 2 and info["status"] == status
+        assert info["k"] == k
+        assert info["result"]["F"] == F              # bitwise: the same kernels on the same data
+        assert np.all(W[:, k:] == 0)
+    srv.close()
+
+
+def test_serving_rejects_requests_larger_than_the_arena():
+    r, p = small_requests(1)[0]
+    srv = bmg.Server(bmg.Server.footprint(p.m, p.n, p.nnz, 64, "fp32") // 2, max_slots=1, device=DEV)
+    with pytest.raises(bmg.BmgError, match="ENOMEM"):
+        srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp32", lam=r.lam)
+    srv.close()
