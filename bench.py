@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
     ap.add_argument("--serve-count", type=int, default=48,
                     help="requests replayed by the serving measurement (256 in the full stream)")
     args = ap.parse_args()
@@ -98,6 +100,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
+    if args.calibrate_copy:
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8,
+                          "copies": 3}))
+        return
     t0 = time.time()
     p = synth.netflix_shape(scale=args.scale)
     log("workload %s generated in %.1fs" % (p.name, time.time() - t0))

@@ -46,7 +46,6 @@ struct BmgError {
   } while (0)
 
 // ============================================================================ constants
-static constexpr int CHUNK = 2048;         // entries per piece of a long row
 static constexpr double ORTH_TOL = 1e-6;   // numerical-rank cut of orth() on unit columns
 static constexpr double SSI_EPS = 1e-12;   // Algorithm 2's cut of small s (relative)
 static constexpr double PINV_REL = 1e-12;  // Nystrom pseudo-inverse cut (relative)
@@ -61,8 +60,8 @@ struct Layout {
   bool lowp;
   // persistent
   size_t csc_ptr, csc_idx, csc_a, perm, r_rows, r_cols, a32_rows, a32_cols;
-  size_t pr_short, pr_long, pr_lp0, pr_prow, pr_pbeg;
-  size_t pc_short, pc_long, pc_lp0, pc_prow, pc_pbeg;
+  size_t pr_short, pr_long, pr_lp0, pr_prow, pr_pbeg, pr_pend, pr_pord;
+  size_t pc_short, pc_long, pc_lp0, pc_prow, pc_pbeg, pc_pend, pc_pord;
   size_t wsum, partial, result, gram_part, small;
   size_t g_W, g_H, g_U, g_Y, d_W64, d_H64, d_R64;  // BF16 mode: shadows and FP64 refresh
   int64_t max_long, max_pieces, wsum_cap, gram_cap;
@@ -92,9 +91,11 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_prec
   L.qmax = 2 * k_cap + 2;
   L.qld = (int)rup(L.qmax, 16);
   L.lowp = prec != BMG_FP64;
-  L.max_long = nnz / CHUNK + 1;
-  L.max_pieces = 2 * (nnz / CHUNK) + 2;
-  L.wsum_cap = std::max(m, n) + L.max_pieces + 8;
+  L.max_long = nnz / LONG_ROW + 1;
+  // every piece but the last of its row holds at least PIECE_MIN entries
+  L.max_pieces = nnz / PIECE_MIN + L.max_long + 1;
+  // one scalar slot per wave of a row-kernel grid (two runs padded to 8 blocks)
+  L.wsum_cap = std::max(m, n) + L.max_pieces + 80;
   L.gram_cap = std::max<int64_t>(64LL * L.qmax * L.qmax, 2048LL * 4096);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += rup((int64_t)bytes + 1, 256); return o; };
@@ -111,11 +112,15 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_prec
   L.pr_lp0 = take(4 * (L.max_long + 1));
   L.pr_prow = take(4 * L.max_pieces);
   L.pr_pbeg = take(8 * L.max_pieces);
+  L.pr_pend = take(8 * L.max_pieces);
+  L.pr_pord = take(4 * L.max_pieces);
   L.pc_short = take(4 * n);
   L.pc_long = take(4 * L.max_long);
   L.pc_lp0 = take(4 * (L.max_long + 1));
   L.pc_prow = take(4 * L.max_pieces);
   L.pc_pbeg = take(8 * L.max_pieces);
+  L.pc_pend = take(8 * L.max_pieces);
+  L.pc_pord = take(4 * L.max_pieces);
   L.wsum = take(16 * L.wsum_cap);
   L.partial = take((size_t)L.max_pieces * 1024);
   L.result = take(8 * 64);
@@ -243,66 +248,122 @@ struct bmg_problem {
     PassScratch sc;
     sc.wsum = wsum;
     sc.partial = partial;
+    sc.partial_bytes = (int64_t)L.max_pieces * 1024;
     sc.result = result;
     return sc;
   }
 };
 
-static void build_plan(bmg_problem *P, int64_t nrows, const int64_t *d_ptr, const int32_t *d_idx,
-                       size_t o_short, size_t o_long, size_t o_lp0, size_t o_prow, size_t o_pbeg,
-                       Plan &pl) {
+// Where the plan's device arrays live in the workspace.
+struct PlanSlots {
+  size_t shorts, longs, lp0, prow, pbeg, pend, pord;
+};
+
+static void build_plan(bmg_problem *P, int64_t nrows, int64_t ncols, const int64_t *d_ptr,
+                       const int32_t *d_idx, const PlanSlots &o, Plan &pl) {
   std::vector<int64_t> ptr(nrows + 1);
   HIPC(hipMemcpyAsync(ptr.data(), d_ptr, 8 * (nrows + 1), hipMemcpyDeviceToHost, P->s));
   HIPC(hipStreamSynchronize(P->s));
-  std::vector<int32_t> shorts, longs, lp0, prow;
-  std::vector<int64_t> pbeg;
+  auto len = [&](int64_t r) { return ptr[r + 1] - ptr[r]; };
+  std::vector<int32_t> shorts, longs;
   shorts.reserve(nrows);
   for (int64_t i = 0; i < nrows; ++i) {
-    const int64_t len = ptr[i + 1] - ptr[i];
-    if (len <= CHUNK) shorts.push_back((int32_t)i);
+    if (len(i) <= LONG_ROW) shorts.push_back((int32_t)i);
     else longs.push_back((int32_t)i);
   }
-  std::stable_sort(shorts.begin(), shorts.end(), [&](int32_t a, int32_t b) {
-    return (ptr[a + 1] - ptr[a]) > (ptr[b + 1] - ptr[b]);
-  });
-  for (int32_t r : longs) {
+  std::stable_sort(shorts.begin(), shorts.end(),
+                   [&](int32_t a, int32_t b) { return len(a) > len(b); });
+  const int64_t n_long = (int64_t)longs.size();
+  REQUIRE(n_long <= P->L.max_long, BMG_EINVAL, "plan larger than its bound");
+  if (!shorts.empty())
+    HIPC(hipMemcpyAsync(P->at<int32_t>(o.shorts), shorts.data(), 4 * shorts.size(),
+                        hipMemcpyHostToDevice, P->s));
+  if (n_long > 0)
+    HIPC(hipMemcpyAsync(P->at<int32_t>(o.longs), longs.data(), 4 * longs.size(),
+                        hipMemcpyHostToDevice, P->s));
+  // --- column ranges and where each long row crosses them (computed on the GPU
+  // into the setup scratch: n_long (nr + 1) < nnz int32 fit its 4 nnz bytes)
+  const int nr = (int)std::max<int64_t>(
+      1, std::min<int64_t>(MAX_RANGES, (ncols + RANGE_COLS - 1) / RANGE_COLS));
+  const int64_t wc = std::max<int64_t>(1, (ncols + nr - 1) / nr);
+  std::vector<int32_t> bnd((size_t)n_long * (nr + 1));
+  if (n_long > 0) {
+    int32_t *d_bnd = P->at<int32_t>(P->L.s_keys_out);
+    HIPC(launch_range_bounds(d_ptr, d_idx, P->at<int32_t>(o.longs), n_long, nr, wc, d_bnd, P->s));
+    HIPC(hipMemcpyAsync(bnd.data(), d_bnd, 4 * bnd.size(), hipMemcpyDeviceToHost, P->s));
+    HIPC(hipStreamSynchronize(P->s));
+  }
+  // --- pieces, row by row: at most LONG_ROW entries, cut at a range end once
+  // they hold PIECE_MIN entries; key = column range of the first entry
+  std::vector<int32_t> lp0, prow, pkey;
+  std::vector<int64_t> pbeg, pend;
+  for (int64_t i = 0; i < n_long; ++i) {
+    const int32_t r = longs[i];
+    const int32_t *B = &bnd[(size_t)i * (nr + 1)];
+    const int64_t L = len(r), base = ptr[r];
     lp0.push_back((int32_t)prow.size());
-    for (int64_t b = ptr[r]; b < ptr[r + 1]; b += CHUNK) {
+    auto emit = [&](int64_t b, int64_t e, int key) {
       prow.push_back(r);
-      pbeg.push_back(b);
+      pbeg.push_back(base + b);
+      pend.push_back(base + e);
+      pkey.push_back(key);
+    };
+    int64_t cur = 0;
+    int sk = 0;
+    for (int kr = 0; kr < nr; ++kr) {
+      const int64_t ek = kr + 1 < nr ? (int64_t)B[kr + 1] : L;
+      while (ek - cur > LONG_ROW) {
+        emit(cur, cur + LONG_ROW, sk);
+        cur += LONG_ROW;
+        sk = kr;
+      }
+      if (ek - cur >= PIECE_MIN) {
+        emit(cur, ek, sk);
+        cur = ek;
+        sk = kr + 1;
+      }
     }
+    if (cur < L) emit(cur, L, std::min(sk, nr - 1));
   }
   lp0.push_back((int32_t)prow.size());
-  REQUIRE((int64_t)longs.size() <= P->L.max_long && (int64_t)prow.size() <= P->L.max_pieces,
-          BMG_EINVAL, "plan larger than its bound");
-  if (!shorts.empty())
-    HIPC(hipMemcpyAsync(P->at<int32_t>(o_short), shorts.data(), 4 * shorts.size(),
-                        hipMemcpyHostToDevice, P->s));
-  if (!longs.empty())
-    HIPC(hipMemcpyAsync(P->at<int32_t>(o_long), longs.data(), 4 * longs.size(),
-                        hipMemcpyHostToDevice, P->s));
-  HIPC(hipMemcpyAsync(P->at<int32_t>(o_lp0), lp0.data(), 4 * lp0.size(), hipMemcpyHostToDevice,
+  const int64_t n_pieces = (int64_t)prow.size();
+  REQUIRE(n_pieces <= P->L.max_pieces, BMG_EINVAL, "plan larger than its bound");
+  // launch order: by key (counting sort; stable in piece order)
+  std::vector<int32_t> pord(n_pieces);
+  {
+    std::vector<int64_t> start(nr + 1, 0);
+    for (int32_t k : pkey) ++start[k + 1];
+    for (int kr = 0; kr < nr; ++kr) start[kr + 1] += start[kr];
+    for (int64_t pc = 0; pc < n_pieces; ++pc) pord[start[pkey[pc]]++] = (int32_t)pc;
+  }
+  HIPC(hipMemcpyAsync(P->at<int32_t>(o.lp0), lp0.data(), 4 * lp0.size(), hipMemcpyHostToDevice,
                       P->s));
-  if (!prow.empty()) {
-    HIPC(hipMemcpyAsync(P->at<int32_t>(o_prow), prow.data(), 4 * prow.size(),
-                        hipMemcpyHostToDevice, P->s));
-    HIPC(hipMemcpyAsync(P->at<int64_t>(o_pbeg), pbeg.data(), 8 * pbeg.size(),
-                        hipMemcpyHostToDevice, P->s));
+  if (n_pieces > 0) {
+    HIPC(hipMemcpyAsync(P->at<int32_t>(o.prow), prow.data(), 4 * n_pieces, hipMemcpyHostToDevice,
+                        P->s));
+    HIPC(hipMemcpyAsync(P->at<int64_t>(o.pbeg), pbeg.data(), 8 * n_pieces, hipMemcpyHostToDevice,
+                        P->s));
+    HIPC(hipMemcpyAsync(P->at<int64_t>(o.pend), pend.data(), 8 * n_pieces, hipMemcpyHostToDevice,
+                        P->s));
+    HIPC(hipMemcpyAsync(P->at<int32_t>(o.pord), pord.data(), 4 * n_pieces, hipMemcpyHostToDevice,
+                        P->s));
   }
   HIPC(hipStreamSynchronize(P->s));  // host vectors go out of scope
   pl.nrows = nrows;
+  pl.ncols = ncols;
   pl.nnz = ptr[nrows];
   pl.ptr = d_ptr;
   pl.idx = d_idx;
-  pl.short_rows = P->at<int32_t>(o_short);
+  pl.short_rows = P->at<int32_t>(o.shorts);
   pl.n_short = (int64_t)shorts.size();
-  pl.long_rows = P->at<int32_t>(o_long);
-  pl.long_p0 = P->at<int32_t>(o_lp0);
-  pl.n_long = (int64_t)longs.size();
-  pl.piece_row = P->at<int32_t>(o_prow);
-  pl.piece_beg = P->at<int64_t>(o_pbeg);
-  pl.n_pieces = (int64_t)prow.size();
-  pl.chunk = CHUNK;
+  pl.long_rows = P->at<int32_t>(o.longs);
+  pl.long_p0 = P->at<int32_t>(o.lp0);
+  pl.n_long = n_long;
+  pl.piece_row = P->at<int32_t>(o.prow);
+  pl.piece_beg = P->at<int64_t>(o.pbeg);
+  pl.piece_end = P->at<int64_t>(o.pend);
+  pl.piece_ord = P->at<int32_t>(o.pord);
+  pl.n_pieces = n_pieces;
 }
 
 // ============================================================================ typed solver
@@ -663,9 +724,12 @@ extern "C" bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_prec
     }
     HIPC(hipStreamSynchronize(P->s));
     // --- plans
-    build_plan(P, m, csr->row_ptr, csr->col, L.pr_short, L.pr_long, L.pr_lp0, L.pr_prow, L.pr_pbeg,
+    build_plan(P, m, n, csr->row_ptr, csr->col,
+               {L.pr_short, L.pr_long, L.pr_lp0, L.pr_prow, L.pr_pbeg, L.pr_pend, L.pr_pord},
                P->urow.pl);
-    build_plan(P, n, cptr, cidx, L.pc_short, L.pc_long, L.pc_lp0, L.pc_prow, L.pc_pbeg, P->ucol.pl);
+    build_plan(P, n, m, cptr, cidx,
+               {L.pc_short, L.pc_long, L.pc_lp0, L.pc_prow, L.pc_pbeg, L.pc_pend, L.pc_pord},
+               P->ucol.pl);
     P->urow.a64 = csr->val;
     P->ucol.a64 = ca;
     P->urow.r = P->at<void>(L.r_rows);

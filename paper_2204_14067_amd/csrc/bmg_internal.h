@@ -13,23 +13,36 @@ typedef uint16_t bf16_t;  // BF16 storage: the upper 16 bits of an FP32 (RNE)
 
 // One compressed orientation of Omega (rows of A for the CSR orientation,
 // rows of A^T for the column-major copy) plus its load-balancing plan:
-//   short rows (length <= chunk) are processed one row per lane group, in
-//   order of decreasing length so the groups of a wave finish together;
-//   long rows are cut into pieces of `chunk` entries, one wave per piece,
-//   whose partial row results are summed in piece order by a fix-up pass.
+//   short rows (length <= LONG_ROW entries) are processed one row per lane
+//   group, in order of decreasing length so the groups of a wave finish together;
+//   long rows are cut into pieces, one wave per piece, whose partial row
+//   results are summed in piece order by a fix-up pass.  A piece holds at most
+//   LONG_ROW entries and is cut where the row crosses into another column range
+//   (ranges of about RANGE_COLS columns of the gathered side) once it holds
+//   PIECE_MIN entries.  Pieces are numbered row by row and launched in order of
+//   their first column range (piece_ord), and each XCD takes a contiguous run of
+//   that order, so the waves resident on an XCD gather from a narrow window of
+//   the other factor that its L2 holds.
+constexpr int LONG_ROW = 2048;
+constexpr int PIECE_MIN = 512;
+constexpr int RANGE_COLS = 4096;
+constexpr int MAX_RANGES = 256;
+
 struct Plan {
   int64_t nrows = 0, nnz = 0;
-  const int64_t *ptr = nullptr;   // [nrows+1]
-  const int32_t *idx = nullptr;   // [nnz] column (or row) index of each entry
+  int64_t ncols = 0;               // rows of the gathered operand (columns of Omega here)
+  const int64_t *ptr = nullptr;    // [nrows+1]
+  const int32_t *idx = nullptr;    // [nnz] column (or row) index of each entry
   const int32_t *short_rows = nullptr;
   int64_t n_short = 0;
-  const int32_t *piece_row = nullptr;
-  const int64_t *piece_beg = nullptr;
+  const int32_t *piece_row = nullptr;  // [n_pieces] row of each piece (row by row)
+  const int64_t *piece_beg = nullptr;  // [n_pieces] entry range [beg, end) of each piece
+  const int64_t *piece_end = nullptr;
+  const int32_t *piece_ord = nullptr;  // [n_pieces] launch order: slot -> piece
   int64_t n_pieces = 0;
   const int32_t *long_rows = nullptr;
   const int32_t *long_p0 = nullptr;  // [n_long+1] first piece of each long row
   int64_t n_long = 0;
-  int chunk = 2048;
 };
 
 // Scratch used by one sparse pass: per-wave scalar partials and per-piece
@@ -38,6 +51,7 @@ struct PassScratch {
   double *wsum = nullptr;      // [max_waves * 2]
   void *partial = nullptr;     // [n_pieces * width] (element type of the pass)
   double *result = nullptr;    // [2] final scalar sums
+  int64_t partial_bytes = 0;   // capacity of partial
   hipEvent_t ev0 = nullptr;    // if set, recorded around the main kernel launch
   hipEvent_t ev1 = nullptr;
 };
@@ -101,6 +115,8 @@ hipError_t launch_gather_csc(int64_t nnz, const int32_t *perm, const int32_t *ri
                              const double *val, int32_t *crow, double *cval, hipStream_t s);
 hipError_t launch_col_ptr(int64_t nnz, int64_t n, const int32_t *sorted_col, int64_t *cptr,
                           hipStream_t s);
+hipError_t launch_range_bounds(const int64_t *ptr, const int32_t *idx, const int32_t *rows,
+                               int64_t n, int nr, int64_t wc, int32_t *out, hipStream_t s);
 hipError_t launch_check_csr(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
                             const double *val, const int32_t *rid, int *flags, hipStream_t s);
 

@@ -132,6 +132,38 @@ __host__ __device__ inline int64_t short_waves(const Plan &pl, int G) {
   return (pl.n_short + S - 1) / S;
 }
 
+// Grid of a row-kernel launch: the short-row waves first, then, from a block
+// index that is a multiple of 8, the piece waves.  Blocks are dealt to the 8
+// XCDs in turn; piece block bb takes launch slots from run (bb % 8) of the
+// piece order, so each XCD works through a contiguous run of column ranges.
+__host__ __device__ inline int64_t piece_block0(const Plan &pl, int G) {
+  const int64_t sb = (short_waves(pl, G) + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  return (sb + 7) / 8 * 8;
+}
+__host__ __device__ inline int64_t piece_blocks(const Plan &pl) {
+  return ((pl.n_pieces + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK + 7) / 8 * 8;
+}
+__host__ __device__ inline int64_t grid_blocks(const Plan &pl, int G) {
+  int64_t b = pl.n_pieces == 0
+                  ? (short_waves(pl, G) + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK
+                  : piece_block0(pl, G) + piece_blocks(pl);
+  return b > 0 ? b : 1;
+}
+// Work of the calling wave: 0 = short-row wave w, 1 = piece w, -1 = none.
+__device__ __forceinline__ int wave_work(const Plan &pl, int G, int64_t &w) {
+  const int wave = threadIdx.x >> 6;
+  const int64_t b = blockIdx.x, pb0 = piece_block0(pl, G);
+  if (b < pb0) {
+    w = b * WAVES_PER_BLOCK + wave;
+    return w < short_waves(pl, G) ? 0 : -1;
+  }
+  const int64_t nb8 = piece_blocks(pl) / 8, bb = b - pb0;
+  const int64_t slot = ((bb % 8) * nb8 + bb / 8) * WAVES_PER_BLOCK + wave;
+  if (slot >= pl.n_pieces) return -1;
+  w = pl.piece_ord[slot];
+  return 1;
+}
+
 // ============================================================================ lane-group row access
 // A lane group of G lanes owns one row of Omega.  A dense k-vector is split in
 // C chunks of G*V consecutive columns (one 128-byte line for G = 8 in FP64);
@@ -220,19 +252,19 @@ __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
                                               const T *__restrict__ X, int ldx,
                                               const TG *__restrict__ Y, int ldy, int k, double lam,
                                               T *__restrict__ Out, int ldo,
-                                              T *__restrict__ partial, double *__restrict__ wsum,
-                                              int64_t total_waves) {
+                                              T *__restrict__ partial, double *__restrict__ wsum) {
   using RowT = Row<T, TG, G, C>;
   constexpr int S = 64 / G, WB = RowT::WB;
   const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
   const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
-  const int64_t sw = short_waves(pl, G);
+  int64_t w = 0;
+  const int kind = wave_work(pl, G, w);
   const bool leader = (sub == 0);
   double ss = 0.0;
   RowT acc;
   acc.zero();
-  if (gw < sw) {
-    const int64_t ri = gw * S + slot;
+  if (kind == 0) {
+    const int64_t ri = w * S + slot;
     if (ri < pl.n_short) {
       const int row = pl.short_rows[ri];
       RowT x;
@@ -245,12 +277,10 @@ __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
       acc.axpy((T)lam, x);
       acc.store(Out + (int64_t)row * ldo, sub, k);
     }
-  } else if (gw < total_waves) {
-    const int64_t pc = gw - sw;
+  } else if (kind == 1) {
+    const int64_t pc = w;
     const int row = pl.piece_row[pc];
-    const int64_t beg = pl.piece_beg[pc];
-    int64_t end = pl.ptr[row + 1];
-    if (end > beg + pl.chunk) end = beg + pl.chunk;
+    const int64_t beg = pl.piece_beg[pc], end = pl.piece_end[pc];
     RowT x;
     x.load(X + (int64_t)row * ldx, sub, k);
     for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
@@ -265,7 +295,7 @@ __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
     if (slot == 0) acc.store(partial + pc * WB, sub, WB);
   }
   ss = wave_sum(ss);
-  if (lane == 0 && gw < total_waves) wsum[gw] = ss;
+  if (lane == 0) wsum[gw] = ss;
 }
 
 // Long rows: Out_row = sum of piece partials (piece order) + lam * x_row.
@@ -333,17 +363,17 @@ template <typename T, typename TG, int G, int C>
 __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
                                                const T *__restrict__ X, int ldx,
                                                const TG *__restrict__ Y, int ldy, int k,
-                                               T *__restrict__ R, double *__restrict__ wsum,
-                                               int64_t total_waves) {
+                                               T *__restrict__ R, double *__restrict__ wsum) {
   using RowT = Row<T, TG, G, C>;
   constexpr int S = 64 / G;
   const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
   const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
-  const int64_t sw = short_waves(pl, G);
+  int64_t w = 0;
+  const int kind = wave_work(pl, G, w);
   const bool leader = (sub == 0);
   double ss = 0.0, sx = 0.0;
-  if (gw < sw) {
-    const int64_t ri = gw * S + slot;
+  if (kind == 0) {
+    const int64_t ri = w * S + slot;
     if (ri < pl.n_short) {
       const int row = pl.short_rows[ri];
       RowT x;
@@ -354,12 +384,10 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
         sddmm_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, R, ss, sx, leader, p, 1, n);
       }
     }
-  } else if (gw < total_waves) {
-    const int64_t pc = gw - sw;
+  } else if (kind == 1) {
+    const int64_t pc = w;
     const int row = pl.piece_row[pc];
-    const int64_t beg = pl.piece_beg[pc];
-    int64_t end = pl.ptr[row + 1];
-    if (end > beg + pl.chunk) end = beg + pl.chunk;
+    const int64_t beg = pl.piece_beg[pc], end = pl.piece_end[pc];
     RowT x;
     x.load(X + (int64_t)row * ldx, sub, k);
     for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
@@ -370,7 +398,7 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
   }
   ss = wave_sum(ss);
   sx = wave_sum(sx);
-  if (lane == 0 && gw < total_waves) {
+  if (lane == 0) {
     wsum[2 * gw] = ss;
     wsum[2 * gw + 1] = sx;
   }
@@ -427,16 +455,16 @@ __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
                                               double coef, const T *__restrict__ X, int ldx,
                                               int kx, const T *__restrict__ M, int ldm,
                                               T *__restrict__ Cm, int ldc,
-                                              T *__restrict__ partial, int64_t total_waves) {
+                                              T *__restrict__ partial) {
   using RowT = Row<T, TG, G, C>;
   constexpr int S = 64 / G, WB = RowT::WB;
   const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
-  const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
-  const int64_t sw = short_waves(pl, G);
+  int64_t w = 0;
+  const int kind = wave_work(pl, G, w);
   RowT acc;
   acc.zero();
-  if (gw < sw) {
-    const int64_t ri = gw * S + slot;
+  if (kind == 0) {
+    const int64_t ri = w * S + slot;
     if (ri < pl.n_short) {
       const int row = pl.short_rows[ri];
       const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
@@ -447,12 +475,9 @@ __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
       lowrank_epilogue<T, TG, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
       acc.store(Cm + (int64_t)row * ldc, sub, wq);
     }
-  } else if (gw < total_waves) {
-    const int64_t pc = gw - sw;
-    const int row = pl.piece_row[pc];
-    const int64_t beg = pl.piece_beg[pc];
-    int64_t end = pl.ptr[row + 1];
-    if (end > beg + pl.chunk) end = beg + pl.chunk;
+  } else if (kind == 1) {
+    const int64_t pc = w;
+    const int64_t beg = pl.piece_beg[pc], end = pl.piece_end[pc];
     for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
       const int64_t rem = (end - p + S - 1) / S;
       const int n = (int)(rem < UNROLL ? rem : UNROLL);
@@ -500,12 +525,6 @@ static inline GC pick_gc(int width, int V) {
   return {8, c < 1 ? 1 : c};
 }
 
-static inline int64_t total_waves(const Plan &pl, int G) { return short_waves(pl, G) + pl.n_pieces; }
-
-static inline dim3 wave_grid(int64_t waves) {
-  int64_t b = (waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  return dim3((unsigned)(b > 0 ? b : 1));
-}
 
 #define BMG_DISPATCH_GC(gc, ...)                                                        \
   do {                                                                                  \
@@ -523,6 +542,8 @@ static inline dim3 wave_grid(int64_t waves) {
     }                                                                                   \
   } while (0)
 
+// Each launch writes one scalar slot (or pair) per wave of its grid, idle
+// waves included, and reduces them in wave order.
 template <typename T, typename TG>
 hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const TG *Y, int ldy, int k,
                        double lam, T *Out, int ldo, PassScratch sc, int64_t *waves_out,
@@ -530,22 +551,22 @@ hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const TG
   constexpr int V = VT<TG>::V;
   if (k > max_width<T>()) return hipErrorInvalidValue;
   const GC gc = pick_gc(k, V);
-  const int64_t tw = total_waves(pl, gc.G);
-  if (waves_out) *waves_out = tw;
+  const int64_t nb = grid_blocks(pl, gc.G), waves = nb * WAVES_PER_BLOCK;
+  if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
   BMG_DISPATCH_GC(gc, {
-    if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
-    hipLaunchKernelGGL((k_grad<T, TG, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, a, X, ldx, Y,
-                       ldy, k, lam, Out, ldo, (T *)sc.partial, sc.wsum, tw);
-    if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
+    hipLaunchKernelGGL((k_grad<T, TG, GG, CC>), dim3((unsigned)nb), dim3(256), 0, s, pl, a, X, ldx,
+                       Y, ldy, k, lam, Out, ldo, (T *)sc.partial, sc.wsum);
     if (pl.n_long > 0) {
       const int64_t thr = pl.n_long * GG;
       hipLaunchKernelGGL((k_grad_fix<T, TG, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
                          dim3(256), 0, s, pl, (const T *)sc.partial, X, ldx, k, lam, Out, ldo);
     }
   });
+  if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
+  if (waves_out) *waves_out = waves;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_reduce_wsum(sc.wsum, tw, 1, sc.result, s);
+  return launch_reduce_wsum(sc.wsum, waves, 1, sc.result, s);
 }
 
 template <typename T, typename TG>
@@ -554,16 +575,16 @@ hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const T
   constexpr int V = VT<TG>::V;
   if (k > max_width<T>()) return hipErrorInvalidValue;
   const GC gc = pick_gc(k, V);
-  const int64_t tw = total_waves(pl, gc.G);
+  const int64_t nb = grid_blocks(pl, gc.G), waves = nb * WAVES_PER_BLOCK;
+  if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
   BMG_DISPATCH_GC(gc, {
-    if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
-    hipLaunchKernelGGL((k_sddmm<T, TG, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, a, X, ldx, Y,
-                       ldy, k, R, sc.wsum, tw);
-    if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
+    hipLaunchKernelGGL((k_sddmm<T, TG, GG, CC>), dim3((unsigned)nb), dim3(256), 0, s, pl, a, X,
+                       ldx, Y, ldy, k, R, sc.wsum);
   });
+  if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_reduce_wsum(sc.wsum, tw, 2, sc.result, s);
+  return launch_reduce_wsum(sc.wsum, waves, 2, sc.result, s);
 }
 
 template <typename T, typename TG>
@@ -572,16 +593,15 @@ hipError_t launch_spmm(const Plan &pl, const T *Sv, const TG *B, int ldb, int q,
                        PassScratch sc, hipStream_t s) {
   constexpr int V = VT<TG>::V;
   const int WMAX = max_width<T>();
+  if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
   for (int c0 = 0; c0 < q; c0 += WMAX) {
     const int wq = (q - c0) < WMAX ? (q - c0) : WMAX;
     const GC gc = pick_gc(wq, V);
-    const int64_t tw = total_waves(pl, gc.G);
+    const int64_t nb = grid_blocks(pl, gc.G);
     BMG_DISPATCH_GC(gc, {
-      if (sc.ev0 && c0 == 0) (void)hipEventRecord(sc.ev0, s);
-      hipLaunchKernelGGL((k_spmm<T, TG, GG, CC>), wave_grid(tw), dim3(256), 0, s, pl, Sv, B + c0,
-                         ldb, wq, coef, X, ldx, kx, M ? M + c0 : M, ldm, Cm + c0, ldc,
-                         (T *)sc.partial, tw);
-      if (sc.ev1 && c0 + WMAX >= q) (void)hipEventRecord(sc.ev1, s);
+      hipLaunchKernelGGL((k_spmm<T, TG, GG, CC>), dim3((unsigned)nb), dim3(256), 0, s, pl, Sv,
+                         B + c0, ldb, wq, coef, X, ldx, kx, M ? M + c0 : M, ldm, Cm + c0, ldc,
+                         (T *)sc.partial);
       if (pl.n_long > 0) {
         const int64_t thr = pl.n_long * GG;
         hipLaunchKernelGGL((k_spmm_fix<T, TG, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
@@ -592,7 +612,35 @@ hipError_t launch_spmm(const Plan &pl, const T *Sv, const TG *B, int ldb, int q,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
   return hipSuccess;
+}
+
+// Offsets (from the row start) of the first entry of each long row at or
+// beyond each column-range boundary: out[i * (nr + 1) + k] for boundary k * wc.
+__global__ void k_range_bounds(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                               const int32_t *__restrict__ rows, int64_t n, int nr, int64_t wc,
+                               int32_t *__restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * (nr + 1)) return;
+  const int64_t i = t / (nr + 1);
+  const int kb = (int)(t % (nr + 1));
+  const int row = rows[i];
+  int64_t b = ptr[row], e = ptr[row + 1];
+  const int64_t b0 = b, c = (int64_t)kb * wc;
+  while (b < e) {
+    const int64_t mid = (b + e) >> 1;
+    if (idx[mid] < c) b = mid + 1; else e = mid;
+  }
+  out[t] = (int32_t)(b - b0);
+}
+hipError_t launch_range_bounds(const int64_t *ptr, const int32_t *idx, const int32_t *rows,
+                               int64_t n, int nr, int64_t wc, int32_t *out, hipStream_t s) {
+  const int64_t t = n * (nr + 1);
+  if (t == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_range_bounds, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, ptr, idx,
+                     rows, n, nr, wc, out);
+  return hipGetLastError();
 }
 
 // ============================================================================ scalar reduction
