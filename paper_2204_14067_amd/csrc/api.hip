@@ -62,7 +62,7 @@ struct Layout {
   size_t csc_ptr, csc_idx, csc_a, perm, r_rows, r_cols, a32_rows, a32_cols;
   size_t pr_short, pr_long, pr_lp0, pr_prow, pr_pbeg, pr_pend, pr_pord;
   size_t pc_short, pc_long, pc_lp0, pc_prow, pc_pbeg, pc_pend, pc_pord;
-  size_t wsum, partial, result, gram_part, small;
+  size_t wsum, wpart, partial, result, gram_part, small;
   size_t g_W, g_H, g_U, g_Y, d_W64, d_H64, d_R64;  // BF16 mode: shadows and FP64 refresh
   int64_t max_long, max_pieces, wsum_cap, gram_cap;
   // scratch region (setup sort / solver blocks overlap)
@@ -122,6 +122,7 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_prec
   L.pc_pend = take(8 * L.max_pieces);
   L.pc_pord = take(4 * L.max_pieces);
   L.wsum = take(16 * L.wsum_cap);
+  L.wpart = take(16 * 256);
   L.partial = take((size_t)L.max_pieces * 1024);
   L.result = take(8 * 64);
   L.gram_part = take(8 * L.gram_cap);
@@ -188,7 +189,7 @@ struct bmg_problem {
   Side urow, ucol;  // user CSR orientation and the built column orientation
   int32_t *perm;    // column-order position -> CSR position
   double *result, *gram_part, *small;
-  double *wsum;
+  double *wsum, *wpart;
   void *partial;
   // statistics of the sparse passes since the last reset
   double bytes = 0.0;
@@ -247,6 +248,7 @@ struct bmg_problem {
   PassScratch scratch() {
     PassScratch sc;
     sc.wsum = wsum;
+    sc.wpart = wpart;
     sc.partial = partial;
     sc.partial_bytes = (int64_t)L.max_pieces * 1024;
     sc.result = result;
@@ -681,6 +683,7 @@ extern "C" bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_prec
     P->gram_part = P->at<double>(L.gram_part);
     P->small = P->at<double>(L.small);
     P->wsum = P->at<double>(L.wsum);
+    P->wpart = P->at<double>(L.wpart);
     P->partial = P->at<void>(L.partial);
     // --- validate the CSR (row ids first; they also feed the transpose)
     int32_t *rid = P->at<int32_t>(L.s_rid);

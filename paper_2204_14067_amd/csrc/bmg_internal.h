@@ -51,6 +51,7 @@ struct PassScratch {
   double *wsum = nullptr;      // [max_waves * 2]
   void *partial = nullptr;     // [n_pieces * width] (element type of the pass)
   double *result = nullptr;    // [2] final scalar sums
+  double *wpart = nullptr;     // [256 * 2] first-stage sums of wsum
   int64_t partial_bytes = 0;   // capacity of partial
   hipEvent_t ev0 = nullptr;    // if set, recorded around the main kernel launch
   hipEvent_t ev1 = nullptr;
@@ -106,7 +107,7 @@ hipError_t launch_normals(uint64_t seed, uint64_t stream, int64_t rows, int cols
                           hipStream_t s);  // entry (i, j) is normal number i*cols + j
 hipError_t launch_gather_perm(int64_t nnz, const int32_t *perm, const double *in, double *out,
                               hipStream_t s);
-hipError_t launch_reduce_wsum(const double *wsum, int64_t waves, int nsum, double *out,
+hipError_t launch_reduce_wsum(const double *wsum, int64_t waves, int nsum, double *tmp, double *out,
                               hipStream_t s);
 // Setup helpers.
 hipError_t launch_row_ids(int64_t m, const int64_t *row_ptr, int32_t *rid, hipStream_t s);

@@ -566,7 +566,7 @@ hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const TG
   if (waves_out) *waves_out = waves;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_reduce_wsum(sc.wsum, waves, 1, sc.result, s);
+  return launch_reduce_wsum(sc.wsum, waves, 1, sc.wpart, sc.result, s);
 }
 
 template <typename T, typename TG>
@@ -584,7 +584,7 @@ hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const T
   if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_reduce_wsum(sc.wsum, waves, 2, sc.result, s);
+  return launch_reduce_wsum(sc.wsum, waves, 2, sc.wpart, sc.result, s);
 }
 
 template <typename T, typename TG>
@@ -644,83 +644,138 @@ hipError_t launch_range_bounds(const int64_t *ptr, const int32_t *idx, const int
 }
 
 // ============================================================================ scalar reduction
-// Sums nsum interleaved per-wave partials in a fixed order: thread t adds
-// waves t, t+256, ... in increasing order, then a fixed binary tree.
-__global__ __launch_bounds__(256) void k_reduce_wsum(const double *__restrict__ wsum, int64_t waves,
-                                                     int nsum, double *__restrict__ out) {
+// Sums nsum interleaved per-wave partials in a fixed order.  Stage 1: block c
+// takes a contiguous run of waves; thread t adds waves t, t+256, ... of the run
+// in increasing order, then a fixed binary tree; stage 2 does the same over
+// the stage-1 sums in one block.
+constexpr int WSUM_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void k_reduce_wsum(const double *__restrict__ wsum,
+                                                     int64_t waves, int nsum, int64_t run,
+                                                     double *__restrict__ out) {
   __shared__ double sh[256];
+  const int64_t w0 = (int64_t)blockIdx.x * run;
+  int64_t w1 = w0 + run;
+  if (w1 > waves) w1 = waves;
   for (int c = 0; c < nsum; ++c) {
     double s = 0.0;
-    for (int64_t w = threadIdx.x; w < waves; w += 256) s += wsum[w * nsum + c];
+    for (int64_t w = w0 + threadIdx.x; w < w1; w += 256) s += wsum[w * nsum + c];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
       if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[c] = sh[0];
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * nsum + c] = sh[0];
     __syncthreads();
   }
 }
 
-hipError_t launch_reduce_wsum(const double *wsum, int64_t waves, int nsum, double *out,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_wsum, dim3(1), dim3(256), 0, s, wsum, waves, nsum, out);
+hipError_t launch_reduce_wsum(const double *wsum, int64_t waves, int nsum, double *tmp,
+                              double *out, hipStream_t s) {
+  int64_t nb = (waves + 1023) / 1024;   // >= 1024 waves per stage-1 block
+  if (nb > WSUM_BLOCKS) nb = WSUM_BLOCKS;
+  if (nb <= 1) {
+    hipLaunchKernelGGL(k_reduce_wsum, dim3(1), dim3(256), 0, s, wsum, waves, nsum, waves, out);
+    return hipGetLastError();
+  }
+  const int64_t run = (waves + nb - 1) / nb;
+  nb = (waves + run - 1) / run;
+  hipLaunchKernelGGL(k_reduce_wsum, dim3((unsigned)nb), dim3(256), 0, s, wsum, waves, nsum, run,
+                     tmp);
+  hipLaunchKernelGGL(k_reduce_wsum, dim3(1), dim3(256), 0, s, (const double *)tmp, nb, nsum, nb,
+                     out);
   return hipGetLastError();
 }
 
 // ============================================================================ tall-skinny Gram
-// part[w][a][b] = sum over the rows of wave w of X[r, :a]^T Y[r, :b]; then
-// out = sum over waves in wave order.  Lane l of a wave owns output column
-// j = 64*blockIdx.z + l and up to IA output rows i0..i0+IA-1; per data row it
-// loads one element of Y (coalesced across lanes) and the IA values of X,
-// which are the same for every lane (uniform loads).  Reads X and Y once.
-template <typename T, int IA>
+// out[a x b] = X[N x a]^T Y[N x b] with FP64 matrix cores (16x16x4 FP64 MFMA).
+// Row block c of the grid covers rows [c rpb, (c+1) rpb); blockIdx.y picks a
+// group of up to 4 x 4 output tiles of 16 x 16.  The four waves of a block
+// take the block's 4-row steps in turn; each lane loads its fragment values
+// straight from memory: lane l holds X[r + l/16][16 t + l%16] (A operand,
+// k = l/16) and Y[r + l/16][16 u + l%16] (B operand), so one load covers four
+// rows x 128 bytes.  The waves' accumulators are added in wave order through
+// LDS into part[c][a][b]; k_gram_reduce then adds the row blocks in order.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_gram(int64_t N, int a, const T *__restrict__ X, int ldx,
                                               int b, const T *__restrict__ Y, int ldy,
-                                              int64_t rows_per_wave, int64_t nwaves,
-                                              double *__restrict__ part) {
-  const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int i0 = blockIdx.y * IA;
-  const int j = blockIdx.z * 64 + lane;
-  if (w >= nwaves) return;
-  const int64_t r0 = w * rows_per_wave;
-  const int64_t r1 = (r0 + rows_per_wave < N) ? r0 + rows_per_wave : N;
-  const int ia = (a - i0) < IA ? (a - i0) : IA;
-  const bool on = j < b;
-  double acc[IA];
+                                              int64_t rpb, double *__restrict__ part) {
+  __shared__ double red[4][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int TA = (a + 15) / 16, TB = (b + 15) / 16, ngj = (TB + 3) / 4;
+  const int ta0 = 4 * (blockIdx.y / ngj), tb0 = 4 * (blockIdx.y % ngj);
+  const int nta = (TA - ta0) < 4 ? (TA - ta0) : 4, ntb = (TB - tb0) < 4 ? (TB - tb0) : 4;
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r1 = (r0 + rpb) < N ? (r0 + rpb) : N;
+  const int kr = lane / 16, cl = lane % 16;
+  d4_t acc[4][4];
 #pragma unroll
-  for (int i = 0; i < IA; ++i) acc[i] = 0.0;
-  int64_t r = r0;
-  for (; r + 2 <= r1; r += 2) {
-    const double y0 = on ? (double)Y[r * ldy + j] : 0.0;
-    const double y1 = on ? (double)Y[(r + 1) * ldy + j] : 0.0;
-    const T *x0 = X + r * ldx + i0, *x1 = X + (r + 1) * ldx + i0;
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int i = 0; i < IA; ++i)
-      if (i < ia) acc[i] += (double)x0[i] * y0 + (double)x1[i] * y1;
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = r0 + 4 * wave; r < r1; r += 16) {
+    const int64_t row = r + kr;
+    const bool rv = row < r1;
+    double av[4], bv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = 16 * (ta0 + i) + cl;
+      av[i] = (rv && i < nta && c < a) ? (double)X[row * ldx + c] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 16 * (tb0 + j) + cl;
+      bv[j] = (rv && j < ntb && c < b) ? (double)Y[row * ldy + c] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (i < nta && j < ntb)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
   }
-  if (r < r1) {
-    const double y0 = on ? (double)Y[r * ldy + j] : 0.0;
-    const T *x0 = X + r * ldx + i0;
+  // D layout (FP64 16x16x4): register v of lane l holds row 4 v + l/16, column l % 16
 #pragma unroll
-    for (int i = 0; i < IA; ++i)
-      if (i < ia) acc[i] += (double)x0[i] * y0;
-  }
-  if (on)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int i = 0; i < IA; ++i)
-      if (i < ia) part[(w * a + i0 + i) * b + j] = acc[i];
+    for (int j = 0; j < 4; ++j) {
+      if (i < nta && j < ntb) {
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wave][4 * lane + v] = acc[i][j][v];
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double s = ((red[0][4 * lane + v] + red[1][4 * lane + v]) + red[2][4 * lane + v]) +
+                             red[3][4 * lane + v];
+            const int oi = 16 * (ta0 + i) + 4 * v + kr, oj = 16 * (tb0 + j) + cl;
+            if (oi < a && oj < b) part[((int64_t)blockIdx.x * a + oi) * b + oj] = s;
+          }
+        }
+      }
+    }
 }
 
-__global__ void k_gram_reduce(int64_t nchunks, int64_t ab, const double *__restrict__ part,
-                              double *__restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ab) return;
+// out[e] = sum over row blocks c (in order) of part[c][e]: 64 elements per
+// block, four lanes per element take blocks c = g, g+4, ... then add in order.
+__global__ __launch_bounds__(256) void k_gram_reduce(int64_t nchunks, int64_t ab,
+                                                     const double *__restrict__ part,
+                                                     double *__restrict__ out) {
+  __shared__ double sh[4][64];
+  const int el = threadIdx.x % 64, g = threadIdx.x / 64;
+  const int64_t e = (int64_t)blockIdx.x * 64 + el;
   double s = 0.0;
-  for (int64_t c = 0; c < nchunks; ++c) s += part[c * ab + e];
-  out[e] = s;
+  if (e < ab) {
+#pragma unroll 8
+    for (int64_t c = g; c < nchunks; c += 4) s += part[c * ab + e];
+  }
+  sh[g][el] = s;
+  __syncthreads();
+  if (g == 0 && e < ab) out[e] = ((sh[0][el] + sh[1][el]) + sh[2][el]) + sh[3][el];
 }
 
 template <typename T>
@@ -728,25 +783,20 @@ hipError_t launch_gram(int64_t N, int a, const T *X, int ldx, int b, const T *Y,
                        double *part, int64_t part_cap, double *out, hipStream_t s) {
   const int64_t ab = (int64_t)a * b;
   if (ab == 0) return hipSuccess;
-  int64_t nwaves = (N + 63) / 64;            // >= 64 rows per wave
-  if (nwaves > 2048) nwaves = 2048;
-  if (nwaves < 1) nwaves = 1;
-  if (nwaves * ab > part_cap) nwaves = part_cap / ab;
-  if (nwaves < 1) return hipErrorInvalidValue;
-  const int64_t rpw = N > 0 ? (N + nwaves - 1) / nwaves : 1;
-  nwaves = N > 0 ? (N + rpw - 1) / rpw : 0;
-  if (nwaves > 0) {
-    const int IA = a > 16 ? 32 : (a > 8 ? 16 : 8);
-    dim3 grid((unsigned)((nwaves + 3) / 4), (unsigned)((a + IA - 1) / IA), (unsigned)((b + 63) / 64));
-    if (IA == 32)
-      hipLaunchKernelGGL((k_gram<T, 32>), grid, dim3(256), 0, s, N, a, X, ldx, b, Y, ldy, rpw, nwaves, part);
-    else if (IA == 16)
-      hipLaunchKernelGGL((k_gram<T, 16>), grid, dim3(256), 0, s, N, a, X, ldx, b, Y, ldy, rpw, nwaves, part);
-    else
-      hipLaunchKernelGGL((k_gram<T, 8>), grid, dim3(256), 0, s, N, a, X, ldx, b, Y, ldy, rpw, nwaves, part);
-  }
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ab + 255) / 256)), dim3(256), 0, s, nwaves, ab,
-                     part, out);
+  const int TA = (a + 15) / 16, TB = (b + 15) / 16;
+  const int ny = ((TA + 3) / 4) * ((TB + 3) / 4);
+  int64_t nx = (N + 255) / 256;                 // >= 256 rows per block
+  const int64_t xmax = (1024 + ny - 1) / ny;    // about 1024 blocks in all
+  if (nx > xmax) nx = xmax;
+  if (nx * ab > part_cap) nx = part_cap / ab;
+  if (nx < 1) nx = 1;
+  if (nx * ab > part_cap) return hipErrorInvalidValue;
+  const int64_t rpb = N > 0 ? ((N + nx - 1) / nx + 3) / 4 * 4 : 4;
+  nx = N > 0 ? (N + rpb - 1) / rpb : 1;
+  hipLaunchKernelGGL((k_gram<T>), dim3((unsigned)nx, (unsigned)ny), dim3(256), 0, s, N, a, X, ldx,
+                     b, Y, ldy, rpb, part);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ab + 63) / 64)), dim3(256), 0, s, nx, ab,
+                     (const double *)part, out);
   return hipGetLastError();
 }
 
