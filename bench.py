@@ -17,7 +17,6 @@ cpu_baseline = the CPU oracle's residual + product pair on the same data.
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -45,8 +44,8 @@ def traffic_for(kernel_symbol, workload):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2204_14067_amd", "csrc", "kernels.hip"), "rb").read()
-    if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+    from paper_2204_14067_amd.build import kernel_sources_sha256
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -262,28 +261,41 @@ def serving(bmg, synth, dev, count):
     return out
 
 
-def time_to_tol(bmg, synth, dev):
+def time_to_tol(bmg, synth, dev, seeds=(11, 12, 13, 14, 15)):
     """Full solves of the 1000 x 1500 workload (|Omega| = 50,000, lambda = 0.5,
     k0 = 8) to relative optimality residual 1e-6 in FP64, FP32 and BF16 (BF16:
-    FP64 refresh every 5 outer iterations, whose PG steps gather FP32)."""
-    from oracle import core
+    FP64 refresh every 5 outer iterations, whose PG steps gather FP32), one per
+    algorithm seed; median and interquartile range of the wall time.  Each
+    solution's objective is evaluated in FP64 by the library (bmg_objective on
+    an FP64 instance of the problem) and compared with the certified optimum
+    stored in tests/golden/small_uniform.json."""
+    import numpy as np
     p = synth.small_uniform()
-    out = {"workload": "small_uniform 1000x1500 nnz=50000 lambda=0.5 k0=8", "tol": 1e-6}
+    out = {"workload": "small_uniform 1000x1500 nnz=50000 lambda=0.5 k0=8", "tol": 1e-6,
+           "seeds": list(seeds)}
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", "small_uniform.json")))
-    for prec, tol in (("fp64", 1e-6), ("fp32", 1e-6), ("bf16", 1e-6)):
-        prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n,
-                                     k_cap=128 if prec == "fp64" else 192, precision=prec,
+    judge = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=256, precision="fp64",
+                                  device=dev)
+    for prec in ("fp64", "fp32", "bf16"):
+        # intermediate prox outputs can reach rank ~130 on the way to the rank-91 optimum
+        prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=256, precision=prec,
                                      device=dev)
-        prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=tol, seed=11, max_iter=2)   # warm caches
-        t0 = time.perf_counter()
-        W, H, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=tol, seed=11, max_iter=1000)
-        dt = time.perf_counter() - t0
-        Wn, Hn = W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k]
-        F64 = core.objective(p, Wn, Hn, p.lam)
-        out[prec] = {"seconds": round(dt, 4), "iters": r["iters"], "rank": k, "tol": tol,
-                     "converged": r["status"] == 0, "residual": r["residual"],
-                     "F": F64, "rel_err_vs_oracle_optimum": (F64 - golden["F"]) / golden["F"]}
-        log("time-to-tol %s: %.3fs, %d iters, k=%d" % (prec, dt, r["iters"], k))
+        prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=seeds[0], max_iter=2)   # warm caches
+        secs, errs, iters, ranks, conv = [], [], [], [], []
+        for sd in seeds:
+            t0 = time.perf_counter()
+            W, H, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=sd, max_iter=1000)
+            secs.append(time.perf_counter() - t0)
+            F64 = judge.bmg_objective(W, H, k, p.lam)
+            errs.append((F64 - golden["F"]) / golden["F"])
+            iters.append(r["iters"]); ranks.append(k); conv.append(r["status"] == 0)
+        q1, med, q3 = (float(v) for v in np.percentile(secs, [25, 50, 75]))
+        out[prec] = {"seconds_median": round(med, 4), "seconds_iqr": [round(q1, 4), round(q3, 4)],
+                     "iters": iters, "rank": ranks, "converged": all(conv),
+                     "max_rel_err_vs_oracle_optimum": max(abs(x) for x in errs)}
+        log("time-to-tol %s: median %.3fs over %d seeds, iters %s" % (prec, med, len(seeds), iters))
+    for prec in ("fp32", "bf16"):
+        out[prec]["speedup_vs_fp64"] = round(out["fp64"]["seconds_median"] / out[prec]["seconds_median"], 3)
     return out
 
 

@@ -102,7 +102,8 @@ typedef struct {
 void bmg_options_default(bmg_options *opt);
 
 /* Bytes of device workspace a problem of this shape needs when the rank may
- * reach k_cap (subspace blocks hold up to 2*k_cap+1 columns).  (host) out. */
+ * reach k_cap (subspace blocks hold up to 2*k_cap+1 columns).  k_cap is at most
+ * 256 in BMG_FP64 and 512 in BMG_FP32 / BMG_BF16 (BMG_EINVAL beyond).  (host) out. */
 bmg_status bmg_workspace_size(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_precision prec,
                               size_t *bytes);
 

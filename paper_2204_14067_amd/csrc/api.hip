@@ -64,7 +64,7 @@ struct Layout {
   size_t pc_short, pc_long, pc_lp0, pc_prow, pc_pbeg, pc_pend, pc_pord;
   size_t wsum, wpart, partial, result, gram_part, small;
   size_t g_W, g_H, g_U, g_Y, d_W64, d_H64, d_R64;  // BF16 mode: shadows and FP64 refresh
-  int64_t max_long, max_pieces, wsum_cap, gram_cap;
+  int64_t max_long, max_pieces, piece_bytes, wsum_cap, gram_cap;
   // scratch region (setup sort / solver blocks overlap)
   size_t scratch;
   size_t s_keys_out, s_vals_in, s_rid, s_temp, s_temp_bytes;
@@ -123,7 +123,13 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_prec
   L.pc_pord = take(4 * L.max_pieces);
   L.wsum = take(16 * L.wsum_cap);
   L.wpart = take(16 * 256);
-  L.partial = take((size_t)L.max_pieces * 1024);
+  {
+    // widest partial row of any pass slice (padded to whole lane-group chunks)
+    const int es = prec == BMG_FP64 ? 8 : 4;
+    const int wmax = std::min(L.qmax, prec == BMG_FP64 ? max_width<double>() : max_width<float>());
+    L.piece_bytes = (int64_t)wmax * es <= 1024 ? 1024 : 2048;
+  }
+  L.partial = take((size_t)L.max_pieces * L.piece_bytes);
   L.result = take(8 * 64);
   L.gram_part = take(8 * L.gram_cap);
   L.small = take(8 * 9 * (size_t)L.qld * L.qld);
@@ -250,7 +256,7 @@ struct bmg_problem {
     sc.wsum = wsum;
     sc.wpart = wpart;
     sc.partial = partial;
-    sc.partial_bytes = (int64_t)L.max_pieces * 1024;
+    sc.partial_bytes = (int64_t)L.max_pieces * L.piece_bytes;
     sc.result = result;
     return sc;
   }

@@ -123,7 +123,7 @@ hipError_t launch_check_csr(int64_t m, int64_t n, const int64_t *row_ptr, const 
 
 // Widest slice one launch handles for element type T.
 // (8 lanes x 16 bytes per chunk, at most 8 chunks: 128 doubles / 256 floats)
-template <typename T> constexpr int max_width() { return 64 * (16 / (int)sizeof(T)); }
+template <typename T> constexpr int max_width() { return 128 * (16 / (int)sizeof(T)); }
 
 }  // namespace bmg
 

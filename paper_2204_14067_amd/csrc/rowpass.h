@@ -1,0 +1,639 @@
+// Row kernels of the sparse passes (gfx950, wave64) of the BM-Global
+// matrix-completion hot path, and their launchers.  Included by one source
+// per element type pair (pass_f64.hip, pass_f32.hip, pass_bf16.hip).
+//
+// Sparse passes over Omega are memory-bound (the paper's own observation on
+// the subspace products, Suppl. A.1.6): per stored entry they stream a 4-byte
+// index and one value and gather one row of a dense factor.  Layout choice:
+// a group of G lanes owns one row of Omega; each lane holds a 16-byte slice
+// (2 doubles / 4 floats) of the k-vectors, so one gathered factor row is a
+// single fully-used cache-line access, dot products need log2(G) butterfly
+// steps inside the group, and the accumulated output row never leaves
+// registers until the row ends.  (Index/value streams use ordinary loads:
+// measured on the 1e8-entry workload, non-temporal loads were up to 30%
+// slower on the column-oriented passes and no faster elsewhere.)
+//
+// Determinism: no floating-point atomics anywhere.  Scalar sums are written
+// per wave and added in a fixed order by a two-stage reduction; long rows are
+// split into fixed pieces whose partial rows are added in piece order.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "bmg_internal.h"
+
+namespace bmg {
+
+// Elements per 16-byte lane slice of the gathered type.
+template <typename TG> struct VT { static constexpr int V = 16 / (int)sizeof(TG); };
+
+// BF16 storage (upper half of an FP32), rounded to nearest even.
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+template <typename To, typename From> __device__ __forceinline__ To cvt(From x) { return (To)x; }
+template <> __device__ __forceinline__ float cvt<float, bf16_t>(bf16_t x) { return bf2f(x); }
+template <> __device__ __forceinline__ double cvt<double, bf16_t>(bf16_t x) { return (double)bf2f(x); }
+template <> __device__ __forceinline__ bf16_t cvt<bf16_t, float>(float x) { return f2bf(x); }
+template <> __device__ __forceinline__ bf16_t cvt<bf16_t, double>(double x) { return f2bf((float)x); }
+
+#ifndef BMG_NT_STREAMS
+#define BMG_NT_STREAMS 0
+#endif
+template <typename T>
+__device__ __forceinline__ T nt_load(const T *p) {
+#if BMG_NT_STREAMS
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
+// Load V consecutive elements row[f0 .. f0+V) of memory type TM into T
+// registers, with per-element bound lim (elements at or beyond lim read as 0
+// and are never touched).
+template <typename T, typename TM, int V>
+__device__ __forceinline__ void ldv(const TM *__restrict__ row, int f0, int lim, T (&x)[V]) {
+  if (f0 + V <= lim) {
+    if constexpr (sizeof(TM) == 8 && V == 2) {
+      const double2 v = *reinterpret_cast<const double2 *>(row + f0);
+      x[0] = (T)v.x; x[1] = (T)v.y;
+      return;
+    } else if constexpr (sizeof(TM) == 4 && (V == 4 || V == 8)) {
+#pragma unroll
+      for (int h = 0; h < V / 4; ++h) {
+        const float4 v = *reinterpret_cast<const float4 *>(row + f0 + 4 * h);
+        x[4 * h] = (T)v.x; x[4 * h + 1] = (T)v.y; x[4 * h + 2] = (T)v.z; x[4 * h + 3] = (T)v.w;
+      }
+      return;
+    } else if constexpr (sizeof(TM) == 2 && V == 8) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(row + f0);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        x[2 * h] = (T)__uint_as_float(w[h] << 16);
+        x[2 * h + 1] = (T)__uint_as_float(w[h] & 0xffff0000u);
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < V; ++e) x[e] = (f0 + e < lim) ? cvt<T, TM>(row[f0 + e]) : T(0);
+}
+
+template <typename T, typename TM, int V>
+__device__ __forceinline__ void stv(TM *__restrict__ row, int f0, int lim, const T (&x)[V]) {
+  if (f0 + V <= lim) {
+    if constexpr (sizeof(TM) == 8 && sizeof(T) == 8 && V == 2) {
+      *reinterpret_cast<double2 *>(row + f0) = make_double2(x[0], x[1]);
+      return;
+    } else if constexpr (sizeof(TM) == 4 && sizeof(T) == 4 && (V == 4 || V == 8)) {
+#pragma unroll
+      for (int h = 0; h < V / 4; ++h)
+        *reinterpret_cast<float4 *>(row + f0 + 4 * h) =
+            make_float4(x[4 * h], x[4 * h + 1], x[4 * h + 2], x[4 * h + 3]);
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < V; ++e)
+    if (f0 + e < lim) row[f0 + e] = cvt<TM, T>(x[e]);
+}
+
+// Butterfly sum inside a lane group of G (xor offsets 1 .. G/2).
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// Sum across the 64/G groups of a wave (xor offsets G .. 32).
+template <int G, typename T>
+__device__ __forceinline__ T slot_sum(T v) {
+#pragma unroll
+  for (int o = G; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+#ifndef BMG_UNROLL
+#define BMG_UNROLL 4
+#endif
+constexpr int UNROLL = BMG_UNROLL;  // entries in flight per lane group
+constexpr int WAVES_PER_BLOCK = 4;
+
+__host__ __device__ inline int64_t short_waves(const Plan &pl, int G) {
+  const int S = 64 / G;
+  return (pl.n_short + S - 1) / S;
+}
+
+// Grid of a row-kernel launch: the short-row waves first, then, from a block
+// index that is a multiple of 8, the piece waves.  Blocks are dealt to the 8
+// XCDs in turn; piece block bb takes launch slots from run (bb % 8) of the
+// piece order, so each XCD works through a contiguous run of column ranges.
+__host__ __device__ inline int64_t piece_block0(const Plan &pl, int G) {
+  const int64_t sb = (short_waves(pl, G) + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  return (sb + 7) / 8 * 8;
+}
+__host__ __device__ inline int64_t piece_blocks(const Plan &pl) {
+  return ((pl.n_pieces + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK + 7) / 8 * 8;
+}
+__host__ __device__ inline int64_t grid_blocks(const Plan &pl, int G) {
+  int64_t b = pl.n_pieces == 0
+                  ? (short_waves(pl, G) + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK
+                  : piece_block0(pl, G) + piece_blocks(pl);
+  return b > 0 ? b : 1;
+}
+// Work of the calling wave: 0 = short-row wave w, 1 = piece w, -1 = none.
+__device__ __forceinline__ int wave_work(const Plan &pl, int G, int64_t &w) {
+  const int wave = threadIdx.x >> 6;
+  const int64_t b = blockIdx.x, pb0 = piece_block0(pl, G);
+  if (b < pb0) {
+    w = b * WAVES_PER_BLOCK + wave;
+    return w < short_waves(pl, G) ? 0 : -1;
+  }
+  const int64_t nb8 = piece_blocks(pl) / 8, bb = b - pb0;
+  const int64_t slot = ((bb % 8) * nb8 + bb / 8) * WAVES_PER_BLOCK + wave;
+  if (slot >= pl.n_pieces) return -1;
+  w = pl.piece_ord[slot];
+  return 1;
+}
+
+// ============================================================================ lane-group row access
+// A lane group of G lanes owns one row of Omega.  A dense k-vector is split in
+// C chunks of G*V consecutive columns (one 128-byte line for G = 8 in FP64);
+// lane `sub` holds columns c*G*V + sub*V .. +V-1 of chunk c.
+template <typename T, typename TG, int G, int C>
+struct Row {
+  static constexpr int V = VT<TG>::V;
+  static constexpr int CW = G * V;       // columns per chunk
+  static constexpr int WB = CW * C;      // columns covered
+  T v[C][V];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < V; ++e) v[c][e] = T(0);
+  }
+  template <typename TM>
+  __device__ __forceinline__ void load(const TM *__restrict__ row, int sub, int lim) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) ldv<T, TM, V>(row, c * CW + sub * V, lim, v[c]);
+  }
+  template <typename TM>
+  __device__ __forceinline__ void store(TM *__restrict__ row, int sub, int lim) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c) stv<T, TM, V>(row, c * CW + sub * V, lim, v[c]);
+  }
+  __device__ __forceinline__ T dot(const Row &o) const {
+    T s = T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < V; ++e) s += v[c][e] * o.v[c][e];
+    return s;
+  }
+  __device__ __forceinline__ void axpy(T a, const Row &o) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < V; ++e) v[c][e] += a * o.v[c][e];
+  }
+};
+
+// ============================================================================ fused residual + product
+// For entries p, p+step, ... (n of them) of one row:
+//   r = x . y_j - a_p ;  acc += r y_j ;  ss += r^2   (ss on the group leader only)
+template <typename T, typename TG, int G, int C>
+__device__ __forceinline__ void grad_block(const Plan &pl, const T *__restrict__ a,
+                                           const TG *__restrict__ Y, int ldy, int k, int sub,
+                                           const Row<T, TG, G, C> &x, Row<T, TG, G, C> &acc, double &ss,
+                                           bool leader, int64_t p, int64_t step, int n) {
+  int j[UNROLL];
+  T av[UNROLL];
+  Row<T, TG, G, C> y[UNROLL];
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    if (u < n) {
+      j[u] = nt_load(pl.idx + p + u * step);
+      av[u] = nt_load(a + p + u * step);
+    } else {
+      j[u] = -1;
+      av[u] = T(0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    if (j[u] >= 0) y[u].load(Y + (int64_t)j[u] * ldy, sub, k);
+    else y[u].zero();
+  }
+  T d[UNROLL];
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) d[u] = x.dot(y[u]);
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) d[u] = group_sum<G>(d[u]);
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    if (u < n) {
+      const T r = d[u] - av[u];
+      acc.axpy(r, y[u]);
+      if (leader) ss += (double)r * (double)r;
+    }
+  }
+}
+
+template <typename T, typename TG, int G, int C>
+__global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
+                                              const T *__restrict__ X, int ldx,
+                                              const TG *__restrict__ Y, int ldy, int k, double lam,
+                                              T *__restrict__ Out, int ldo,
+                                              T *__restrict__ partial, double *__restrict__ wsum) {
+  using RowT = Row<T, TG, G, C>;
+  constexpr int S = 64 / G, WB = RowT::WB;
+  const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
+  const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+  int64_t w = 0;
+  const int kind = wave_work(pl, G, w);
+  const bool leader = (sub == 0);
+  double ss = 0.0;
+  RowT acc;
+  acc.zero();
+  if (kind == 0) {
+    const int64_t ri = w * S + slot;
+    if (ri < pl.n_short) {
+      const int row = pl.short_rows[ri];
+      RowT x;
+      x.load(X + (int64_t)row * ldx, sub, k);
+      const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
+      for (int64_t p = beg; p < end; p += UNROLL) {
+        const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
+        grad_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, acc, ss, leader, p, 1, n);
+      }
+      acc.axpy((T)lam, x);
+      acc.store(Out + (int64_t)row * ldo, sub, k);
+    }
+  } else if (kind == 1) {
+    const int64_t pc = w;
+    const int row = pl.piece_row[pc];
+    const int64_t beg = pl.piece_beg[pc], end = pl.piece_end[pc];
+    RowT x;
+    x.load(X + (int64_t)row * ldx, sub, k);
+    for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
+      const int64_t rem = (end - p + S - 1) / S;
+      const int n = (int)(rem < UNROLL ? rem : UNROLL);
+      grad_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, acc, ss, leader, p, S, n);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < RowT::V; ++e) acc.v[c][e] = slot_sum<G>(acc.v[c][e]);
+    if (slot == 0) acc.store(partial + pc * WB, sub, WB);
+  }
+  ss = wave_sum(ss);
+  if (lane == 0) wsum[gw] = ss;
+}
+
+// Long rows: Out_row = sum of piece partials (piece order) + lam * x_row.
+template <typename T, typename TG, int G, int C>
+__global__ __launch_bounds__(256) void k_grad_fix(Plan pl, const T *__restrict__ partial,
+                                                  const T *__restrict__ X, int ldx, int k,
+                                                  double lam, T *__restrict__ Out, int ldo) {
+  using RowT = Row<T, TG, G, C>;
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
+  if (g >= pl.n_long) return;
+  const int row = pl.long_rows[g];
+  RowT acc, t;
+  acc.zero();
+  for (int pc = pl.long_p0[g]; pc < pl.long_p0[g + 1]; ++pc) {
+    t.load(partial + (int64_t)pc * RowT::WB, sub, RowT::WB);
+    acc.axpy(T(1), t);
+  }
+  RowT x;
+  x.load(X + (int64_t)row * ldx, sub, k);
+  acc.axpy((T)lam, x);
+  acc.store(Out + (int64_t)row * ldo, sub, k);
+}
+
+// ============================================================================ sampled residual
+template <typename T, typename TG, int G, int C>
+__device__ __forceinline__ void sddmm_block(const Plan &pl, const T *__restrict__ a,
+                                            const TG *__restrict__ Y, int ldy, int k, int sub,
+                                            const Row<T, TG, G, C> &x, T *__restrict__ R, double &ss,
+                                            double &sx, bool leader, int64_t p, int64_t step,
+                                            int n) {
+  int j[UNROLL];
+  T av[UNROLL];
+  Row<T, TG, G, C> y[UNROLL];
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    if (u < n) {
+      j[u] = nt_load(pl.idx + p + u * step);
+      av[u] = a ? nt_load(a + p + u * step) : T(0);
+    } else {
+      j[u] = -1;
+      av[u] = T(0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    if (j[u] >= 0) y[u].load(Y + (int64_t)j[u] * ldy, sub, k);
+    else y[u].zero();
+  }
+  T d[UNROLL];
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) d[u] = group_sum<G>(x.dot(y[u]));
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    if (u < n && leader) {
+      const T r = d[u] - av[u];
+      if (R) R[p + u * step] = r;
+      ss += (double)r * (double)r;
+      sx += (double)r * (double)d[u];
+    }
+  }
+}
+
+template <typename T, typename TG, int G, int C>
+__global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
+                                               const T *__restrict__ X, int ldx,
+                                               const TG *__restrict__ Y, int ldy, int k,
+                                               T *__restrict__ R, double *__restrict__ wsum) {
+  using RowT = Row<T, TG, G, C>;
+  constexpr int S = 64 / G;
+  const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
+  const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+  int64_t w = 0;
+  const int kind = wave_work(pl, G, w);
+  const bool leader = (sub == 0);
+  double ss = 0.0, sx = 0.0;
+  if (kind == 0) {
+    const int64_t ri = w * S + slot;
+    if (ri < pl.n_short) {
+      const int row = pl.short_rows[ri];
+      RowT x;
+      x.load(X + (int64_t)row * ldx, sub, k);
+      const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
+      for (int64_t p = beg; p < end; p += UNROLL) {
+        const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
+        sddmm_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, R, ss, sx, leader, p, 1, n);
+      }
+    }
+  } else if (kind == 1) {
+    const int64_t pc = w;
+    const int row = pl.piece_row[pc];
+    const int64_t beg = pl.piece_beg[pc], end = pl.piece_end[pc];
+    RowT x;
+    x.load(X + (int64_t)row * ldx, sub, k);
+    for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
+      const int64_t rem = (end - p + S - 1) / S;
+      const int n = (int)(rem < UNROLL ? rem : UNROLL);
+      sddmm_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, R, ss, sx, leader, p, S, n);
+    }
+  }
+  ss = wave_sum(ss);
+  sx = wave_sum(sx);
+  if (lane == 0) {
+    wsum[2 * gw] = ss;
+    wsum[2 * gw + 1] = sx;
+  }
+}
+
+// ============================================================================ sparse x dense
+template <typename T, typename TG, int G, int C>
+__device__ __forceinline__ void spmm_block(const Plan &pl, const T *__restrict__ Sv,
+                                           const TG *__restrict__ B, int ldb, int wq, int sub,
+                                           Row<T, TG, G, C> &acc, int64_t p, int64_t step, int n) {
+  int j[UNROLL];
+  T sv[UNROLL];
+  Row<T, TG, G, C> b[UNROLL];
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    if (u < n) {
+      j[u] = nt_load(pl.idx + p + u * step);
+      sv[u] = nt_load(Sv + p + u * step);
+    } else {
+      j[u] = -1;
+      sv[u] = T(0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    if (j[u] >= 0) b[u].load(B + (int64_t)j[u] * ldb, sub, wq);
+    else b[u].zero();
+  }
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) acc.axpy(sv[u], b[u]);
+}
+
+// acc <- coef * acc + x_row . M[:, slice]
+template <typename T, typename TG, int G, int C>
+__device__ __forceinline__ void lowrank_epilogue(Row<T, TG, G, C> &acc, double coef,
+                                                 const T *__restrict__ xr, int kx,
+                                                 const T *__restrict__ M, int ldm, int wq,
+                                                 int sub) {
+  using RowT = Row<T, TG, G, C>;
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int e = 0; e < RowT::V; ++e) acc.v[c][e] *= (T)coef;
+  for (int r = 0; r < kx; ++r) {
+    RowT mv;
+    mv.load(M + (int64_t)r * ldm, sub, wq);
+    acc.axpy(xr[r], mv);
+  }
+}
+
+template <typename T, typename TG, int G, int C>
+__global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
+                                              const TG *__restrict__ B, int ldb, int wq,
+                                              double coef, const T *__restrict__ X, int ldx,
+                                              int kx, const T *__restrict__ M, int ldm,
+                                              T *__restrict__ Cm, int ldc,
+                                              T *__restrict__ partial) {
+  using RowT = Row<T, TG, G, C>;
+  constexpr int S = 64 / G, WB = RowT::WB;
+  const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
+  int64_t w = 0;
+  const int kind = wave_work(pl, G, w);
+  RowT acc;
+  acc.zero();
+  if (kind == 0) {
+    const int64_t ri = w * S + slot;
+    if (ri < pl.n_short) {
+      const int row = pl.short_rows[ri];
+      const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
+      for (int64_t p = beg; p < end; p += UNROLL) {
+        const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
+        spmm_block<T, TG, G, C>(pl, Sv, B, ldb, wq, sub, acc, p, 1, n);
+      }
+      lowrank_epilogue<T, TG, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
+      acc.store(Cm + (int64_t)row * ldc, sub, wq);
+    }
+  } else if (kind == 1) {
+    const int64_t pc = w;
+    const int64_t beg = pl.piece_beg[pc], end = pl.piece_end[pc];
+    for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
+      const int64_t rem = (end - p + S - 1) / S;
+      const int n = (int)(rem < UNROLL ? rem : UNROLL);
+      spmm_block<T, TG, G, C>(pl, Sv, B, ldb, wq, sub, acc, p, S, n);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < RowT::V; ++e) acc.v[c][e] = slot_sum<G>(acc.v[c][e]);
+    if (slot == 0) acc.store(partial + pc * WB, sub, WB);
+  }
+}
+
+template <typename T, typename TG, int G, int C>
+__global__ __launch_bounds__(256) void k_spmm_fix(Plan pl, const T *__restrict__ partial,
+                                                  double coef, const T *__restrict__ X, int ldx,
+                                                  int kx, const T *__restrict__ M, int ldm, int wq,
+                                                  T *__restrict__ Cm, int ldc) {
+  using RowT = Row<T, TG, G, C>;
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
+  if (g >= pl.n_long) return;
+  const int row = pl.long_rows[g];
+  RowT acc, t;
+  acc.zero();
+  for (int pc = pl.long_p0[g]; pc < pl.long_p0[g + 1]; ++pc) {
+    t.load(partial + (int64_t)pc * RowT::WB, sub, RowT::WB);
+    acc.axpy(T(1), t);
+  }
+  lowrank_epilogue<T, TG, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
+  acc.store(Cm + (int64_t)row * ldc, sub, wq);
+}
+
+// ============================================================================ launchers
+// Lane group G and chunk count C for a width w (V elements of the gathered type
+// per lane): G = 2 or 4 for narrow rows (one partial line), G = 8 with
+// C = ceil(w / (8 V)) line-sized chunks up to 8 chunks, beyond that G = 16 with
+// C = ceil(w / (16 V)) two-line chunks.
+struct GC {
+  int G, C;
+};
+static inline GC pick_gc(int width, int V) {
+  if (width <= 2 * V) return {2, 1};
+  if (width <= 4 * V) return {4, 1};
+  if (width <= 64 * V) {
+    const int c = (width + 8 * V - 1) / (8 * V);
+    return {8, c < 1 ? 1 : c};
+  }
+  const int c = (width + 16 * V - 1) / (16 * V);
+  return {16, c < 5 ? 5 : c};
+}
+// bytes of one piece's partial row for a launch of geometry gc
+template <typename T, typename TG>
+static inline int64_t partial_row_bytes(const GC &gc) {
+  return (int64_t)gc.G * VT<TG>::V * gc.C * (int64_t)sizeof(T);
+}
+
+
+#define BMG_DISPATCH_GC(gc, ...)                                                        \
+  do {                                                                                  \
+    if (gc.G == 2) { constexpr int GG = 2, CC = 1; __VA_ARGS__; }                       \
+    else if (gc.G == 4) { constexpr int GG = 4, CC = 1; __VA_ARGS__; }                  \
+    else if (gc.G == 16) switch (gc.C) {                                                \
+      case 5: { constexpr int GG = 16, CC = 5; __VA_ARGS__; } break;                    \
+      case 6: { constexpr int GG = 16, CC = 6; __VA_ARGS__; } break;                    \
+      case 7: { constexpr int GG = 16, CC = 7; __VA_ARGS__; } break;                    \
+      default: { constexpr int GG = 16, CC = 8; __VA_ARGS__; } break;                   \
+    }                                                                                   \
+    else switch (gc.C) {                                                                \
+      case 1: { constexpr int GG = 8, CC = 1; __VA_ARGS__; } break;                     \
+      case 2: { constexpr int GG = 8, CC = 2; __VA_ARGS__; } break;                     \
+      case 3: { constexpr int GG = 8, CC = 3; __VA_ARGS__; } break;                     \
+      case 4: { constexpr int GG = 8, CC = 4; __VA_ARGS__; } break;                     \
+      case 5: { constexpr int GG = 8, CC = 5; __VA_ARGS__; } break;                     \
+      case 6: { constexpr int GG = 8, CC = 6; __VA_ARGS__; } break;                     \
+      case 7: { constexpr int GG = 8, CC = 7; __VA_ARGS__; } break;                     \
+      default: { constexpr int GG = 8, CC = 8; __VA_ARGS__; } break;                    \
+    }                                                                                   \
+  } while (0)
+
+// Each launch writes one scalar slot (or pair) per wave of its grid, idle
+// waves included, and reduces them in wave order.
+template <typename T, typename TG>
+hipError_t launch_grad(const Plan &pl, const T *a, const T *X, int ldx, const TG *Y, int ldy, int k,
+                       double lam, T *Out, int ldo, PassScratch sc, int64_t *waves_out,
+                       hipStream_t s) {
+  constexpr int V = VT<TG>::V;
+  if (k > max_width<T>()) return hipErrorInvalidValue;
+  const GC gc = pick_gc(k, V);
+  if (pl.n_pieces * partial_row_bytes<T, TG>(gc) > sc.partial_bytes) return hipErrorInvalidValue;
+  const int64_t nb = grid_blocks(pl, gc.G), waves = nb * WAVES_PER_BLOCK;
+  if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
+  BMG_DISPATCH_GC(gc, {
+    hipLaunchKernelGGL((k_grad<T, TG, GG, CC>), dim3((unsigned)nb), dim3(256), 0, s, pl, a, X, ldx,
+                       Y, ldy, k, lam, Out, ldo, (T *)sc.partial, sc.wsum);
+    if (pl.n_long > 0) {
+      const int64_t thr = pl.n_long * GG;
+      hipLaunchKernelGGL((k_grad_fix<T, TG, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
+                         dim3(256), 0, s, pl, (const T *)sc.partial, X, ldx, k, lam, Out, ldo);
+    }
+  });
+  if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
+  if (waves_out) *waves_out = waves;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_wsum(sc.wsum, waves, 1, sc.wpart, sc.result, s);
+}
+
+template <typename T, typename TG>
+hipError_t launch_sddmm(const Plan &pl, const T *a, const T *X, int ldx, const TG *Y, int ldy, int k,
+                        T *R, PassScratch sc, hipStream_t s) {
+  constexpr int V = VT<TG>::V;
+  if (k > max_width<T>()) return hipErrorInvalidValue;
+  const GC gc = pick_gc(k, V);
+  const int64_t nb = grid_blocks(pl, gc.G), waves = nb * WAVES_PER_BLOCK;
+  if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
+  BMG_DISPATCH_GC(gc, {
+    hipLaunchKernelGGL((k_sddmm<T, TG, GG, CC>), dim3((unsigned)nb), dim3(256), 0, s, pl, a, X,
+                       ldx, Y, ldy, k, R, sc.wsum);
+  });
+  if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_wsum(sc.wsum, waves, 2, sc.wpart, sc.result, s);
+}
+
+template <typename T, typename TG>
+hipError_t launch_spmm(const Plan &pl, const T *Sv, const TG *B, int ldb, int q, double coef,
+                       const T *X, int ldx, int kx, const T *M, int ldm, T *Cm, int ldc,
+                       PassScratch sc, hipStream_t s) {
+  constexpr int V = VT<TG>::V;
+  const int WMAX = max_width<T>();
+  if (sc.ev0) (void)hipEventRecord(sc.ev0, s);
+  for (int c0 = 0; c0 < q; c0 += WMAX) {
+    const int wq = (q - c0) < WMAX ? (q - c0) : WMAX;
+    const GC gc = pick_gc(wq, V);
+    if (pl.n_pieces * partial_row_bytes<T, TG>(gc) > sc.partial_bytes) return hipErrorInvalidValue;
+    const int64_t nb = grid_blocks(pl, gc.G);
+    BMG_DISPATCH_GC(gc, {
+      hipLaunchKernelGGL((k_spmm<T, TG, GG, CC>), dim3((unsigned)nb), dim3(256), 0, s, pl, Sv,
+                         B + c0, ldb, wq, coef, X, ldx, kx, M ? M + c0 : M, ldm, Cm + c0, ldc,
+                         (T *)sc.partial);
+      if (pl.n_long > 0) {
+        const int64_t thr = pl.n_long * GG;
+        hipLaunchKernelGGL((k_spmm_fix<T, TG, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
+                           dim3(256), 0, s, pl, (const T *)sc.partial, coef, X, ldx, kx,
+                           M ? M + c0 : M, ldm, wq, Cm + c0, ldc);
+      }
+    });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
+  return hipSuccess;
+}
+
+}  // namespace bmg

@@ -68,11 +68,12 @@ def case(name):
 # ----------------------------------------------------------------------------- primitives
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("k", [1, 5, 16, 17, 64, 128])
+@pytest.mark.parametrize("k", [1, 5, 16, 17, 64, 128, 129, 256])
 def test_sddmm_parity(name, k):
+    """k > 128 runs 16-lane groups (FP64 rows of more than 8 cache lines)."""
     p = case(name)
     print("sddmm", name, p.m, p.n, p.nnz, "k", k, flush=True)
-    dp = to_dev(p, k_cap=128)
+    dp = to_dev(p, k_cap=128 if k <= 128 else 256)
     ld = bmg.round_ld(k)
     W, H = factors(p, k, ld, seed=k)
     R, hs = dp.bmg_sddmm(t(W), t(H), k)
@@ -109,11 +110,13 @@ def test_spmm_parity(name, q, transpose):
 
 
 @pytest.mark.parametrize("name", ["tiny", "tall_m_gt_n", "long_rows", "powerlaw"])
-def test_bm_epochs_parity(name):
+@pytest.mark.parametrize("k", [6, 150])
+def test_bm_epochs_parity(name, k):
     p = case(name)
-    k, lam = 6, 0.7
-    dp = to_dev(p, k_cap=16)
-    ld = bmg.round_ld(16)
+    lam = 0.7
+    kc = 16 if k <= 16 else 256
+    dp = to_dev(p, k_cap=kc)
+    ld = bmg.round_ld(kc)
     W, H = factors(p, k, ld, seed=3)
     Wd, Hd = t(W), t(H)
     Fbm = dp.bmg_bm_epochs(Wd, Hd, k, lam, epochs=2)
@@ -309,3 +312,45 @@ def test_netflix_shape_full_size_sampled_rows():
     for j in cols:
         sel = np.nonzero(p.col == j)[0]
         assert np.allclose(GH[j, :k], Rg[sel] @ W[prow[sel], :k], rtol=1e-10, atol=1e-9)
+
+
+def test_yahoo_shape_full_size_sampled_rows_and_fp32_step():
+    """624,961 x 1,000,990, |Omega| = 2.5e8 (capped power law, exponent 1.1):
+    FP64 sampled residual and both sparse products on sampled rows / columns
+    against the oracle on those rows only (both orientations cut long rows at
+    column ranges), then one FP32 outer iteration whose reported objective must
+    match the oracle's FP64 objective at the returned factors."""
+    p = synth.yahoo_shape()
+    k = 8
+    dp = to_dev(p, k_cap=16)
+    W, H = factors(p, k, 16, seed=9)
+    W *= 0.3; H *= 0.3
+    R, _ = dp.bmg_sddmm(t(W), t(H), k)
+    Rg = R.cpu().numpy()
+    L = np.diff(p.row_ptr)
+    rows = np.union1d(np.random.default_rng(3).choice(p.m, 32, replace=False), np.argsort(L)[-4:])
+    for i in rows:
+        a, b = p.row_ptr[i], p.row_ptr[i + 1]
+        ro = W[i, :k] @ H[p.col[a:b], :k].T - p.val[a:b]
+        assert np.allclose(Rg[a:b], ro, rtol=1e-12, atol=1e-12)
+    GW = dp.bmg_spmm(R, t(H)).cpu().numpy()
+    for i in rows:
+        a, b = p.row_ptr[i], p.row_ptr[i + 1]
+        assert np.allclose(GW[i, :k], Rg[a:b] @ H[p.col[a:b], :k], rtol=1e-10, atol=1e-9)
+    GH = dp.bmg_spmm(R, t(W), transpose=True).cpu().numpy()
+    C = np.bincount(p.col, minlength=p.n)
+    cols = np.union1d(np.random.default_rng(4).choice(p.n, 12, replace=False), np.argsort(C)[-2:])
+    sel = np.nonzero(np.isin(p.col, cols))[0]
+    prow = np.searchsorted(p.row_ptr, sel, side="right") - 1
+    for j in cols:
+        s = p.col[sel] == j
+        assert np.allclose(GH[j, :k], Rg[sel[s]] @ W[prow[s], :k], rtol=1e-10, atol=1e-9)
+    del dp, R, Rg, GW, GH
+    torch.cuda.empty_cache()
+    # one outer iteration in FP32; F is reported in FP64 from the returned factors
+    d32 = to_dev(p, k_cap=128, precision="fp32")   # one step can reach 2 k0 + 1 columns
+    Wd, Hd, kk, r = d32.bmg_solve(lam=p.lam, k_init=p.k0, max_iter=1, tol=0.0, seed=5)
+    Wn, Hn = Wd.cpu().numpy()[:, :kk], Hd.cpu().numpy()[:, :kk]
+    F_orc = core.objective(p, Wn, Hn, p.lam)
+    assert kk >= 1
+    assert abs(r["F"] - F_orc) <= 1e-5 * abs(F_orc), (r["F"], F_orc)
