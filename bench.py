@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -145,7 +145,7 @@ def main():
         "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision], "data": "synthetic",
         "config": {"workload": "%s: %dx%d, nnz=%d, capped Zipf(1.2) degrees, rank-20 truth + "
                                "noise var 0.25, lambda=20, k0=16" % (workload, p.m, p.n, p.nnz),
                    "step": "init (HMT+Nystrom) + 3 BM epochs + 1 inexact PG step + objective",

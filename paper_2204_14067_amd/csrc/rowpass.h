@@ -129,8 +129,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 constexpr int UNROLL = BMG_UNROLL;  // entries in flight per lane group
 constexpr int WAVES_PER_BLOCK = 4;
 
+// Short rows: a team of max(8, G) lanes per row, 64 / team rows per wave.
 __host__ __device__ inline int64_t short_waves(const Plan &pl, int G) {
-  const int S = 64 / G;
+  const int S = 64 / (G > 8 ? G : 8);
   return (pl.n_short + S - 1) / S;
 }
 
@@ -249,6 +250,98 @@ __device__ __forceinline__ void grad_block(const Plan &pl, const T *__restrict__
   }
 }
 
+// ============================================================================ short rows
+// A team of TL = max(8, G) lanes owns one short row.  The team loads the row's
+// indices and values TL at a time (one cache line per load instruction) and
+// hands each entry to one of its E = TL / G lane groups by a lane shuffle; each
+// group gathers and accumulates its entries (UNROLL in flight), and the groups'
+// rows are added at the end of the row.  Entry e of a chunk goes to group
+// e % E; lane e % TL of the team loaded it in load slot e / TL.
+template <int G> struct Team {
+  static constexpr int TL = G > 8 ? G : 8;              // lanes per row
+  static constexpr int E = TL / G;                      // groups per row
+  static constexpr int LPL = (UNROLL + G - 1) / G;      // loads per lane per chunk
+  static constexpr int CH = TL * LPL;                   // entries per chunk
+  static constexpr int NI = CH / E;                     // entries per group per chunk
+};
+
+enum TeamMode { TM_GRAD = 0, TM_SDDMM = 1, TM_SPMM = 2 };
+
+// GRAD: acc += r y, ss += r^2 with r = x.y - a;  SDDMM: R = r, ss += r^2,
+// sx += r (x.y);  SPMM: acc += a y.  On return every group of the team holds
+// the row's sum in acc; ss / sx are held by the group leaders.
+template <typename T, typename TG, int G, int C, int MODE>
+__device__ __forceinline__ void team_row(const Plan &pl, int row, const T *__restrict__ a,
+                                         const TG *__restrict__ Y, int ldy, int width,
+                                         const Row<T, TG, G, C> &x, Row<T, TG, G, C> &acc,
+                                         T *__restrict__ R, double &ss, double &sx, int tbase,
+                                         int tl) {
+  using TM = Team<G>;
+  using RowT = Row<T, TG, G, C>;
+  const int eg = tl / G, sub = tl % G;
+  const bool leader = (sub == 0);
+  const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
+  for (int64_t p0 = beg; p0 < end; p0 += TM::CH) {
+    int jl[TM::LPL];
+    T al[TM::LPL];
+#pragma unroll
+    for (int l = 0; l < TM::LPL; ++l) {
+      const int64_t pe = p0 + l * TM::TL + tl;
+      jl[l] = pe < end ? nt_load(pl.idx + pe) : -1;
+      al[l] = (pe < end && a) ? nt_load(a + pe) : T(0);
+    }
+    // batches stay rolled (UNROLL gathers in flight are enough); only G = 2
+    // has two load slots, and it has a single batch
+    static_assert(TM::LPL == 1 || TM::NI <= UNROLL, "load slot must be known at compile time");
+#pragma unroll 1
+    for (int i0 = 0; i0 < TM::NI; i0 += UNROLL) {
+      int j[UNROLL];
+      T av[UNROLL];
+      RowT y[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const int eo = TM::E * (i0 + u);       // chunk offset of this step's group-0 entry
+        if (i0 + u < TM::NI) {
+          const int src = tbase + eg + eo % TM::TL;
+          j[u] = __shfl(jl[TM::LPL == 1 ? 0 : eo / TM::TL], src, 64);
+          av[u] = __shfl(al[TM::LPL == 1 ? 0 : eo / TM::TL], src, 64);
+        } else {
+          j[u] = -1;
+          av[u] = T(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        if (j[u] >= 0) y[u].load(Y + (int64_t)j[u] * ldy, sub, width);
+        else y[u].zero();
+      }
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        if (MODE == TM_SPMM) {
+          acc.axpy(av[u], y[u]);
+        } else {
+          const T d = group_sum<G>(x.dot(y[u]));
+          const T res = d - av[u];
+          if (MODE == TM_GRAD) acc.axpy(j[u] >= 0 ? res : T(0), y[u]);
+          if (leader && j[u] >= 0) {
+            if (MODE == TM_SDDMM && R) R[p0 + eg + TM::E * (i0 + u)] = res;
+            ss += (double)res * (double)res;
+            if (MODE == TM_SDDMM) sx += (double)res * (double)d;
+          }
+        }
+      }
+    }
+  }
+  if (MODE != TM_SDDMM && TM::E > 1) {
+#pragma unroll
+    for (int o = G; o < TM::TL; o <<= 1)
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < RowT::V; ++e) acc.v[c][e] += __shfl_xor(acc.v[c][e], o, 64);
+  }
+}
+
 template <typename T, typename TG, int G, int C>
 __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
                                               const T *__restrict__ X, int ldx,
@@ -266,18 +359,20 @@ __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
   RowT acc;
   acc.zero();
   if (kind == 0) {
-    const int64_t ri = w * S + slot;
+    constexpr int TL = Team<G>::TL;
+    const int team = lane / TL, tl = lane % TL;
+    const int64_t ri = w * (64 / TL) + team;
     if (ri < pl.n_short) {
       const int row = pl.short_rows[ri];
       RowT x;
       x.load(X + (int64_t)row * ldx, sub, k);
-      const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
-      for (int64_t p = beg; p < end; p += UNROLL) {
-        const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
-        grad_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, acc, ss, leader, p, 1, n);
+      double sx = 0.0;
+      team_row<T, TG, G, C, TM_GRAD>(pl, row, a, Y, ldy, k, x, acc, (T *)nullptr, ss, sx,
+                                     team * TL, tl);
+      if (tl < G) {
+        acc.axpy((T)lam, x);
+        acc.store(Out + (int64_t)row * ldo, sub, k);
       }
-      acc.axpy((T)lam, x);
-      acc.store(Out + (int64_t)row * ldo, sub, k);
     }
   } else if (kind == 1) {
     const int64_t pc = w;
@@ -375,16 +470,14 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
   const bool leader = (sub == 0);
   double ss = 0.0, sx = 0.0;
   if (kind == 0) {
-    const int64_t ri = w * S + slot;
+    constexpr int TL = Team<G>::TL;
+    const int team = lane / TL, tl = lane % TL;
+    const int64_t ri = w * (64 / TL) + team;
     if (ri < pl.n_short) {
       const int row = pl.short_rows[ri];
-      RowT x;
+      RowT x, acc;
       x.load(X + (int64_t)row * ldx, sub, k);
-      const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
-      for (int64_t p = beg; p < end; p += UNROLL) {
-        const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
-        sddmm_block<T, TG, G, C>(pl, a, Y, ldy, k, sub, x, R, ss, sx, leader, p, 1, n);
-      }
+      team_row<T, TG, G, C, TM_SDDMM>(pl, row, a, Y, ldy, k, x, acc, R, ss, sx, team * TL, tl);
     }
   } else if (kind == 1) {
     const int64_t pc = w;
@@ -466,16 +559,19 @@ __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
   RowT acc;
   acc.zero();
   if (kind == 0) {
-    const int64_t ri = w * S + slot;
+    constexpr int TL = Team<G>::TL;
+    const int team = lane / TL, tl = lane % TL;
+    const int64_t ri = w * (64 / TL) + team;
     if (ri < pl.n_short) {
       const int row = pl.short_rows[ri];
-      const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
-      for (int64_t p = beg; p < end; p += UNROLL) {
-        const int n = (int)((end - p) < UNROLL ? (end - p) : UNROLL);
-        spmm_block<T, TG, G, C>(pl, Sv, B, ldb, wq, sub, acc, p, 1, n);
+      RowT none;
+      double s0 = 0.0, s1 = 0.0;
+      team_row<T, TG, G, C, TM_SPMM>(pl, row, Sv, B, ldb, wq, none, acc, (T *)nullptr, s0, s1,
+                                     team * TL, tl);
+      if (tl < G) {
+        lowrank_epilogue<T, TG, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
+        acc.store(Cm + (int64_t)row * ldc, sub, wq);
       }
-      lowrank_epilogue<T, TG, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
-      acc.store(Cm + (int64_t)row * ldc, sub, wq);
     }
   } else if (kind == 1) {
     const int64_t pc = w;
