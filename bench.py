@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
-    ap.add_argument("--serve-count", type=int, default=48,
+    ap.add_argument("--serve-count", type=int, default=256,
                     help="requests replayed by the serving measurement (256 in the full stream)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -203,9 +203,10 @@ def serving(bmg, synth, dev, count):
     """Serving stream: requests arrive (Poisson, 20/s) with m ~ U[500, 20000],
     n ~ U[1000, 50000], density ~ U[0.5%, 2%], rank 3..15, noise variance 0.05,
     lambda above the noise level on Omega; FP32 solves to residual 1e-5 through
-    the server (admission by footprint in an 8 GiB arena, 8 slots).  Latency =
-    completion - arrival.  Baseline: the same problems one after another with
-    the plain FP64 solver to the same residual."""
+    the server (admission by footprint in an 8 GiB arena, 8 slots, sparse passes
+    of the running problems sharing launches).  Latency = completion - arrival.
+    Also the same requests all submitted at once (capacity).  Baseline: the same
+    problems one after another with the plain FP64 solver to the same residual."""
     import numpy as np
     reqs = synth.serving_stream(count=count)
     t0 = time.time()
@@ -213,21 +214,34 @@ def serving(bmg, synth, dev, count):
     log("serving: %d requests generated in %.1fs (nnz %.1fM..%.1fM)" % (
         count, time.time() - t0, min(p.nnz for p in probs) / 1e6, max(p.nnz for p in probs) / 1e6))
     opts = dict(tol=1e-5, k_init=8, max_iter=3000, seed=7)
-    srv = bmg.Server(8 << 30, max_slots=8, device=dev)
-    tickets = []
-    start = time.perf_counter()
-    for r, p in zip(reqs, probs):
-        delay = r.arrival - (time.perf_counter() - start)
-        if delay > 0:
-            time.sleep(delay)
-        tickets.append(srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=128, precision="fp32",
-                                  lam=r.lam, **opts))
-    srv.drain()
-    makespan = time.perf_counter() - start
-    infos = [srv.poll(t)[0] for t in tickets]
-    st = srv.stats()
-    srv.close()
-    lat = np.array([i["total_s"] for i in infos])
+
+    def run(paced):
+        srv = bmg.Server(8 << 30, max_slots=8, device=dev)
+        tickets = []
+        start = time.perf_counter()
+        for r, p in zip(reqs, probs):
+            if paced:
+                delay = r.arrival - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=128,
+                                      precision="fp32", lam=r.lam, **opts))
+        srv.drain()
+        makespan = time.perf_counter() - start
+        infos = [srv.poll(t)[0] for t in tickets]
+        st = srv.stats()
+        srv.close()
+        lat = np.array([i["total_s"] for i in infos])
+        return infos, {"p50_s": round(float(np.percentile(lat, 50)), 4),
+                       "p99_s": round(float(np.percentile(lat, 99)), 4),
+                       "throughput_per_s": round(count / makespan, 3),
+                       "makespan_s": round(makespan, 3), "peak_running": st["peak_running"],
+                       "peak_arena_GB": round(st["peak_bytes"] / 1e9, 3),
+                       "shared_launches": st["shared_launches"],
+                       "batched_passes": st["batched_passes"]}
+
+    infos, paced = run(True)
+    binfos, burst = run(False)
     ok = sum(1 for i in infos if i["state"] == 2 and i["status"] == 0)
     # plain FP64 solver, one problem at a time, same tolerance
     t1 = time.perf_counter()
@@ -246,18 +260,18 @@ def serving(bmg, synth, dev, count):
     plain_total = time.perf_counter() - t1
     rel = [abs(i["result"]["F"] - f) / abs(f) for i, (_, f) in zip(infos, plain)
            if i["state"] == 2 and f == f and f != 0]
-    out = {"requests": count, "converged": ok, "p50_s": round(float(np.percentile(lat, 50)), 4),
-           "p99_s": round(float(np.percentile(lat, 99)), 4),
-           "throughput_per_s": round(count / makespan, 3), "makespan_s": round(makespan, 3),
-           "arrival_span_s": round(reqs[-1].arrival, 3), "peak_running": st["peak_running"],
-           "peak_arena_GB": round(st["peak_bytes"] / 1e9, 3),
+    same = all(a["result"]["F"] == b["result"]["F"] for a, b in zip(infos, binfos))
+    out = {"requests": count, "converged": ok, "arrival_span_s": round(reqs[-1].arrival, 3),
+           "poisson_20_per_s": paced, "all_at_once": burst,
            "plain_fp64_sequential": {"total_s": round(plain_total, 3),
                                      "p50_solve_s": round(float(np.median([p[0] for p in plain])), 4),
                                      "throughput_per_s": round(count / plain_total, 3)},
+           "capacity_vs_plain_fp64": round(burst["throughput_per_s"] * plain_total / count, 3),
            "max_rel_F_diff_vs_fp64": float(max(rel)) if rel else None,
+           "F_identical_paced_vs_burst": same,
            "ranks": sorted({i["k"] for i in infos})}
-    log("serving: p50 %.3fs p99 %.3fs, %.2f req/s (plain fp64 sequential %.2f req/s)" % (
-        out["p50_s"], out["p99_s"], out["throughput_per_s"], out["plain_fp64_sequential"]["throughput_per_s"]))
+    log("serving: p50 %.3fs p99 %.3fs at 20/s; all at once %.2f req/s vs plain fp64 sequential %.2f req/s" % (
+        paced["p50_s"], paced["p99_s"], burst["throughput_per_s"], out["plain_fp64_sequential"]["throughput_per_s"]))
     return out
 
 

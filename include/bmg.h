@@ -209,6 +209,10 @@ bmg_status bmg_server_poll(bmg_server *s, uint64_t ticket, bmg_request_info *inf
 bmg_status bmg_server_drain(bmg_server *s);
 /* Peak number of concurrently running problems and peak arena bytes in use. */
 bmg_status bmg_server_stats(bmg_server *s, int *peak_running, size_t *peak_bytes);
+/* Shared launches of sparse passes so far, and the passes they ran (the
+ * running problems' passes that are pending together of the same precision,
+ * kind and width class share one launch).  (host) out, either may be NULL. */
+bmg_status bmg_server_batch_stats(bmg_server *s, int64_t *launches, int64_t *passes);
 /* Waits for running requests, drops queued ones, frees host state. */
 void bmg_server_destroy(bmg_server *s);
 

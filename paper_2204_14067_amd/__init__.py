@@ -211,7 +211,10 @@ class Server:
     def stats(self):
         pr, pb = ctypes.c_int(0), ctypes.c_size_t(0)
         _lib.check(_lib.load().bmg_server_stats(self._h, ctypes.byref(pr), ctypes.byref(pb)))
-        return {"peak_running": pr.value, "peak_bytes": pb.value}
+        bl, bp = ctypes.c_int64(0), ctypes.c_int64(0)
+        _lib.check(_lib.load().bmg_server_batch_stats(self._h, ctypes.byref(bl), ctypes.byref(bp)))
+        return {"peak_running": pr.value, "peak_bytes": pb.value, "shared_launches": bl.value,
+                "batched_passes": bp.value}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "BMG_OK", 1: "BMG_NOT_CONVERGED", -1: "BMG_EINVAL", -2: "BMG_
 EXPORTS = ["bmg_options_default", "bmg_workspace_size", "bmg_problem_create", "bmg_problem_destroy",
            "bmg_sddmm", "bmg_spmm", "bmg_bm_epochs", "bmg_objective", "bmg_prox_step", "bmg_solve",
            "bmg_last_error", "bmg_server_footprint", "bmg_server_create", "bmg_server_submit",
-           "bmg_server_poll", "bmg_server_drain", "bmg_server_stats", "bmg_server_destroy"]
+           "bmg_server_poll", "bmg_server_drain", "bmg_server_stats", "bmg_server_batch_stats",
+           "bmg_server_destroy"]
 
 
 class BmgCsr(ctypes.Structure):
@@ -99,12 +100,13 @@ def load():
     lib.bmg_server_poll.argtypes = [p, ctypes.c_uint64, P(BmgRequestInfo), p, p, i32]
     lib.bmg_server_drain.argtypes = [p]
     lib.bmg_server_stats.argtypes = [p, P(i32), P(ctypes.c_size_t)]
+    lib.bmg_server_batch_stats.argtypes = [p, P(i64), P(i64)]
     lib.bmg_server_destroy.argtypes = [p]
     lib.bmg_server_destroy.restype = None
     for f in ["bmg_workspace_size", "bmg_problem_create", "bmg_sddmm", "bmg_spmm", "bmg_bm_epochs",
               "bmg_objective", "bmg_prox_step", "bmg_solve", "bmg_server_footprint",
               "bmg_server_create", "bmg_server_submit", "bmg_server_poll", "bmg_server_drain",
-              "bmg_server_stats"]:
+              "bmg_server_stats", "bmg_server_batch_stats"]:
         getattr(lib, f).restype = ctypes.c_int
     lib.bmg_last_error.argtypes = []
     lib.bmg_last_error.restype = ctypes.c_char_p

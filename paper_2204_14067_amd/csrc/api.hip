@@ -12,11 +12,15 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <type_traits>
 #include <vector>
 
+#include "batch.h"
 #include "bmg.h"
 #include "bmg_internal.h"
 
@@ -185,6 +189,106 @@ struct Side {  // one orientation of Omega
   void *r = nullptr;  // stored residual in this orientation's order (T)
 };
 
+// ============================================================================ pass batcher
+// A pass waits in the queue until every attached problem has a pass queued or
+// BATCH_WINDOW_S has passed since it was queued; then the first queued pass
+// of its kind (precision, mode, width class) launches up to BATCH_MAX passes
+// of that kind together, in queue order.
+static constexpr double BATCH_WINDOW_S = 100e-6;
+
+struct bmg::PassBatcher {
+  struct Item {
+    int key = 0, prec = 0, mode = 0;
+    PassArg<double, double> a64;
+    PassArg<float, float> a32;
+    PassArg<float, bf16_t> a16;
+    hipEvent_t ready = nullptr, done = nullptr;   // owned by the problem
+    bool taken = false, finished = false;
+    hipError_t err = hipSuccess;
+  };
+  std::mutex mu;
+  std::condition_variable cv;
+  hipStream_t bs = nullptr;
+  int attached = 0;
+  long launches = 0, passes = 0;
+  std::deque<Item *> q;
+
+  hipError_t launch(std::vector<Item *> &b) {
+    hipError_t e = hipSuccess;
+    for (Item *x : b)
+      if (e == hipSuccess) e = hipStreamWaitEvent(bs, x->ready, 0);
+    if (e != hipSuccess) return e;
+    const int n = (int)b.size(), mode = b[0]->mode;
+    if (b[0]->prec == 0) {
+      PassArg<double, double> d[BATCH_MAX];
+      for (int i = 0; i < n; ++i) d[i] = b[i]->a64;
+      e = launch_batch<double, double>(d, n, mode, bs);
+    } else if (b[0]->prec == 1) {
+      PassArg<float, float> d[BATCH_MAX];
+      for (int i = 0; i < n; ++i) d[i] = b[i]->a32;
+      e = launch_batch<float, float>(d, n, mode, bs);
+    } else {
+      PassArg<float, bf16_t> d[BATCH_MAX];
+      for (int i = 0; i < n; ++i) d[i] = b[i]->a16;
+      e = launch_batch<float, bf16_t>(d, n, mode, bs);
+    }
+    for (Item *x : b)
+      if (e == hipSuccess) e = hipEventRecord(x->done, bs);
+    return e;
+  }
+
+  // Queues the pass (its inputs are ready once `s` reaches this point) and
+  // returns when it is launched, with `s` made to wait for its completion.
+  hipError_t submit(Item &it, hipStream_t s) {
+    hipError_t e = hipEventRecord(it.ready, s);
+    if (e != hipSuccess) return e;
+    std::unique_lock<std::mutex> lk(mu);
+    it.taken = it.finished = false;
+    it.err = hipSuccess;
+    q.push_back(&it);
+    const auto until = std::chrono::steady_clock::now() +
+                       std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                           std::chrono::duration<double>(BATCH_WINDOW_S));
+    cv.notify_all();
+    while (!it.taken) {
+      Item *lead = nullptr;
+      for (Item *x : q)
+        if (x->key == it.key) { lead = x; break; }
+      if (lead != &it) {
+        cv.wait(lk);
+        continue;
+      }
+      cv.wait_until(lk, until, [&] { return it.taken || (int)q.size() >= attached; });
+      if (it.taken) break;
+      std::vector<Item *> b;
+      for (auto i = q.begin(); i != q.end() && (int)b.size() < BATCH_MAX;) {
+        if ((*i)->key == it.key) {
+          (*i)->taken = true;
+          b.push_back(*i);
+          i = q.erase(i);
+        } else {
+          ++i;
+        }
+      }
+      lk.unlock();
+      const hipError_t le = launch(b);
+      lk.lock();
+      launches += 1;
+      passes += (long)b.size();
+      for (Item *x : b) {
+        x->err = le;
+        x->finished = true;
+      }
+      cv.notify_all();
+    }
+    cv.wait(lk, [&] { return it.finished; });
+    e = it.err;
+    lk.unlock();
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, it.done, 0);
+    return e;
+  }
+};
+
 struct bmg_problem {
   Layout L;
   bmg_precision prec;
@@ -197,6 +301,9 @@ struct bmg_problem {
   double *result, *gram_part, *small;
   double *wsum, *wpart;
   void *partial;
+  // serving: sparse passes go through a shared batcher when set
+  PassBatcher *batcher = nullptr;
+  PassBatcher::Item bitem;
   // statistics of the sparse passes since the last reset
   double bytes = 0.0;
   int passes = 0;
@@ -244,6 +351,8 @@ struct bmg_problem {
   ~bmg_problem() {
     for (const Pend &q : pend) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (bitem.ready) (void)hipEventDestroy(bitem.ready);
+    if (bitem.done) (void)hipEventDestroy(bitem.done);
   }
 
   template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -483,12 +592,47 @@ struct Engine {
     const double *dM = put(M, slot);
     HIPC(launch_gemm_ts<T>(N, a, X, ldx, b, dM, b, Cm, ldc, beta, s));
   }
+  // ---------------------------------------------------------------- pass dispatch
+  // mode 0 fused residual + product, 1 sampled residual, 2 sparse x dense
+  // (arguments as in launch_grad / launch_sddmm / launch_spmm).  Through the
+  // problem's batcher when it has one and the width fits one lane-group slice.
+  template <typename TY>
+  void pass(int mode, const Plan &pl, const T *a, const T *X, int ldx, const TY *Y, int ldy,
+            int width, double lam, double coef, T *out, int ldo, int kx, const T *M, int ldm,
+            PassScratch sc) {
+    if (P->batcher && width <= max_width<T>()) {
+      PassArg<T, TY> d;
+      d.pl = pl;
+      d.a = a; d.X = X; d.Y = Y; d.M = M; d.out = out;
+      d.partial = (T *)sc.partial; d.wsum = sc.wsum; d.result = sc.result;
+      d.partial_bytes = sc.partial_bytes;
+      d.lam = lam; d.coef = coef;
+      d.ldx = ldx; d.ldy = ldy; d.width = width; d.ldo = ldo; d.kx = kx; d.ldm = ldm;
+      PassBatcher::Item &it = P->bitem;
+      if (!it.ready) HIPC(hipEventCreateWithFlags(&it.ready, hipEventDisableTiming));
+      if (!it.done) HIPC(hipEventCreateWithFlags(&it.done, hipEventDisableTiming));
+      it.mode = mode;
+      if constexpr (std::is_same<T, double>::value) { it.prec = 0; it.a64 = d; }
+      else if constexpr (std::is_same<TY, float>::value) { it.prec = 1; it.a32 = d; }
+      else { it.prec = 2; it.a16 = d; }
+      it.key = (it.prec * 4 + mode) * 1024 + width_class<TY>(width);
+      HIPC(P->batcher->submit(it, s));
+      return;
+    }
+    if (mode == 0)
+      HIPC((launch_grad<T, TY>(pl, a, X, ldx, Y, ldy, width, lam, out, ldo, sc, nullptr, s)));
+    else if (mode == 1)
+      HIPC((launch_sddmm<T, TY>(pl, a, X, ldx, Y, ldy, width, out, sc, s)));
+    else
+      HIPC((launch_spmm<T, TY>(pl, a, Y, ldy, width, coef, X, ldx, kx, M, ldm, out, ldo, sc, s)));
+  }
+
   // ---------------------------------------------------------------- sparse passes
   // BM gradient on the rows side: G = R H + lam W (+ f = 1/2 sum r^2)
   double grad_rows(const T *W, const T *H, int k, double lam, T *G) {
     with_gather(1, H, n, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
-      HIPC((launch_grad<T, TY>(R->pl, avals(R), W, ldk, Yg, ldk, k, lam, G, ldk, sx(0), nullptr, s)));
+      pass<TY>(0, R->pl, avals(R), W, ldk, Yg, ldk, k, lam, 0.0, G, ldk, 0, nullptr, 0, sx(0));
     });
     count(R->pl, 4.0 + sizeof(T), (double)n * k * sizeof(TG) + 2.0 * m * k * sizeof(T));
     double h[1];
@@ -498,7 +642,7 @@ struct Engine {
   double grad_cols(const T *W, const T *H, int k, double lam, T *G) {
     with_gather(0, W, m, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
-      HIPC((launch_grad<T, TY>(C->pl, avals(C), H, ldk, Yg, ldk, k, lam, G, ldk, sx(0), nullptr, s)));
+      pass<TY>(0, C->pl, avals(C), H, ldk, Yg, ldk, k, lam, 0.0, G, ldk, 0, nullptr, 0, sx(0));
     });
     count(C->pl, 4.0 + sizeof(T), (double)m * k * sizeof(TG) + 2.0 * n * k * sizeof(T));
     double h[1];
@@ -509,7 +653,8 @@ struct Engine {
   double curvature(Side *sd, const T *X, const T *Y, int k, int64_t nx, int64_t ny) {
     with_gather(sd == R ? 1 : 0, Y, ny, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
-      HIPC((launch_sddmm<T, TY>(sd->pl, (const T *)nullptr, X, ldk, Yg, ldk, k, (T *)nullptr, sx(1), s)));
+      pass<TY>(1, sd->pl, (const T *)nullptr, X, ldk, Yg, ldk, k, 0.0, 0.0, (T *)nullptr, 0, 0,
+               nullptr, 0, sx(1));
     });
     count(sd->pl, 4.0, (double)nx * k * sizeof(T) + (double)ny * k * sizeof(TG));
     double h[2];
@@ -520,7 +665,8 @@ struct Engine {
   void sddmm_store(Side *sd, const T *X, const T *Y, int k, int64_t nx, int64_t ny, double out[2]) {
     with_gather(sd == R ? 1 : 0, Y, ny, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
-      HIPC((launch_sddmm<T, TY>(sd->pl, avals(sd), X, ldk, Yg, ldk, k, (T *)sd->r, sx(1), s)));
+      pass<TY>(1, sd->pl, avals(sd), X, ldk, Yg, ldk, k, 0.0, 0.0, (T *)sd->r, 0, 0, nullptr, 0,
+               sx(1));
     });
     count(sd->pl, 4.0 + 2.0 * sizeof(T), (double)nx * k * sizeof(T) + (double)ny * k * sizeof(TG));
     fetch(out, P->result, 2);
@@ -529,7 +675,8 @@ struct Engine {
     if (R->pl.nnz == 0) return 0.0;
     with_gather(1, H, n, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
-      HIPC((launch_sddmm<T, TY>(R->pl, avals(R), W, ldk, Yg, ldk, k, (T *)nullptr, sx(1), s)));
+      pass<TY>(1, R->pl, avals(R), W, ldk, Yg, ldk, k, 0.0, 0.0, (T *)nullptr, 0, 0, nullptr, 0,
+               sx(1));
     });
     count(R->pl, 4.0 + sizeof(T), (double)m * k * sizeof(T) + (double)n * k * sizeof(TG));
     double h[2];
@@ -553,8 +700,7 @@ struct Engine {
     if (z.k > 0) dM = put_t(gram(m, z.k, z.W, ldk, q, U, qld), 0);
     with_gather(2, U, m, q, qld, [&](auto Ug) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Ug)>>;
-      HIPC((launch_spmm<T, TY>(C->pl, z.s_cols, Ug, qld, q, -z.alpha, z.H, ldk, z.k, dM, q, Y, qld,
-                               sx(2), s)));
+      pass<TY>(2, C->pl, z.s_cols, z.H, ldk, Ug, qld, q, 0.0, -z.alpha, Y, qld, z.k, dM, q, sx(2));
     });
     count(C->pl, 4.0 + sizeof(T), (double)m * q * sizeof(TG) + (double)n * q * sizeof(T));
   }
@@ -565,8 +711,7 @@ struct Engine {
     if (z.k > 0) dM = put_t(gram(n, z.k, z.H, ldk, q, Y, qld), 1);
     with_gather(3, Y, n, q, qld, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
-      HIPC((launch_spmm<T, TY>(R->pl, z.s_rows, Yg, qld, q, -z.alpha, z.W, ldk, z.k, dM, q, V, qld,
-                               sx(2), s)));
+      pass<TY>(2, R->pl, z.s_rows, z.W, ldk, Yg, qld, q, 0.0, -z.alpha, V, qld, z.k, dM, q, sx(2));
     });
     count(R->pl, 4.0 + sizeof(T), (double)n * q * sizeof(TG) + (double)m * q * sizeof(T));
   }
@@ -1485,3 +1630,45 @@ extern "C" bmg_status bmg_solve(bmg_problem *P, double *W, double *H, int ld, co
     return fail(e.st, e.msg);
   }
 }
+
+// ============================================================================ batcher API (serving)
+namespace bmg {
+PassBatcher *batcher_create() {
+  PassBatcher *b = new PassBatcher();
+  if (hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return nullptr;
+  }
+  return b;
+}
+void batcher_destroy(PassBatcher *b) {
+  if (!b) return;
+  if (b->bs) {
+    (void)hipStreamSynchronize(b->bs);
+    (void)hipStreamDestroy(b->bs);
+  }
+  delete b;
+}
+void batcher_attach(bmg_problem *P, PassBatcher *b) {
+  if (!P || !b) return;
+  std::lock_guard<std::mutex> lk(b->mu);
+  P->batcher = b;
+  b->attached += 1;
+}
+void batcher_detach(bmg_problem *P) {
+  if (!P || !P->batcher) return;
+  PassBatcher *b = P->batcher;
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->attached -= 1;
+    P->batcher = nullptr;
+  }
+  b->cv.notify_all();   // a leader waiting for every attached problem re-checks
+}
+void batcher_stats(PassBatcher *b, long *launches, long *passes) {
+  if (!b) return;
+  std::lock_guard<std::mutex> lk(b->mu);
+  if (launches) *launches = b->launches;
+  if (passes) *passes = b->passes;
+}
+}  // namespace bmg

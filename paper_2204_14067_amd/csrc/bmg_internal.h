@@ -57,6 +57,42 @@ struct PassScratch {
   hipEvent_t ev1 = nullptr;
 };
 
+// ---------------------------------------------------------------- batched passes
+// One sparse pass of one problem, for a launch shared by several problems.
+// mode 0: fused residual + product (out = R Y + lam X, a = values);
+// mode 1: sampled residual (out = R entries or null, a = values or null);
+// mode 2: sparse x dense (out = coef S Y + X M, a = S).
+template <typename T, typename TG>
+struct PassArg {
+  Plan pl;
+  const T *a = nullptr;
+  const T *X = nullptr;
+  const TG *Y = nullptr;
+  const T *M = nullptr;
+  T *out = nullptr;
+  T *partial = nullptr;
+  double *wsum = nullptr;
+  double *result = nullptr;
+  int64_t partial_bytes = 0;
+  double lam = 0.0, coef = 0.0;
+  int ldx = 0, ldy = 0, width = 0, ldo = 0, kx = 0, ldm = 0;
+};
+constexpr int BATCH_MAX = 8;
+template <typename T, typename TG>
+struct BatchArg {
+  PassArg<T, TG> d[BATCH_MAX];
+  int64_t b0[BATCH_MAX + 1];   // first block of each pass (multiples of 8)
+  int nd;
+};
+// Launches nd passes of the same mode and width class in one grid (plus the
+// long-row fix-ups and one scalar reduction per pass); the width of every pass
+// must be at most max_width<T>().
+template <typename T, typename TG>
+hipError_t launch_batch(const PassArg<T, TG> *d, int nd, int mode, hipStream_t s);
+// lane-group geometry class of a width (passes of one class can share a launch)
+template <typename TG>
+int width_class(int width);
+
 // ---------------------------------------------------------------- launchers (kernels.hip)
 // All return hipError_t of the launch; widths/ld are in elements.
 

@@ -12,4 +12,6 @@ namespace bmg {
                                          const T *, int, int, const T *, int, T *, int, PassScratch, \
                                          hipStream_t);
 BMG_INST_PASS(float, bf16_t)
+template hipError_t launch_batch<float, bf16_t>(const PassArg<float, bf16_t> *, int, int, hipStream_t);
+template int width_class<bf16_t>(int);
 }  // namespace bmg

@@ -12,4 +12,6 @@ namespace bmg {
                                          const T *, int, int, const T *, int, T *, int, PassScratch, \
                                          hipStream_t);
 BMG_INST_PASS(float, float)
+template hipError_t launch_batch<float, float>(const PassArg<float, float> *, int, int, hipStream_t);
+template int width_class<float>(int);
 }  // namespace bmg

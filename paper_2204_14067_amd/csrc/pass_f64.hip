@@ -12,4 +12,6 @@ namespace bmg {
                                          const T *, int, int, const T *, int, T *, int, PassScratch, \
                                          hipStream_t);
 BMG_INST_PASS(double, double)
+template hipError_t launch_batch<double, double>(const PassArg<double, double> *, int, int, hipStream_t);
+template int width_class<double>(int);
 }  // namespace bmg

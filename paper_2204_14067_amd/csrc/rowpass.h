@@ -152,10 +152,10 @@ __host__ __device__ inline int64_t grid_blocks(const Plan &pl, int G) {
                   : piece_block0(pl, G) + piece_blocks(pl);
   return b > 0 ? b : 1;
 }
-// Work of the calling wave: 0 = short-row wave w, 1 = piece w, -1 = none.
-__device__ __forceinline__ int wave_work(const Plan &pl, int G, int64_t &w) {
+// Work of the calling wave of block b: 0 = short-row wave w, 1 = piece w, -1 = none.
+__device__ __forceinline__ int wave_work(const Plan &pl, int G, int64_t b, int64_t &w) {
   const int wave = threadIdx.x >> 6;
-  const int64_t b = blockIdx.x, pb0 = piece_block0(pl, G);
+  const int64_t pb0 = piece_block0(pl, G);
   if (b < pb0) {
     w = b * WAVES_PER_BLOCK + wave;
     return w < short_waves(pl, G) ? 0 : -1;
@@ -342,18 +342,19 @@ __device__ __forceinline__ void team_row(const Plan &pl, int row, const T *__res
   }
 }
 
+// Fused residual + product pass; blk is the block's index within its pass.
 template <typename T, typename TG, int G, int C>
-__global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
-                                              const T *__restrict__ X, int ldx,
-                                              const TG *__restrict__ Y, int ldy, int k, double lam,
-                                              T *__restrict__ Out, int ldo,
-                                              T *__restrict__ partial, double *__restrict__ wsum) {
+__device__ __forceinline__ void grad_body(const Plan &pl, int64_t blk, const T *__restrict__ a,
+                                          const T *__restrict__ X, int ldx,
+                                          const TG *__restrict__ Y, int ldy, int k, double lam,
+                                          T *__restrict__ Out, int ldo, T *__restrict__ partial,
+                                          double *__restrict__ wsum) {
   using RowT = Row<T, TG, G, C>;
   constexpr int S = 64 / G, WB = RowT::WB;
   const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
-  const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+  const int64_t gw = blk * WAVES_PER_BLOCK + (threadIdx.x >> 6);
   int64_t w = 0;
-  const int kind = wave_work(pl, G, w);
+  const int kind = wave_work(pl, G, blk, w);
   const bool leader = (sub == 0);
   double ss = 0.0;
   RowT acc;
@@ -393,6 +394,14 @@ __global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
   }
   ss = wave_sum(ss);
   if (lane == 0) wsum[gw] = ss;
+}
+template <typename T, typename TG, int G, int C>
+__global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
+                                              const T *__restrict__ X, int ldx,
+                                              const TG *__restrict__ Y, int ldy, int k, double lam,
+                                              T *__restrict__ Out, int ldo,
+                                              T *__restrict__ partial, double *__restrict__ wsum) {
+  grad_body<T, TG, G, C>(pl, blockIdx.x, a, X, ldx, Y, ldy, k, lam, Out, ldo, partial, wsum);
 }
 
 // Long rows: Out_row = sum of piece partials (piece order) + lam * x_row.
@@ -457,16 +466,16 @@ __device__ __forceinline__ void sddmm_block(const Plan &pl, const T *__restrict_
 }
 
 template <typename T, typename TG, int G, int C>
-__global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
-                                               const T *__restrict__ X, int ldx,
-                                               const TG *__restrict__ Y, int ldy, int k,
-                                               T *__restrict__ R, double *__restrict__ wsum) {
+__device__ __forceinline__ void sddmm_body(const Plan &pl, int64_t blk, const T *__restrict__ a,
+                                           const T *__restrict__ X, int ldx,
+                                           const TG *__restrict__ Y, int ldy, int k,
+                                           T *__restrict__ R, double *__restrict__ wsum) {
   using RowT = Row<T, TG, G, C>;
   constexpr int S = 64 / G;
   const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
-  const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+  const int64_t gw = blk * WAVES_PER_BLOCK + (threadIdx.x >> 6);
   int64_t w = 0;
-  const int kind = wave_work(pl, G, w);
+  const int kind = wave_work(pl, G, blk, w);
   const bool leader = (sub == 0);
   double ss = 0.0, sx = 0.0;
   if (kind == 0) {
@@ -497,6 +506,13 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
     wsum[2 * gw] = ss;
     wsum[2 * gw + 1] = sx;
   }
+}
+template <typename T, typename TG, int G, int C>
+__global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
+                                               const T *__restrict__ X, int ldx,
+                                               const TG *__restrict__ Y, int ldy, int k,
+                                               T *__restrict__ R, double *__restrict__ wsum) {
+  sddmm_body<T, TG, G, C>(pl, blockIdx.x, a, X, ldx, Y, ldy, k, R, wsum);
 }
 
 // ============================================================================ sparse x dense
@@ -545,7 +561,7 @@ __device__ __forceinline__ void lowrank_epilogue(Row<T, TG, G, C> &acc, double c
 }
 
 template <typename T, typename TG, int G, int C>
-__global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
+__device__ __forceinline__ void spmm_body(const Plan &pl, int64_t blk, const T *__restrict__ Sv,
                                               const TG *__restrict__ B, int ldb, int wq,
                                               double coef, const T *__restrict__ X, int ldx,
                                               int kx, const T *__restrict__ M, int ldm,
@@ -555,7 +571,7 @@ __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
   constexpr int S = 64 / G, WB = RowT::WB;
   const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
   int64_t w = 0;
-  const int kind = wave_work(pl, G, w);
+  const int kind = wave_work(pl, G, blk, w);
   RowT acc;
   acc.zero();
   if (kind == 0) {
@@ -587,6 +603,16 @@ __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
       for (int e = 0; e < RowT::V; ++e) acc.v[c][e] = slot_sum<G>(acc.v[c][e]);
     if (slot == 0) acc.store(partial + pc * WB, sub, WB);
   }
+}
+
+template <typename T, typename TG, int G, int C>
+__global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
+                                              const TG *__restrict__ B, int ldb, int wq,
+                                              double coef, const T *__restrict__ X, int ldx,
+                                              int kx, const T *__restrict__ M, int ldm,
+                                              T *__restrict__ Cm, int ldc,
+                                              T *__restrict__ partial) {
+  spmm_body<T, TG, G, C>(pl, blockIdx.x, Sv, B, ldb, wq, coef, X, ldx, kx, M, ldm, Cm, ldc, partial);
 }
 
 template <typename T, typename TG, int G, int C>
@@ -730,6 +756,128 @@ hipError_t launch_spmm(const Plan &pl, const T *Sv, const TG *B, int ldb, int q,
   }
   if (sc.ev1) (void)hipEventRecord(sc.ev1, s);
   return hipSuccess;
+}
+
+// ============================================================================ batched passes
+// Blocks [b0[d], b0[d+1]) of the grid run pass d; each pass keeps its own block
+// numbering (so its wave-to-work mapping, and its results, do not depend on
+// the other passes of the launch).
+template <typename T, typename TG, int G, int C, int MODE>
+__global__ __launch_bounds__(256) void k_batch(BatchArg<T, TG> A) {
+  int d = 0;
+  while (d + 1 < A.nd && (int64_t)blockIdx.x >= A.b0[d + 1]) ++d;
+  const PassArg<T, TG> &D = A.d[d];
+  const int64_t blk = (int64_t)blockIdx.x - A.b0[d];
+  if (blk >= grid_blocks(D.pl, G)) return;   // padding to a multiple of 8 blocks
+  if (MODE == 0)
+    grad_body<T, TG, G, C>(D.pl, blk, D.a, D.X, D.ldx, D.Y, D.ldy, D.width, D.lam, D.out, D.ldo,
+                           D.partial, D.wsum);
+  else if (MODE == 1)
+    sddmm_body<T, TG, G, C>(D.pl, blk, D.a, D.X, D.ldx, D.Y, D.ldy, D.width, D.out, D.wsum);
+  else
+    spmm_body<T, TG, G, C>(D.pl, blk, D.a, D.Y, D.ldy, D.width, D.coef, D.X, D.ldx, D.kx, D.M,
+                           D.ldm, D.out, D.ldo, D.partial);
+}
+
+// Block d sums the nsum interleaved per-wave slots of pass d in the order of
+// launch_reduce_wsum (runs of at least 1024 waves, at most 256 runs, each run
+// thread-strided then a binary tree, then the same over the run sums), so a
+// batched pass reports bit for bit what it reports alone.
+template <typename T, typename TG>
+__global__ __launch_bounds__(256) void k_batch_reduce(BatchArg<T, TG> A, int G, int nsum) {
+  __shared__ double sh[256];
+  __shared__ double runs[2][256];
+  const PassArg<T, TG> &D = A.d[blockIdx.x];
+  const int64_t waves = grid_blocks(D.pl, G) * WAVES_PER_BLOCK;
+  int64_t nb = (waves + 1023) / 1024;
+  if (nb > 256) nb = 256;
+  int64_t run = waves;
+  if (nb > 1) {
+    run = (waves + nb - 1) / nb;
+    nb = (waves + run - 1) / run;
+  } else {
+    nb = 1;
+  }
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t w0 = b * run, w1 = (w0 + run) < waves ? (w0 + run) : waves;
+    for (int c = 0; c < nsum; ++c) {
+      double s = 0.0;
+      for (int64_t w = w0 + threadIdx.x; w < w1; w += 256) s += D.wsum[w * nsum + c];
+      sh[threadIdx.x] = s;
+      __syncthreads();
+      for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) runs[c][b] = sh[0];
+      __syncthreads();
+    }
+  }
+  for (int c = 0; c < nsum; ++c) {
+    if (nb == 1) {
+      if (threadIdx.x == 0) D.result[c] = runs[c][0];
+      continue;
+    }
+    sh[threadIdx.x] = (int64_t)threadIdx.x < nb ? runs[c][threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) D.result[c] = sh[0];
+    __syncthreads();
+  }
+}
+
+template <typename TG>
+int width_class(int width) {
+  const GC gc = pick_gc(width, VT<TG>::V);
+  return gc.G * 16 + gc.C;
+}
+
+template <typename T, typename TG>
+hipError_t launch_batch(const PassArg<T, TG> *d, int nd, int mode, hipStream_t s) {
+  constexpr int V = VT<TG>::V;
+  if (nd < 1 || nd > BATCH_MAX) return hipErrorInvalidValue;
+  const GC gc = pick_gc(d[0].width, V);
+  BatchArg<T, TG> A;
+  A.nd = nd;
+  A.b0[0] = 0;
+  for (int i = 0; i < nd; ++i) {
+    if (d[i].width > max_width<T>() || width_class<TG>(d[i].width) != gc.G * 16 + gc.C)
+      return hipErrorInvalidValue;
+    if (mode != 1 && d[i].pl.n_pieces * partial_row_bytes<T, TG>(gc) > d[i].partial_bytes)
+      return hipErrorInvalidValue;
+    A.d[i] = d[i];
+    A.b0[i + 1] = A.b0[i] + (grid_blocks(d[i].pl, gc.G) + 7) / 8 * 8;
+  }
+  for (int i = nd + 1; i <= BATCH_MAX; ++i) A.b0[i] = A.b0[nd];
+  const dim3 grid((unsigned)A.b0[nd]);
+  BMG_DISPATCH_GC(gc, {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_batch<T, TG, GG, CC, 0>), grid, dim3(256), 0, s, A);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_batch<T, TG, GG, CC, 1>), grid, dim3(256), 0, s, A);
+    else
+      hipLaunchKernelGGL((k_batch<T, TG, GG, CC, 2>), grid, dim3(256), 0, s, A);
+    for (int i = 0; i < nd; ++i) {
+      const PassArg<T, TG> &D = d[i];
+      if (D.pl.n_long == 0 || mode == 1) continue;
+      const int64_t thr = D.pl.n_long * GG;
+      if (mode == 0)
+        hipLaunchKernelGGL((k_grad_fix<T, TG, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
+                           dim3(256), 0, s, D.pl, (const T *)D.partial, D.X, D.ldx, D.width, D.lam,
+                           D.out, D.ldo);
+      else
+        hipLaunchKernelGGL((k_spmm_fix<T, TG, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
+                           dim3(256), 0, s, D.pl, (const T *)D.partial, D.coef, D.X, D.ldx, D.kx,
+                           D.M, D.ldm, D.width, D.out, D.ldo);
+    }
+  });
+  if (mode != 2)
+    hipLaunchKernelGGL((k_batch_reduce<T, TG>), dim3((unsigned)nd), dim3(256), 0, s, A, gc.G,
+                       mode == 0 ? 1 : 2);
+  return hipGetLastError();
 }
 
 }  // namespace bmg

@@ -5,6 +5,9 @@
 // request whose footprint fits a first-fit allocation of the caller's device
 // arena, copies its CSR to the device, runs bmg_problem_create / bmg_solve on
 // the slot's own HIP stream, copies the factors back and releases the memory.
+// While solving, each problem is attached to the server's pass batcher: the
+// sparse passes of the running problems that are pending at the same time
+// share one launch (batch.h).
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -19,6 +22,7 @@
 #include <thread>
 #include <vector>
 
+#include "batch.h"
 #include "bmg.h"
 
 namespace {
@@ -79,6 +83,7 @@ struct bmg_server {
   int running = 0, peak_running = 0;
   size_t used = 0, peak_used = 0;
   int outstanding = 0;
+  bmg::PassBatcher *batcher = nullptr;
 
   bool alloc(size_t bytes, size_t *off) {
     for (size_t i = 0; i < free_list.size(); ++i) {
@@ -150,7 +155,9 @@ void bmg_server::run(Request *r, hipStream_t st) {
     s = bmg_problem_create(&csr, r->k_cap, r->prec, ws, r->ws_bytes, st, &P);
     if (s == BMG_OK) {
       int k = 0;
+      bmg::batcher_attach(P, batcher);
       s = bmg_solve(P, d_W, d_H, r->ld, &r->opt, &k, &r->res);
+      bmg::batcher_detach(P);
       r->k = k;
       r->W.resize((size_t)r->m * r->ld);
       r->H.resize((size_t)r->n * r->ld);
@@ -220,6 +227,11 @@ extern "C" bmg_status bmg_server_create(void *arena, size_t arena_bytes, int max
   S->arena_bytes = arena_bytes;
   S->free_list.push_back({0, arena_bytes / 256 * 256});
   (void)hipGetDevice(&S->device);
+  S->batcher = bmg::batcher_create();
+  if (!S->batcher) {
+    delete S;
+    return BMG_EDEVICE;
+  }
   for (int i = 0; i < max_slots; ++i) S->workers.emplace_back([S] { S->worker(); });
   *out = S;
   return BMG_OK;
@@ -300,6 +312,15 @@ extern "C" bmg_status bmg_server_stats(bmg_server *S, int *peak_running, size_t 
   return BMG_OK;
 }
 
+extern "C" bmg_status bmg_server_batch_stats(bmg_server *S, int64_t *launches, int64_t *passes) {
+  if (!S) return BMG_EINVAL;
+  long l = 0, p = 0;
+  bmg::batcher_stats(S->batcher, &l, &p);
+  if (launches) *launches = l;
+  if (passes) *passes = p;
+  return BMG_OK;
+}
+
 extern "C" void bmg_server_destroy(bmg_server *S) {
   if (!S) return;
   {
@@ -314,5 +335,6 @@ extern "C" void bmg_server_destroy(bmg_server *S) {
   }
   S->cv.notify_all();
   for (auto &t : S->workers) t.join();
+  bmg::batcher_destroy(S->batcher);
   delete S;
 }

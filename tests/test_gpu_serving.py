@@ -1,5 +1,6 @@
 """Serving loop (bmg_server_*): continuous admission by HBM footprint, several
-problems running at once, and every result identical alone and in the mix."""
+problems running at once with their sparse passes sharing launches, and every
+result identical to the same problem solved alone by the plain entry point."""
 import math
 
 import numpy as np
@@ -39,6 +40,8 @@ def test_serving_alone_equals_mix_and_admission_binds():
     print("stats", st, "arena", arena, flush=True)
     assert st["peak_bytes"] <= arena
     assert 1 <= st["peak_running"] <= 4
+    # passes of concurrently running problems shared launches
+    assert st["batched_passes"] > st["shared_launches"] > 0
     for (r, p), t, (k, F, status) in zip(items, tickets, alone):
         info, W, H = srv.poll(t, p.m, p.n, 64)
         print("mix", p.name, info["k"], info["result"]["F"], info["queued_s"], info["run_s"], flush=True)
