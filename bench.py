@@ -208,9 +208,12 @@ def serving(bmg, synth, dev, count):
     Also the same requests all submitted at once (capacity).  Baseline: the same
     problems one after another with the plain FP64 solver to the same residual."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     reqs = synth.serving_stream(count=count)
     t0 = time.time()
-    probs = [synth.request_problem(r) for r in reqs]
+    # the generator runs in C without the GIL: build the requests in parallel
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        probs = list(ex.map(synth.request_problem, reqs))
     log("serving: %d requests generated in %.1fs (nnz %.1fM..%.1fM)" % (
         count, time.time() - t0, min(p.nnz for p in probs) / 1e6, max(p.nnz for p in probs) / 1e6))
     opts = dict(tol=1e-5, k_init=8, max_iter=3000, seed=7)

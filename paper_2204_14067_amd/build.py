@@ -14,8 +14,16 @@ ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libbmg.so")
 # the row kernels of the sparse passes (rowpass.h) are instantiated once per
 # element type pair in their own source, so the heavy sources compile in parallel
-SOURCES = ["pass_f64.hip", "pass_f32.hip", "pass_bf16.hip", "kernels.hip", "api.hip", "linalg.cpp",
-           "server.cpp"]
+# (source, object name, extra flags); .cpp sources with HIP calls go through
+# hipcc as host C++, the pure-host linear algebra through g++ (twice: baseline
+# and x86-64-v3, chosen at run time by linalg_dispatch.cpp)
+SOURCES = [("pass_f64.hip", "pass_f64", []), ("pass_f32.hip", "pass_f32", []),
+           ("pass_bf16.hip", "pass_bf16", []), ("kernels.hip", "kernels", []),
+           ("api.hip", "api", []), ("server.cpp", "server", []),
+           ("linalg.cpp", "linalg_generic", ["-DLA_IMPL=la_generic"]),
+           ("linalg.cpp", "linalg_v3", ["-DLA_IMPL=la_v3", "-march=x86-64-v3"]),
+           ("linalg_dispatch.cpp", "linalg_dispatch", [])]
+HOST_ONLY = ("linalg.cpp", "linalg_dispatch.cpp")
 # every source that defines device code (hashed by bench.py to match counter records)
 KERNEL_SOURCES = ["bmg_internal.h", "rowpass.h", "pass_f64.hip", "pass_f32.hip", "pass_bf16.hip",
                   "kernels.hip"]
@@ -25,14 +33,19 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc")]
 
 
-def _compile(src: str, objdir: str, verbose: bool) -> str:
-    obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc"] + FLAGS + ["-c", os.path.join(HERE, "csrc", src), "-o", obj]
-    if src.endswith(".cpp"):   # host-only C++ (no device code)
-        cmd = ["hipcc", "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"] + \
-            [f for f in FLAGS if not f.startswith("--offload")
-             and f not in ("-Xclang", "-target-feature", "-packed-fp32-ops")] \
-            + ["-c", os.path.join(HERE, "csrc", src), "-o", obj]
+def _compile(entry, objdir: str, verbose: bool) -> str:
+    src, name, extra = entry
+    obj = os.path.join(objdir, name + ".o")
+    path = os.path.join(HERE, "csrc", src)
+    host_flags = [f for f in FLAGS if not f.startswith("--offload")
+                  and f not in ("-Xclang", "-target-feature", "-packed-fp32-ops")]
+    if src in HOST_ONLY:       # plain host C++
+        cmd = ["g++"] + host_flags + extra + ["-c", path, "-o", obj]
+    elif src.endswith(".cpp"):  # host C++ calling the HIP runtime
+        cmd = ["hipcc", "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"] + host_flags \
+            + extra + ["-c", path, "-o", obj]
+    else:
+        cmd = ["hipcc"] + FLAGS + extra + ["-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

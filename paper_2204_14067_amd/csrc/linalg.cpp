@@ -14,12 +14,28 @@
 #include <numeric>
 #include <vector>
 
-#include "linalg.h"
+// Built twice (baseline x86-64 and x86-64-v3 with AVX2/FMA) into namespaces
+// bmg::la_generic and bmg::la_v3; linalg_dispatch.cpp picks one at run time.
+#ifndef LA_IMPL
+#error "compile with -DLA_IMPL=la_generic or -DLA_IMPL=la_v3"
+#endif
 
 namespace bmg {
-namespace la {
+namespace LA_IMPL {
 
 static inline double &at(std::vector<double> &A, int n, int i, int j) { return A[(size_t)i * n + j]; }
+
+// a . b with eight independent partial sums added in a fixed order (the
+// compiler can keep them in vector registers; a single running sum is one
+// long dependency chain).  Deterministic for given inputs.
+static inline double dot(const double *a, const double *b, int n) {
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int i = 0;
+  for (; i + 8 <= n; i += 8)
+    for (int l = 0; l < 8; ++l) s[l] += a[i + l] * b[i + l];
+  for (int l = 0; i < n; ++i, ++l) s[l] += a[i] * b[i];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
 
 void sym_eig(int n, const double *A0, double *w, double *Vout) {
   if (n <= 0) return;
@@ -50,12 +66,7 @@ void sym_eig(int n, const double *A0, double *w, double *Vout) {
     if (vv == 0.0) continue;
     const double tau = 2.0 / vv;
     taus[k] = tau;
-    for (int i = k + 1; i < n; ++i) {
-      double acc = 0.0;
-      const double *row = &A[(size_t)i * n];
-      for (int j = k + 1; j < n; ++j) acc += row[j] * v[j];
-      p[i] = tau * acc;
-    }
+    for (int i = k + 1; i < n; ++i) p[i] = tau * dot(&A[(size_t)i * n + k + 1], v + k + 1, n - k - 1);
     double pv = 0.0;
     for (int i = k + 1; i < n; ++i) pv += p[i] * v[i];
     for (int i = k + 1; i < n; ++i) wv[i] = p[i] - 0.5 * tau * pv * v[i];
@@ -84,9 +95,7 @@ void sym_eig(int n, const double *A0, double *w, double *Vout) {
       // for each column c >= k+1 of Q (row c of Z): q_c[k+1:] -= tau v (v^T q_c[k+1:])
       for (int c = k + 1; c < n; ++c) {
         double *zc = &Z[(size_t)c * n];
-        double acc = 0.0;
-        for (int i = k + 1; i < n; ++i) acc += v[i] * zc[i];
-        acc *= tau;
+        const double acc = tau * dot(v + k + 1, zc + k + 1, n - k - 1);
         for (int i = k + 1; i < n; ++i) zc[i] -= acc * v[i];
       }
     }
@@ -112,7 +121,7 @@ void sym_eig(int n, const double *A0, double *w, double *Vout) {
     const double mu = d[hi] - es / den;
     double x = d[lo] - mu, z = e[lo];
     for (int k = lo; k < hi; ++k) {
-      const double r = hypot(x, z);
+      const double r = sqrt(x * x + z * z);   // Gram-matrix entries: no overflow risk
       double c = 1.0, s = 0.0;
       if (r != 0.0) { c = x / r; s = -z / r; }
       if (k > lo) e[k - 1] = r;
@@ -219,5 +228,5 @@ bool spd_inv(int n, const double *A, double *Ainv) {
   return true;
 }
 
-}  // namespace la
+}  // namespace LA_IMPL
 }  // namespace bmg
