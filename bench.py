@@ -164,7 +164,7 @@ def main():
                     for c in range(3)},
     }
     if not args.no_extras:
-        out["precision_modes"] = precision_steps(bmg, p, dev, k0, lam)
+        out["precision_modes"] = precision_steps(bmg, p, dev, k0, lam, recs[-1]["F"])
         out["time_to_tol"] = time_to_tol(bmg, synth, dev)
         out["serve"] = serving(bmg, synth, dev, args.serve_count)
     if not args.no_cpu_baseline:
@@ -173,9 +173,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def precision_steps(bmg, p, dev, k0, lam, steps=2):
+def precision_steps(bmg, p, dev, k0, lam, F64, steps=2):
     """The same step (one outer iteration from the same start) in the lower
-    precision modes on the same workload."""
+    precision modes on the same workload; rel_F_vs_fp64 compares the objective
+    each mode reports after the step (FP64 evaluation of its factors) with the
+    FP64 mode's."""
     import torch
     out = {}
     for prec in ("fp32", "bf16"):
@@ -193,6 +195,8 @@ def precision_steps(bmg, p, dev, k0, lam, steps=2):
         kms = [sum(r["kernel_ms"][c] for r in recs) / steps for c in range(3)]
         out[prec] = {"ms_per_step": round(dt * 1e3, 3),
                      "GB/s": round(sum(r["sparse_bytes"] for r in recs) / steps / dt / 1e9, 2),
+                     "rank_after_step": recs[-1]["k"],
+                     "rel_F_vs_fp64": abs(recs[-1]["F"] - F64) / abs(F64),
                      "kernel_ms_per_step": {KERNEL_SYMBOLS[c]: round(kms[c], 3) for c in range(3)}}
         log("step %s: %.1f ms" % (prec, dt * 1e3))
         del prob

@@ -95,6 +95,12 @@ typedef struct {
   double kernel_ms[3];
   double kernel_bytes[3];
   int kernel_launches[3];
+  /* host time of the solve in the q x q FP64 linear algebra, and waiting for
+   * the device (the synchronisations that bring small results to the host),
+   * and the number of those synchronisations */
+  double host_la_seconds;
+  double host_wait_seconds;
+  int host_syncs;
 } bmg_result;
 
 /* Fills the defaults: alpha 1.99, tol 1e-6, ssi_tol_floor 1e-12, psi0 0.1,

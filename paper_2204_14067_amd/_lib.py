@@ -46,7 +46,9 @@ class BmgResult(ctypes.Structure):
                 ("residual", ctypes.c_double), ("eps", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("sparse_bytes", ctypes.c_double),
                 ("sparse_passes", ctypes.c_int), ("kernel_ms", ctypes.c_double * 3),
-                ("kernel_bytes", ctypes.c_double * 3), ("kernel_launches", ctypes.c_int * 3)]
+                ("kernel_bytes", ctypes.c_double * 3), ("kernel_launches", ctypes.c_int * 3),
+                ("host_la_seconds", ctypes.c_double), ("host_wait_seconds", ctypes.c_double),
+                ("host_syncs", ctypes.c_int)]
 
     def as_dict(self):
         out = {}

@@ -49,6 +49,42 @@ struct BmgError {
     if (!(cond)) throw BmgError{st, msg}; \
   } while (0)
 
+// ============================================================================ host accounting
+// Host time in the q x q linear algebra and in waits for the device, per solve
+// (each solve runs on one host thread).
+static thread_local double t_la_acc = 0.0, t_wait_acc = 0.0;
+static thread_local int n_sync_acc = 0;
+struct HostTimer {
+  double &acc;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  explicit HostTimer(double &a) : acc(a) {}
+  ~HostTimer() {
+    acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+namespace lat {
+inline void sym_eig(int n, const double *A, double *w, double *V) {
+  HostTimer t(t_la_acc);
+  la::sym_eig(n, A, w, V);
+}
+inline int chol_pivoted(int n, const double *G, double tol, int *perm, double *R) {
+  HostTimer t(t_la_acc);
+  return la::chol_pivoted(n, G, tol, perm, R);
+}
+inline bool chol(int n, const double *G, double *R) {
+  HostTimer t(t_la_acc);
+  return la::chol(n, G, R);
+}
+inline void tri_inv_upper(int n, const double *R, double *Rinv) {
+  HostTimer t(t_la_acc);
+  la::tri_inv_upper(n, R, Rinv);
+}
+inline bool spd_inv(int n, const double *A, double *Ainv) {
+  HostTimer t(t_la_acc);
+  return la::spd_inv(n, A, Ainv);
+}
+}  // namespace lat
+
 // ============================================================================ constants
 static constexpr double ORTH_TOL = 1e-6;   // numerical-rank cut of orth() on unit columns
 static constexpr double SSI_EPS = 1e-12;   // Algorithm 2's cut of small s (relative)
@@ -555,7 +591,11 @@ struct Engine {
   }
   void fetch(double *h, const double *d, size_t cnt) {
     HIPC(hipMemcpyAsync(h, d, 8 * cnt, hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
+    {
+      HostTimer t(t_wait_acc);
+      HIPC(hipStreamSynchronize(s));
+    }
+    n_sync_acc += 1;
     if (!P->pend.empty()) P->resolve_timing();
   }
   // ---------------------------------------------------------------- dense helpers
@@ -565,6 +605,19 @@ struct Engine {
     HIPC(launch_gram<T>(N, a, X, ldx, b, Y, ldy, P->gram_part, P->L.gram_cap, P->small, s));
     fetch(h.data(), P->small, (size_t)a * b);
     return h;
+  }
+  // X^T Y (a x b) into device staging slot `slot` as T, without a host round trip
+  T *gram_dev(int64_t N, int a, const T *X, int ldx, int b, const T *Y, int ldy, int slot) {
+    double *d = P->small + (size_t)(slot + 1) * P->L.qld * P->L.qld;
+    REQUIRE((size_t)a * b <= (size_t)P->L.qld * P->L.qld, BMG_EINVAL, "small matrix too large");
+    if (a == 0 || b == 0) return (T *)d;
+    if constexpr (sizeof(T) == 8) {
+      HIPC(launch_gram<T>(N, a, X, ldx, b, Y, ldy, P->gram_part, P->L.gram_cap, d, s));
+    } else {
+      HIPC(launch_gram<T>(N, a, X, ldx, b, Y, ldy, P->gram_part, P->L.gram_cap, P->small, s));
+      HIPC((launch_convert<double, T>((int64_t)a * b, P->small, (T *)d, s)));
+    }
+    return (T *)d;
   }
   // upload a small FP64 matrix into the device staging area (slot 0..7)
   double *put(const std::vector<double> &h, int slot) {
@@ -697,7 +750,7 @@ struct Engine {
   void z_t(const ZOp &z, const T *U, int q, T *Y) {
     if (q == 0) return;
     T *dM = nullptr;
-    if (z.k > 0) dM = put_t(gram(m, z.k, z.W, ldk, q, U, qld), 0);
+    if (z.k > 0) dM = gram_dev(m, z.k, z.W, ldk, q, U, qld, 0);
     with_gather(2, U, m, q, qld, [&](auto Ug) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Ug)>>;
       pass<TY>(2, C->pl, z.s_cols, z.H, ldk, Ug, qld, q, 0.0, -z.alpha, Y, qld, z.k, dM, q, sx(2));
@@ -708,7 +761,7 @@ struct Engine {
   void z_n(const ZOp &z, const T *Y, int q, T *V) {
     if (q == 0) return;
     T *dM = nullptr;
-    if (z.k > 0) dM = put_t(gram(n, z.k, z.H, ldk, q, Y, qld), 1);
+    if (z.k > 0) dM = gram_dev(n, z.k, z.H, ldk, q, Y, qld, 1);
     with_gather(3, Y, n, q, qld, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
       pass<TY>(2, R->pl, z.s_rows, z.W, ldk, Yg, qld, q, 0.0, -z.alpha, V, qld, z.k, dM, q, sx(2));
@@ -737,12 +790,12 @@ struct Engine {
       for (int j = 0; j < c2; ++j)
         Gn[(size_t)i * c2 + j] = G[(size_t)nz[i] * c + nz[j]] / (dn[i] * dn[j]);
     std::vector<int> perm(c2);
-    const int r = la::chol_pivoted(c2, Gn.data(), ORTH_TOL * ORTH_TOL, perm.data(), Rp.data());
+    const int r = lat::chol_pivoted(c2, Gn.data(), ORTH_TOL * ORTH_TOL, perm.data(), Rp.data());
     if (r == 0) return 0;
     std::vector<double> R11((size_t)r * r), Ri((size_t)r * r);
     for (int i = 0; i < r; ++i)
       for (int j = 0; j < r; ++j) R11[(size_t)i * r + j] = (j >= i) ? Rp[(size_t)i * c2 + j] : 0.0;
-    la::tri_inv_upper(r, R11.data(), Ri.data());
+    lat::tri_inv_upper(r, R11.data(), Ri.data());
     std::vector<double> Cm((size_t)c * r, 0.0);  // Q1 = M Cm
     for (int jj = 0; jj < r; ++jj) {
       const int col = nz[perm[jj]];
@@ -752,22 +805,22 @@ struct Engine {
     gemm(N, c, M, qld, r, Cm, tmp, qld, 0.0);
     // re-orthogonalise
     std::vector<double> G2 = gram(N, r, tmp, qld, r, tmp, qld), R2((size_t)r * r), R2i((size_t)r * r);
-    if (!la::chol(r, G2.data(), R2.data())) {
+    if (!lat::chol(r, G2.data(), R2.data())) {
       // loss of orthogonality beyond repair by one pass: fall back to a second pivoted pass
       std::vector<int> p2(r);
       std::vector<double> Rq((size_t)r * r);
-      const int r2 = la::chol_pivoted(r, G2.data(), 1e-14, p2.data(), Rq.data());
+      const int r2 = lat::chol_pivoted(r, G2.data(), 1e-14, p2.data(), Rq.data());
       REQUIRE(r2 > 0, BMG_ENONFINITE, "orthonormalisation broke down");
       std::vector<double> Q11((size_t)r2 * r2), Qi((size_t)r2 * r2), C2((size_t)r * r2, 0.0);
       for (int i = 0; i < r2; ++i)
         for (int j = 0; j < r2; ++j) Q11[(size_t)i * r2 + j] = (j >= i) ? Rq[(size_t)i * r + j] : 0.0;
-      la::tri_inv_upper(r2, Q11.data(), Qi.data());
+      lat::tri_inv_upper(r2, Q11.data(), Qi.data());
       for (int jj = 0; jj < r2; ++jj)
         for (int l = 0; l < r2; ++l) C2[(size_t)p2[jj] * r2 + l] = Qi[(size_t)jj * r2 + l];
       gemm(N, r, tmp, qld, r2, C2, U, qld, 0.0);
       return r2;
     }
-    la::tri_inv_upper(r, R2.data(), R2i.data());
+    lat::tri_inv_upper(r, R2.data(), R2i.data());
     gemm(N, r, tmp, qld, r, R2i, U, qld, 0.0);
     return r;
   }
@@ -994,7 +1047,7 @@ struct Method : Engine<T, TG> {
     std::vector<double> Pk = gram(noth, k, oth, ldk, k, oth, ldk);
     for (int i = 0; i < k; ++i) Pk[(size_t)i * k + i] += lam;
     std::vector<double> Pi((size_t)k * k);
-    REQUIRE(la::spd_inv(k, Pk.data(), Pi.data()), BMG_ENONFINITE, "BM preconditioner not SPD");
+    REQUIRE(lat::spd_inv(k, Pk.data(), Pi.data()), BMG_ENONFINITE, "BM preconditioner not SPD");
     std::vector<double> GG = gram(nown, k, G, ldk, k, G, ldk);
     // <G, D> = -tr(G^T G P), ||D||^2 = tr(P G^T G P)
     const double gd = trace_prod(GG, Pi, k);
@@ -1043,7 +1096,7 @@ struct Method : Engine<T, TG> {
     out.q = q;
     if (q == 0) return out;
     std::vector<double> w(q), V((size_t)q * q);
-    la::sym_eig(q, Tq.data(), w.data(), V.data());
+    lat::sym_eig(q, Tq.data(), w.data(), V.data());
     out.sig_hat.resize(q);
     for (int j = 0; j < q; ++j) {
       out.sig_hat[j] = sqrt(std::max(w[j], 0.0));
@@ -1089,7 +1142,7 @@ struct Method : Engine<T, TG> {
     for (it = 1; it <= max_iter && q > 0; ++it) {
       std::vector<double> Tm = gram(n, q, Y, qld, q, Y, qld);
       std::vector<double> theta(q);
-      la::sym_eig(q, Tm.data(), theta.data(), nullptr);
+      lat::sym_eig(q, Tm.data(), theta.data(), nullptr);
       z_n(z, Y, q, V);                 // L(U) = Z Z^T U (Ritz rotation omitted: same range)
       q = orth(m, V, q, U, tmp);       // U^{t,i+1}
       z_t(z, U, q, Y);
@@ -1168,7 +1221,7 @@ struct Method : Engine<T, TG> {
       std::vector<double> Rh = gram(m, r2, B1, qld, r, B3, qld);  // R^ = Q^^T A Q (r2 x r)
       // pseudo-inverse of C through its eigen-decomposition
       std::vector<double> cw(r), cv((size_t)r * r), Cp((size_t)r * r, 0.0);
-      la::sym_eig(r, Cm.data(), cw.data(), cv.data());
+      lat::sym_eig(r, Cm.data(), cw.data(), cv.data());
       for (int l = 0; l < r; ++l) {
         if (!(cw[0] > 0.0) || !(cw[l] > PINV_REL * cw[0])) continue;
         const double inv = 1.0 / cw[l];
@@ -1189,7 +1242,7 @@ struct Method : Engine<T, TG> {
           Mn[(size_t)i * r2 + j] = a;
         }
       std::vector<double> mw(r2), mv((size_t)r2 * r2);
-      la::sym_eig(r2, Mn.data(), mw.data(), mv.data());
+      lat::sym_eig(r2, Mn.data(), mw.data(), mv.data());
       std::vector<int> pos;
       for (int l = 0; l < r2; ++l)
         if (mw[0] > 0.0 && mw[l] > SSI_EPS * mw[0]) pos.push_back(l);
@@ -1382,6 +1435,8 @@ struct Method : Engine<T, TG> {
   // Algorithm 1
   bmg_status solve(const bmg_options &o, State &S, bmg_result *res) {
     const auto t0 = std::chrono::steady_clock::now();
+    t_la_acc = t_wait_acc = 0.0;
+    n_sync_acc = 0;
     init_state(S);
     S.psi = o.psi0;
     initialize(S, o.k_init, o.lambda, o.seed);
@@ -1438,6 +1493,9 @@ struct Method : Engine<T, TG> {
         res->kernel_bytes[c] = P->kbytes[c];
         res->kernel_launches[c] = P->klaunch[c];
       }
+      res->host_la_seconds = t_la_acc;
+      res->host_wait_seconds = t_wait_acc;
+      res->host_syncs = n_sync_acc;
       res->k = S.k;
       res->iters = t;
       res->ssi_iters = ssi_total;
@@ -1529,7 +1587,7 @@ extern "C" bmg_status bmg_objective(bmg_problem *P, const double *W, const doubl
       std::vector<double> WW = M.gram(M.m, k, Wi, P->L.ldk, k, Wi, P->L.ldk);
       std::vector<double> HH = M.gram(M.n, k, Hi, P->L.ldk, k, Hi, P->L.ldk);
       std::vector<double> w(k), V((size_t)k * k), Sm((size_t)k * k), T1((size_t)k * k), T2((size_t)k * k);
-      la::sym_eig(k, WW.data(), w.data(), V.data());
+      lat::sym_eig(k, WW.data(), w.data(), V.data());
       for (int i = 0; i < k; ++i)
         for (int j = 0; j < k; ++j) Sm[(size_t)i * k + j] = sqrt(std::max(w[i], 0.0)) * V[(size_t)j * k + i];
       for (int i = 0; i < k; ++i)
@@ -1544,7 +1602,7 @@ extern "C" bmg_status bmg_objective(bmg_problem *P, const double *W, const doubl
           for (int l = 0; l < k; ++l) a += T1[(size_t)i * k + l] * Sm[(size_t)j * k + l];
           T2[(size_t)i * k + j] = a;
         }
-      la::sym_eig(k, T2.data(), w.data(), nullptr);
+      lat::sym_eig(k, T2.data(), w.data(), nullptr);
       for (int i = 0; i < k; ++i) nuc += sqrt(std::max(w[i], 0.0));
     }
     if (F) *F = f + lambda * nuc;

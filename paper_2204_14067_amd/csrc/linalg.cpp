@@ -186,31 +186,42 @@ int chol_pivoted(int n, const double *G, double tol, int *perm, double *R) {
 }
 
 bool chol(int n, const double *G, double *R) {
+  // right-looking: row j of R from the current Schur complement (upper
+  // triangle only, kept in R itself), then a rank-1 update of the trailing rows
   memset(R, 0, sizeof(double) * (size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int l = i; l < n; ++l) R[(size_t)i * n + l] = G[(size_t)i * n + l];
   for (int j = 0; j < n; ++j) {
-    double s = G[(size_t)j * n + j];
-    for (int k = 0; k < j; ++k) s -= R[(size_t)k * n + j] * R[(size_t)k * n + j];
+    double *rj = &R[(size_t)j * n];
+    const double s = rj[j];
     if (!(s > 0.0)) return false;
-    const double rjj = sqrt(s);
-    R[(size_t)j * n + j] = rjj;
+    const double rjj = sqrt(s), inv = 1.0 / rjj;
+    rj[j] = rjj;
+    for (int l = j + 1; l < n; ++l) rj[l] *= inv;
     for (int i = j + 1; i < n; ++i) {
-      double t = G[(size_t)j * n + i];
-      for (int k = 0; k < j; ++k) t -= R[(size_t)k * n + j] * R[(size_t)k * n + i];
-      R[(size_t)j * n + i] = t / rjj;
+      double *ri = &R[(size_t)i * n];
+      const double f = rj[i];
+      for (int l = i; l < n; ++l) ri[l] -= f * rj[l];
     }
   }
   return true;
 }
 
 void tri_inv_upper(int n, const double *R, double *X) {
-  // solve R X = I column by column (back substitution)
+  // rows from the bottom: X[i, :] = (e_i - sum_{k > i} R[i, k] X[k, :]) / R[i, i];
+  // row k of X is zero left of column k, so each update is a contiguous axpy
   memset(X, 0, sizeof(double) * (size_t)n * n);
-  for (int c = 0; c < n; ++c) {
-    for (int i = c; i >= 0; --i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = i + 1; k <= c; ++k) s -= R[(size_t)i * n + k] * X[(size_t)k * n + c];
-      X[(size_t)i * n + c] = s / R[(size_t)i * n + i];
+  for (int i = n - 1; i >= 0; --i) {
+    double *xi = &X[(size_t)i * n];
+    const double *ri = &R[(size_t)i * n];
+    for (int k = i + 1; k < n; ++k) {
+      const double f = ri[k];
+      const double *xk = &X[(size_t)k * n];
+      for (int c = k; c < n; ++c) xi[c] -= f * xk[c];
     }
+    const double inv = 1.0 / ri[i];
+    xi[i] = 1.0;
+    for (int c = i; c < n; ++c) xi[c] *= inv;
   }
 }
 
@@ -218,12 +229,13 @@ bool spd_inv(int n, const double *A, double *Ainv) {
   std::vector<double> R((size_t)n * n), Ri((size_t)n * n);
   if (!chol(n, A, R.data())) return false;
   tri_inv_upper(n, R.data(), Ri.data());
-  // A^{-1} = R^{-1} R^{-T}
+  // A^{-1} = R^{-1} R^{-T}: entry (i, j) is the dot of rows i and j of R^{-1}
+  // from column max(i, j) on (the rows are zero left of their diagonal)
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int k = std::max(i, j); k < n; ++k) s += Ri[(size_t)i * n + k] * Ri[(size_t)j * n + k];
+    for (int j = i; j < n; ++j) {
+      const double s = dot(&Ri[(size_t)i * n + j], &Ri[(size_t)j * n + j], n - j);
       Ainv[(size_t)i * n + j] = s;
+      Ainv[(size_t)j * n + i] = s;
     }
   return true;
 }
