@@ -222,19 +222,15 @@ __device__ __forceinline__ void grad_block(const Plan &pl, const T *__restrict__
   Row<T, TG, G, C> y[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
-    if (u < n) {
-      j[u] = nt_load(pl.idx + p + u * step);
-      av[u] = nt_load(a + p + u * step);
-    } else {
-      j[u] = -1;
-      av[u] = T(0);
-    }
+    // entries past the block read entry p (always valid) and are masked out
+    const int64_t pp = p + (u < n ? u * step : 0);
+    const int jv = nt_load(pl.idx + pp);
+    const T avv = nt_load(a + pp);
+    j[u] = u < n ? jv : -1;
+    av[u] = u < n ? avv : T(0);
   }
 #pragma unroll
-  for (int u = 0; u < UNROLL; ++u) {
-    if (j[u] >= 0) y[u].load(Y + (int64_t)j[u] * ldy, sub, k);
-    else y[u].zero();
-  }
+  for (int u = 0; u < UNROLL; ++u) y[u].load(Y + (int64_t)(j[u] < 0 ? 0 : j[u]) * ldy, sub, k);
   T d[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) d[u] = x.dot(y[u]);
@@ -242,11 +238,9 @@ __device__ __forceinline__ void grad_block(const Plan &pl, const T *__restrict__
   for (int u = 0; u < UNROLL; ++u) d[u] = group_sum<G>(d[u]);
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
-    if (u < n) {
-      const T r = d[u] - av[u];
-      acc.axpy(r, y[u]);
-      if (leader) ss += (double)r * (double)r;
-    }
+    const T r = d[u] - av[u];
+    acc.axpy(u < n ? r : T(0), y[u]);
+    if (leader && u < n) ss += (double)r * (double)r;
   }
 }
 
@@ -286,9 +280,13 @@ __device__ __forceinline__ void team_row(const Plan &pl, int row, const T *__res
     T al[TM::LPL];
 #pragma unroll
     for (int l = 0; l < TM::LPL; ++l) {
+      // entries past the row read its last entry (valid) and are masked out
       const int64_t pe = p0 + l * TM::TL + tl;
-      jl[l] = pe < end ? nt_load(pl.idx + pe) : -1;
-      al[l] = (pe < end && a) ? nt_load(a + pe) : T(0);
+      const int64_t pc = pe < end ? pe : end - 1;
+      const int jv = nt_load(pl.idx + pc);
+      const T avv = a ? nt_load(a + pc) : T(0);
+      jl[l] = pe < end ? jv : -1;
+      al[l] = pe < end ? avv : T(0);
     }
     // batches stay rolled (UNROLL gathers in flight are enough); only G = 2
     // has two load slots, and it has a single batch
@@ -311,10 +309,8 @@ __device__ __forceinline__ void team_row(const Plan &pl, int row, const T *__res
         }
       }
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        if (j[u] >= 0) y[u].load(Y + (int64_t)j[u] * ldy, sub, width);
-        else y[u].zero();
-      }
+      for (int u = 0; u < UNROLL; ++u)
+        y[u].load(Y + (int64_t)(j[u] < 0 ? 0 : j[u]) * ldy, sub, width);
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
         if (MODE == TM_SPMM) {
@@ -438,19 +434,14 @@ __device__ __forceinline__ void sddmm_block(const Plan &pl, const T *__restrict_
   Row<T, TG, G, C> y[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
-    if (u < n) {
-      j[u] = nt_load(pl.idx + p + u * step);
-      av[u] = a ? nt_load(a + p + u * step) : T(0);
-    } else {
-      j[u] = -1;
-      av[u] = T(0);
-    }
+    const int64_t pp = p + (u < n ? u * step : 0);
+    const int jv = nt_load(pl.idx + pp);
+    const T avv = a ? nt_load(a + pp) : T(0);
+    j[u] = u < n ? jv : -1;
+    av[u] = u < n ? avv : T(0);
   }
 #pragma unroll
-  for (int u = 0; u < UNROLL; ++u) {
-    if (j[u] >= 0) y[u].load(Y + (int64_t)j[u] * ldy, sub, k);
-    else y[u].zero();
-  }
+  for (int u = 0; u < UNROLL; ++u) y[u].load(Y + (int64_t)(j[u] < 0 ? 0 : j[u]) * ldy, sub, k);
   T d[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) d[u] = group_sum<G>(x.dot(y[u]));
@@ -525,19 +516,14 @@ __device__ __forceinline__ void spmm_block(const Plan &pl, const T *__restrict__
   Row<T, TG, G, C> b[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
-    if (u < n) {
-      j[u] = nt_load(pl.idx + p + u * step);
-      sv[u] = nt_load(Sv + p + u * step);
-    } else {
-      j[u] = -1;
-      sv[u] = T(0);
-    }
+    const int64_t pp = p + (u < n ? u * step : 0);
+    const int jv = nt_load(pl.idx + pp);
+    const T svv = nt_load(Sv + pp);
+    j[u] = u < n ? jv : -1;
+    sv[u] = u < n ? svv : T(0);
   }
 #pragma unroll
-  for (int u = 0; u < UNROLL; ++u) {
-    if (j[u] >= 0) b[u].load(B + (int64_t)j[u] * ldb, sub, wq);
-    else b[u].zero();
-  }
+  for (int u = 0; u < UNROLL; ++u) b[u].load(B + (int64_t)(j[u] < 0 ? 0 : j[u]) * ldb, sub, wq);
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) acc.axpy(sv[u], b[u]);
 }
