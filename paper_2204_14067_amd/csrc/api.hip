@@ -1460,8 +1460,13 @@ struct Method : Engine<T, TG> {
         changed |= bm_half(false, S.W, S.H, S.k, o.lambda);
       }
       F_bm = bm_objective(S.W, S.H, S.k, o.lambda);
-      // FP32 passes cannot resolve Ritz values below ~1e-7 of the largest
-      const double floor = std::max(o.ssi_tol_floor, sizeof(T) == 4 ? 1e-6 : 0.0);
+      // FP32 passes cannot resolve Ritz values below ~1e-7 of the largest, and
+      // passes gathering BF16 operands (relative rounding up to 2^-9) not below
+      // ~1e-3: the subspace iteration stops at that resolution instead of
+      // running into its iteration cap (refresh steps gather FP32)
+      const bool bf16_gathers = kShadow && !refresh && !hi;
+      const double floor =
+          std::max(o.ssi_tol_floor, bf16_gathers ? 1e-3 : sizeof(T) == 4 ? 1e-6 : 0.0);
       const double tau = std::max(floor, std::min(1e-4, 0.1 * S.res_prev * S.res_prev));
       StepInfo st = pg_step(S, changed, o.lambda, o.alpha, tau, o.ssi_max_iter, o.seed, t, refresh);
       ssi_total += st.iters;

@@ -624,7 +624,7 @@ __global__ __launch_bounds__(256) void k_spmm_fix(Plan pl, const T *__restrict__
 // ============================================================================ launchers
 // Lane group G and chunk count C for a width w (V elements of the gathered type
 // per lane): G = 2 or 4 for narrow rows (one partial line), G = 8 with
-// C = ceil(w / (8 V)) line-sized chunks up to 8 chunks, beyond that G = 16 with
+// C = ceil(w / (8 V)) line-sized chunks up to 4 chunks, beyond that G = 16 with
 // C = ceil(w / (16 V)) two-line chunks.
 struct GC {
   int G, C;
@@ -632,12 +632,14 @@ struct GC {
 static inline GC pick_gc(int width, int V) {
   if (width <= 2 * V) return {2, 1};
   if (width <= 4 * V) return {4, 1};
-  if (width <= 64 * V) {
+  if (width <= 32 * V) {
     const int c = (width + 8 * V - 1) / (8 * V);
     return {8, c < 1 ? 1 : c};
   }
+  // wider rows: 16-lane groups keep the per-lane registers (and so the
+  // occupancy) of at most 4 chunks up to 64 V columns
   const int c = (width + 16 * V - 1) / (16 * V);
-  return {16, c < 5 ? 5 : c};
+  return {16, c < 3 ? 3 : c};
 }
 // bytes of one piece's partial row for a launch of geometry gc
 template <typename T, typename TG>
@@ -651,6 +653,8 @@ static inline int64_t partial_row_bytes(const GC &gc) {
     if (gc.G == 2) { constexpr int GG = 2, CC = 1; __VA_ARGS__; }                       \
     else if (gc.G == 4) { constexpr int GG = 4, CC = 1; __VA_ARGS__; }                  \
     else if (gc.G == 16) switch (gc.C) {                                                \
+      case 3: { constexpr int GG = 16, CC = 3; __VA_ARGS__; } break;                    \
+      case 4: { constexpr int GG = 16, CC = 4; __VA_ARGS__; } break;                    \
       case 5: { constexpr int GG = 16, CC = 5; __VA_ARGS__; } break;                    \
       case 6: { constexpr int GG = 16, CC = 6; __VA_ARGS__; } break;                    \
       case 7: { constexpr int GG = 16, CC = 7; __VA_ARGS__; } break;                    \
@@ -660,11 +664,7 @@ static inline int64_t partial_row_bytes(const GC &gc) {
       case 1: { constexpr int GG = 8, CC = 1; __VA_ARGS__; } break;                     \
       case 2: { constexpr int GG = 8, CC = 2; __VA_ARGS__; } break;                     \
       case 3: { constexpr int GG = 8, CC = 3; __VA_ARGS__; } break;                     \
-      case 4: { constexpr int GG = 8, CC = 4; __VA_ARGS__; } break;                     \
-      case 5: { constexpr int GG = 8, CC = 5; __VA_ARGS__; } break;                     \
-      case 6: { constexpr int GG = 8, CC = 6; __VA_ARGS__; } break;                     \
-      case 7: { constexpr int GG = 8, CC = 7; __VA_ARGS__; } break;                     \
-      default: { constexpr int GG = 8, CC = 8; __VA_ARGS__; } break;                    \
+      default: { constexpr int GG = 8, CC = 4; __VA_ARGS__; } break;                    \
     }                                                                                   \
   } while (0)
 

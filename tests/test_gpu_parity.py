@@ -68,7 +68,7 @@ def case(name):
 # ----------------------------------------------------------------------------- primitives
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("k", [1, 5, 16, 17, 64, 128, 129, 256])
+@pytest.mark.parametrize("k", [1, 5, 16, 17, 64, 80, 128, 129, 256])
 def test_sddmm_parity(name, k):
     """k > 128 runs 16-lane groups (FP64 rows of more than 8 cache lines)."""
     p = case(name)
