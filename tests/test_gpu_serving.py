@@ -58,3 +58,32 @@ def test_serving_rejects_requests_larger_than_the_arena():
     with pytest.raises(bmg.BmgError, match="ENOMEM"):
         srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp32", lam=r.lam)
     srv.close()
+
+
+def test_serving_mixed_precisions_equal_plain_solves():
+    """FP64, FP32 and BF16 requests in one server: passes of one precision share
+    launches, and every result is bit for bit the plain entry point's."""
+    items = small_requests(6)
+    precs = ["fp64", "fp32", "bf16", "fp64", "fp32", "bf16"]
+    opts = dict(tol=1e-5, k_init=8, max_iter=2000, seed=9)
+    plain = []
+    for (r, p), pr in zip(items, precs):
+        dp = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision=pr,
+                                   device=DEV)
+        W, H, k, res = dp.bmg_solve(lam=r.lam, **opts)
+        plain.append((k, res["F"], res["status"], W.cpu().numpy()[:, :k].copy()))
+    srv = bmg.Server(sum(bmg.Server.footprint(p.m, p.n, p.nnz, 64, pr)
+                         for (_, p), pr in zip(items, precs)) + (1 << 20), max_slots=6, device=DEV)
+    tickets = [srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision=pr, lam=r.lam,
+                          **opts) for (r, p), pr in zip(items, precs)]
+    srv.drain()
+    st = srv.stats()
+    print("stats", st, flush=True)
+    assert st["batched_passes"] > st["shared_launches"] > 0
+    for (r, p), pr, t, (k, F, status, W0) in zip(items, precs, tickets, plain):
+        info, W, H = srv.poll(t, p.m, p.n, 64)
+        print(pr, p.name, info["k"], info["result"]["F"], F, flush=True)
+        assert info["state"] == 2 and info["status"] == status
+        assert info["k"] == k and info["result"]["F"] == F
+        assert np.array_equal(W[:, :k], W0)
+    srv.close()
