@@ -177,7 +177,7 @@ hipError_t launch_gram(int64_t N, int a, const T *X, int ldx, int b, const T *Y,
   if (ab == 0) return hipSuccess;
   const int TA = (a + 15) / 16, TB = (b + 15) / 16;
   const int ny = ((TA + 3) / 4) * ((TB + 3) / 4);
-  int64_t nx = (N + 255) / 256;                 // >= 256 rows per block
+  int64_t nx = (N + 63) / 64;                   // >= 64 rows per block
   const int64_t xmax = (1024 + ny - 1) / ny;    // about 1024 blocks in all
   if (nx > xmax) nx = xmax;
   if (nx * ab > part_cap) nx = part_cap / ab;
