@@ -17,8 +17,10 @@ Function -> passage it follows -> what pins it (tests/test_oracle_*.py):
                           solver = preconditioned steepest descent, exact line search (reading)
                           -> brute-force minimisation of the 1-D quadratic; monotone F~
   orth                    range basis used by eq-ssi, eq. rt0, eq. rt      -> span tests
-  lmsvd                   Algorithm 2 with p_t = 0 (Suppl. A.1.2)
-                          -> dense eigendecomposition of Z Z^T
+  lmsvd                   Algorithm 2, history length p_t >= 0 (Suppl. A.1.2)
+                          -> dense eigendecomposition of Z Z^T; Ritz values against the
+                             dense compression of Z Z^T onto an SVD basis of the subspace;
+                             fewer iterations with history on a slow spectrum
   prox_from_basis         eqs. exactSVD, approxSVD, truncate (Suppl. A.1.1)
                           -> full SVD + soft-threshold (eq. proxnuc) when the basis spans ran(Z)
   initialize              HMT + Nystrom, eq. nys (Suppl. A.1.4)
@@ -333,29 +335,58 @@ class LmsvdResult:
 
 
 SSI_EPS = 1e-12          # Algorithm 2's cut of small s, relative to the largest
+LMSVD_EIG_TOL = 1e-6     # cut of the small eigenvalues of P^T P (eq. PUi; history columns
+                         # have unit norm, so the eigenvalues lie in [0, p])
 
 
 def lmsvd(zop: ZOperator, U0: np.ndarray, tau: float, max_iter: int = 50,
-          keep_level: float = 0.0) -> LmsvdResult:
-    """Algorithm 2 (LmSVD) with history length p_t = 0 (Suppl. A.1.2).
+          keep_level: float = 0.0, p: int = 0, trace: Optional[list] = None) -> LmsvdResult:
+    """Algorithm 2 (LmSVD) with history length p_t = p (Suppl. A.1.2).
 
-    L_t(U) = Z Z^T U.  With p = 0 the block subspace S_{t,i} is ran(U^{t,i}); the
-    subspace optimisation is the Rayleigh-Ritz rotation U^{t,i} V with V the
-    eigenvectors of L^{t,i} = (U^{t,i})^T L_t(U^{t,i}); then
-    U^{t,i+1} = orth(L_t(U^{t,i} V)).  The loop stops once the eigenvalues of
-    L^{t,i} above ``keep_level`` (those the threshold will keep: the square of
-    alpha * lambda) differ from those of L^{t,i-1} by at most
-    tau * (largest eigenvalue).
-    Output columns are those of the last U with s_j = ||Z^T u_j|| > eps."""
+    L_t(U) = Z Z^T U.  The block subspace S_{t,i} is ran(U^{t,i}, ..., U^{t,i-p'})
+    with p' = min(p, i) and U^{t,j} = orth(L_t(Uhat^{t,j-1})).  Its orthonormal
+    basis is Q = [U^{t,i}, P S] (eq. orth-W): P projects the history blocks onto
+    ker((U^{t,i})^T) (eq. PUi) and S = U~ Lambda^{-1/2} over the eigenpairs of
+    P^T P above LMSVD_EIG_TOL (the trimming of nearly zero eigenvalues).  The
+    subspace optimisation (eq. lmsvd-opt) keeps the k_t leading eigenvectors V of
+    L^{t,i} = Q^T L_t(Q) = (Z^T Q)^T (Z^T Q); Uhat^{t,i} = Q V, and
+    U^{t,i+1} = orth(L_t(Uhat^{t,i})).  Z^T Q needs no new product:
+    Z^T P = Z^T U_old - (Z^T U^{t,i}) C with C = (U^{t,i})^T U_old.
+    With p = 0, Q = U^{t,i} and this is the block subspace iteration with a
+    Rayleigh-Ritz rotation.
+    The loop stops once the k_t leading eigenvalues of L^{t,i} above
+    ``keep_level`` (those the threshold will keep: the square of alpha * lambda)
+    differ from those of L^{t,i-1} by at most tau * (largest eigenvalue).
+    Output columns are those of the last U with s_j = ||Z^T u_j|| > eps.
+    ``trace``, when given, receives per iteration the basis Q, the history block
+    U_old, the eigenvalues of P^T P and the k_t leading Ritz values."""
     U = orth(U0)
     Y = zop.rmatmul(U)
+    hist = []                      # (U^{t,j}, Z^T U^{t,j}) for j = i-1, ..., i-p'
     prev = None
     it = 0
     theta = np.zeros(0)
     for it in range(1, max_iter + 1):
-        T = Y.T @ Y
-        theta, V = eigh_desc(T)
-        U = orth(zop.matmul(Y @ V))
+        kt = U.shape[1]
+        Q, Qz, lam, Uold = U, Y, np.zeros(0), None
+        if hist:
+            Uold = np.column_stack([h[0] for h in hist])
+            Yold = np.column_stack([h[1] for h in hist])
+            C = U.T @ Uold
+            Pm = Uold - U @ C                                  # eq. PUi
+            lam, Ut = eigh_desc(Pm.T @ Pm)
+            keep = lam > LMSVD_EIG_TOL
+            S = Ut[:, keep] / np.sqrt(lam[keep])
+            Q = np.column_stack([U, Pm @ S])                   # eq. orth-W
+            Qz = np.column_stack([Y, (Yold - Y @ C) @ S])      # Z^T Q
+        th, V = eigh_desc(Qz.T @ Qz)                           # L^{t,i}
+        theta, V = th[:kt], V[:, :kt]                          # eq. lmsvd-opt
+        if trace is not None:
+            trace.append({"Q": Q, "Uold": Uold, "lam": lam, "theta": theta})
+        Unew = orth(zop.matmul(Qz @ V))                        # orth(L_t(Q V))
+        if p > 0:
+            hist = ([(U, Y)] + hist)[:p]
+        U = Unew
         Y = zop.rmatmul(U)
         done = False
         if prev is not None and len(prev) == len(theta) and len(theta) > 0:
@@ -477,6 +508,7 @@ class Options:
     ssi_tol_floor: float = 1e-12
     psi0: float = 0.1
     seed: int = 0
+    lmsvd_p: int = 0             # p_t of Algorithm 2 (history blocks)
 
 
 @dataclass
@@ -505,22 +537,23 @@ class SolveResult:
 
 
 def prox_step_standalone(prob, W, H, lam: float, alpha: float = 1.99, seed: int = 0,
-                         tau: float = 1e-12, max_iter: int = 50):
+                         tau: float = 1e-12, max_iter: int = 50, p: int = 0):
     """One inexact PG step from X~ = W H^T with no history: warm start orth(W~)
     (eq. rt0 without a previous prox output) plus the safeguard column of eq. rt
     with no retained vector (a unit random vector, stream STREAM_SAFEGUARD + 0),
-    Algorithm 2 with p = 0 to tolerance tau, exact SVD and threshold alpha*lam.
+    Algorithm 2 with history length p to tolerance tau, exact SVD and threshold
+    alpha*lam.
     Returns (ProxResult, LmsvdResult, relative residual).  For m > n the step
     runs on the transpose (Sec. 1) and the output factors are swapped back."""
     if prob.m > prob.n:
-        pr, ls, res = prox_step_standalone(transpose(prob), H, W, lam, alpha, seed, tau, max_iter)
+        pr, ls, res = prox_step_standalone(transpose(prob), H, W, lam, alpha, seed, tau, max_iter, p)
         pr.W, pr.H = pr.H, pr.W
         return pr, ls, res
     R = sddmm(prob, W, H)
     zop = ZOperator(prob, W, H, R, alpha)
     Ubase = orth(W)
     U0 = orth(np.column_stack([Ubase, safeguard_column(Ubase, None, 0.0, seed, 0)]))
-    ls = lmsvd(zop, U0, tau, max_iter, (alpha * lam) ** 2)
+    ls = lmsvd(zop, U0, tau, max_iter, (alpha * lam) ** 2, p)
     pr = prox_from_basis(ls.Uhat, ls.Y, alpha * lam)
     return pr, ls, relative_residual(prob, W, H, R, ls.Uhat, pr.W, pr.H)
 
@@ -611,7 +644,7 @@ def _solve(prob, opt: Options, callback=None) -> SolveResult:
         else:
             U0 = Ubase
         tau = ssi_tolerance(res_prev, opt.ssi_tol_floor)
-        ls = lmsvd(zop, U0, tau, opt.ssi_max_iter, (alpha * lam) ** 2)
+        ls = lmsvd(zop, U0, tau, opt.ssi_max_iter, (alpha * lam) ** 2, opt.lmsvd_p)
         pr = prox_from_basis(ls.Uhat, ls.Y, alpha * lam)
         eps2 = zop.fro2() - float(np.sum(pr.sigma_hat ** 2))
         res = relative_residual(prob, Wt, Ht, R, ls.Uhat, pr.W, pr.H)

@@ -187,6 +187,91 @@ def test_lmsvd_finds_dominant_subspace():
     assert np.allclose(np.linalg.svd(ls.Y, compute_uv=False)[:3], s[:3], rtol=1e-9)
 
 
+class _DenseOp:
+    """Z given as a dense matrix, with the two products Algorithm 2 uses."""
+
+    def __init__(self, Z):
+        self.Z = Z
+
+    def matmul(self, B):
+        return self.Z @ B
+
+    def rmatmul(self, U):
+        return self.Z.T @ U
+
+
+def _slow_spectrum(m, n, decay, seed):
+    """Z = U diag(decay^j) V^T with random orthonormal U, V: eigenvalues of Z Z^T
+    so close that the block subspace iteration converges slowly."""
+    r = min(m, n)
+    Uz = np.linalg.qr(rand((m, r), seed))[0]
+    Vz = np.linalg.qr(rand((n, r), seed + 1))[0]
+    s = decay ** np.arange(r)
+    return Uz @ np.diag(s) @ Vz.T, s
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_lmsvd_history_ritz_values_are_optimal_over_the_subspace(p):
+    # eqs. PUi, orth-W, lmsvd-opt: the k_t Ritz values are the leading eigenvalues
+    # of Z Z^T compressed onto ran(U^{t,i}, ..., U^{t,i-p}), whose basis here comes
+    # from an SVD of the stacked blocks (not from the projection of eq. PUi)
+    Z, _ = _slow_spectrum(60, 90, 0.98, 11)
+    kt = 4
+    tr = []
+    core.lmsvd(_DenseOp(Z), rand((60, kt), 12), 0.0, max_iter=6, p=p, trace=tr)
+    assert len(tr) == 6
+    checked = 0
+    for i, rec in enumerate(tr):
+        Q, Uold = rec["Q"], rec["Uold"]
+        assert np.allclose(Q.T @ Q, np.eye(Q.shape[1]), atol=1e-12)
+        if i == 0:
+            assert Uold is None and Q.shape[1] == kt
+            continue
+        assert Uold.shape[1] == kt * min(p, i)
+        # the inputs keep every history direction well away from the cut
+        assert rec["lam"].min() > 10 * core.LMSVD_EIG_TOL
+        Ui = Q[:, :kt]
+        Ub, sb, _ = np.linalg.svd(np.column_stack([Ui, Uold]), full_matrices=False)
+        B = Ub[:, sb > 1e-8]
+        assert B.shape[1] == Q.shape[1]
+        assert np.allclose(B @ (B.T @ Q), Q, atol=1e-10)
+        ev = np.sort(np.linalg.eigvalsh(B.T @ Z @ Z.T @ B))[::-1][:kt]
+        assert np.allclose(rec["theta"], ev, rtol=1e-11, atol=1e-14)
+        checked += 1
+    assert checked == 5
+
+
+def test_lmsvd_history_reaches_dominant_subspace_in_fewer_iterations():
+    # Algorithm 2 with p >= 1 converges to the same leading eigenpairs as p = 0
+    # (dense eigendecomposition) and, on a slowly decaying spectrum, in fewer
+    # iterations: the point of the history blocks
+    Z, s = _slow_spectrum(80, 120, 0.95, 21)
+    kt = 5
+    U0 = rand((80, kt), 22)
+    its = {}
+    for p in (0, 1, 2):
+        ls = core.lmsvd(_DenseOp(Z), U0, 1e-13, max_iter=2000, p=p)
+        its[p] = ls.iters
+        assert ls.iters < 2000
+        assert np.allclose(ls.ritz, s[:kt] ** 2, rtol=1e-9)
+        Pu = ls.Uhat @ ls.Uhat.T
+        Ud = np.linalg.svd(Z)[0][:, :kt]
+        assert np.allclose(Pu @ Ud, Ud, atol=1e-5)
+    assert its[1] < 0.8 * its[0] and its[2] < its[1]
+
+
+def test_solve_with_lmsvd_history_matches_dense_proximal_gradient():
+    p = tiny_problem(40, 60, 700, lam=0.3, rank=3, seed=5)
+    A, M = dense.to_dense(p)
+    Xd, _ = dense.proximal_gradient_dense(A, M, 0.3, alpha=1.99, tol=1e-14)
+    Fd = dense.mc_objective_dense(Xd, A, M, 0.3)
+    for hp in (1, 2):
+        res = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-11, seed=3, lmsvd_p=hp))
+        assert res.converged
+        assert math.isclose(res.F, Fd, rel_tol=1e-11)
+        assert np.allclose((res.W @ res.H.T)[M], Xd[M], atol=1e-6)
+
+
 def test_prox_with_full_basis_equals_closed_form():
     """eq. proxnuc: with Uhat spanning R^m the inexact step is the exact prox."""
     p = tiny_problem(12, 20, 120, lam=0.4)
