@@ -73,6 +73,8 @@ typedef struct {
   int refresh_every;    /* BF16 mode: FP64 refresh period (outer iterations)     */
   int verbose;          /* print one line per outer iteration to stderr          */
   int timing;           /* time every sparse-pass kernel with HIP events         */
+  int lmsvd_p;          /* p_t of Algorithm 2: history blocks of the subspace     *
+                         * (0: block subspace iteration; at most 4, see below)   */
   uint64_t seed;        /* counter-based RNG seed (sketch and safeguard draws)   */
 } bmg_options;
 
@@ -104,7 +106,16 @@ typedef struct {
 } bmg_result;
 
 /* Fills the defaults: alpha 1.99, tol 1e-6, ssi_tol_floor 1e-12, psi0 0.1,
- * bm_epochs 3, max_iter 500, ssi_max_iter 50, k_init 8, refresh_every 5. */
+ * bm_epochs 3, max_iter 500, ssi_max_iter 50, k_init 8, refresh_every 5,
+ * lmsvd_p 0.
+ * lmsvd_p = p >= 1 (Algorithm 2 with history, Suppl. A.1.2: the Ritz step runs
+ * over ran(U^{t,i}, ..., U^{t,i-p}) with the basis of eqs. PUi and orth-W) needs
+ * device memory beyond the workspace: (2p-1) blocks of min(m,n) x qb and 3p
+ * blocks of max(m,n) x qb elements of the working precision, qb = 2 k_cap + 2
+ * rounded up to a multiple of 16
+ * (FP64 in BMG_FP64, FP32 otherwise).  The first solve or prox step that asks for
+ * a larger p than before allocates it with hipMalloc; the problem keeps it
+ * until bmg_problem_destroy.  BMG_EINVAL for p outside [0, 4]. */
 void bmg_options_default(bmg_options *opt);
 
 /* Bytes of device workspace a problem of this shape needs when the rank may

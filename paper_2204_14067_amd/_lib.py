@@ -37,7 +37,8 @@ class BmgOptions(ctypes.Structure):
                 ("bm_epochs", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("ssi_max_iter", ctypes.c_int), ("k_init", ctypes.c_int),
                 ("refresh_every", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("timing", ctypes.c_int), ("seed", ctypes.c_uint64)]
+                ("timing", ctypes.c_int), ("lmsvd_p", ctypes.c_int),
+                ("seed", ctypes.c_uint64)]
 
 
 class BmgResult(ctypes.Structure):

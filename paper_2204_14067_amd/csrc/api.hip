@@ -89,6 +89,9 @@ inline bool spd_inv(int n, const double *A, double *Ainv) {
 static constexpr double ORTH_TOL = 1e-6;   // numerical-rank cut of orth() on unit columns
 static constexpr double SSI_EPS = 1e-12;   // Algorithm 2's cut of small s (relative)
 static constexpr double PINV_REL = 1e-12;  // Nystrom pseudo-inverse cut (relative)
+static constexpr double LMSVD_EIG_TOL = 1e-6;  // cut of small eigenvalues of P^T P (eq. PUi;
+                                                // history columns have unit norm)
+static constexpr int LMSVD_MAX_HIST = 4;       // largest history length p_t accepted
 static constexpr uint64_t STREAM_SKETCH = 1, STREAM_SAFEGUARD = 0x100;
 
 static inline int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -354,6 +357,9 @@ struct bmg_problem {
   std::vector<Pend> pend;
   hipEvent_t last_a = nullptr, last_b = nullptr;
   int last_cls = 0;
+  // history blocks of Algorithm 2 with p_t >= 1 (allocated on first use)
+  char *hist = nullptr;
+  size_t hist_bytes = 0;
   double kms[3] = {0, 0, 0}, kbytes[3] = {0, 0, 0};
   int klaunch[3] = {0, 0, 0};
   hipEvent_t get_event() {
@@ -389,6 +395,7 @@ struct bmg_problem {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (bitem.ready) (void)hipEventDestroy(bitem.ready);
     if (bitem.done) (void)hipEventDestroy(bitem.done);
+    if (hist) (void)hipFree(hist);
   }
 
   template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -840,6 +847,7 @@ extern "C" void bmg_options_default(bmg_options *o) {
   o->k_init = 8;
   o->refresh_every = 5;
   o->verbose = 0;
+  o->lmsvd_p = 0;
   o->seed = 0;
 }
 
@@ -1130,11 +1138,14 @@ struct Method : Engine<T, TG> {
     return out;
   }
 
-  // ------------------------------------------------------------ Algorithm 2 with p = 0
-  // U0 (m x q0, orthonormal) in Ubuf.  On return *Uout / *Yout point at the
-  // final basis (q columns) and Z^T of it; Tq is their Gram matrix.
+  // ------------------------------------------------------------ Algorithm 2
+  // U0 (m x q0, orthonormal) in Ubuf (block B1 or B2).  On return *Uout / *Yout
+  // point at the final basis (q columns) and Z^T of it; Tq is their Gram matrix.
+  // History length p_t = hist_p.
+  int hist_p = 0;
   int lmsvd(const ZOp &z, T *Ubuf, int q, double tau, int max_iter, double keep_level,
             T **Uout, T **Yout, std::vector<double> &Tq, int *iters) {
+    if (hist_p > 0) return lmsvd_hist(z, Ubuf, q, tau, max_iter, keep_level, Uout, Yout, Tq, iters);
     T *U = Ubuf, *Y = blk(P->L.b_Y), *V = blk(P->L.b_B3), *tmp = blk(P->L.b_B4);
     z_t(z, U, q, Y);
     std::vector<double> prev;
@@ -1146,19 +1157,31 @@ struct Method : Engine<T, TG> {
       z_n(z, Y, q, V);                 // L(U) = Z Z^T U (Ritz rotation omitted: same range)
       q = orth(m, V, q, U, tmp);       // U^{t,i+1}
       z_t(z, U, q, Y);
-      bool done = false;
-      if (!prev.empty() && prev.size() == theta.size()) {
-        double dmax = 0.0;
-        for (size_t j = 0; j < theta.size(); ++j)
-          if (j == 0 || theta[j] > keep_level) dmax = std::max(dmax, fabs(theta[j] - prev[j]));
-        done = dmax <= tau * std::max(theta[0], 0.0);
-      }
-      prev = theta;
-      if (done) break;
+      if (ritz_converged(theta, prev, tau, keep_level)) break;
     }
     *iters = std::min(it, max_iter);
+    return finish(U, Y, q, blk(P->L.b_B4), blk(P->L.b_Y2), Uout, Yout, Tq);
+  }
+
+  // stopping test: the leading Ritz values above keep_level (and the largest)
+  // moved by at most tau * largest since the previous iteration
+  static bool ritz_converged(const std::vector<double> &theta, std::vector<double> &prev,
+                             double tau, double keep_level) {
+    bool done = false;
+    if (!prev.empty() && prev.size() == theta.size() && !theta.empty()) {
+      double dmax = 0.0;
+      for (size_t j = 0; j < theta.size(); ++j)
+        if (j == 0 || theta[j] > keep_level) dmax = std::max(dmax, fabs(theta[j] - prev[j]));
+      done = dmax <= tau * std::max(theta[0], 0.0);
+    }
+    prev = theta;
+    return done;
+  }
+
+  // Algorithm 2's final cut: keep columns with s_j = ||Z^T u_j|| > eps * max
+  // (selected columns go to Usel / Ysel, which must differ from U / Y)
+  int finish(T *U, T *Y, int q, T *Usel, T *Ysel, T **Uout, T **Yout, std::vector<double> &Tq) {
     Tq = gram(n, q, Y, qld, q, Y, qld);
-    // Algorithm 2's final cut: keep columns with s_j = ||Z^T u_j|| > eps * max
     double smax = 0.0;
     for (int j = 0; j < q; ++j) smax = std::max(smax, sqrt(std::max(Tq[(size_t)j * q + j], 0.0)));
     std::vector<int> J;
@@ -1168,19 +1191,180 @@ struct Method : Engine<T, TG> {
       const int qj = (int)J.size();
       std::vector<double> Sel((size_t)q * qj, 0.0), Tj((size_t)qj * qj);
       for (int c = 0; c < qj; ++c) Sel[(size_t)J[c] * qj + c] = 1.0;
-      T *U2 = blk(P->L.b_B4), *Y2 = blk(P->L.b_Y2);
-      gemm(m, q, U, qld, qj, Sel, U2, qld, 0.0);
-      gemm(n, q, Y, qld, qj, Sel, Y2, qld, 0.0);
+      gemm(m, q, U, qld, qj, Sel, Usel, qld, 0.0);
+      gemm(n, q, Y, qld, qj, Sel, Ysel, qld, 0.0);
       for (int a = 0; a < qj; ++a)
         for (int b = 0; b < qj; ++b) Tj[(size_t)a * qj + b] = Tq[(size_t)J[a] * q + J[b]];
       Tq = Tj;
-      U = U2;
-      Y = Y2;
+      U = Usel;
+      Y = Ysel;
       q = qj;
     }
     *Uout = U;
     *Yout = Y;
     return q;
+  }
+
+  // Device memory of the history path: (2p - 1) m-side and 3p n-side blocks of
+  // qld columns, kept by the problem across calls.
+  T *hist_mem(int hp) {
+    const size_t mb = (size_t)rup((int64_t)sizeof(T) * m * qld, 256);
+    const size_t nb = (size_t)rup((int64_t)sizeof(T) * n * qld, 256);
+    const size_t need = (size_t)(2 * hp - 1) * mb + (size_t)(3 * hp) * nb;
+    if (P->hist_bytes < need) {
+      HIPC(hipStreamSynchronize(s));
+      if (P->hist) HIPC(hipFree(P->hist));
+      P->hist = nullptr;
+      P->hist_bytes = 0;
+      if (hipMalloc((void **)&P->hist, need) != hipSuccess) {
+        (void)hipGetLastError();
+        P->hist = nullptr;
+        throw BmgError{BMG_ENOMEM, "no device memory for the history blocks of the subspace iteration"};
+      }
+      P->hist_bytes = need;
+    }
+    return (T *)P->hist;
+  }
+
+  // Algorithm 2 with p_t = hist_p >= 1.  U^{t,i} and Z^T U^{t,i} live in a ring
+  // of hist_p + 1 block pairs; the last hist_p iterates are the history.  Per
+  // iteration, with U_old the history blocks and Y_old = Z^T U_old:
+  //   C = U^T U_old,  P = U_old - U C (eq. PUi),  P^T P = U~ Lambda U~^T,
+  //   S = U~ Lambda^{-1/2} over the eigenvalues above LMSVD_EIG_TOL (trimming),
+  //   Q = [U, P S] (eq. orth-W),  Z^T Q = [Y, E] with E = (Y_old - Y C) S,
+  //   L = (Z^T Q)^T (Z^T Q) = Q^T L_t(Q), V = its k_t leading eigenvectors
+  //   (eq. lmsvd-opt),  Z^T Uhat = [Y, E] V,  U^{t,i+1} = orth(Z Z^T Uhat).
+  // Two sparse passes per iteration, as with p_t = 0: Z^T of the basis comes
+  // from products already made.
+  int lmsvd_hist(const ZOp &z, T *Ubuf, int q, double tau, int max_iter, double keep_level,
+                 T **Uout, T **Yout, std::vector<double> &Tq, int *iters) {
+    const int hp = hist_p;
+    T *B1 = blk(P->L.b_B1), *B2 = blk(P->L.b_B2);
+    REQUIRE(Ubuf == B1 || Ubuf == B2, BMG_EINVAL, "subspace iteration: unexpected start block");
+    char *hm = (char *)hist_mem(hp);
+    const size_t mb = (size_t)rup((int64_t)sizeof(T) * m * qld, 256);
+    const size_t nb = (size_t)rup((int64_t)sizeof(T) * n * qld, 256);
+    std::vector<T *> Ur(hp + 1), Yr(hp + 1), Pm(hp), Bm(hp), Em(hp);
+    Ur[0] = Ubuf;
+    Ur[1] = Ubuf == B1 ? B2 : B1;
+    Yr[0] = blk(P->L.b_Y);
+    Yr[1] = blk(P->L.b_Y2);
+    size_t o = 0;
+    for (int j = 2; j <= hp; ++j, o += mb) Ur[j] = (T *)(hm + o);
+    for (int j = 0; j < hp; ++j, o += mb) Pm[j] = (T *)(hm + o);
+    for (int j = 2; j <= hp; ++j, o += nb) Yr[j] = (T *)(hm + o);
+    for (int j = 0; j < hp; ++j, o += nb) Bm[j] = (T *)(hm + o);
+    for (int j = 0; j < hp; ++j, o += nb) Em[j] = (T *)(hm + o);
+    T *Yh = (T *)(hm + o);
+    T *V = blk(P->L.b_B3), *tmp = blk(P->L.b_B4);
+    int cur = 0;
+    std::vector<int> hs, hw;          // ring slots and widths of the history, newest first
+    z_t(z, Ur[cur], q, Yr[cur]);
+    std::vector<double> prev;
+    int it = 0;
+    for (it = 1; it <= max_iter && q > 0; ++it) {
+      T *U = Ur[cur], *Y = Yr[cur];
+      const int kt = q, nh = (int)hs.size();
+      int r = 0;
+      std::vector<int> ew;              // widths of the column blocks of E
+      std::vector<double> Lm;
+      if (nh == 0) {
+        Lm = gram(n, q, Y, qld, q, Y, qld);
+      } else {
+        std::vector<int> off(nh + 1, 0);
+        for (int j = 0; j < nh; ++j) off[j + 1] = off[j] + hw[j];
+        const int qo = off[nh];
+        for (int j = 0; j < nh; ++j) {
+          std::vector<double> negC = gram(m, q, U, qld, hw[j], Ur[hs[j]], qld);
+          for (double &v : negC) v = -v;
+          HIPC(launch_copy_cols<T>(m, hw[j], Ur[hs[j]], qld, Pm[j], qld, s));
+          gemm(m, q, U, qld, hw[j], negC, Pm[j], qld, 1.0);      // P block j
+          HIPC(launch_copy_cols<T>(n, hw[j], Yr[hs[j]], qld, Bm[j], qld, s));
+          gemm(n, q, Y, qld, hw[j], negC, Bm[j], qld, 1.0);      // Z^T of P block j
+        }
+        std::vector<double> G((size_t)qo * qo);
+        for (int a = 0; a < nh; ++a)
+          for (int b = a; b < nh; ++b) {
+            std::vector<double> g = gram(m, hw[a], Pm[a], qld, hw[b], Pm[b], qld);
+            for (int i = 0; i < hw[a]; ++i)
+              for (int j = 0; j < hw[b]; ++j) {
+                G[(size_t)(off[a] + i) * qo + off[b] + j] = g[(size_t)i * hw[b] + j];
+                G[(size_t)(off[b] + j) * qo + off[a] + i] = g[(size_t)i * hw[b] + j];
+              }
+          }
+        std::vector<double> lam(qo), Ut((size_t)qo * qo);
+        lat::sym_eig(qo, G.data(), lam.data(), Ut.data());
+        while (r < qo && lam[r] > LMSVD_EIG_TOL) ++r;
+        // E = B S in column blocks of at most qld
+        for (int c0 = 0; c0 < r; c0 += qld) ew.push_back(std::min(qld, r - c0));
+        for (size_t l = 0; l < ew.size(); ++l) {
+          const int c0 = (int)l * qld;
+          for (int j = 0; j < nh; ++j) {
+            std::vector<double> Sj((size_t)hw[j] * ew[l]);
+            for (int i = 0; i < hw[j]; ++i)
+              for (int c = 0; c < ew[l]; ++c)
+                Sj[(size_t)i * ew[l] + c] = Ut[(size_t)(off[j] + i) * qo + c0 + c] / sqrt(lam[c0 + c]);
+            gemm(n, hw[j], Bm[j], qld, ew[l], Sj, Em[l], qld, j ? 1.0 : 0.0);
+          }
+        }
+        // L = [Y, E]^T [Y, E]
+        const int qq = q + r;
+        Lm.assign((size_t)qq * qq, 0.0);
+        auto put_block = [&](int r0, int c0, int ra, int cb, const std::vector<double> &g) {
+          for (int i = 0; i < ra; ++i)
+            for (int j = 0; j < cb; ++j) {
+              Lm[(size_t)(r0 + i) * qq + c0 + j] = g[(size_t)i * cb + j];
+              Lm[(size_t)(c0 + j) * qq + r0 + i] = g[(size_t)i * cb + j];
+            }
+        };
+        put_block(0, 0, q, q, gram(n, q, Y, qld, q, Y, qld));
+        for (size_t a = 0; a < ew.size(); ++a) {
+          put_block(0, q + (int)a * qld, q, ew[a], gram(n, q, Y, qld, ew[a], Em[a], qld));
+          for (size_t b = a; b < ew.size(); ++b)
+            put_block(q + (int)a * qld, q + (int)b * qld, ew[a], ew[b],
+                      gram(n, ew[a], Em[a], qld, ew[b], Em[b], qld));
+        }
+      }
+      const int qq = q + r;
+      std::vector<double> th(qq), Vv((size_t)qq * qq);
+      lat::sym_eig(qq, Lm.data(), th.data(), Vv.data());
+      std::vector<double> theta(th.begin(), th.begin() + kt);
+      // Z^T Uhat = [Y, E] V(:, 1:k_t)
+      {
+        std::vector<double> Vt((size_t)q * kt);
+        for (int i = 0; i < q; ++i)
+          for (int c = 0; c < kt; ++c) Vt[(size_t)i * kt + c] = Vv[(size_t)i * qq + c];
+        gemm(n, q, Y, qld, kt, Vt, Yh, qld, 0.0);
+        for (size_t l = 0; l < ew.size(); ++l) {
+          std::vector<double> Vl((size_t)ew[l] * kt);
+          for (int i = 0; i < ew[l]; ++i)
+            for (int c = 0; c < kt; ++c)
+              Vl[(size_t)i * kt + c] = Vv[(size_t)(q + (int)l * qld + i) * qq + c];
+          gemm(n, ew[l], Em[l], qld, kt, Vl, Yh, qld, 1.0);
+        }
+      }
+      z_n(z, Yh, kt, V);                 // L_t(Uhat^{t,i})
+      // U^{t,i+1} goes into the ring slot that leaves the history (or a free one)
+      int nxt = -1;
+      if (nh == hp) {
+        nxt = hs.back();
+      } else {
+        for (int j = 0; j <= hp && nxt < 0; ++j)
+          if (j != cur && std::find(hs.begin(), hs.end(), j) == hs.end()) nxt = j;
+      }
+      q = orth(m, V, kt, Ur[nxt], tmp);
+      hs.insert(hs.begin(), cur);
+      hw.insert(hw.begin(), kt);
+      if ((int)hs.size() > hp) {
+        hs.pop_back();
+        hw.pop_back();
+      }
+      cur = nxt;
+      z_t(z, Ur[cur], q, Yr[cur]);
+      if (ritz_converged(theta, prev, tau, keep_level)) break;
+    }
+    *iters = std::min(it, max_iter);
+    return finish(Ur[cur], Yr[cur], q, tmp, Yh, Uout, Yout, Tq);
   }
 
   // ------------------------------------------------------------ state of Algorithm 1
@@ -1435,6 +1619,7 @@ struct Method : Engine<T, TG> {
   // Algorithm 1
   bmg_status solve(const bmg_options &o, State &S, bmg_result *res) {
     const auto t0 = std::chrono::steady_clock::now();
+    hist_p = o.lmsvd_p;
     t_la_acc = t_wait_acc = 0.0;
     n_sync_acc = 0;
     init_state(S);
@@ -1620,10 +1805,13 @@ extern "C" bmg_status bmg_objective(bmg_problem *P, const double *W, const doubl
 extern "C" bmg_status bmg_prox_step(bmg_problem *P, double *W, double *H, int *k_inout, int ld,
                                     const bmg_options *opt, double *sigma, double *residual) {
   if (!k_inout || !opt) return fail(BMG_EINVAL, "bmg_prox_step: null argument");
+  if (opt->lmsvd_p < 0 || opt->lmsvd_p > LMSVD_MAX_HIST || opt->ssi_max_iter < 1)
+    return fail(BMG_EINVAL, "bmg_prox_step: bad options");
   bmg_status st = check_factors(P, W, H, *k_inout, ld);
   if (st != BMG_OK) return st;
   try {
     Method<double> M(P);
+    M.hist_p = opt->lmsvd_p;
     Method<double>::State S;
     M.init_state(S);
     const int k = *k_inout;
@@ -1653,7 +1841,8 @@ extern "C" bmg_status bmg_solve(bmg_problem *P, double *W, double *H, int ld, co
   if (!P || !opt || !W || !H) return fail(BMG_EINVAL, "bmg_solve: null argument");
   if (ld < 8 || ld % 8) return fail(BMG_EINVAL, "bmg_solve: ld must be a positive multiple of 8");
   if (opt->lambda <= 0.0 || opt->alpha <= 0.0 || opt->bm_epochs < 0 || opt->max_iter < 0 ||
-      opt->ssi_max_iter < 1 || opt->k_init < 1)
+      opt->ssi_max_iter < 1 || opt->k_init < 1 || opt->lmsvd_p < 0 ||
+      opt->lmsvd_p > LMSVD_MAX_HIST)
     return fail(BMG_EINVAL, "bmg_solve: bad options");
   P->reset_stats();
   P->timing = opt->timing != 0;

@@ -165,6 +165,29 @@ def test_prox_step_parity(name):
     assert math.isclose(res, reso, rel_tol=1e-5, abs_tol=1e-12)
 
 
+@pytest.mark.parametrize("hp", [1, 2])
+@pytest.mark.parametrize("name", ["tiny", "tall_m_gt_n", "long_rows", "powerlaw"])
+def test_prox_step_parity_lmsvd_history(name, hp):
+    """Algorithm 2 with p_t = 1, 2 history blocks: the same prox output as the
+    oracle's LmSVD with that history length."""
+    p = case(name)
+    lam, alpha, k = 0.4, 1.99, 4
+    dp = to_dev(p, k_cap=32)
+    W, H = factors(p, k, 32, seed=5)
+    Wd, Hd = t(W), t(H)
+    kg, sig, res = dp.bmg_prox_step(Wd, Hd, k, lam=lam, alpha=alpha, seed=9, ssi_tol_floor=1e-13,
+                                    ssi_max_iter=200, lmsvd_p=hp)
+    pr, ls, reso = core.prox_step_standalone(p, W[:, :k], H[:, :k], lam, alpha, seed=9, tau=1e-13,
+                                             max_iter=200, p=hp)
+    print("prox history", name, hp, kg, pr.k, ls.iters, flush=True)
+    assert kg == pr.k
+    assert np.allclose(sig, pr.sigma, rtol=1e-8, atol=1e-10 * max(pr.sigma.max(initial=0), 1))
+    Wg, Hg = Wd.cpu().numpy()[:, :kg], Hd.cpu().numpy()[:, :kg]
+    d = math.sqrt(core.diff_fro2_factored(Wg, Hg, pr.W, pr.H))
+    assert d <= 1e-7 * max(1.0, math.sqrt(core.fro2_factored(pr.W, pr.H)))
+    assert math.isclose(res, reso, rel_tol=1e-5, abs_tol=1e-12)
+
+
 # ----------------------------------------------------------------------------- solver
 
 def solve_both(p, lam, k0, tol, k_cap=64, precision="fp64", seed=3, orc=None):
@@ -187,6 +210,38 @@ def test_solve_parity_fp64(shape):
     # the returned factors reproduce the reported objective (recomputed by the oracle)
     Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
     assert math.isclose(Fw, r["F"], rel_tol=1e-10)
+
+
+@pytest.mark.parametrize("hp", [1, 2])
+@pytest.mark.parametrize("shape", [(40, 60, 700), (60, 40, 700), (120, 200, 4000)])
+def test_solve_parity_fp64_lmsvd_history(shape, hp):
+    m, n, nnz = shape
+    p = synth.tiny(m, n, nnz, rank=3, lam=0.3, seed=m + n)
+    recs = []
+    orc = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-10, seed=3, max_iter=3000, lmsvd_p=hp),
+                     callback=recs.append)
+    dp = to_dev(p, k_cap=64)
+    W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-10, seed=3, max_iter=3000, lmsvd_p=hp)
+    print("solve history", shape, hp, r["ssi_iters"], sum(x.ssi_iters for x in recs), r["F"], orc.F,
+          flush=True)
+    assert r["status"] == 0 and orc.converged
+    assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
+    assert k == orc.k
+    Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
+    assert math.isclose(Fw, r["F"], rel_tol=1e-10)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp32", 1e-5), ("bf16", 1e-3)])
+def test_solve_lmsvd_history_reduced_precision(precision, bar):
+    p = synth.tiny(150, 220, 5000, rank=3, lam=0.3, seed=31)
+    dp = to_dev(p, k_cap=64, precision=precision)
+    W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-6 if precision == "fp32" else 1e-5, seed=3,
+                              max_iter=600, lmsvd_p=1)
+    Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
+    Fstar = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-11, seed=3)).F
+    print("history", precision, r["status"], r["iters"], r["ssi_iters"], Fw, Fstar, flush=True)
+    assert r["status"] == 0
+    assert abs(Fw - Fstar) <= bar * Fstar
 
 
 def test_solve_full_omega_closed_form():
@@ -280,6 +335,9 @@ def test_invalid_inputs_are_rejected():
     dp = to_dev(p, k_cap=8)
     with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
         dp.bmg_solve(lam=-1.0)
+    for hp in (-1, 5):
+        with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
+            dp.bmg_solve(lam=0.1, lmsvd_p=hp)
 
 
 # ----------------------------------------------------------------------------- full size, sampled

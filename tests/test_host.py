@@ -40,8 +40,11 @@ def test_library_exports_every_declared_symbol(lib):
 def test_options_default(lib):
     from paper_2204_14067_amd import _lib
     o = _lib.BmgOptions()
+    o.lmsvd_p, o.seed, o.timing = 7, 123, 1
     lib.bmg_options_default(ctypes.byref(o))
     assert o.alpha == 1.99 and o.bm_epochs == 3 and o.psi0 == 0.1 and o.tol == 1e-6
+    assert o.k_init == 8 and o.refresh_every == 5 and o.ssi_max_iter == 50
+    assert o.lmsvd_p == 0 and o.seed == 0 and o.timing == 0
 
 
 def test_workspace_size_and_argument_checks(lib):
