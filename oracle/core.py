@@ -509,6 +509,14 @@ class Options:
     psi0: float = 0.1
     seed: int = 0
     lmsvd_p: int = 0             # p_t of Algorithm 2 (history blocks)
+    # PG step size: "fixed" (alpha every step) or "sparsa" (Suppl. on the SpaRSA
+    # variant: BB step of eq. proxBB clipped to [alpha_min, alpha_max], then
+    # backtracking by sparsa_beta until eq. back holds with sparsa_delta)
+    step_rule: str = "fixed"
+    alpha_min: float = 1.99      # < 2 delta / L (L = 1): eq. back holds there
+    alpha_max: float = 1e3
+    sparsa_beta: float = 0.5
+    sparsa_delta: float = 0.999
 
 
 @dataclass
@@ -522,6 +530,8 @@ class IterRecord:
     ssi_iters: int
     eps: float
     added_column: bool
+    alpha: float = 1.99          # step of the accepted PG step
+    trials: int = 1              # prox computations of the step (backtracking)
 
 
 @dataclass
@@ -592,6 +602,31 @@ def relative_residual(prob, Wt, Ht, R, Uhat, Wn, Hn) -> float:
     return d / (1.0 + np.sqrt(fro2_factored(Wt, Ht)) + np.sqrt(sumsq(prob, R)))
 
 
+def bb_step(W, H, Wp, Hp, R, Rp, alpha_min: float, alpha_max: float) -> float:
+    """Barzilai-Borwein step of eq. proxBB between the PG points X~_t = W H^T and
+    X~_{t-1} = Wp Hp^T, with R, Rp the sampled residuals there (grad f = R on
+    Omega), read as the step
+        ||X~_t - X~_{t-1}||_F^2 / <X~_t - X~_{t-1}, grad f(X~_t) - grad f(X~_{t-1})>,
+    the numerator by eq. trace (sign corrected) and the denominator
+    ||R - Rp||^2 since grad f(X) - grad f(Y) = P_Omega(X - Y) for (MC); clipped
+    to [alpha_min, alpha_max] (alpha_max when the denominator vanishes)."""
+    num = diff_fro2_factored(W, H, Wp, Hp)
+    den = float(np.dot(R - Rp, R - Rp))
+    a = num / den if den > 0.0 else alpha_max
+    return min(alpha_max, max(alpha_min, a))
+
+
+def back_condition(prob, R, Wn, Hn, d2: float, alpha: float, delta: float):
+    """eq. back at X+ = Wn Hn^T from X~ with sampled residual R:
+        f(X+) <= f(X~) + <grad f(X~), X+ - X~> + delta / alpha ||X+ - X~||^2,
+    <grad f(X~), X+ - X~> = <R, R+ - R> on Omega (R+ the residual at X+) and
+    d2 = ||X+ - X~||_F^2.  Returns (holds, left side, right side)."""
+    Rn = sddmm(prob, Wn, Hn)
+    lhs = 0.5 * float(np.dot(Rn, Rn))
+    rhs = 0.5 * float(np.dot(R, R)) + float(np.dot(R, Rn - R)) + delta / alpha * d2
+    return lhs <= rhs, lhs, rhs
+
+
 def solve(prob, opt: Options, callback=None) -> SolveResult:
     """Runs :func:`_solve` with single-threaded BLAS (the dense steps are small;
     threaded BLAS only adds contention with the OpenMP sparse loops).  The
@@ -608,8 +643,19 @@ def solve(prob, opt: Options, callback=None) -> SolveResult:
 def _solve(prob, opt: Options, callback=None) -> SolveResult:
     """Algorithm 1 (BM-Global) for (MC): per outer iteration y BM epochs, then
     one inexact PG step with warm start (eqs. rt0 / rt0-1), rank safeguard
-    (eq. rt), LmSVD (Algorithm 2, p = 0), exact SVD + threshold, and the rank
-    update k = rank(Sigma)."""
+    (eq. rt), LmSVD (Algorithm 2), exact SVD + threshold, and the rank
+    update k = rank(Sigma).  With step_rule "sparsa" the step from the second
+    PG step on is the BB step (bb_step) times sparsa_beta^i for the smallest i
+    whose prox output satisfies eq. back, floored at alpha_min (where eq. back
+    holds for L = 1); every trial restarts LmSVD from the same warm start.  The
+    stopping residual is ||X~ - X+|| at the accepted alpha_t unscaled: it does
+    not decrease with the step (alpha ||G_alpha|| is nondecreasing in alpha for
+    the prox-gradient mapping G_alpha), so for alpha_t >= alpha it bounds the
+    fixed-step residual from above."""
+    sparsa = opt.step_rule == "sparsa"
+    if opt.step_rule not in ("fixed", "sparsa"):
+        raise ValueError("step_rule must be 'fixed' or 'sparsa'")
+    prev_pt = None                                  # (W~, H~, R) of the previous PG step
     lam, alpha = opt.lam, opt.alpha
     init, _ = initialize(prob, lam, opt.k0, opt.seed)
     W, H = init.W, init.H
@@ -636,7 +682,6 @@ def _solve(prob, opt: Options, callback=None) -> SolveResult:
         changed = not (np.array_equal(Wt, W) and np.array_equal(Ht, H))
         # ---- convex lifting: Z_t = X~_t - alpha grad f(X~_t)
         R = sddmm(prob, Wt, Ht)
-        zop = ZOperator(prob, Wt, Ht, R, alpha)
         Ubase = orth(np.column_stack([U_cur, Wt if changed else U_prev]))
         add = trunc_prev <= 1 or rank_cur == rank_prev or Ubase.shape[1] == 0
         if add:
@@ -644,8 +689,24 @@ def _solve(prob, opt: Options, callback=None) -> SolveResult:
         else:
             U0 = Ubase
         tau = ssi_tolerance(res_prev, opt.ssi_tol_floor)
-        ls = lmsvd(zop, U0, tau, opt.ssi_max_iter, (alpha * lam) ** 2, opt.lmsvd_p)
-        pr = prox_from_basis(ls.Uhat, ls.Y, alpha * lam)
+        a = alpha
+        if sparsa and prev_pt is not None:
+            a = bb_step(Wt, Ht, prev_pt[0], prev_pt[1], R, prev_pt[2], opt.alpha_min, opt.alpha_max)
+        trials, ssi_sum = 0, 0
+        while True:
+            trials += 1
+            zop = ZOperator(prob, Wt, Ht, R, a)
+            ls = lmsvd(zop, U0, tau, opt.ssi_max_iter, (a * lam) ** 2, opt.lmsvd_p)
+            ssi_sum += ls.iters
+            pr = prox_from_basis(ls.Uhat, ls.Y, a * lam)
+            if not sparsa or a <= opt.alpha_min:
+                break
+            d = step_norm(ls.Uhat, Wt, Ht, pr.W, pr.H)
+            if back_condition(prob, R, pr.W, pr.H, d * d, a, opt.sparsa_delta)[0]:
+                break
+            a = max(opt.alpha_min, a * opt.sparsa_beta)
+        if sparsa:
+            prev_pt = (Wt, Ht, R)
         eps2 = zop.fro2() - float(np.sum(pr.sigma_hat ** 2))
         res = relative_residual(prob, Wt, Ht, R, ls.Uhat, pr.W, pr.H)
         # ---- safeguard bookkeeping
@@ -662,7 +723,8 @@ def _solve(prob, opt: Options, callback=None) -> SolveResult:
         rank_prev, rank_cur = rank_cur, pr.k
         W, H = pr.W, pr.H
         F = objective(prob, W, H, lam)
-        rec = IterRecord(t, F, F_bm, res, pr.k, q, ls.iters, float(np.sqrt(max(eps2, 0.0))), add)
+        rec = IterRecord(t, F, F_bm, res, pr.k, q, ssi_sum, float(np.sqrt(max(eps2, 0.0))), add,
+                         a, trials)
         hist.append(rec)
         if callback:
             callback(rec)

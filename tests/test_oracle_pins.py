@@ -410,3 +410,69 @@ def test_golden_small_uniform_is_certified(golden_dir):
     assert g["converged"] and g["residual"] <= 1e-10
     assert 0 <= g["dual_gap"] <= 1e-8 * g["F"]
     assert g["dual_value"] <= g["F"]
+
+
+# ----------------------------------------------------------------------------- SpaRSA step
+
+def test_bb_step_matches_dense_definition():
+    # eq. proxBB read as ||dX||^2 / <dX, d grad f>, with grad f = P_Omega(X - A)
+    p = tiny_problem(30, 45, 500, lam=0.2)
+    A, M = dense.to_dense(p)
+    W, H, Wp, Hp = rand((30, 3), 1), rand((45, 3), 2), rand((30, 2), 3), rand((45, 2), 4)
+    R, Rp = core.sddmm(p, W, H), core.sddmm(p, Wp, Hp)
+    dX = W @ H.T - Wp @ Hp.T
+    dG = np.where(M, W @ H.T - A, 0.0) - np.where(M, Wp @ Hp.T - A, 0.0)
+    want = float(np.sum(dX * dX)) / float(np.sum(dX * dG))
+    assert 1.0 < want < 1e3
+    assert math.isclose(core.bb_step(W, H, Wp, Hp, R, Rp, 1e-3, 1e6), want, rel_tol=1e-10)
+    assert core.bb_step(W, H, Wp, Hp, R, Rp, 2 * want, 1e6) == 2 * want
+    assert core.bb_step(W, H, Wp, Hp, R, Rp, 1e-3, 0.5 * want) == 0.5 * want
+    assert core.bb_step(W, H, W, H, R, R, 1.0, 7.0) == 7.0
+
+
+def test_back_condition_matches_dense_definition():
+    p = tiny_problem(30, 45, 500, lam=0.2)
+    A, M = dense.to_dense(p)
+    W, H, Wn, Hn = rand((30, 3), 5), rand((45, 3), 6), rand((30, 2), 7), rand((45, 2), 8)
+    X, Xn = W @ H.T, Wn @ Hn.T
+    f = lambda Y: 0.5 * float(np.sum(np.where(M, Y - A, 0.0) ** 2))  # noqa: E731
+    G = np.where(M, X - A, 0.0)
+    d2 = float(np.sum((Xn - X) ** 2))
+    for alpha, delta in [(1.99, 0.999), (50.0, 0.5), (0.1, 0.9)]:
+        rhs = f(X) + float(np.sum(G * (Xn - X))) + delta / alpha * d2
+        ok, lhs, r = core.back_condition(p, core.sddmm(p, W, H), Wn, Hn, d2, alpha, delta)
+        assert math.isclose(lhs, f(Xn), rel_tol=1e-12) and math.isclose(r, rhs, rel_tol=1e-12)
+        assert ok == (f(Xn) <= rhs)
+    # any step alpha < 2 delta / L (L = 1) satisfies it: the descent lemma
+    ok, _, _ = core.back_condition(p, core.sddmm(p, W, H), Wn, Hn, d2, 1.99, 0.999)
+    assert ok
+
+
+def test_sparsa_with_equal_bounds_is_the_fixed_step():
+    p = tiny_problem(40, 60, 700, lam=0.3, rank=3, seed=5)
+    ra, rb = [], []
+    a = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-9, seed=3), callback=ra.append)
+    b = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-9, seed=3, step_rule="sparsa",
+                                   alpha_min=1.99, alpha_max=1.99), callback=rb.append)
+    assert a.iters == b.iters and np.array_equal(a.W, b.W) and np.array_equal(a.H, b.H)
+    assert [r.residual for r in ra] == [r.residual for r in rb]
+    assert all(r.trials == 1 and r.alpha == 1.99 for r in rb)
+
+
+def test_sparsa_solve_reaches_the_optimum_in_fewer_iterations():
+    # the SpaRSA variant: same optimum as the dense proximal gradient, fewer outer
+    # iterations than the fixed step, paid for with backtracking prox computations
+    p = synth.tiny(300, 500, 30000, rank=8, lam=1.0, seed=4)
+    fx, sp = [], []
+    a = core.solve(p, core.Options(lam=1.0, k0=8, tol=1e-9, seed=1), callback=fx.append)
+    b = core.solve(p, core.Options(lam=1.0, k0=8, tol=1e-9, seed=1, step_rule="sparsa"),
+                   callback=sp.append)
+    assert a.converged and b.converged
+    # optimality of the SpaRSA output certified by the dual (no solver involved)
+    _, R = core.loss(p, b.W, b.H)
+    gap, _, _ = dense.duality_gap(p, R, b.F, 1.0)
+    assert -1e-9 * b.F <= gap <= 5e-8 * b.F      # the fixed step at this tol: 1.0e-8
+    assert math.isclose(b.F, a.F, rel_tol=1e-10)
+    assert b.iters < a.iters
+    assert sum(r.trials for r in sp) > b.iters
+    assert all(1.99 <= r.alpha <= 1e3 for r in sp) and max(r.alpha for r in sp) > 1.99
