@@ -60,6 +60,18 @@ typedef struct {
 
 typedef struct bmg_problem bmg_problem;
 
+/* Step-size rule of the PG step (Algorithm 1, convex-lifting phase). */
+typedef enum {
+  BMG_STEP_FIXED = 0,  /* alpha at every step (Sec. 6.1: alpha = 1.99 for L = 1)      */
+  BMG_STEP_SPARSA = 1  /* Suppl., the SpaRSA variant: from the second PG step on, the  *
+                        * BB step of eq. proxBB (read as ||dX||^2 / <dX, d grad f>)   *
+                        * clipped to [alpha_min, alpha_max], times sparsa_beta^i for   *
+                        * the smallest i whose prox output satisfies eq. back with     *
+                        * sparsa_delta, floored at alpha_min; every trial is a full    *
+                        * subspace iteration + prox from the same warm start.  The     *
+                        * stop residual ||X~ - X+|| is taken at the accepted step      */
+} bmg_step_rule;
+
 typedef struct {
   double lambda;        /* regularisation weight of (MC)                         */
   double alpha;         /* fixed PG step (Sec. 6.1: L = 1, alpha = 1.99)         */
@@ -76,6 +88,11 @@ typedef struct {
   int lmsvd_p;          /* p_t of Algorithm 2: history blocks of the subspace     *
                          * (0: block subspace iteration; at most 4, see below)   */
   uint64_t seed;        /* counter-based RNG seed (sketch and safeguard draws)   */
+  int step_rule;        /* bmg_step_rule                                         */
+  double alpha_min;     /* SpaRSA: step bounds (alpha_min < 2 delta / L, L = 1)  */
+  double alpha_max;
+  double sparsa_beta;   /* SpaRSA: backtracking factor in (0, 1)                 */
+  double sparsa_delta;  /* SpaRSA: delta of eq. back in (0, 1)                   */
 } bmg_options;
 
 typedef struct {
@@ -103,11 +120,18 @@ typedef struct {
   double host_la_seconds;
   double host_wait_seconds;
   int host_syncs;
+  int pg_trials;      /* prox computations summed over all PG steps (backtracking) */
+  double alpha_last;  /* step of the last PG step                                */
 } bmg_result;
 
 /* Fills the defaults: alpha 1.99, tol 1e-6, ssi_tol_floor 1e-12, psi0 0.1,
  * bm_epochs 3, max_iter 500, ssi_max_iter 50, k_init 8, refresh_every 5,
- * lmsvd_p 0.
+ * lmsvd_p 0, step_rule BMG_STEP_FIXED, alpha_min 1.99, alpha_max 1e3,
+ * sparsa_beta 0.5, sparsa_delta 0.999.
+ * BMG_STEP_SPARSA keeps the previous PG point (W, H and its residual) and the
+ * warm start in device memory beyond the workspace (min(m,n) x (2 k_cap + 2)
+ * rounded up to 16, plus (m + n) x ld_k and nnz elements of the working
+ * precision), allocated on first use and kept until bmg_problem_destroy.
  * lmsvd_p = p >= 1 (Algorithm 2 with history, Suppl. A.1.2: the Ritz step runs
  * over ran(U^{t,i}, ..., U^{t,i-p}) with the basis of eqs. PUi and orth-W) needs
  * device memory beyond the workspace: (2p-1) blocks of min(m,n) x qb and 3p

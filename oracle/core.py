@@ -602,15 +602,32 @@ def relative_residual(prob, Wt, Ht, R, Uhat, Wn, Hn) -> float:
     return d / (1.0 + np.sqrt(fro2_factored(Wt, Ht)) + np.sqrt(sumsq(prob, R)))
 
 
+def diff_fro2_split(W1, H1, W0, H0) -> float:
+    """||W1 H1^T - W0 H0^T||_F^2 for two nearby iterates.  eq. trace adds three
+    traces of size ||X||^2 and loses all digits once the difference is below
+    ~1e-8 ||X||.  With Q an orthonormal basis of ran(W1) and E_i = (I - Q Q^T) W_i,
+        ||dX||^2 = ||(Q^T W1) H1^T - (Q^T W0) H0^T||_F^2 + ||E1 H1^T - E0 H0^T||_F^2
+    (Pythagoras over ran(Q) and its complement): the first term is an explicit
+    difference, the second eq. trace on the small remainders E_i."""
+    if W1.shape[1] == 0 or W0.shape[1] == 0:
+        return diff_fro2_factored(W1, H1, W0, H0)
+    Q = orth(W1)
+    D = (Q.T @ W1) @ H1.T - (Q.T @ W0) @ H0.T
+    E1 = W1 - Q @ (Q.T @ W1)
+    E0 = W0 - Q @ (Q.T @ W0)
+    return float(np.sum(D * D)) + diff_fro2_factored(E1, H1, E0, H0)
+
+
 def bb_step(W, H, Wp, Hp, R, Rp, alpha_min: float, alpha_max: float) -> float:
     """Barzilai-Borwein step of eq. proxBB between the PG points X~_t = W H^T and
     X~_{t-1} = Wp Hp^T, with R, Rp the sampled residuals there (grad f = R on
     Omega), read as the step
         ||X~_t - X~_{t-1}||_F^2 / <X~_t - X~_{t-1}, grad f(X~_t) - grad f(X~_{t-1})>,
-    the numerator by eq. trace (sign corrected) and the denominator
-    ||R - Rp||^2 since grad f(X) - grad f(Y) = P_Omega(X - Y) for (MC); clipped
-    to [alpha_min, alpha_max] (alpha_max when the denominator vanishes)."""
-    num = diff_fro2_factored(W, H, Wp, Hp)
+    the numerator by diff_fro2_split (eq. trace rearranged so that nothing
+    cancels) and the denominator ||R - Rp||^2 since
+    grad f(X) - grad f(Y) = P_Omega(X - Y) for (MC); clipped to
+    [alpha_min, alpha_max] (alpha_max when the denominator vanishes)."""
+    num = diff_fro2_split(W, H, Wp, Hp)
     den = float(np.dot(R - Rp, R - Rp))
     a = num / den if den > 0.0 else alpha_max
     return min(alpha_max, max(alpha_min, a))
@@ -619,11 +636,15 @@ def bb_step(W, H, Wp, Hp, R, Rp, alpha_min: float, alpha_max: float) -> float:
 def back_condition(prob, R, Wn, Hn, d2: float, alpha: float, delta: float):
     """eq. back at X+ = Wn Hn^T from X~ with sampled residual R:
         f(X+) <= f(X~) + <grad f(X~), X+ - X~> + delta / alpha ||X+ - X~||^2,
-    <grad f(X~), X+ - X~> = <R, R+ - R> on Omega (R+ the residual at X+) and
-    d2 = ||X+ - X~||_F^2.  Returns (holds, left side, right side)."""
+    d2 = ||X+ - X~||_F^2.  The MC loss is quadratic, so
+        f(X+) - f(X~) - <grad f(X~), X+ - X~> = 1/2 ||P_Omega(X+ - X~)||^2
+                                              = 1/2 ||R+ - R||^2
+    exactly (R+ the residual at X+), and the test is made in that form: the
+    three f terms are large and nearly cancel once steps are small.  Returns
+    (holds, left side 1/2 ||R+ - R||^2, right side delta / alpha * d2)."""
     Rn = sddmm(prob, Wn, Hn)
-    lhs = 0.5 * float(np.dot(Rn, Rn))
-    rhs = 0.5 * float(np.dot(R, R)) + float(np.dot(R, Rn - R)) + delta / alpha * d2
+    lhs = 0.5 * float(np.dot(Rn - R, Rn - R))
+    rhs = delta / alpha * d2
     return lhs <= rhs, lhs, rhs
 
 

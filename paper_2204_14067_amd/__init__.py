@@ -33,10 +33,15 @@ def _stream_handle(device):
 
 
 def options(**kw) -> BmgOptions:
-    """bmg_options with the library defaults, overridden by keyword (lam= sets lambda)."""
+    """bmg_options with the library defaults, overridden by keyword (lam= sets
+    lambda; step_rule= takes "fixed" / "sparsa" or the enum value)."""
     o = BmgOptions()
     _lib.load().bmg_options_default(ctypes.byref(o))
     for key, v in kw.items():
+        if key == "step_rule" and isinstance(v, str):
+            v = {"fixed": _lib.BMG_STEP_FIXED, "sparsa": _lib.BMG_STEP_SPARSA}[v]
+        if not hasattr(o, "lambda_" if key in ("lam", "lambda") else key):
+            raise TypeError("unknown option %r" % key)
         setattr(o, "lambda_" if key in ("lam", "lambda") else key, v)
     return o
 

@@ -15,6 +15,7 @@ SO = os.path.join(HERE, "libbmg.so")
 BMG_OK, BMG_NOT_CONVERGED = 0, 1
 BMG_EINVAL, BMG_ENOMEM, BMG_EDEVICE, BMG_ENONFINITE, BMG_ECANCELLED = -1, -2, -3, -4, -5
 BMG_FP64, BMG_FP32, BMG_BF16 = 0, 1, 2
+BMG_STEP_FIXED, BMG_STEP_SPARSA = 0, 1
 STATUS_NAMES = {0: "BMG_OK", 1: "BMG_NOT_CONVERGED", -1: "BMG_EINVAL", -2: "BMG_ENOMEM",
                 -3: "BMG_EDEVICE", -4: "BMG_ENONFINITE", -5: "BMG_ECANCELLED"}
 
@@ -38,7 +39,9 @@ class BmgOptions(ctypes.Structure):
                 ("ssi_max_iter", ctypes.c_int), ("k_init", ctypes.c_int),
                 ("refresh_every", ctypes.c_int), ("verbose", ctypes.c_int),
                 ("timing", ctypes.c_int), ("lmsvd_p", ctypes.c_int),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("step_rule", ctypes.c_int),
+                ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
+                ("sparsa_beta", ctypes.c_double), ("sparsa_delta", ctypes.c_double)]
 
 
 class BmgResult(ctypes.Structure):
@@ -49,7 +52,8 @@ class BmgResult(ctypes.Structure):
                 ("sparse_passes", ctypes.c_int), ("kernel_ms", ctypes.c_double * 3),
                 ("kernel_bytes", ctypes.c_double * 3), ("kernel_launches", ctypes.c_int * 3),
                 ("host_la_seconds", ctypes.c_double), ("host_wait_seconds", ctypes.c_double),
-                ("host_syncs", ctypes.c_int)]
+                ("host_syncs", ctypes.c_int), ("pg_trials", ctypes.c_int),
+                ("alpha_last", ctypes.c_double)]
 
     def as_dict(self):
         out = {}

@@ -360,6 +360,9 @@ struct bmg_problem {
   // history blocks of Algorithm 2 with p_t >= 1 (allocated on first use)
   char *hist = nullptr;
   size_t hist_bytes = 0;
+  // state of the SpaRSA step rule (allocated on first use)
+  char *sp = nullptr;
+  size_t sp_bytes = 0;
   double kms[3] = {0, 0, 0}, kbytes[3] = {0, 0, 0};
   int klaunch[3] = {0, 0, 0};
   hipEvent_t get_event() {
@@ -396,6 +399,7 @@ struct bmg_problem {
     if (bitem.ready) (void)hipEventDestroy(bitem.ready);
     if (bitem.done) (void)hipEventDestroy(bitem.done);
     if (hist) (void)hipFree(hist);
+    if (sp) (void)hipFree(sp);
   }
 
   template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -731,6 +735,18 @@ struct Engine {
     count(sd->pl, 4.0 + 2.0 * sizeof(T), (double)nx * k * sizeof(T) + (double)ny * k * sizeof(TG));
     fetch(out, P->result, 2);
   }
+  // 1/2 sum over Omega of (w_i . h_j - v_p)^2 for values v in CSR order
+  double loss_vs(const T *v, const T *W, const T *H, int k) {
+    if (R->pl.nnz == 0) return 0.0;
+    with_gather(1, H, n, k, ldk, [&](auto Yg) {
+      using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
+      pass<TY>(1, R->pl, v, W, ldk, Yg, ldk, k, 0.0, 0.0, (T *)nullptr, 0, 0, nullptr, 0, sx(1));
+    });
+    count(R->pl, 4.0 + sizeof(T), (double)m * k * sizeof(T) + (double)n * k * sizeof(TG));
+    double h[2];
+    fetch(h, P->result, 2);
+    return 0.5 * h[0];
+  }
   double loss(const T *W, const T *H, int k) {
     if (R->pl.nnz == 0) return 0.0;
     with_gather(1, H, n, k, ldk, [&](auto Yg) {
@@ -765,13 +781,15 @@ struct Engine {
     count(C->pl, 4.0 + sizeof(T), (double)m * q * sizeof(TG) + (double)n * q * sizeof(T));
   }
   // V (m x q) = Z Y = W (H^T Y) - alpha S Y
-  void z_n(const ZOp &z, const T *Y, int q, T *V) {
+  // (Y and V at leading dimension ld, qld when not given)
+  void z_n(const ZOp &z, const T *Y, int q, T *V, int ld = 0) {
     if (q == 0) return;
+    const int l = ld > 0 ? ld : qld;
     T *dM = nullptr;
-    if (z.k > 0) dM = gram_dev(n, z.k, z.H, ldk, q, Y, qld, 1);
-    with_gather(3, Y, n, q, qld, [&](auto Yg) {
+    if (z.k > 0) dM = gram_dev(n, z.k, z.H, ldk, q, Y, l, 1);
+    with_gather(3, Y, n, q, l, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
-      pass<TY>(2, R->pl, z.s_rows, z.W, ldk, Yg, qld, q, 0.0, -z.alpha, V, qld, z.k, dM, q, sx(2));
+      pass<TY>(2, R->pl, z.s_rows, z.W, ldk, Yg, l, q, 0.0, -z.alpha, V, l, z.k, dM, q, sx(2));
     });
     count(R->pl, 4.0 + sizeof(T), (double)n * q * sizeof(TG) + (double)m * q * sizeof(T));
   }
@@ -849,6 +867,11 @@ extern "C" void bmg_options_default(bmg_options *o) {
   o->verbose = 0;
   o->lmsvd_p = 0;
   o->seed = 0;
+  o->step_rule = BMG_STEP_FIXED;
+  o->alpha_min = 1.99;
+  o->alpha_max = 1e3;
+  o->sparsa_beta = 0.5;
+  o->sparsa_delta = 0.999;
 }
 
 extern "C" bmg_status bmg_workspace_size(int64_t m, int64_t n, int64_t nnz, int k_cap,
@@ -1452,10 +1475,126 @@ struct Method : Engine<T, TG> {
 
   // One inexact PG step from X~ = W H^T (Algorithm 1, convex lifting phase).
   struct StepInfo {
-    int q = 0, iters = 0;
+    int q = 0, iters = 0, trials = 0;
     bool added = false;
-    double residual = 0.0, eps = 0.0;
+    double residual = 0.0, eps = 0.0, alpha = 0.0;
   };
+
+  // ------------------------------------------------------------ SpaRSA step rule
+  // (Suppl., the SpaRSA variant): from the second PG step on, the step is the
+  // BB step of eq. proxBB clipped to [alpha_min, alpha_max], shrunk by beta
+  // until the prox output satisfies eq. back, floored at alpha_min (eq. back
+  // holds there for L = 1).  Every trial restarts the subspace iteration from
+  // the same warm start.
+  bool sparsa = false;
+  bmg_options sp_opt{};
+  bool sp_have_prev = false;
+  int sp_kprev = 0;
+  struct SpMem {
+    T *U0, *W, *H, *R, *X;
+  };
+  // the kept warm start (m x qld), the previous PG point (W, H at ldk), its
+  // row-order residual and the sampled values of this step's X~ (nnz each):
+  // device memory allocated on first use, kept by the problem
+  SpMem sparsa_mem() {
+    const size_t bu = (size_t)rup((int64_t)sizeof(T) * m * qld, 256);
+    const size_t bw = (size_t)rup((int64_t)sizeof(T) * m * ldk, 256);
+    const size_t bh = (size_t)rup((int64_t)sizeof(T) * n * ldk, 256);
+    const size_t br = (size_t)rup((int64_t)sizeof(T) * std::max<int64_t>(R->pl.nnz, 1), 256);
+    const size_t need = bu + bw + bh + 2 * br;
+    if (P->sp_bytes < need) {
+      HIPC(hipStreamSynchronize(s));
+      if (P->sp) HIPC(hipFree(P->sp));
+      P->sp = nullptr;
+      P->sp_bytes = 0;
+      if (hipMalloc((void **)&P->sp, need) != hipSuccess) {
+        (void)hipGetLastError();
+        P->sp = nullptr;
+        throw BmgError{BMG_ENOMEM, "no device memory for the SpaRSA step rule"};
+      }
+      P->sp_bytes = need;
+    }
+    char *b = P->sp;
+    return SpMem{(T *)b, (T *)(b + bu), (T *)(b + bu + bw), (T *)(b + bu + bw + bh),
+                 (T *)(b + bu + bw + bh + br)};
+  }
+  // eq. proxBB read as the BB step ||dX||^2 / <dX, d grad f> between this PG
+  // point X~ = W H^T and the previous one (grad f(X) - grad f(Y) = P_Omega(X - Y)
+  // for (MC), so the denominator is ||R - R_prev||^2).  The numerator splits
+  // over ran(Q), Q = orth(W), and its complement so that nothing cancels (the
+  // three traces of eq. trace lose every digit once ||dX|| < ~1e-8 ||X||):
+  //   ||dX||^2 = ||H (Q^T W)^T - H_prev (Q^T W_prev)^T||^2 + ||E H^T - E_prev H_prev^T||^2,
+  // E = (I - Q Q^T) W, E_prev = (I - Q Q^T) W_prev (small; eq. trace on them).
+  // Scratch: Bq (m x qld), B3, B4 (m x qld), Dn (n x qld).  R_prev is consumed.
+  double bb_step(const T *W, const T *H, int k, const SpMem &sm, T *Bq, T *B3, T *B4, T *Dn) {
+    const int kp = sp_kprev;
+    auto three = [&](const T *W1, int l1, const T *H1, int k1, const T *W0, int l0, const T *H0, int k0) {
+      double v = 0.0;
+      if (k1 > 0) v += trace_prod(gram(m, k1, W1, l1, k1, W1, l1), gram(n, k1, H1, ldk, k1, H1, ldk), k1);
+      if (k0 > 0) v += trace_prod(gram(m, k0, W0, l0, k0, W0, l0), gram(n, k0, H0, ldk, k0, H0, ldk), k0);
+      if (k1 > 0 && k0 > 0) {
+        std::vector<double> A = gram(m, k0, W0, l0, k1, W1, l1), B = gram(n, k0, H0, ldk, k1, H1, ldk);
+        double c = 0.0;
+        for (size_t i = 0; i < A.size(); ++i) c += A[i] * B[i];
+        v -= 2.0 * c;
+      }
+      return v;
+    };
+    double num = 0.0;
+    int r = 0;
+    if (k > 0 && kp > 0) {
+      HIPC(launch_copy_cols<T>(m, k, W, ldk, B3, qld, s));
+      r = orth(m, B3, k, Bq, B4);
+    }
+    if (r == 0) {
+      num = three(W, ldk, H, k, sm.W, ldk, sm.H, kp);
+    } else {
+      std::vector<double> G1 = gram(m, r, Bq, qld, k, W, ldk);       // Q^T W      (r x k)
+      std::vector<double> G0 = gram(m, r, Bq, qld, kp, sm.W, ldk);   // Q^T W_prev (r x kp)
+      auto tr = [](const std::vector<double> &G, int a, int b, double sg) {
+        std::vector<double> t((size_t)a * b);  // sg * G^T laid out b x a
+        for (int i = 0; i < a; ++i)
+          for (int j = 0; j < b; ++j) t[(size_t)j * a + i] = sg * G[(size_t)i * b + j];
+        return t;
+      };
+      gemm(n, k, H, ldk, r, tr(G1, r, k, 1.0), Dn, qld, 0.0);
+      gemm(n, kp, sm.H, ldk, r, tr(G0, r, kp, -1.0), Dn, qld, 1.0);
+      num = fro2(n, Dn, qld, r);
+      std::vector<double> nG1(G1), nG0(G0);
+      for (double &v : nG1) v = -v;
+      for (double &v : nG0) v = -v;
+      HIPC(launch_copy_cols<T>(m, k, W, ldk, B3, qld, s));
+      gemm(m, r, Bq, qld, k, nG1, B3, qld, 1.0);                    // E
+      HIPC(launch_copy_cols<T>(m, kp, sm.W, ldk, B4, qld, s));
+      gemm(m, r, Bq, qld, kp, nG0, B4, qld, 1.0);                   // E_prev
+      num += three(B3, qld, H, k, B4, qld, sm.H, kp);
+    }
+    num = std::max(num, 0.0);
+    double den = 0.0;
+    if (R->pl.nnz > 0) {
+      HIPC(launch_axpy<T>(R->pl.nnz, 1, -1.0, (const T *)R->r, 1, sm.R, 1, s));
+      den = gram(R->pl.nnz, 1, sm.R, 1, 1, sm.R, 1)[0];
+    }
+    const double ab = den > 0.0 ? num / den : sp_opt.alpha_max;
+    return std::min(sp_opt.alpha_max, std::max(sp_opt.alpha_min, ab));
+  }
+  // eq. back at X+ = Wn Hn^T (rank kn) from X~:
+  //   f(X+) <= f(X~) + <grad f(X~), X+ - X~> + delta / alpha ||X+ - X~||^2.
+  // For the quadratic MC loss the left side minus the first two terms is
+  // exactly 1/2 ||P_Omega(X+ - X~)||^2, tested in that form (the f terms nearly
+  // cancel once steps are small): one sampled pass of X+ against the sampled
+  // values of X~ (xs = R~ + A), with FP32 gathers in the BF16 mode.
+  // d2 = ||X+ - X~||^2.
+  bool back_condition(State &S, int kn, const T *xs, double d2, double alpha, double delta) {
+    double lhs = 0.0;
+    if (R->pl.nnz > 0) {
+      const bool eg = this->exact_gather;
+      this->exact_gather = true;
+      lhs = E::loss_vs(xs, S.Wn, S.Hn, kn);
+      this->exact_gather = eg;
+    }
+    return lhs <= delta / alpha * d2;
+  }
   // FP64 sampled residual of both orientations from the FP32 masters (BF16
   // mode refresh): R in FP64 from FP64 copies of W, H and the FP64 values,
   // stored back in the pass type.
@@ -1502,7 +1641,6 @@ struct Method : Engine<T, TG> {
         E::sddmm_store(C, S.H, S.W, k, n, m, sc);
       }
     }
-    ZOp z{S.W, S.H, k, alpha, (const T *)R->r, (const T *)C->r};
     const bool hi_before = this->exact_gather;
     this->exact_gather = kShadow && (fp64_refresh || hi_before);
     // warm start (eqs. rt0 / rt0-1): orth([U_t, W~_t]) or orth([U_t, U_{t-1}])
@@ -1549,50 +1687,82 @@ struct Method : Engine<T, TG> {
       U0 = B1;
       info.added = true;
     }
-    // subspace iteration
-    T *Uf = nullptr, *Yf = nullptr;
-    std::vector<double> Tq;
-    const int q = lmsvd(z, U0, q0, tau, ssi_max, (alpha * lam) * (alpha * lam), &Uf, &Yf, Tq,
-                        &info.iters);
-    info.q = q;
+    // step size: the fixed alpha, or the BB step of eq. proxBB (SpaRSA rule)
+    double a = alpha;
+    T *U0keep = nullptr, *sm_x = nullptr;
+    if (sparsa) {
+      SpMem sm = sparsa_mem();
+      U0keep = sm.U0;
+      sm_x = sm.X;
+      if (R->pl.nnz > 0) {  // sampled values of X~ = R~ + A
+        HIPC(launch_copy_cols<T>(R->pl.nnz, 1, (const T *)R->r, 1, sm.X, 1, s));
+        HIPC(launch_axpy<T>(R->pl.nnz, 1, 1.0, avals(R), 1, sm.X, 1, s));
+      }
+      if (sp_have_prev)
+        a = bb_step(S.W, S.H, k, sm, U0 == B1 ? B2 : B1, blk(P->L.b_B3), B4, blk(P->L.b_Y2));
+      // the point of this step becomes the previous one of the next
+      HIPC(launch_copy_cols<T>(m, k, S.W, ldk, sm.W, ldk, s));
+      HIPC(launch_copy_cols<T>(n, k, S.H, ldk, sm.H, ldk, s));
+      if (R->pl.nnz > 0) HIPC(launch_copy_cols<T>(R->pl.nnz, 1, (const T *)R->r, 1, sm.R, 1, s));
+      sp_kprev = k;
+      sp_have_prev = true;
+      if (q0 > 0) HIPC(launch_copy_cols<T>(m, q0, U0, qld, U0keep, qld, s));
+    }
     // new U_cur goes into the old U_prev buffer
     std::swap(S.Ucur, S.Uprev);
     std::swap(S.kc, S.kp);
-    Tail tl = prox_tail(Uf, Yf, q, Tq, alpha * lam, S.Wn, S.Hn, S.Ucur, S.uvec);
-    S.kc = tl.k;
-    // ||X~ - X+|| = sqrt(||Uhat^T X~ - Uhat^T X+||^2 + ||(I - Uhat Uhat^T) X~||^2)
+    T *Uf = nullptr, *Yf = nullptr;
+    std::vector<double> Tq;
+    Tail tl;
+    int q = 0;
     double d2 = 0.0, x2 = 0.0;
-    if (q > 0) {
-      T *Dt = (Yf == blk(P->L.b_Y2)) ? blk(P->L.b_Y) : blk(P->L.b_Y2);  // n x q scratch
-      std::vector<double> A1 = gram(m, k, S.W, ldk, q, Uf, qld);        // W~^T Uhat
-      std::vector<double> A2 = gram(m, tl.k, S.Wn, ldk, q, Uf, qld);    // W+^T Uhat
-      for (double &v : A2) v = -v;
-      // Dt = H~ (W~^T Uhat) - H+ (W+^T Uhat)  =  (Uhat^T X~ - Uhat^T X+)^T
-      if (k > 0) gemm(n, k, S.H, ldk, q, A1, Dt, qld, 0.0);
-      else HIPC(launch_fill<T>(Dt, n, q, qld, 0.0, s));
-      if (tl.k > 0) gemm(n, tl.k, S.Hn, ldk, q, A2, Dt, qld, 1.0);
-      d2 = fro2(n, Dt, qld, q);
-      if (k > 0) {
-        T *Em = blk(P->L.b_D);
-        HIPC(launch_copy_cols<T>(m, k, S.W, ldk, Em, ldk, s));
-        std::vector<double> negA1(A1);
-        for (double &v : negA1) v = -v;
-        gemm(m, q, Uf, qld, k, [&] {  // (Uhat^T W~) laid out q x k
-          std::vector<double> t2((size_t)q * k);
-          for (int i = 0; i < k; ++i)
-            for (int j = 0; j < q; ++j) t2[(size_t)j * k + i] = negA1[(size_t)i * q + j];
-          return t2;
-        }(), Em, ldk, 1.0);
-        std::vector<double> EE = gram(m, k, Em, ldk, k, Em, ldk);
-        std::vector<double> HH = gram(n, k, S.H, ldk, k, S.H, ldk);
-        d2 += std::max(0.0, trace_prod(EE, HH, k));
-      }
-    } else if (k > 0) {
-      d2 = trace_prod(gram(m, k, S.W, ldk, k, S.W, ldk), gram(n, k, S.H, ldk, k, S.H, ldk), k);
-    }
     if (k > 0) x2 = trace_prod(gram(m, k, S.W, ldk, k, S.W, ldk), gram(n, k, S.H, ldk, k, S.H, ldk), k);
+    for (info.trials = 1;; ++info.trials) {
+      if (info.trials > 1 && q0 > 0) HIPC(launch_copy_cols<T>(m, q0, U0keep, qld, U0, qld, s));
+      ZOp z{S.W, S.H, k, a, (const T *)R->r, (const T *)C->r};
+      int it = 0;
+      q = lmsvd(z, U0, q0, tau, ssi_max, (a * lam) * (a * lam), &Uf, &Yf, Tq, &it);
+      info.iters += it;
+      tl = prox_tail(Uf, Yf, q, Tq, a * lam, S.Wn, S.Hn, S.Ucur, S.uvec);
+      S.kc = tl.k;
+      // ||X~ - X+|| = sqrt(||Uhat^T X~ - Uhat^T X+||^2 + ||(I - Uhat Uhat^T) X~||^2)
+      d2 = 0.0;
+      if (q > 0) {
+        T *Dt = (Yf == blk(P->L.b_Y2)) ? blk(P->L.b_Y) : blk(P->L.b_Y2);  // n x q scratch
+        std::vector<double> A1 = gram(m, k, S.W, ldk, q, Uf, qld);        // W~^T Uhat
+        std::vector<double> A2 = gram(m, tl.k, S.Wn, ldk, q, Uf, qld);    // W+^T Uhat
+        for (double &v : A2) v = -v;
+        // Dt = H~ (W~^T Uhat) - H+ (W+^T Uhat)  =  (Uhat^T X~ - Uhat^T X+)^T
+        if (k > 0) gemm(n, k, S.H, ldk, q, A1, Dt, qld, 0.0);
+        else HIPC(launch_fill<T>(Dt, n, q, qld, 0.0, s));
+        if (tl.k > 0) gemm(n, tl.k, S.Hn, ldk, q, A2, Dt, qld, 1.0);
+        d2 = fro2(n, Dt, qld, q);
+        if (k > 0) {
+          T *Em = blk(P->L.b_D);
+          HIPC(launch_copy_cols<T>(m, k, S.W, ldk, Em, ldk, s));
+          std::vector<double> negA1(A1);
+          for (double &v : negA1) v = -v;
+          gemm(m, q, Uf, qld, k, [&] {  // (Uhat^T W~) laid out q x k
+            std::vector<double> t2((size_t)q * k);
+            for (int i = 0; i < k; ++i)
+              for (int j = 0; j < q; ++j) t2[(size_t)j * k + i] = negA1[(size_t)i * q + j];
+            return t2;
+          }(), Em, ldk, 1.0);
+          std::vector<double> EE = gram(m, k, Em, ldk, k, Em, ldk);
+          std::vector<double> HH = gram(n, k, S.H, ldk, k, S.H, ldk);
+          d2 += std::max(0.0, trace_prod(EE, HH, k));
+        }
+      } else {
+        d2 = x2;
+      }
+      if (!sparsa || a <= sp_opt.alpha_min) break;
+      if (back_condition(S, tl.k, sm_x, d2, a, sp_opt.sparsa_delta)) break;
+      a = std::max(sp_opt.alpha_min, a * sp_opt.sparsa_beta);
+    }
+    info.q = q;
+    info.alpha = a;
     info.residual = sqrt(d2) / (1.0 + sqrt(std::max(x2, 0.0)) + sqrt(sr[0]));
-    const double z2 = x2 - 2.0 * alpha * sr[1] + alpha * alpha * sr[0];
+    const double z2 = x2 - 2.0 * a * sr[1] + a * a * sr[0];
     info.eps = sqrt(std::max(z2 - tl.sum_sig2, 0.0));
     // safeguard bookkeeping
     this->exact_gather = hi_before;
@@ -1620,6 +1790,9 @@ struct Method : Engine<T, TG> {
   bmg_status solve(const bmg_options &o, State &S, bmg_result *res) {
     const auto t0 = std::chrono::steady_clock::now();
     hist_p = o.lmsvd_p;
+    sparsa = o.step_rule == BMG_STEP_SPARSA;
+    sp_opt = o;
+    sp_have_prev = false;
     t_la_acc = t_wait_acc = 0.0;
     n_sync_acc = 0;
     init_state(S);
@@ -1629,7 +1802,8 @@ struct Method : Engine<T, TG> {
     const int every = std::max(1, o.refresh_every);
     bool hi = false;                    // BF16 mode switched to FP32 gathers
     double last_refresh = INFINITY;
-    int t = 0, ssi_total = 0;
+    int t = 0, ssi_total = 0, trials_total = 0;
+    double alpha_last = o.alpha;
     bool conv = false;
     for (t = 0; t < o.max_iter; ++t) {
       // BF16 mode: every `every`-th iteration is a refresh: no BM phase (the
@@ -1655,13 +1829,17 @@ struct Method : Engine<T, TG> {
       const double tau = std::max(floor, std::min(1e-4, 0.1 * S.res_prev * S.res_prev));
       StepInfo st = pg_step(S, changed, o.lambda, o.alpha, tau, o.ssi_max_iter, o.seed, t, refresh);
       ssi_total += st.iters;
+      trials_total += st.trials;
+      alpha_last = st.alpha;
       resid = st.residual;
       eps = st.eps;
       F = objective_balanced(S, o.lambda, refresh);
       REQUIRE(std::isfinite(F) && std::isfinite(resid), BMG_ENONFINITE, "non-finite objective");
       if (o.verbose)
-        fprintf(stderr, "[bmg] t=%d F=%.15g F_bm=%.15g res=%.3e k=%d q=%d ssi=%d eps=%.3e add=%d\n", t,
-                F, F_bm, resid, S.k, st.q, st.iters, eps, (int)st.added);
+        fprintf(stderr,
+                "[bmg] t=%d F=%.15g F_bm=%.15g res=%.3e k=%d q=%d ssi=%d eps=%.3e add=%d alpha=%.4g "
+                "trials=%d\n",
+                t, F, F_bm, resid, S.k, st.q, st.iters, eps, (int)st.added, st.alpha, st.trials);
       S.res_prev = resid;
       if (kShadow && refresh && !hi) {
         if (resid <= 1e-3 || resid > 0.7 * last_refresh) hi = true;
@@ -1689,6 +1867,8 @@ struct Method : Engine<T, TG> {
       res->k = S.k;
       res->iters = t;
       res->ssi_iters = ssi_total;
+      res->pg_trials = trials_total;
+      res->alpha_last = alpha_last;
       res->status = conv ? BMG_OK : BMG_NOT_CONVERGED;
       res->F = F;
       res->F_bm = F_bm;
@@ -1802,16 +1982,26 @@ extern "C" bmg_status bmg_objective(bmg_problem *P, const double *W, const doubl
   return BMG_OK;
 }
 
+static bool step_rule_ok(const bmg_options *o) {
+  if (o->step_rule == BMG_STEP_FIXED) return true;
+  return o->step_rule == BMG_STEP_SPARSA && o->alpha_min > 0.0 && o->alpha_max >= o->alpha_min &&
+         o->sparsa_beta > 0.0 && o->sparsa_beta < 1.0 && o->sparsa_delta > 0.0 &&
+         o->sparsa_delta < 1.0 && std::isfinite(o->alpha_max);
+}
+
 extern "C" bmg_status bmg_prox_step(bmg_problem *P, double *W, double *H, int *k_inout, int ld,
                                     const bmg_options *opt, double *sigma, double *residual) {
   if (!k_inout || !opt) return fail(BMG_EINVAL, "bmg_prox_step: null argument");
-  if (opt->lmsvd_p < 0 || opt->lmsvd_p > LMSVD_MAX_HIST || opt->ssi_max_iter < 1)
+  if (opt->lmsvd_p < 0 || opt->lmsvd_p > LMSVD_MAX_HIST || opt->ssi_max_iter < 1 ||
+      !(opt->alpha > 0.0) || !step_rule_ok(opt))
     return fail(BMG_EINVAL, "bmg_prox_step: bad options");
   bmg_status st = check_factors(P, W, H, *k_inout, ld);
   if (st != BMG_OK) return st;
   try {
     Method<double> M(P);
     M.hist_p = opt->lmsvd_p;
+    M.sparsa = opt->step_rule == BMG_STEP_SPARSA;
+    M.sp_opt = *opt;
     Method<double>::State S;
     M.init_state(S);
     const int k = *k_inout;
@@ -1842,7 +2032,7 @@ extern "C" bmg_status bmg_solve(bmg_problem *P, double *W, double *H, int ld, co
   if (ld < 8 || ld % 8) return fail(BMG_EINVAL, "bmg_solve: ld must be a positive multiple of 8");
   if (opt->lambda <= 0.0 || opt->alpha <= 0.0 || opt->bm_epochs < 0 || opt->max_iter < 0 ||
       opt->ssi_max_iter < 1 || opt->k_init < 1 || opt->lmsvd_p < 0 ||
-      opt->lmsvd_p > LMSVD_MAX_HIST)
+      opt->lmsvd_p > LMSVD_MAX_HIST || !step_rule_ok(opt))
     return fail(BMG_EINVAL, "bmg_solve: bad options");
   P->reset_stats();
   P->timing = opt->timing != 0;

@@ -244,6 +244,48 @@ def test_solve_lmsvd_history_reduced_precision(precision, bar):
     assert abs(Fw - Fstar) <= bar * Fstar
 
 
+@pytest.mark.parametrize("shape", [(40, 60, 700), (60, 40, 700), (120, 200, 4000), (300, 500, 30000)])
+def test_solve_parity_fp64_sparsa(shape):
+    """SpaRSA step rule (BB step + backtracking on eq. back) against the oracle's."""
+    m, n, nnz = shape
+    lam = 1.0 if nnz > 10000 else 0.3
+    p = synth.tiny(m, n, nnz, rank=3 if nnz < 10000 else 8, lam=lam, seed=m + n)
+    recs = []
+    orc = core.solve(p, core.Options(lam=lam, k0=4, tol=1e-10, seed=3, max_iter=3000,
+                                     step_rule="sparsa"), callback=recs.append)
+    dp = to_dev(p, k_cap=128)
+    W, H, k, r = dp.bmg_solve(lam=lam, k_init=4, tol=1e-10, seed=3, max_iter=3000, step_rule="sparsa")
+    print("sparsa", shape, r["iters"], orc.iters, r["pg_trials"], sum(x.trials for x in recs),
+          r["alpha_last"], recs[-1].alpha, r["F"], orc.F, flush=True)
+    assert r["status"] == 0 and orc.converged
+    assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
+    assert k == orc.k
+    assert r["pg_trials"] >= r["iters"]
+    Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], lam)
+    assert math.isclose(Fw, r["F"], rel_tol=1e-10)
+
+
+def test_sparsa_with_equal_bounds_is_the_fixed_step_bitwise():
+    p = synth.tiny(120, 200, 4000, rank=3, lam=0.3, seed=320)
+    outs = []
+    for kw in ({}, {"step_rule": "sparsa", "alpha_min": 1.99, "alpha_max": 1.99}):
+        W, H, k, r = to_dev(p, k_cap=64).bmg_solve(lam=0.3, k_init=4, tol=1e-10, seed=3, **kw)
+        outs.append((W.cpu().numpy(), H.cpu().numpy(), k, r["iters"], r["pg_trials"]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2:] == outs[1][2:] and outs[1][4] == outs[1][3]
+
+
+def test_solve_sparsa_fp32_objective_error():
+    p = synth.tiny(150, 220, 5000, rank=3, lam=0.3, seed=31)
+    dp = to_dev(p, k_cap=64, precision="fp32")
+    W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-6, seed=3, max_iter=600, step_rule="sparsa")
+    Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
+    Fstar = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-11, seed=3)).F
+    print("sparsa fp32", r["status"], r["iters"], r["pg_trials"], Fw, Fstar, flush=True)
+    assert r["status"] == 0
+    assert abs(Fw - Fstar) <= 1e-5 * Fstar
+
+
 def test_solve_full_omega_closed_form():
     m, n, lam = 30, 45, 1.5
     p = synth.tiny(m, n, m * n, rank=4, seed=12)
@@ -338,6 +380,11 @@ def test_invalid_inputs_are_rejected():
     for hp in (-1, 5):
         with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
             dp.bmg_solve(lam=0.1, lmsvd_p=hp)
+    for kw in ({"step_rule": 2}, {"step_rule": "sparsa", "sparsa_beta": 1.0},
+               {"step_rule": "sparsa", "alpha_min": 5.0, "alpha_max": 2.0},
+               {"step_rule": "sparsa", "sparsa_delta": 0.0}):
+        with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
+            dp.bmg_solve(lam=0.1, **kw)
 
 
 # ----------------------------------------------------------------------------- full size, sampled

@@ -45,6 +45,8 @@ def test_options_default(lib):
     assert o.alpha == 1.99 and o.bm_epochs == 3 and o.psi0 == 0.1 and o.tol == 1e-6
     assert o.k_init == 8 and o.refresh_every == 5 and o.ssi_max_iter == 50
     assert o.lmsvd_p == 0 and o.seed == 0 and o.timing == 0
+    assert o.step_rule == _lib.BMG_STEP_FIXED and o.alpha_min == 1.99 and o.alpha_max == 1e3
+    assert o.sparsa_beta == 0.5 and o.sparsa_delta == 0.999
 
 
 def test_workspace_size_and_argument_checks(lib):

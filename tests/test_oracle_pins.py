@@ -430,6 +430,21 @@ def test_bb_step_matches_dense_definition():
     assert core.bb_step(W, H, W, H, R, R, 1.0, 7.0) == 7.0
 
 
+def test_diff_fro2_split_resolves_nearby_iterates():
+    W1, H1, V = rand((40, 4), 1), rand((60, 4), 2), rand((40, 4), 3)
+    W0, H0 = rand((40, 3), 4), rand((60, 3), 5)
+    d = float(np.sum((W1 @ H1.T - W0 @ H0.T) ** 2))
+    assert math.isclose(core.diff_fro2_split(W1, H1, W0, H0), d, rel_tol=1e-12)
+    # W0 = W1 + delta V, H0 = H1: dX = -delta V H1^T exactly
+    for delta in (1e-4, 1e-9, 1e-12):
+        exact = delta ** 2 * float(np.sum((V @ H1.T) ** 2))
+        got = core.diff_fro2_split(W1, H1, W1 + delta * V, H1)
+        assert math.isclose(got, exact, rel_tol=1e-3), (delta, got, exact)
+    # where eq. trace has lost every digit
+    three = core.diff_fro2_factored(W1, H1, W1 + 1e-9 * V, H1)
+    assert not math.isclose(three, 1e-18 * float(np.sum((V @ H1.T) ** 2)), rel_tol=1e-1)
+
+
 def test_back_condition_matches_dense_definition():
     p = tiny_problem(30, 45, 500, lam=0.2)
     A, M = dense.to_dense(p)
@@ -438,11 +453,14 @@ def test_back_condition_matches_dense_definition():
     f = lambda Y: 0.5 * float(np.sum(np.where(M, Y - A, 0.0) ** 2))  # noqa: E731
     G = np.where(M, X - A, 0.0)
     d2 = float(np.sum((Xn - X) ** 2))
-    for alpha, delta in [(1.99, 0.999), (50.0, 0.5), (0.1, 0.9)]:
+    for alpha, delta in [(1.99, 0.999), (50.0, 0.5), (0.1, 0.9), (2.1, 0.9)]:
         rhs = f(X) + float(np.sum(G * (Xn - X))) + delta / alpha * d2
         ok, lhs, r = core.back_condition(p, core.sddmm(p, W, H), Wn, Hn, d2, alpha, delta)
-        assert math.isclose(lhs, f(Xn), rel_tol=1e-12) and math.isclose(r, rhs, rel_tol=1e-12)
+        # the curvature term of the quadratic loss, and the literal eq. back
+        assert math.isclose(lhs, f(Xn) - f(X) - float(np.sum(G * (Xn - X))), rel_tol=1e-9)
+        assert math.isclose(r, delta / alpha * d2, rel_tol=1e-12)
         assert ok == (f(Xn) <= rhs)
+    assert not core.back_condition(p, core.sddmm(p, W, H), Wn, Hn, d2, 50.0, 0.5)[0]
     # any step alpha < 2 delta / L (L = 1) satisfies it: the descent lemma
     ok, _, _ = core.back_condition(p, core.sddmm(p, W, H), Wn, Hn, d2, 1.99, 0.999)
     assert ok
