@@ -169,6 +169,8 @@ def main():
         out["precision_modes"] = precision_steps(bmg, p, dev, k0, lam, recs[-1]["F"])
         out["time_to_tol"] = time_to_tol(bmg, synth, dev)
         out["time_to_tol_gpu_bound"] = time_to_tol_gpu_bound(bmg, synth, dev)
+        out["sparsa_step"] = sparsa_step(bmg, synth, dev, out["time_to_tol"]["fp64"],
+                                         out["time_to_tol_gpu_bound"]["lambda_100"]["fp64"])
         out["serve"] = serving(bmg, synth, dev, args.serve_count)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -226,6 +228,45 @@ def lmsvd_history(bmg, synth, dev, prob, W, H, k0, lam, recs0, sec0, steps=3):
             log("%s lmsvd_p=%d: median %.3fs, subspace iterations %s" % (name, hp, np.median(secs), ssi))
         out[name] = rec
         del prob2
+    return out
+
+
+def sparsa_step(bmg, synth, dev, fixed_small, fixed_quarter):
+    """The SpaRSA step rule (BB step + backtracking on eq. back) against the
+    fixed step alpha = 1.99, FP64: the 1000 x 1500 solve to 1e-6 (five seeds,
+    objective against the certified optimum) and the quarter-scale
+    Netflix-shaped solve at lambda 100 to 1e-4 (three seeds).  Fixed-step
+    figures are those of the time-to-tolerance runs above."""
+    import numpy as np
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "small_uniform.json")))
+    out = {}
+    cases = [("small_uniform tol 1e-6", synth.small_uniform(), 0.5, 8, 1e-6, (11, 12, 13, 14, 15), 256,
+              fixed_small),
+             ("netflix_shape x0.25 lambda 100 tol 1e-4", synth.netflix_shape(scale=0.25), 100.0, 16, 1e-4,
+              (3, 4, 5), 128, fixed_quarter)]
+    for name, p, lm, kk, tol, seeds, kc, fixed in cases:
+        prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=kc, precision="fp64",
+                                     device=dev)
+        prob.bmg_solve(lam=lm, k_init=kk, tol=tol, seed=seeds[0], max_iter=2, step_rule="sparsa")
+        secs, iters, trials, ssi, Fs = [], [], [], [], []
+        for sd in seeds:
+            t0 = time.perf_counter()
+            W, H, k, r = prob.bmg_solve(lam=lm, k_init=kk, tol=tol, seed=sd, max_iter=1000,
+                                        step_rule="sparsa")
+            secs.append(time.perf_counter() - t0)
+            iters.append(r["iters"]); trials.append(r["pg_trials"]); ssi.append(r["ssi_iters"])
+            Fs.append(r["F"])
+        rec = {"seconds_median": round(float(np.median(secs)), 4), "iters": iters, "prox_computations": trials,
+               "ssi_iters": ssi, "fixed_step_seconds_median": fixed["seconds_median"],
+               "fixed_step_iters": fixed["iters"]}
+        if name.startswith("small"):
+            rec["max_rel_err_vs_oracle_optimum"] = max(abs(F - golden["F"]) / golden["F"] for F in Fs)
+        else:
+            rec["F"] = Fs
+        out[name] = rec
+        log("sparsa %s: median %.3fs (fixed %.3fs), iters %s (fixed %s), prox computations %s" % (
+            name, rec["seconds_median"], fixed["seconds_median"], iters, fixed["iters"], trials))
+        del prob
     return out
 
 
