@@ -16,6 +16,10 @@ Function -> passage it follows -> what pins it (tests/test_oracle_*.py):
   bm_epoch                BM phase + non-increase condition (Sec. 3, eq. nonincrease);
                           solver = preconditioned steepest descent, exact line search (reading)
                           -> brute-force minimisation of the 1-D quadratic; monotone F~
+  polymf_epoch            polyMF-SS (Sec. 6.1.1): column-pair BCD, exact quartic line search
+                          -> quartic coefficients against the dense block objective; the
+                             step against a fine grid; monotone F~ per block; solves reach
+                             the dense optimum
   orth                    range basis used by eq-ssi, eq. rt0, eq. rt      -> span tests
   lmsvd                   Algorithm 2, history length p_t >= 0 (Suppl. A.1.2)
                           -> dense eigendecomposition of Z Z^T; Ritz values against the
@@ -241,6 +245,66 @@ def bm_epoch(prob, W, H, lam):
     W1, sw = bm_half_step_W(prob, W, H, lam)
     H1, sh = bm_half_step_H(prob, W1, H, lam)
     return W1, H1, (sw, sh)
+
+
+# ----------------------------------------------------------------------------- polyMF-SS BM solver
+
+def quartic_min(c1: float, c2: float, c3: float, c4: float) -> float:
+    """Global minimiser over t >= 0 of psi(t) = c1 t + c2 t^2 + c3 t^3 + c4 t^4
+    (c4 >= 0): the best of t = 0 and the positive real roots of psi'."""
+    cands = [0.0]
+    for r in np.roots([4.0 * c4, 3.0 * c3, 2.0 * c2, c1]):
+        if abs(r.imag) <= 1e-9 * max(1.0, abs(r.real)) and r.real > 0.0:
+            cands.append(float(r.real))
+    psi = lambda t: ((c4 * t + c3) * t + c2) * t * t + c1 * t  # noqa: E731
+    return min(cands, key=lambda t: (psi(t), t))
+
+
+def polymf_block(prob, W, H, j: int, lam: float, R):
+    """One block of the polyMF-SS BM solver (Sec. 6.1.1: block coordinate
+    descent with exact line search, a block being column j of W and of H).
+
+    On the block, phi(w, h) = 1/2 ||P_Omega(R - w_j h_j^T + w h^T)||^2
+    + lam/2 (||w||^2 + ||h||^2).  Direction (reading): the block gradient
+        g_w = R h_j + lam w_j,   g_h = R^T w_j + lam h_j
+    scaled entrywise by the diagonal of the block Hessian of each half,
+        d_w[i] = -g_w[i] / (sum_{l in Omega_i} h_l^2 + lam)   (and likewise d_h),
+    so that t = 1 is the exact minimiser when only one half moves.  Along
+    (w + t d_w, h + t d_h) every sampled residual is r + t a + t^2 b with
+        a = d_w[i] h_l + w_i d_h[l],   b = d_w[i] d_h[l],
+    so phi is a quartic in t; the step is its exact minimiser over t >= 0.
+    Returns (W, H, R, t) with the residual R updated on Omega."""
+    rows, cols = prob.rows(), prob.col
+    w, h = W[:, j].copy(), H[:, j].copy()
+    ones = np.ones(prob.nnz)
+    gw = spmm(prob, R, h[:, None])[:, 0] + lam * w
+    gh = spmm_t(prob, R, w[:, None])[:, 0] + lam * h
+    cw = spmm(prob, ones, (h * h)[:, None])[:, 0] + lam
+    ch = spmm_t(prob, ones, (w * w)[:, None])[:, 0] + lam
+    dw, dh = -gw / cw, -gh / ch
+    a = dw[rows] * h[cols] + w[rows] * dh[cols]
+    b = dw[rows] * dh[cols]
+    c1 = float(np.dot(R, a)) + lam * (float(np.dot(w, dw)) + float(np.dot(h, dh)))
+    c2 = 0.5 * float(np.dot(a, a)) + float(np.dot(R, b)) \
+        + 0.5 * lam * (float(np.dot(dw, dw)) + float(np.dot(dh, dh)))
+    c3 = float(np.dot(a, b))
+    c4 = 0.5 * float(np.dot(b, b))
+    t = quartic_min(c1, c2, c3, c4)
+    W, H = W.copy(), H.copy()
+    W[:, j] = w + t * dw
+    H[:, j] = h + t * dh
+    return W, H, R + t * a + t * t * b, t
+
+
+def polymf_epoch(prob, W, H, lam):
+    """One polyMF-SS epoch: blocks j = 0, ..., k-1 in order, from the residual
+    of the incoming factors.  F~ never increases (eq. nonincrease)."""
+    R = sddmm(prob, W, H)
+    steps = []
+    for j in range(W.shape[1]):
+        W, H, R, t = polymf_block(prob, W, H, j, lam, R)
+        steps.append(t)
+    return W, H, steps
 
 
 # ----------------------------------------------------------------------------- linear algebra helpers
@@ -513,6 +577,7 @@ class Options:
     # variant: BB step of eq. proxBB clipped to [alpha_min, alpha_max], then
     # backtracking by sparsa_beta until eq. back holds with sparsa_delta)
     step_rule: str = "fixed"
+    bm_solver: str = "psd"       # "psd": preconditioned steepest descent; "polymf": polyMF-SS
     alpha_min: float = 1.99      # < 2 delta / L (L = 1): eq. back holds there
     alpha_max: float = 1e3
     sparsa_beta: float = 0.5
@@ -676,6 +741,8 @@ def _solve(prob, opt: Options, callback=None) -> SolveResult:
     sparsa = opt.step_rule == "sparsa"
     if opt.step_rule not in ("fixed", "sparsa"):
         raise ValueError("step_rule must be 'fixed' or 'sparsa'")
+    if opt.bm_solver not in ("psd", "polymf"):
+        raise ValueError("bm_solver must be 'psd' or 'polymf'")
     prev_pt = None                                  # (W~, H~, R) of the previous PG step
     lam, alpha = opt.lam, opt.alpha
     init, _ = initialize(prob, lam, opt.k0, opt.seed)
@@ -698,7 +765,10 @@ def _solve(prob, opt: Options, callback=None) -> SolveResult:
         for _ in range(opt.bm_epochs):
             if Wt.shape[1] == 0:
                 break
-            Wt, Ht, _ = bm_epoch(prob, Wt, Ht, lam)
+            if opt.bm_solver == "polymf":
+                Wt, Ht, _ = polymf_epoch(prob, Wt, Ht, lam)
+            else:
+                Wt, Ht, _ = bm_epoch(prob, Wt, Ht, lam)
         F_bm = bm_objective(prob, Wt, Ht, lam)
         changed = not (np.array_equal(Wt, W) and np.array_equal(Ht, H))
         # ---- convex lifting: Z_t = X~_t - alpha grad f(X~_t)

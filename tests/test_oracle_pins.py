@@ -494,3 +494,68 @@ def test_sparsa_solve_reaches_the_optimum_in_fewer_iterations():
     assert b.iters < a.iters
     assert sum(r.trials for r in sp) > b.iters
     assert all(1.99 <= r.alpha <= 1e3 for r in sp) and max(r.alpha for r in sp) > 1.99
+
+
+# ----------------------------------------------------------------------------- polyMF-SS
+
+def test_polymf_block_direction_and_exact_quartic_step():
+    # Sec. 6.1.1: a block is column j of W and of H; exact line search
+    p = tiny_problem(30, 45, 600, lam=0.3)
+    A, M = dense.to_dense(p)
+    lam, j = 0.3, 1
+    W, H = rand((30, 3), 11), rand((45, 3), 12)
+    R = core.sddmm(p, W, H)
+    W1, H1, R1, t = core.polymf_block(p, W, H, j, lam, R)
+    G = np.where(M, W @ H.T - A, 0.0)
+    w, h = W[:, j], H[:, j]
+    dw = -(G @ h + lam * w) / (M @ (h * h) + lam)
+    dh = -(G.T @ w + lam * h) / (M.T @ (w * w) + lam)
+    assert t > 0
+    assert np.allclose(W1[:, j], w + t * dw, atol=1e-12) and np.allclose(H1[:, j], h + t * dh, atol=1e-12)
+    assert np.array_equal(np.delete(W1, j, 1), np.delete(W, j, 1))
+    # the updated residual is the residual of the new factors
+    assert np.allclose(R1, core.sddmm(p, W1, H1), atol=1e-12)
+
+    def phi(s):
+        Ws, Hs = W.copy(), H.copy()
+        Ws[:, j] = w + s * dw
+        Hs[:, j] = h + s * dh
+        return 0.5 * float(np.sum(np.where(M, Ws @ Hs.T - A, 0.0) ** 2)) \
+            + 0.5 * lam * (float(np.sum(Ws * Ws)) + float(np.sum(Hs * Hs)))
+    grid = np.linspace(0.0, 3.0 * t + 1.0, 3001)
+    vals = np.array([phi(s) for s in grid])
+    assert phi(t) <= vals.min() + 1e-12 * abs(vals.min())
+    e = 1e-5 * t
+    assert abs(phi(t + e) - phi(t - e)) / (2 * e) <= 1e-6 * abs(phi(0.0) - phi(t)) / t
+
+
+def test_quartic_min_cases():
+    # psi(t) = c1 t + c2 t^2 + c3 t^3 + c4 t^4 over t >= 0
+    assert core.quartic_min(-2.0, 1.0, 0.0, 0.0) == pytest.approx(1.0)       # quadratic
+    assert core.quartic_min(1.0, 1.0, 0.0, 0.0) == 0.0                        # ascent
+    # two local minima (roots of psi' at 1, 2, 4 scaled): the global one wins
+    # psi'(t) = 4 (t - 1)(t - 2)(t - 4) = 4 t^3 - 28 t^2 + 56 t - 32
+    c4, c3, c2, c1 = 1.0, -28.0 / 3, 28.0, -32.0
+    psi = lambda s: ((c4 * s + c3) * s + c2) * s * s + c1 * s  # noqa: E731
+    best = min((1.0, 4.0), key=psi)
+    assert best == 4.0 and core.quartic_min(c1, c2, c3, c4) == pytest.approx(best, rel=1e-9)
+    # psi'(t) = 4 (t - 1)(t - 3)(t - 4): here the nearer minimum t = 1 is the global one
+    c4, c3, c2, c1 = 1.0, -32.0 / 3, 38.0, -48.0
+    assert core.quartic_min(c1, c2, c3, c4) == pytest.approx(1.0, rel=1e-9)
+
+
+def test_polymf_epoch_is_monotone_and_solves():
+    p = tiny_problem(40, 60, 700, lam=0.3, rank=3, seed=5)
+    A, M = dense.to_dense(p)
+    W, H = rand((40, 4), 1), rand((60, 4), 2)
+    F = [core.bm_objective(p, W, H, 0.3)]
+    for _ in range(4):
+        R = core.sddmm(p, W, H)
+        for j in range(4):
+            W, H, R, _ = core.polymf_block(p, W, H, j, 0.3, R)
+            F.append(core.bm_objective(p, W, H, 0.3))
+    assert all(b <= a * (1 + 1e-14) for a, b in zip(F, F[1:])) and F[-1] < F[0]
+    res = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-11, seed=3, bm_solver="polymf"))
+    Xd, _ = dense.proximal_gradient_dense(A, M, 0.3, alpha=1.99, tol=1e-14)
+    assert res.converged
+    assert math.isclose(res.F, dense.mc_objective_dense(Xd, A, M, 0.3), rel_tol=1e-11)
