@@ -72,6 +72,14 @@ typedef enum {
                         * stop residual ||X~ - X+|| is taken at the accepted step      */
 } bmg_step_rule;
 
+/* Solver of the BM phase (Algorithm 1; any solver meeting eq. nonincrease). */
+typedef enum {
+  BMG_BM_PSD = 0,    /* preconditioned steepest descent, exact line search, W step then H step */
+  BMG_BM_POLYMF = 1  /* polyMF-SS (Sec. 6.1.1): block coordinate descent over the column pairs  *
+                      * (w_j, h_j), direction = block gradient scaled by the diagonal of each   *
+                      * half's block Hessian, step = exact minimiser of the block quartic      */
+} bmg_bm_solver;
+
 typedef struct {
   double lambda;        /* regularisation weight of (MC)                         */
   double alpha;         /* fixed PG step (Sec. 6.1: L = 1, alpha = 1.99)         */
@@ -89,6 +97,7 @@ typedef struct {
                          * (0: block subspace iteration; at most 4, see below)   */
   uint64_t seed;        /* counter-based RNG seed (sketch and safeguard draws)   */
   int step_rule;        /* bmg_step_rule                                         */
+  int bm_solver;        /* bmg_bm_solver                                         */
   double alpha_min;     /* SpaRSA: step bounds (alpha_min < 2 delta / L, L = 1)  */
   double alpha_max;
   double sparsa_beta;   /* SpaRSA: backtracking factor in (0, 1)                 */
@@ -126,7 +135,7 @@ typedef struct {
 
 /* Fills the defaults: alpha 1.99, tol 1e-6, ssi_tol_floor 1e-12, psi0 0.1,
  * bm_epochs 3, max_iter 500, ssi_max_iter 50, k_init 8, refresh_every 5,
- * lmsvd_p 0, step_rule BMG_STEP_FIXED, alpha_min 1.99, alpha_max 1e3,
+ * lmsvd_p 0, bm_solver BMG_BM_PSD, step_rule BMG_STEP_FIXED, alpha_min 1.99, alpha_max 1e3,
  * sparsa_beta 0.5, sparsa_delta 0.999.
  * BMG_STEP_SPARSA keeps the previous PG point (W, H and its residual) and the
  * warm start in device memory beyond the workspace (min(m,n) x (2 k_cap + 2)
@@ -182,6 +191,13 @@ bmg_status bmg_spmm(bmg_problem *p, const double *S, const double *B, int q, int
  * in place.  F_bm: (host) BM objective after the last step. */
 bmg_status bmg_bm_epochs(bmg_problem *p, double *W, double *H, int k, int ld, double lambda,
                          int epochs, double *F_bm);
+
+/* The BM phase with the polyMF-SS solver instead: `epochs` sweeps over the
+ * column pairs j = 0..k-1 (Sec. 6.1.1), each block moved to the exact minimiser
+ * of the BM objective along its direction (a quartic in the step).  Same
+ * arguments and outputs as bmg_bm_epochs; BMG_EINVAL for lambda <= 0. */
+bmg_status bmg_polymf_epochs(bmg_problem *p, double *W, double *H, int k, int ld, double lambda,
+                             int epochs, double *F_bm);
 
 /* Objective of (MC) at X = W H^T:  F = 1/2 ||P_Omega(X - A)||^2 + lambda ||X||_*,
  * the nuclear norm from the k x k core of thin QR factors of W and H. (host) F. */

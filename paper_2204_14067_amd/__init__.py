@@ -40,6 +40,8 @@ def options(**kw) -> BmgOptions:
     for key, v in kw.items():
         if key == "step_rule" and isinstance(v, str):
             v = {"fixed": _lib.BMG_STEP_FIXED, "sparsa": _lib.BMG_STEP_SPARSA}[v]
+        if key == "bm_solver" and isinstance(v, str):
+            v = {"psd": _lib.BMG_BM_PSD, "polymf": _lib.BMG_BM_POLYMF}[v]
         if not hasattr(o, "lambda_" if key in ("lam", "lambda") else key):
             raise TypeError("unknown option %r" % key)
         setattr(o, "lambda_" if key in ("lam", "lambda") else key, v)
@@ -133,6 +135,13 @@ class Problem:
         F = ctypes.c_double(0.0)
         _lib.check(_lib.load().bmg_bm_epochs(self._h, _ptr(W), _ptr(H), k, ld, lam, epochs,
                                              ctypes.byref(F)))
+        return F.value
+
+    def bmg_polymf_epochs(self, W, H, k, lam, epochs=1):
+        ld = self._factors(W, H, k)
+        F = ctypes.c_double(0.0)
+        _lib.check(_lib.load().bmg_polymf_epochs(self._h, _ptr(W), _ptr(H), k, ld, lam, epochs,
+                                                 ctypes.byref(F)))
         return F.value
 
     def bmg_objective(self, W, H, k, lam):

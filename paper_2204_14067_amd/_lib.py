@@ -16,12 +16,14 @@ BMG_OK, BMG_NOT_CONVERGED = 0, 1
 BMG_EINVAL, BMG_ENOMEM, BMG_EDEVICE, BMG_ENONFINITE, BMG_ECANCELLED = -1, -2, -3, -4, -5
 BMG_FP64, BMG_FP32, BMG_BF16 = 0, 1, 2
 BMG_STEP_FIXED, BMG_STEP_SPARSA = 0, 1
+BMG_BM_PSD, BMG_BM_POLYMF = 0, 1
 STATUS_NAMES = {0: "BMG_OK", 1: "BMG_NOT_CONVERGED", -1: "BMG_EINVAL", -2: "BMG_ENOMEM",
                 -3: "BMG_EDEVICE", -4: "BMG_ENONFINITE", -5: "BMG_ECANCELLED"}
 
 # the C ABI's exported entry points (checked by the CPU tests)
 EXPORTS = ["bmg_options_default", "bmg_workspace_size", "bmg_problem_create", "bmg_problem_destroy",
-           "bmg_sddmm", "bmg_spmm", "bmg_bm_epochs", "bmg_objective", "bmg_prox_step", "bmg_solve",
+           "bmg_sddmm", "bmg_spmm", "bmg_bm_epochs", "bmg_polymf_epochs", "bmg_objective",
+           "bmg_prox_step", "bmg_solve",
            "bmg_last_error", "bmg_server_footprint", "bmg_server_create", "bmg_server_submit",
            "bmg_server_poll", "bmg_server_drain", "bmg_server_stats", "bmg_server_batch_stats",
            "bmg_server_destroy"]
@@ -39,7 +41,7 @@ class BmgOptions(ctypes.Structure):
                 ("ssi_max_iter", ctypes.c_int), ("k_init", ctypes.c_int),
                 ("refresh_every", ctypes.c_int), ("verbose", ctypes.c_int),
                 ("timing", ctypes.c_int), ("lmsvd_p", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("step_rule", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("step_rule", ctypes.c_int), ("bm_solver", ctypes.c_int),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("sparsa_beta", ctypes.c_double), ("sparsa_delta", ctypes.c_double)]
 
@@ -98,6 +100,7 @@ def load():
     lib.bmg_sddmm.argtypes = [p, p, p, i32, i32, p, P(d)]
     lib.bmg_spmm.argtypes = [p, p, p, i32, i32, p, i32, i32]
     lib.bmg_bm_epochs.argtypes = [p, p, p, i32, i32, d, i32, P(d)]
+    lib.bmg_polymf_epochs.argtypes = [p, p, p, i32, i32, d, i32, P(d)]
     lib.bmg_objective.argtypes = [p, p, p, i32, i32, d, P(d)]
     lib.bmg_prox_step.argtypes = [p, p, p, P(i32), i32, P(BmgOptions), P(d), P(d)]
     lib.bmg_solve.argtypes = [p, p, p, i32, P(BmgOptions), P(i32), P(BmgResult)]
@@ -111,6 +114,7 @@ def load():
     lib.bmg_server_destroy.argtypes = [p]
     lib.bmg_server_destroy.restype = None
     for f in ["bmg_workspace_size", "bmg_problem_create", "bmg_sddmm", "bmg_spmm", "bmg_bm_epochs",
+              "bmg_polymf_epochs",
               "bmg_objective", "bmg_prox_step", "bmg_solve", "bmg_server_footprint",
               "bmg_server_create", "bmg_server_submit", "bmg_server_poll", "bmg_server_drain",
               "bmg_server_stats", "bmg_server_batch_stats"]:

@@ -868,6 +868,7 @@ extern "C" void bmg_options_default(bmg_options *o) {
   o->lmsvd_p = 0;
   o->seed = 0;
   o->step_rule = BMG_STEP_FIXED;
+  o->bm_solver = BMG_BM_PSD;
   o->alpha_min = 1.99;
   o->alpha_max = 1e3;
   o->sparsa_beta = 0.5;
@@ -1042,6 +1043,57 @@ extern "C" bmg_status bmg_spmm(bmg_problem *P, const double *S, const double *B,
 }
 
 // ============================================================================ the method (internal orientation)
+// Global minimiser over t >= 0 of psi(t) = c1 t + c2 t^2 + c3 t^3 + c4 t^4
+// (c4 >= 0): psi' is a cubic; the real roots of psi'' cut [0, B] (B a bound on
+// the roots of psi') into intervals where psi' is monotone, bisection finds
+// the root in each interval where psi' changes sign, and the best of t = 0
+// and those roots is returned.
+static double quartic_min(double c1, double c2, double c3, double c4) {
+  const double a = 4.0 * c4, b = 3.0 * c3, c = 2.0 * c2, d = c1;
+  auto dpsi = [&](double t) { return ((a * t + b) * t + c) * t + d; };
+  auto psi = [&](double t) { return (((c4 * t + c3) * t + c2) * t + c1) * t; };
+  double B;
+  if (a > 0.0) B = 1.0 + std::max(std::max(fabs(b), fabs(c)), fabs(d)) / a;
+  else if (b != 0.0) B = 1.0 + std::max(fabs(c), fabs(d)) / fabs(b);
+  else if (c != 0.0) B = 1.0 + fabs(d / c);
+  else return 0.0;
+  std::vector<double> cut{0.0};
+  // roots of psi'' = c + 2 b t + 3 a t^2
+  if (a > 0.0) {
+    const double disc = 4.0 * b * b - 12.0 * a * c;
+    if (disc > 0.0) {
+      const double sq = sqrt(disc);
+      const double q = -0.5 * (2.0 * b + (b >= 0.0 ? sq : -sq));
+      double r1 = q / (3.0 * a), r2 = q != 0.0 ? c / q : r1;
+      if (r1 > r2) std::swap(r1, r2);
+      if (r1 > 0.0 && r1 < B) cut.push_back(r1);
+      if (r2 > 0.0 && r2 < B && r2 != r1) cut.push_back(r2);
+    }
+  } else if (b != 0.0) {
+    const double r = -c / (2.0 * b);
+    if (r > 0.0 && r < B) cut.push_back(r);
+  }
+  cut.push_back(B);
+  double best = 0.0, fbest = 0.0;
+  for (size_t i = 0; i + 1 < cut.size(); ++i) {
+    double lo = cut[i], hi = cut[i + 1];
+    double flo = dpsi(lo), fhi = dpsi(hi);
+    if (flo == 0.0) { hi = lo; fhi = 0.0; }
+    else if ((flo < 0.0) == (fhi < 0.0) && fhi != 0.0) continue;
+    for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      const double fm = dpsi(mid);
+      if ((fm < 0.0) == (flo < 0.0) && fm != 0.0) { lo = mid; flo = fm; }
+      else { hi = mid; fhi = fm; }
+    }
+    const double t = fabs(flo) < fabs(fhi) ? lo : hi;
+    const double ft = psi(t);
+    if (t > 0.0 && ft < fbest) { best = t; fbest = ft; }
+  }
+  return best;
+}
+
 template <typename T, typename TG = T>
 struct Method : Engine<T, TG> {
   using E = Engine<T, TG>;
@@ -1067,6 +1119,55 @@ struct Method : Engine<T, TG> {
   // ------------------------------------------------------------ BM phase
   // One preconditioned steepest-descent step with exact line search on the
   // rows-side factor (W when rows_side, else H).  Returns true if it moved.
+  // polyMF-SS epoch (Sec. 6.1.1): block coordinate descent over the column
+  // pairs (w_j, h_j), j = 0..k-1, from the residual of the incoming factors.
+  // Per block: the direction from one pass per orientation (each pass first
+  // applies the previous block's step to that orientation's stored residual),
+  // the quartic's coefficients from one pass, and its exact minimiser over
+  // t >= 0 on the host.  Returns whether any block moved.
+  bool polymf_epoch(T *W, T *H, int k, double lam) {
+    if (k == 0) return false;
+    double sr[2] = {0, 0}, sc[2] = {0, 0};
+    const bool eg = this->exact_gather;
+    this->exact_gather = true;
+    if (R->pl.nnz > 0) {
+      E::sddmm_store(R, W, H, k, m, n, sr);
+      E::sddmm_store(C, H, W, k, n, m, sc);
+    }
+    this->exact_gather = eg;
+    const int64_t nv = rup(std::max(m, n), 64);
+    T *vb = blk(P->L.b_vec);
+    T *dw = vb + 2 * nv, *su = vb + 3 * nv, *dh = vb + 4 * nv, *sv = vb + 5 * nv;
+    double *part = (double *)P->partial;
+    bool changed = false;
+    int jp = -1;
+    for (int j = 0; j < k; ++j) {
+      HIPC(launch_col_grad<T>(R->pl, (T *)R->r, W, H, ldk, jp, su, sv, j, lam, dw, part, s));
+      HIPC(launch_col_grad<T>(C->pl, (T *)C->r, H, W, ldk, jp, sv, su, j, lam, dh, part, s));
+      E::count(R->pl, 4.0 + 2.0 * sizeof(T), (double)(m + n) * sizeof(T) * (jp >= 0 ? 3 : 1));
+      E::count(C->pl, 4.0 + 2.0 * sizeof(T), (double)(m + n) * sizeof(T) * (jp >= 0 ? 3 : 1));
+      HIPC(launch_col_quartic<T>(R->pl, (const T *)R->r, m, n, W, H, ldk, j, dw, dh, P->wsum,
+                                 2 * P->L.wsum_cap, P->wpart, P->result, s));
+      E::count(R->pl, 4.0 + sizeof(T), (double)(m + n) * sizeof(T) * 2);
+      double h[9];
+      E::fetch(h, P->result, 9);
+      const double c1 = h[0] + lam * (h[5] + h[7]);
+      const double c2 = 0.5 * h[1] + h[2] + 0.5 * lam * (h[6] + h[8]);
+      const double c3 = h[3], c4 = 0.5 * h[4];
+      REQUIRE(std::isfinite(c1) && std::isfinite(c2) && std::isfinite(c3) && std::isfinite(c4),
+              BMG_ENONFINITE, "non-finite polyMF-SS line search");
+      const double t = quartic_min(c1, c2, c3, c4);
+      if (t > 0.0) {
+        HIPC(launch_col_step<T>(m, n, W, H, ldk, j, dw, dh, t, su, sv, s));
+        jp = j;
+        changed = true;
+      } else {
+        jp = -1;
+      }
+    }
+    return changed;
+  }
+
   bool bm_half(bool rows_side, T *W, T *H, int k, double lam) {
     const int64_t nown = rows_side ? m : n, noth = rows_side ? n : m;
     T *own = rows_side ? W : H;
@@ -1815,8 +1916,12 @@ struct Method : Engine<T, TG> {
       this->exact_gather = kShadow && hi;
       bool changed = false;
       for (int e = 0; e < o.bm_epochs && S.k > 0 && !(kShadow && refresh && !hi); ++e) {
-        changed |= bm_half(true, S.W, S.H, S.k, o.lambda);
-        changed |= bm_half(false, S.W, S.H, S.k, o.lambda);
+        if (o.bm_solver == BMG_BM_POLYMF) {
+          changed |= polymf_epoch(S.W, S.H, S.k, o.lambda);
+        } else {
+          changed |= bm_half(true, S.W, S.H, S.k, o.lambda);
+          changed |= bm_half(false, S.W, S.H, S.k, o.lambda);
+        }
       }
       F_bm = bm_objective(S.W, S.H, S.k, o.lambda);
       // FP32 passes cannot resolve Ritz values below ~1e-7 of the largest, and
@@ -1943,6 +2048,29 @@ extern "C" bmg_status bmg_bm_epochs(bmg_problem *P, double *W, double *H, int k,
   return BMG_OK;
 }
 
+extern "C" bmg_status bmg_polymf_epochs(bmg_problem *P, double *W, double *H, int k, int ld,
+                                        double lambda, int epochs, double *F_bm) {
+  bmg_status st = check_factors(P, W, H, k, ld);
+  if (st != BMG_OK) return st;
+  if (epochs < 0 || !(lambda > 0.0)) return fail(BMG_EINVAL, "bmg_polymf_epochs: bad arguments");
+  try {
+    Method<double> M(P);
+    double *Wi = M.blk(P->L.b_W), *Hi = M.blk(P->L.b_H);
+    load_factors<double>(P, W, H, k, ld, Wi, Hi);
+    for (int e = 0; e < epochs && k > 0; ++e) M.polymf_epoch(Wi, Hi, k, lambda);
+    if (F_bm) *F_bm = M.bm_objective(Wi, Hi, k, lambda);
+    if (k > 0) {
+      const double *a = P->transposed ? Hi : Wi, *b = P->transposed ? Wi : Hi;
+      HIPC(launch_copy_cols<double>(P->m_user, k, a, P->L.ldk, W, ld, P->s));
+      HIPC(launch_copy_cols<double>(P->n_user, k, b, P->L.ldk, H, ld, P->s));
+    }
+    HIPC(hipStreamSynchronize(P->s));
+  } catch (const BmgError &e) {
+    return fail(e.st, e.msg);
+  }
+  return BMG_OK;
+}
+
 extern "C" bmg_status bmg_objective(bmg_problem *P, const double *W, const double *H, int k, int ld,
                                     double lambda, double *F) {
   bmg_status st = check_factors(P, W, H, k, ld);
@@ -2032,7 +2160,8 @@ extern "C" bmg_status bmg_solve(bmg_problem *P, double *W, double *H, int ld, co
   if (ld < 8 || ld % 8) return fail(BMG_EINVAL, "bmg_solve: ld must be a positive multiple of 8");
   if (opt->lambda <= 0.0 || opt->alpha <= 0.0 || opt->bm_epochs < 0 || opt->max_iter < 0 ||
       opt->ssi_max_iter < 1 || opt->k_init < 1 || opt->lmsvd_p < 0 ||
-      opt->lmsvd_p > LMSVD_MAX_HIST || !step_rule_ok(opt))
+      opt->lmsvd_p > LMSVD_MAX_HIST || !step_rule_ok(opt) ||
+      (opt->bm_solver != BMG_BM_PSD && opt->bm_solver != BMG_BM_POLYMF))
     return fail(BMG_EINVAL, "bmg_solve: bad options");
   P->reset_stats();
   P->timing = opt->timing != 0;

@@ -157,6 +157,28 @@ hipError_t launch_range_bounds(const int64_t *ptr, const int32_t *idx, const int
 hipError_t launch_check_csr(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
                             const double *val, const int32_t *rid, int *flags, hipStream_t s);
 
+// polyMF-SS column passes (colpass.hip).  One orientation, own-side factor X
+// and gathered factor Y at leading dimension ld:
+//  * jp >= 0: r += su[row] Y[l, jp] + X[row, jp] sv[l] - su[row] sv[l] (the
+//    step su, sv of block jp, already applied to X[:, jp], Y[:, jp]);
+//  * jn >= 0: dir[row] = -(sum r Y[l, jn] + lam X[row, jn]) / (sum Y[l, jn]^2 + lam);
+//    part: 2 doubles per piece of the plan.
+template <typename T>
+hipError_t launch_col_grad(const Plan &pl, T *r, const T *X, const T *Y, int ld, int jp, const T *su,
+                           const T *sv, int jn, double lam, T *dir, double *part, hipStream_t s);
+// out[0..4] = sum over Omega (rows orientation) of r a, a^2, r b, a b, b^2 with
+// a = dw_i H[l, j] + W[i, j] dh_l, b = dw_i dh_l; out[5..8] = W[:, j].dw, dw.dw,
+// H[:, j].dh, dh.dh.  bpart: 5 doubles per 4 work units (bpart_cap doubles);
+// dpart: 512 doubles.
+template <typename T>
+hipError_t launch_col_quartic(const Plan &pl, const T *r, int64_t m, int64_t n, const T *W,
+                              const T *H, int ld, int j, const T *dw, const T *dh, double *bpart,
+                              int64_t bpart_cap, double *dpart, double *out, hipStream_t s);
+// su = t dw, sv = t dh; W[:, j] += su; H[:, j] += sv.
+template <typename T>
+hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, const T *dw, const T *dh,
+                           double t, T *su, T *sv, hipStream_t s);
+
 // Widest slice one launch handles for element type T.
 // (8 lanes x 16 bytes per chunk, at most 8 chunks: 128 doubles / 256 floats)
 template <typename T> constexpr int max_width() { return 128 * (16 / (int)sizeof(T)); }

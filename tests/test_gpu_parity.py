@@ -136,6 +136,26 @@ def test_bm_epochs_parity(name, k):
     assert np.all(Wd.cpu().numpy()[:, k:] == 0)
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_polymf_epochs_parity(name):
+    """polyMF-SS BM epochs (column-pair BCD, exact quartic step) against the oracle's."""
+    p = case(name)
+    k, lam = 5, 0.7
+    dp = to_dev(p, k_cap=8)
+    W, H = factors(p, k, 8, seed=21)
+    Wd, Hd = t(W), t(H)
+    F = dp.bmg_polymf_epochs(Wd, Hd, k, lam, epochs=2)
+    Wo, Ho = W[:, :k], H[:, :k]
+    for _ in range(2):
+        Wo, Ho, _ = core.polymf_epoch(p, Wo, Ho, lam)
+    Fo = core.bm_objective(p, Wo, Ho, lam)
+    Wg, Hg = Wd.cpu().numpy()[:, :k], Hd.cpu().numpy()[:, :k]
+    print("polymf", name, F, Fo, flush=True)
+    assert math.isclose(F, Fo, rel_tol=1e-10)
+    sw, sh = np.abs(Wo).max(), np.abs(Ho).max()
+    assert np.allclose(Wg, Wo, rtol=0, atol=1e-8 * sw) and np.allclose(Hg, Ho, rtol=0, atol=1e-8 * sh)
+
+
 @pytest.mark.parametrize("name", ["tiny", "tall_m_gt_n", "powerlaw"])
 def test_objective_parity(name):
     p = case(name)
@@ -286,6 +306,34 @@ def test_solve_sparsa_fp32_objective_error():
     assert abs(Fw - Fstar) <= 1e-5 * Fstar
 
 
+@pytest.mark.parametrize("shape", [(40, 60, 700), (60, 40, 700), (120, 200, 4000)])
+def test_solve_parity_fp64_polymf(shape):
+    m, n, nnz = shape
+    p = synth.tiny(m, n, nnz, rank=3, lam=0.3, seed=m + n)
+    orc = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-10, seed=3, max_iter=3000, bm_solver="polymf"))
+    dp = to_dev(p, k_cap=64)
+    W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-10, seed=3, max_iter=3000, bm_solver="polymf")
+    print("solve polymf", shape, r["iters"], orc.iters, r["F"], orc.F, flush=True)
+    assert r["status"] == 0 and orc.converged
+    assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
+    assert k == orc.k
+    Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
+    assert math.isclose(Fw, r["F"], rel_tol=1e-10)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp32", 1e-5), ("bf16", 1e-3)])
+def test_solve_polymf_reduced_precision(precision, bar):
+    p = synth.tiny(150, 220, 5000, rank=3, lam=0.3, seed=31)
+    dp = to_dev(p, k_cap=64, precision=precision)
+    W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-6 if precision == "fp32" else 1e-5, seed=3,
+                              max_iter=600, bm_solver="polymf")
+    Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
+    Fstar = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-11, seed=3)).F
+    print("polymf", precision, r["status"], r["iters"], Fw, Fstar, flush=True)
+    assert r["status"] == 0
+    assert abs(Fw - Fstar) <= bar * Fstar
+
+
 def test_solve_full_omega_closed_form():
     m, n, lam = 30, 45, 1.5
     p = synth.tiny(m, n, m * n, rank=4, seed=12)
@@ -380,7 +428,9 @@ def test_invalid_inputs_are_rejected():
     for hp in (-1, 5):
         with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
             dp.bmg_solve(lam=0.1, lmsvd_p=hp)
-    for kw in ({"step_rule": 2}, {"step_rule": "sparsa", "sparsa_beta": 1.0},
+    with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
+        dp.bmg_polymf_epochs(t(np.zeros((6, 8))), t(np.zeros((7, 8))), 2, -1.0)
+    for kw in ({"bm_solver": 2}, {"step_rule": 2}, {"step_rule": "sparsa", "sparsa_beta": 1.0},
                {"step_rule": "sparsa", "alpha_min": 5.0, "alpha_max": 2.0},
                {"step_rule": "sparsa", "sparsa_delta": 0.0}):
         with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
