@@ -171,6 +171,9 @@ def main():
         out["time_to_tol_gpu_bound"] = time_to_tol_gpu_bound(bmg, synth, dev)
         out["sparsa_step"] = sparsa_step(bmg, synth, dev, out["time_to_tol"]["fp64"],
                                          out["time_to_tol_gpu_bound"]["lambda_100"]["fp64"])
+        if args.precision == "fp64":
+            out["polymf_bm"] = polymf_bm(bmg, synth, dev, prob, p, out["time_to_tol"]["fp64"],
+                                         out["time_to_tol_gpu_bound"]["lambda_100"]["fp64"])
         out["serve"] = serving(bmg, synth, dev, args.serve_count)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -267,6 +270,61 @@ def sparsa_step(bmg, synth, dev, fixed_small, fixed_quarter):
         log("sparsa %s: median %.3fs (fixed %.3fs), iters %s (fixed %s), prox computations %s" % (
             name, rec["seconds_median"], fixed["seconds_median"], iters, fixed["iters"], trials))
         del prob
+    return out
+
+
+def polymf_bm(bmg, synth, dev, prob, p, fixed_small, fixed_quarter):
+    """The polyMF-SS BM solver against the preconditioned steepest descent, FP64:
+    three epochs of each from the same factors on the benchmark workload
+    (rank 16, lambda 20; BM objective after each epoch and time per epoch), then
+    the 1000 x 1500 solve to 1e-6 (five seeds) and the quarter-scale
+    Netflix-shaped solve at lambda 100 to 1e-4 (three seeds) with polyMF-SS in
+    the BM phase.  Steepest-descent figures of the solves are those of the
+    time-to-tolerance runs above."""
+    import numpy as np
+    import torch
+    k, lam = 16, 20.0
+    rng = np.random.default_rng(7)
+    W0 = np.zeros((p.m, 64)); H0 = np.zeros((p.n, 64))
+    W0[:, :k] = 0.3 * rng.standard_normal((p.m, k))
+    H0[:, :k] = 0.3 * rng.standard_normal((p.n, k))
+    out = {"epochs_netflix_shape_k16": {}}
+    for name, fn in (("psd", prob.bmg_bm_epochs), ("polymf", prob.bmg_polymf_epochs)):
+        W = torch.as_tensor(W0, device=dev); H = torch.as_tensor(H0, device=dev)
+        Fs, ts = [], []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Fs.append(fn(W, H, k, lam, epochs=1))
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        out["epochs_netflix_shape_k16"][name] = {"F_bm_after_epoch": Fs,
+                                                 "ms_per_epoch": [round(x * 1e3, 2) for x in ts]}
+        log("BM %s: F after epochs %s, ms %s" % (name, ["%.6g" % f for f in Fs], ["%.1f" % (x * 1e3) for x in ts]))
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "small_uniform.json")))
+    cases = [("small_uniform tol 1e-6", synth.small_uniform(), 0.5, 8, 1e-6, (11, 12, 13, 14, 15), 256,
+              fixed_small),
+             ("netflix_shape x0.25 lambda 100 tol 1e-4", synth.netflix_shape(scale=0.25), 100.0, 16, 1e-4,
+              (3, 4, 5), 128, fixed_quarter)]
+    for name, q, lm, kk, tol, seeds, kc, fixed in cases:
+        pq = bmg.Problem.from_host(q.row_ptr, q.col, q.val, q.m, q.n, k_cap=kc, precision="fp64", device=dev)
+        pq.bmg_solve(lam=lm, k_init=kk, tol=tol, seed=seeds[0], max_iter=2, bm_solver="polymf")
+        secs, iters, Fs = [], [], []
+        for sd in seeds:
+            t0 = time.perf_counter()
+            W, H, k2, r = pq.bmg_solve(lam=lm, k_init=kk, tol=tol, seed=sd, max_iter=1000, bm_solver="polymf")
+            secs.append(time.perf_counter() - t0)
+            iters.append(r["iters"]); Fs.append(r["F"])
+        rec = {"seconds_median": round(float(np.median(secs)), 4), "iters": iters,
+               "psd_seconds_median": fixed["seconds_median"], "psd_iters": fixed["iters"]}
+        if name.startswith("small"):
+            rec["max_rel_err_vs_oracle_optimum"] = max(abs(F - golden["F"]) / golden["F"] for F in Fs)
+        else:
+            rec["F"] = Fs
+        out[name] = rec
+        log("polymf %s: median %.3fs (psd %.3fs), iters %s (psd %s)" % (
+            name, rec["seconds_median"], fixed["seconds_median"], iters, fixed["iters"]))
+        del pq
     return out
 
 

@@ -1135,20 +1135,20 @@ struct Method : Engine<T, TG> {
       E::sddmm_store(C, H, W, k, n, m, sc);
     }
     this->exact_gather = eg;
-    const int64_t nv = rup(std::max(m, n), 64);
-    T *vb = blk(P->L.b_vec);
-    T *dw = vb + 2 * nv, *su = vb + 3 * nv, *dh = vb + 4 * nv, *sv = vb + 5 * nv;
+    // per-row records of both sides (free during the BM phase: the gradient
+    // blocks of the steepest-descent solver)
+    Q4<T> *Gm = (Q4<T> *)blk(P->L.b_G), *Gn = (Q4<T> *)blk(P->L.b_D);
     double *part = (double *)P->partial;
-    bool changed = false;
-    int jp = -1;
+    HIPC(launch_col_pack0<T>(m, n, W, H, ldk, Gm, Gn, s));
+    bool changed = false, upd = false;
     for (int j = 0; j < k; ++j) {
-      HIPC(launch_col_grad<T>(R->pl, (T *)R->r, W, H, ldk, jp, su, sv, j, lam, dw, part, s));
-      HIPC(launch_col_grad<T>(C->pl, (T *)C->r, H, W, ldk, jp, sv, su, j, lam, dh, part, s));
-      E::count(R->pl, 4.0 + 2.0 * sizeof(T), (double)(m + n) * sizeof(T) * (jp >= 0 ? 3 : 1));
-      E::count(C->pl, 4.0 + 2.0 * sizeof(T), (double)(m + n) * sizeof(T) * (jp >= 0 ? 3 : 1));
-      HIPC(launch_col_quartic<T>(R->pl, (const T *)R->r, m, n, W, H, ldk, j, dw, dh, P->wsum,
-                                 2 * P->L.wsum_cap, P->wpart, P->result, s));
-      E::count(R->pl, 4.0 + sizeof(T), (double)(m + n) * sizeof(T) * 2);
+      HIPC(launch_col_grad<T>(R->pl, (T *)R->r, Gm, Gn, upd, lam, part, s));
+      HIPC(launch_col_grad<T>(C->pl, (T *)C->r, Gn, Gm, upd, lam, part, s));
+      E::count(R->pl, 4.0 + (upd ? 2.0 : 1.0) * sizeof(T), (double)(m + n) * 4 * sizeof(T));
+      E::count(C->pl, 4.0 + (upd ? 2.0 : 1.0) * sizeof(T), (double)(m + n) * 4 * sizeof(T));
+      HIPC(launch_col_quartic<T>(R->pl, (const T *)R->r, m, n, Gm, Gn, P->wsum, 2 * P->L.wsum_cap,
+                                 P->wpart, P->result, s));
+      E::count(R->pl, 4.0 + sizeof(T), (double)(m + n) * 4 * sizeof(T));
       double h[9];
       E::fetch(h, P->result, 9);
       const double c1 = h[0] + lam * (h[5] + h[7]);
@@ -1157,13 +1157,9 @@ struct Method : Engine<T, TG> {
       REQUIRE(std::isfinite(c1) && std::isfinite(c2) && std::isfinite(c3) && std::isfinite(c4),
               BMG_ENONFINITE, "non-finite polyMF-SS line search");
       const double t = quartic_min(c1, c2, c3, c4);
-      if (t > 0.0) {
-        HIPC(launch_col_step<T>(m, n, W, H, ldk, j, dw, dh, t, su, sv, s));
-        jp = j;
-        changed = true;
-      } else {
-        jp = -1;
-      }
+      HIPC(launch_col_step<T>(m, n, W, H, ldk, j, j + 1 < k ? j + 1 : -1, t, Gm, Gn, s));
+      upd = t > 0.0;
+      changed |= upd;
     }
     return changed;
   }

@@ -157,27 +157,37 @@ hipError_t launch_range_bounds(const int64_t *ptr, const int32_t *idx, const int
 hipError_t launch_check_csr(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
                             const double *val, const int32_t *rid, int *flags, hipStream_t s);
 
-// polyMF-SS column passes (colpass.hip).  One orientation, own-side factor X
-// and gathered factor Y at leading dimension ld:
-//  * jp >= 0: r += su[row] Y[l, jp] + X[row, jp] sv[l] - su[row] sv[l] (the
-//    step su, sv of block jp, already applied to X[:, jp], Y[:, jp]);
-//  * jn >= 0: dir[row] = -(sum r Y[l, jn] + lam X[row, jn]) / (sum Y[l, jn]^2 + lam);
-//    part: 2 doubles per piece of the plan.
+// polyMF-SS column passes (colpass.hip).  Per block j every row of each side
+// has a record {prev, step, x, dir}: the value of block j-1 after its step,
+// that step, the value of block j, and block j's direction.
 template <typename T>
-hipError_t launch_col_grad(const Plan &pl, T *r, const T *X, const T *Y, int ld, int jp, const T *su,
-                           const T *sv, int jn, double lam, T *dir, double *part, hipStream_t s);
+struct alignas(4 * sizeof(T)) Q4 {
+  T x, y, z, w;
+};
+// records of block 0: {0, 0, W[i, 0], 0} and {0, 0, H[l, 0], 0}
+template <typename T>
+hipError_t launch_col_pack0(int64_t m, int64_t n, const T *W, const T *H, int ld, Q4<T> *Gm, Q4<T> *Gn,
+                            hipStream_t s);
+// One orientation (own records Gown, gathered records Goth): with upd, the
+// stored residual takes the previous block's step,
+//   r += s_row y'_l + x'_row s_l - s_row s_l;
+// then Gown[row].w = -(sum r y_l + lam x_row) / (sum y_l^2 + lam).
+// part: 2 doubles per piece of the plan.
+template <typename T>
+hipError_t launch_col_grad(const Plan &pl, T *r, Q4<T> *Gown, const Q4<T> *Goth, bool upd, double lam,
+                           double *part, hipStream_t s);
 // out[0..4] = sum over Omega (rows orientation) of r a, a^2, r b, a b, b^2 with
-// a = dw_i H[l, j] + W[i, j] dh_l, b = dw_i dh_l; out[5..8] = W[:, j].dw, dw.dw,
-// H[:, j].dh, dh.dh.  bpart: 5 doubles per 4 work units (bpart_cap doubles);
-// dpart: 512 doubles.
+// a = dw_i h_l + w_i dh_l, b = dw_i dh_l; out[5..8] = w.dw, dw.dw, h.dh, dh.dh.
+// bpart: 5 doubles per 4 work units (bpart_cap doubles); dpart: 512 doubles.
 template <typename T>
-hipError_t launch_col_quartic(const Plan &pl, const T *r, int64_t m, int64_t n, const T *W,
-                              const T *H, int ld, int j, const T *dw, const T *dh, double *bpart,
-                              int64_t bpart_cap, double *dpart, double *out, hipStream_t s);
-// su = t dw, sv = t dh; W[:, j] += su; H[:, j] += sv.
+hipError_t launch_col_quartic(const Plan &pl, const T *r, int64_t m, int64_t n, const Q4<T> *Gm,
+                              const Q4<T> *Gn, double *bpart, int64_t bpart_cap, double *dpart,
+                              double *out, hipStream_t s);
+// Block j moves by t along its direction: X[:, j] += t dir; the records are
+// rewritten for block jn (jn < 0: none).
 template <typename T>
-hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, const T *dw, const T *dh,
-                           double t, T *su, T *sv, hipStream_t s);
+hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, int jn, double t, Q4<T> *Gm,
+                           Q4<T> *Gn, hipStream_t s);
 
 // Widest slice one launch handles for element type T.
 // (8 lanes x 16 bytes per chunk, at most 8 chunks: 128 doubles / 256 floats)

@@ -46,45 +46,38 @@ __device__ __forceinline__ Unit unit_of(const Plan &pl, int64_t u) {
   return x;
 }
 
-// One orientation: own-side factor X (rows of this orientation), gathered
-// factor Y (indexed by idx), both at leading dimension ld.
-//  * upd: r += su[row] y'_l + x'_row sv[l] - su[row] sv[l] with x' = X[:, jp],
-//    y' = Y[:, jp] (the block jp just stepped by su, sv, already applied to X, Y)
-//  * next (jn >= 0): g = sum r y_l, c = sum y_l^2 with y = Y[:, jn]; the
-//    direction dir[row] = -(g + lam x_row) / (c + lam), x = X[:, jn]
+// One orientation.  Gown holds one record per row of this orientation, Goth
+// one per gathered index (Q4 layout: prev, step, x, dir):
+//  * upd: r += s_row y'_l + x'_row s_l - s_row s_l, with x' / y' the values of
+//    the block just stepped (already moved by s) on each side;
+//  * nxt: g = sum r y_l, c = sum y_l^2 over the row (y = the block's current
+//    value on the gathered side), and the direction
+//    dir = -(g + lam x_row) / (c + lam) goes to Gown[row].w.
 template <typename T>
 __global__ __launch_bounds__(64 * CP_WAVES) void k_col_grad(Plan pl, T *__restrict__ r,
-                                                         const T *__restrict__ X,
-                                                         const T *__restrict__ Y, int ld, int jp,
-                                                         const T *__restrict__ su,
-                                                         const T *__restrict__ sv, int jn,
-                                                         double lam, T *__restrict__ dir,
+                                                         Q4<T> *__restrict__ Gown,
+                                                         const Q4<T> *__restrict__ Goth, int upd,
+                                                         int nxt, double lam,
                                                          double *__restrict__ part) {
   const int64_t u = (int64_t)blockIdx.x * CP_WAVES + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (u >= pl.n_short + pl.n_pieces) return;
   const Unit w = unit_of(pl, u);
-  const bool upd = jp >= 0, nxt = jn >= 0;
-  double ux = 0.0, xp = 0.0;
-  if (upd) {
-    ux = (double)su[w.row];
-    xp = (double)X[w.row * ld + jp];
-  }
+  const Q4<T> own = Gown[w.row];
+  const double xp = (double)own.x, so = (double)own.y;
   double g = 0.0, c = 0.0;
   for (int64_t e = w.beg + lane; e < w.end; e += 64) {
-    const int64_t l = pl.idx[e];
+    const Q4<T> ot = Goth[pl.idx[e]];
     double rr = (double)r[e];
     if (upd) {
-      const double yp = (double)Y[l * ld + jp], vl = (double)sv[l];
-      rr += ux * yp + xp * vl - ux * vl;
+      const double yp = (double)ot.x, sl = (double)ot.y;
+      rr += so * yp + xp * sl - so * sl;
       r[e] = (T)rr;
       rr = (double)r[e];
     }
-    if (nxt) {
-      const double y = (double)Y[l * ld + jn];
-      g += rr * y;
-      c += y * y;
-    }
+    const double y = (double)ot.z;
+    g += rr * y;
+    c += y * y;
   }
   if (!nxt) return;
   g = wave_sum64(g);
@@ -94,15 +87,14 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_col_grad(Plan pl, T *__restri
     part[2 * w.p] = g;
     part[2 * w.p + 1] = c;
   } else {
-    const double x = (double)X[w.row * ld + jn];
-    dir[w.row] = (T)(-(g + lam * x) / (c + lam));
+    Gown[w.row].w = (T)(-(g + lam * (double)own.z) / (c + lam));
   }
 }
 
 // Long rows: sum the pieces' (g, c) in piece order, then the direction.
 template <typename T>
-__global__ void k_col_fix(Plan pl, const double *__restrict__ part, const T *__restrict__ X, int ld,
-                          int jn, double lam, T *__restrict__ dir) {
+__global__ void k_col_fix(Plan pl, const double *__restrict__ part, double lam,
+                          Q4<T> *__restrict__ Gown) {
   const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (L >= pl.n_long) return;
   double g = 0.0, c = 0.0;
@@ -111,7 +103,7 @@ __global__ void k_col_fix(Plan pl, const double *__restrict__ part, const T *__r
     c += part[2 * p + 1];
   }
   const int64_t row = pl.long_rows[L];
-  dir[row] = (T)(-(g + lam * (double)X[row * ld + jn]) / (c + lam));
+  Gown[row].w = (T)(-(g + lam * (double)Gown[row].z) / (c + lam));
 }
 
 // Coefficient sums of the quartic along (w + t dw, h + t dh) on the rows
@@ -119,10 +111,8 @@ __global__ void k_col_fix(Plan pl, const double *__restrict__ part, const T *__r
 // per block: sum r a, sum a^2, sum r b, sum a b, sum b^2.
 template <typename T>
 __global__ __launch_bounds__(64 * CP_WAVES) void k_col_quartic(Plan pl, const T *__restrict__ r,
-                                                            const T *__restrict__ W,
-                                                            const T *__restrict__ H, int ld, int j,
-                                                            const T *__restrict__ dw,
-                                                            const T *__restrict__ dh,
+                                                            const Q4<T> *__restrict__ Gm,
+                                                            const Q4<T> *__restrict__ Gn,
                                                             double *__restrict__ bpart) {
   __shared__ double sm[CP_WAVES][5];
   const int64_t u = (int64_t)blockIdx.x * CP_WAVES + threadIdx.x / 64;
@@ -130,10 +120,11 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_col_quartic(Plan pl, const T 
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
   if (u < pl.n_short + pl.n_pieces) {
     const Unit w = unit_of(pl, u);
-    const double x = (double)W[w.row * ld + j], dx = (double)dw[w.row];
+    const Q4<T> own = Gm[w.row];
+    const double x = (double)own.z, dx = (double)own.w;
     for (int64_t e = w.beg + lane; e < w.end; e += 64) {
-      const int64_t l = pl.idx[e];
-      const double y = (double)H[l * ld + j], dy = (double)dh[l], rr = (double)r[e];
+      const Q4<T> ot = Gn[pl.idx[e]];
+      const double y = (double)ot.z, dy = (double)ot.w, rr = (double)r[e];
       const double a = dx * y + x * dy, b = dx * dy;
       s0 += rr * a;
       s1 += a * a;
@@ -160,26 +151,24 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_col_quartic(Plan pl, const T 
 
 constexpr int DOT_BLOCKS = 128;
 
-// Per block b: sum w dw, sum dw^2 over its slice of the m rows and
-// sum h dh, sum dh^2 over its slice of the n rows.
+// Per block b: sum x d, sum d^2 over its slice of the m records and of the
+// n records (x = the block's current value, d = its direction).
 template <typename T>
-__global__ __launch_bounds__(256) void k_col_dots(int64_t m, int64_t n, const T *__restrict__ W,
-                                                  const T *__restrict__ H, int ld, int j,
-                                                  const T *__restrict__ dw,
-                                                  const T *__restrict__ dh,
+__global__ __launch_bounds__(256) void k_col_dots(int64_t m, int64_t n, const Q4<T> *__restrict__ Gm,
+                                                  const Q4<T> *__restrict__ Gn,
                                                   double *__restrict__ dpart) {
   __shared__ double sm[4][4];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += stride) {
-    const double d = (double)dw[i];
-    v[0] += (double)W[i * ld + j] * d;
-    v[1] += d * d;
+    const Q4<T> g = Gm[i];
+    v[0] += (double)g.z * (double)g.w;
+    v[1] += (double)g.w * (double)g.w;
   }
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-    const double d = (double)dh[i];
-    v[2] += (double)H[i * ld + j] * d;
-    v[3] += d * d;
+    const Q4<T> g = Gn[i];
+    v[2] += (double)g.z * (double)g.w;
+    v[3] += (double)g.w * (double)g.w;
   }
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
 #pragma unroll
@@ -219,77 +208,101 @@ __global__ __launch_bounds__(256) void k_col_reduce(const double *__restrict__ b
                                           sm[3][threadIdx.x];
 }
 
-// su = t dw, sv = t dh; W[:, j] += su, H[:, j] += sv.
+// Block j moves by t along its direction (t = 0: no move) and the records
+// are rewritten for block jn (jn < 0: none):
+//   G[i] = {x_i + t d_i, t d_i, X[i, jn], 0},  X[i, j] = x_i + t d_i.
 template <typename T>
 __global__ void k_col_step(int64_t m, int64_t n, T *__restrict__ W, T *__restrict__ H, int ld, int j,
-                           const T *__restrict__ dw, const T *__restrict__ dh, double t,
-                           T *__restrict__ su, T *__restrict__ sv) {
+                           int jn, double t, Q4<T> *__restrict__ Gm, Q4<T> *__restrict__ Gn) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
-    const T s = (T)(t * (double)dw[i]);
-    su[i] = s;
-    W[i * ld + j] += s;
+    const Q4<T> g = Gm[i];
+    const T s = (T)(t * (double)g.w);
+    const T x = g.z + s;
+    if (t != 0.0) W[i * ld + j] = x;
+    Gm[i] = Q4<T>{x, s, jn >= 0 ? W[i * ld + jn] : (T)0, (T)0};
   }
   if (i < n) {
-    const T s = (T)(t * (double)dh[i]);
-    sv[i] = s;
-    H[i * ld + j] += s;
+    const Q4<T> g = Gn[i];
+    const T s = (T)(t * (double)g.w);
+    const T x = g.z + s;
+    if (t != 0.0) H[i * ld + j] = x;
+    Gn[i] = Q4<T>{x, s, jn >= 0 ? H[i * ld + jn] : (T)0, (T)0};
   }
+}
+
+// Records for the first block: {0, 0, X[i, 0], 0}.
+template <typename T>
+__global__ void k_col_pack0(int64_t m, int64_t n, const T *__restrict__ W, const T *__restrict__ H,
+                            int ld, Q4<T> *__restrict__ Gm, Q4<T> *__restrict__ Gn) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) Gm[i] = Q4<T>{(T)0, (T)0, W[i * ld], (T)0};
+  if (i < n) Gn[i] = Q4<T>{(T)0, (T)0, H[i * ld], (T)0};
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_col_grad(const Plan &pl, T *r, const T *X, const T *Y, int ld, int jp, const T *su,
-                           const T *sv, int jn, double lam, T *dir, double *part, hipStream_t s) {
-  const int64_t units = pl.n_short + pl.n_pieces;
-  if (units > 0) {
-    const int64_t nb = (units + CP_WAVES - 1) / CP_WAVES;
-    hipLaunchKernelGGL((k_col_grad<T>), dim3((unsigned)nb), dim3(64 * CP_WAVES), 0, s, pl, r, X, Y, ld,
-                       jp, su, sv, jn, lam, dir, part);
-  }
-  if (jn >= 0 && pl.n_long > 0)
-    hipLaunchKernelGGL((k_col_fix<T>), dim3((unsigned)((pl.n_long + 255) / 256)), dim3(256), 0, s, pl,
-                       (const double *)part, X, ld, jn, lam, dir);
+hipError_t launch_col_pack0(int64_t m, int64_t n, const T *W, const T *H, int ld, Q4<T> *Gm, Q4<T> *Gn,
+                            hipStream_t s) {
+  const int64_t mx = m > n ? m : n;
+  if (mx > 0)
+    hipLaunchKernelGGL((k_col_pack0<T>), dim3((unsigned)((mx + 255) / 256)), dim3(256), 0, s, m, n, W, H,
+                       ld, Gm, Gn);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_col_quartic(const Plan &pl, const T *r, int64_t m, int64_t n, const T *W,
-                              const T *H, int ld, int j, const T *dw, const T *dh, double *bpart,
-                              int64_t bpart_cap, double *dpart, double *out, hipStream_t s) {
+hipError_t launch_col_grad(const Plan &pl, T *r, Q4<T> *Gown, const Q4<T> *Goth, bool upd, double lam,
+                           double *part, hipStream_t s) {
+  const int64_t units = pl.n_short + pl.n_pieces;
+  if (units > 0) {
+    const int64_t nb = (units + CP_WAVES - 1) / CP_WAVES;
+    hipLaunchKernelGGL((k_col_grad<T>), dim3((unsigned)nb), dim3(64 * CP_WAVES), 0, s, pl, r, Gown, Goth,
+                       upd ? 1 : 0, 1, lam, part);
+  }
+  if (pl.n_long > 0)
+    hipLaunchKernelGGL((k_col_fix<T>), dim3((unsigned)((pl.n_long + 255) / 256)), dim3(256), 0, s, pl,
+                       (const double *)part, lam, Gown);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_col_quartic(const Plan &pl, const T *r, int64_t m, int64_t n, const Q4<T> *Gm,
+                              const Q4<T> *Gn, double *bpart, int64_t bpart_cap, double *dpart,
+                              double *out, hipStream_t s) {
   const int64_t units = pl.n_short + pl.n_pieces;
   const int64_t nb = (units + CP_WAVES - 1) / CP_WAVES;
   if (nb * 5 > bpart_cap) return hipErrorInvalidValue;
   if (nb > 0)
-    hipLaunchKernelGGL((k_col_quartic<T>), dim3((unsigned)nb), dim3(64 * CP_WAVES), 0, s, pl, r, W, H,
-                       ld, j, dw, dh, bpart);
-  hipLaunchKernelGGL((k_col_dots<T>), dim3(DOT_BLOCKS), dim3(256), 0, s, m, n, W, H, ld, j, dw, dh,
-                     dpart);
+    hipLaunchKernelGGL((k_col_quartic<T>), dim3((unsigned)nb), dim3(64 * CP_WAVES), 0, s, pl, r, Gm, Gn,
+                       bpart);
+  hipLaunchKernelGGL((k_col_dots<T>), dim3(DOT_BLOCKS), dim3(256), 0, s, m, n, Gm, Gn, dpart);
   hipLaunchKernelGGL(k_col_reduce, dim3(1), dim3(256), 0, s, (const double *)bpart, nb,
                      (const double *)dpart, out);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, const T *dw, const T *dh,
-                           double t, T *su, T *sv, hipStream_t s) {
+hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, int jn, double t, Q4<T> *Gm,
+                           Q4<T> *Gn, hipStream_t s) {
   const int64_t mx = m > n ? m : n;
   if (mx > 0)
     hipLaunchKernelGGL((k_col_step<T>), dim3((unsigned)((mx + 255) / 256)), dim3(256), 0, s, m, n, W, H,
-                       ld, j, dw, dh, t, su, sv);
+                       ld, j, jn, t, Gm, Gn);
   return hipGetLastError();
 }
 
 #define BMG_INST_COL(T)                                                                            \
-  template hipError_t launch_col_grad<T>(const Plan &, T *, const T *, const T *, int, int,         \
-                                         const T *, const T *, int, double, T *, double *,         \
-                                         hipStream_t);                                              \
-  template hipError_t launch_col_quartic<T>(const Plan &, const T *, int64_t, int64_t, const T *,  \
-                                            const T *, int, int, const T *, const T *, double *,   \
-                                            int64_t, double *, double *, hipStream_t);              \
-  template hipError_t launch_col_step<T>(int64_t, int64_t, T *, T *, int, int, const T *, const T *, \
-                                         double, T *, T *, hipStream_t);
+  template hipError_t launch_col_pack0<T>(int64_t, int64_t, const T *, const T *, int, Q4<T> *,     \
+                                          Q4<T> *, hipStream_t);                                    \
+  template hipError_t launch_col_grad<T>(const Plan &, T *, Q4<T> *, const Q4<T> *, bool, double,   \
+                                         double *, hipStream_t);                                    \
+  template hipError_t launch_col_quartic<T>(const Plan &, const T *, int64_t, int64_t,              \
+                                            const Q4<T> *, const Q4<T> *, double *, int64_t,        \
+                                            double *, double *, hipStream_t);                       \
+  template hipError_t launch_col_step<T>(int64_t, int64_t, T *, T *, int, int, int, double, Q4<T> *, \
+                                         Q4<T> *, hipStream_t);
 BMG_INST_COL(double)
 BMG_INST_COL(float)
 
