@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--bm-solver", default="psd", choices=["psd", "polymf"],
+                    help="BM solver of the step (psd: gradient steps, the default; polymf: polyMF-SS)")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -118,7 +120,8 @@ def main():
     log("problem resident on %s (%.2f GB workspace)" % (dev, prob.ws.numel() / 1e9))
 
     def step():
-        return prob.bmg_solve(W, H, lam=lam, k_init=k0, max_iter=1, tol=0.0, seed=1003, timing=1)[3]
+        return prob.bmg_solve(W, H, lam=lam, k_init=k0, max_iter=1, tol=0.0, seed=1003, timing=1,
+                              bm_solver=args.bm_solver)[3]
 
     for i in range(args.warmup):
         r = step()
@@ -149,7 +152,8 @@ def main():
         "config": {"workload": "%s: %dx%d, nnz=%d, capped Zipf(1.2) degrees, rank-20 truth + "
                                "noise var 0.25, lambda=20, k0=16" % (workload, p.m, p.n, p.nnz),
                    "step": "init (HMT+Nystrom) + 3 BM epochs + 1 inexact PG step + objective",
-                   "precision": args.precision, "rank_after_step": recs[-1]["k"],
+                   "precision": args.precision, "bm_solver": args.bm_solver,
+                   "rank_after_step": recs[-1]["k"],
                    "ssi_iters_per_step": recs[-1]["ssi_iters"],
                    "sparse_passes_per_step": recs[-1]["sparse_passes"],
                    "frac_of_hbm_peak_whole_step": round(value / PEAK_HBM_GBS, 4)},
