@@ -469,6 +469,27 @@ def test_netflix_shape_full_size_sampled_rows():
         assert np.allclose(GH[j, :k], Rg[sel] @ W[prow[sel], :k], rtol=1e-10, atol=1e-9)
 
 
+def test_netflix_shape_full_size_polymf_block():
+    """One polyMF-SS block (an epoch at k = 1) on the full 1e8-entry workload:
+    both direction passes (long rows cut into pieces), the quartic sums and the
+    step, against the oracle's block on the whole problem."""
+    p = synth.netflix_shape()
+    lam = 20.0
+    dp = to_dev(p, k_cap=8)
+    W, H = factors(p, 1, 8, seed=17)
+    W *= 0.3; H *= 0.3
+    Wd, Hd = t(W), t(H)
+    F = dp.bmg_polymf_epochs(Wd, Hd, 1, lam, epochs=1)
+    Wo, Ho, Ro, step = core.polymf_block(p, W[:, :1], H[:, :1], 0, lam, core.sddmm(p, W[:, :1], H[:, :1]))
+    del Ro
+    Fo = core.bm_objective(p, Wo, Ho, lam)
+    print("polymf full size: step", step, "F", F, Fo, flush=True)
+    assert step > 0 and math.isclose(F, Fo, rel_tol=1e-10)
+    Wg, Hg = Wd.cpu().numpy()[:, :1], Hd.cpu().numpy()[:, :1]
+    assert np.allclose(Wg, Wo, rtol=0, atol=1e-9 * np.abs(Wo).max())
+    assert np.allclose(Hg, Ho, rtol=0, atol=1e-9 * np.abs(Ho).max())
+
+
 def test_yahoo_shape_full_size_sampled_rows_and_fp32_step():
     """624,961 x 1,000,990, |Omega| = 2.5e8 (capped power law, exponent 1.1):
     FP64 sampled residual and both sparse products on sampled rows / columns
