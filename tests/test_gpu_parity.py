@@ -334,6 +334,23 @@ def test_solve_polymf_reduced_precision(precision, bar):
     assert abs(Fw - Fstar) <= bar * Fstar
 
 
+@pytest.mark.parametrize("shape", [(60, 40, 700), (120, 200, 4000)])
+def test_solve_parity_all_variants_together(shape):
+    """polyMF-SS BM phase, SpaRSA step rule and LmSVD with one history block in
+    one solve, against the oracle with the same options."""
+    m, n, nnz = shape
+    p = synth.tiny(m, n, nnz, rank=3, lam=0.3, seed=m + n + 1)
+    orc = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-10, seed=5, max_iter=3000, bm_solver="polymf",
+                                     step_rule="sparsa", lmsvd_p=1))
+    dp = to_dev(p, k_cap=64)
+    W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-10, seed=5, max_iter=3000, bm_solver="polymf",
+                              step_rule="sparsa", lmsvd_p=1)
+    print("all variants", shape, r["iters"], orc.iters, r["pg_trials"], r["F"], orc.F, flush=True)
+    assert r["status"] == 0 and orc.converged
+    assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
+    assert k == orc.k
+
+
 def test_solve_full_omega_closed_form():
     m, n, lam = 30, 45, 1.5
     p = synth.tiny(m, n, m * n, rank=4, seed=12)
