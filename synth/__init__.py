@@ -16,6 +16,8 @@ Workloads (all synthetic; no dataset records are reproduced):
 * ``yahoo_shape``    624,961 x 1,000,990, |Omega| ~ 2.5e8, capped power law
   (exponent 1.1), rank-30 truth plus noise of variance 0.5, unclipped;
   lambda = 50, k0 = 32.
+* ``rke``            regularized kernel estimation: n objects in R^3, about
+  deg/2 random partners each, noisy squared distances, symmetric storage.
 * ``serving_stream`` 256 problems, Poisson arrivals at 20/s, m ~ U[500, 20000],
   n ~ U[1000, 50000], density ~ U[0.5%, 2%], rank ~ U{3..15}, noise variance
   0.05, lambda relative to the sampling/noise level (see serving_stream).
@@ -183,6 +185,35 @@ def tiny(m: int, n: int, nnz: int, rank: int = 2, var_e: float = 0.01, lam: floa
                        keep_truth=True)
     return Problem("tiny_%dx%d_nnz%d" % (m, n, nnz), m, n, row_ptr, col, val, lam, k0, U, V,
                    dict(seed=seed, rank=rank, var_e=var_e, pattern="uniform"))
+
+
+def rke(n: int, deg: int, dim: int = 3, noise: float = 0.1, lam: float = 1.0, k0: int = 8,
+        seed: int = 1006) -> Problem:
+    """Regularized kernel estimation input (QSDP section): n objects at
+    Gaussian positions in R^dim; each object draws deg/2 partners uniformly
+    (pairs deduplicated), and each pair carries the squared distance times
+    (1 + noise * N(0, 1)), floored at 0.  Stored as a symmetric n x n CSR with
+    both (i, j) and (j, i) and the value d_ij^2."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, dim))
+    half = max(1, deg // 2)
+    i = np.repeat(np.arange(n, dtype=np.int64), half)
+    j = rng.integers(0, n - 1, size=i.size)
+    j = j + (j >= i)                                    # j != i
+    a, b = np.minimum(i, j), np.maximum(i, j)
+    key = np.unique(a * n + b)
+    a, b = key // n, key % n
+    d2 = np.sum((x[a] - x[b]) ** 2, axis=1) * (1.0 + noise * rng.standard_normal(a.size))
+    d2 = np.maximum(d2, 0.0)
+    r = np.concatenate([a, b])
+    c = np.concatenate([b, a])
+    v = np.concatenate([d2, d2])
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(r, minlength=n), out=row_ptr[1:])
+    return Problem("rke_n%d_pairs%d" % (n, a.size), n, n, row_ptr, c.astype(np.int32), v, lam, k0,
+                   meta=dict(seed=seed, dim=dim, noise=noise, deg=deg, pattern="rke"))
 
 
 @dataclass
