@@ -199,6 +199,32 @@ bmg_status bmg_bm_epochs(bmg_problem *p, double *W, double *H, int k, int ld, do
 bmg_status bmg_polymf_epochs(bmg_problem *p, double *W, double *H, int k, int ld, double lambda,
                              int epochs, double *F_bm);
 
+/* ------------------------------------------------------------------ kernel-estimation QSDP
+ * BM-Global on  min f(X) + lambda tr(X)  over {X psd, <E, X> = 0} (QSDP section,
+ * unit weights), f(X) = 1/2 sum over pairs (X_ii + X_jj - 2 X_ij - d_ij^2)^2, in the
+ * BM form X = W W^T, W^T e = 0 (eq. bm2).  The problem must be BMG_FP64 and
+ * square with Omega and its values symmetric: both (i, j) and (j, i) stored with
+ * the value d_ij^2 (BMG_EINVAL otherwise). */
+
+/* r (device, nnz, CSR order, or NULL) = ||w_i - w_j||^2 - d_ij^2 for every stored
+ * entry; deg (device, n, or NULL) = the row sums of r; sumsq (host) = sum r^2
+ * over stored entries (twice the sum over pairs).  W (device, n x ld). */
+bmg_status bmg_rke_residual(bmg_problem *p, const double *W, int k, int ld, double *r, double *deg,
+                            double *sumsq);
+
+/* Algorithm 1 on that problem: the first PG step from X = 0 (subspace iteration
+ * from J times an n x k_init Gaussian block), then per outer iteration bm_epochs
+ * nonlinear conjugate-gradient steps on W with the exact (quartic) line search,
+ * and one PG step with alpha = opt->alpha / (2 + 2 max degree) (a bound on
+ * ||A^* A||), whose prox P_S+(J Z J) (Lemma PiX) comes from block subspace
+ * iteration on the shifted operator; the positive Ritz pairs give the new W and
+ * rank.  Stops when ||X~ - X+||_F / (1 + ||X~||_F + ||grad f~||_F) <= opt->tol.
+ * Uses opt->lambda, alpha, tol, bm_epochs, max_iter, ssi_max_iter, ssi_tol_floor,
+ * k_init, seed, verbose.  W (device, n x ld) output, *k_out its rank; res (host)
+ * fills k, iters, ssi_iters, status, F, residual, seconds, sparse bytes/passes. */
+bmg_status bmg_rke_solve(bmg_problem *p, double *W, int ld, const bmg_options *opt, int *k_out,
+                         bmg_result *res);
+
 /* Objective of (MC) at X = W H^T:  F = 1/2 ||P_Omega(X - A)||^2 + lambda ||X||_*,
  * the nuclear norm from the k x k core of thin QR factors of W and H. (host) F. */
 bmg_status bmg_objective(bmg_problem *p, const double *W, const double *H, int k, int ld,

@@ -172,6 +172,28 @@ class Problem:
         _lib.check(st, allow=(BMG_OK, BMG_NOT_CONVERGED))
         return W, H, k.value, r.as_dict()
 
+    # -------------------------------------------------------------- kernel-estimation QSDP
+    def bmg_rke_residual(self, W, k):
+        """(r in CSR order, row sums of r, sum r^2) at X = W W^T (symmetric Omega)."""
+        ld = W.stride(0)
+        r = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=self.device)
+        deg = torch.empty(max(self.n, 1), dtype=torch.float64, device=self.device)
+        s2 = ctypes.c_double(0.0)
+        _lib.check(_lib.load().bmg_rke_residual(self._h, _ptr(W), k, ld, _ptr(r), _ptr(deg),
+                                                ctypes.byref(s2)))
+        return r[:self.nnz], deg[:self.n], s2.value
+
+    def bmg_rke_solve(self, **opts):
+        """BM-Global on the kernel-estimation QSDP; returns (W, k, result dict)."""
+        o = options(**opts)
+        W = torch.zeros((self.n, round_ld(self.k_cap)), dtype=torch.float64, device=self.device)
+        k = ctypes.c_int(0)
+        r = BmgResult()
+        st = _lib.load().bmg_rke_solve(self._h, _ptr(W), W.stride(0), ctypes.byref(o), ctypes.byref(k),
+                                       ctypes.byref(r))
+        _lib.check(st, allow=(BMG_OK, BMG_NOT_CONVERGED))
+        return W, k.value, r.as_dict()
+
 
 class Server:
     """Request loop over many problems on one GPU (bmg_server_*): admission by

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "BMG_OK", 1: "BMG_NOT_CONVERGED", -1: "BMG_EINVAL", -2: "BMG_
 # the C ABI's exported entry points (checked by the CPU tests)
 EXPORTS = ["bmg_options_default", "bmg_workspace_size", "bmg_problem_create", "bmg_problem_destroy",
            "bmg_sddmm", "bmg_spmm", "bmg_bm_epochs", "bmg_polymf_epochs", "bmg_objective",
-           "bmg_prox_step", "bmg_solve",
+           "bmg_prox_step", "bmg_solve", "bmg_rke_residual", "bmg_rke_solve",
            "bmg_last_error", "bmg_server_footprint", "bmg_server_create", "bmg_server_submit",
            "bmg_server_poll", "bmg_server_drain", "bmg_server_stats", "bmg_server_batch_stats",
            "bmg_server_destroy"]
@@ -101,6 +101,8 @@ def load():
     lib.bmg_spmm.argtypes = [p, p, p, i32, i32, p, i32, i32]
     lib.bmg_bm_epochs.argtypes = [p, p, p, i32, i32, d, i32, P(d)]
     lib.bmg_polymf_epochs.argtypes = [p, p, p, i32, i32, d, i32, P(d)]
+    lib.bmg_rke_residual.argtypes = [p, p, i32, i32, p, p, P(d)]
+    lib.bmg_rke_solve.argtypes = [p, p, i32, P(BmgOptions), P(i32), P(BmgResult)]
     lib.bmg_objective.argtypes = [p, p, p, i32, i32, d, P(d)]
     lib.bmg_prox_step.argtypes = [p, p, p, P(i32), i32, P(BmgOptions), P(d), P(d)]
     lib.bmg_solve.argtypes = [p, p, p, i32, P(BmgOptions), P(i32), P(BmgResult)]
@@ -114,7 +116,7 @@ def load():
     lib.bmg_server_destroy.argtypes = [p]
     lib.bmg_server_destroy.restype = None
     for f in ["bmg_workspace_size", "bmg_problem_create", "bmg_sddmm", "bmg_spmm", "bmg_bm_epochs",
-              "bmg_polymf_epochs",
+              "bmg_polymf_epochs", "bmg_rke_residual", "bmg_rke_solve",
               "bmg_objective", "bmg_prox_step", "bmg_solve", "bmg_server_footprint",
               "bmg_server_create", "bmg_server_submit", "bmg_server_poll", "bmg_server_drain",
               "bmg_server_stats", "bmg_server_batch_stats"]:

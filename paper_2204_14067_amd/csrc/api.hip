@@ -2106,6 +2106,383 @@ extern "C" bmg_status bmg_objective(bmg_problem *P, const double *W, const doubl
   return BMG_OK;
 }
 
+// ============================================================================ kernel-estimation QSDP
+// BM-Global for min f(X) + lambda tr(X) over {X psd, <E, X> = 0} with
+// f(X) = 1/2 sum over pairs (X_ii + X_jj - 2 X_ij - d_ij^2)^2 (QSDP section), in
+// the BM form X = W W^T, W^T e = 0 (eq. bm2).  Omega is stored symmetrically,
+// so sums over stored entries count every pair twice.  FP64.
+struct RkeMethod : Method<double> {
+  using M = Method<double>;
+  using M::P; using M::s; using M::ldk; using M::qld; using M::n; using M::R;
+  using M::gram; using M::gemm; using M::orth; using M::blk; using M::fro2;
+  explicit RkeMethod(bmg_problem *p) : M(p) {
+    const int64_t nv = rup(n, 64);
+    deg = blk(P->L.b_vec) + 2 * nv;
+    adeg = blk(P->L.b_vec) + 3 * nv;
+  }
+  double *deg, *adeg;
+
+  // r (stored, CSR order) = ||w_i - w_j||^2 - d_ij^2, deg / adeg per row;
+  // returns sum over stored entries of r^2
+  double residual(const double *W, int k) {
+    HIPC(launch_rke_res(R->pl, W, ldk, k, (const double *)R->a64, (double *)R->r, deg, adeg,
+                        (double *)P->partial, P->wsum, 2 * P->L.wsum_cap, P->result, s));
+    E::count(R->pl, 4.0 + 16.0, (double)n * k * 8.0);
+    double h[1];
+    E::fetch(h, P->result, 1);
+    return h[0];
+  }
+  // out (ld ldo) = L_r U: the sparse x dense pass with the stored r, then deg U - (.)
+  void lap(const double *U, int q, int ldu, double *out, int ldo) {
+    if (q == 0) return;
+    E::template pass<double>(2, R->pl, (const double *)R->r, (const double *)nullptr, ldk, U, ldu, q, 0.0,
+                             1.0, out, ldo, 0, nullptr, 0, E::sx(2));
+    E::count(R->pl, 4.0 + 8.0, (double)n * q * 16.0);
+    HIPC(launch_rowscale_sub(n, q, deg, U, ldu, out, ldo, s));
+  }
+  // Y = M U with M = W W^T - alpha L_r - alpha lambda J (U^T e = 0: J U = U)
+  void apply_M(const double *W, int k, double alpha, double lam, const double *U, int q, double *Y,
+               double *tmp) {
+    lap(U, q, qld, tmp, qld);
+    if (k > 0) {
+      std::vector<double> G = gram(n, k, W, ldk, q, U, qld);
+      gemm(n, k, W, ldk, q, G, Y, qld, 0.0);
+    } else {
+      HIPC(launch_fill<double>(Y, n, q, qld, 0.0, s));
+    }
+    HIPC(launch_axpy<double>(n, q, -alpha, tmp, qld, Y, qld, s));
+    HIPC(launch_axpy<double>(n, q, -alpha * lam, U, qld, Y, qld, s));
+  }
+  double dot(const double *A, const double *B, int k) {
+    std::vector<double> g = gram(n, k, A, ldk, k, B, ldk);
+    double t = 0.0;
+    for (int i = 0; i < k; ++i) t += g[(size_t)i * k + i];
+    return t;
+  }
+  // BM phase: `steps` nonlinear CG steps (Polak-Ribiere, restart at negative
+  // beta or a non-descent direction) with the exact quartic line search.
+  void bm_phase(double *W, int k, double lam, int steps) {
+    double *G = blk(P->L.b_G), *D = blk(P->L.b_D), *Gp = blk(P->L.b_H);
+    double gp2 = 0.0;
+    for (int st = 0; st < steps; ++st) {
+      residual(W, k);
+      lap(W, k, ldk, G, ldk);
+      HIPC(launch_axpy<double>(n, k, lam, W, ldk, G, ldk, s));
+      HIPC(launch_center_cols(n, k, G, ldk, s));
+      const double g2 = dot(G, G, k);
+      bool sd = st == 0;
+      if (!sd) {
+        const double beta = std::max(0.0, (g2 - dot(G, Gp, k)) / gp2);
+        HIPC(launch_axpy<double>(n, k, beta - 1.0, D, ldk, D, ldk, s));   // D = beta D
+        HIPC(launch_axpy<double>(n, k, -1.0, G, ldk, D, ldk, s));          // D -= G
+        if (dot(D, G, k) >= 0.0) sd = true;
+      }
+      if (sd) {
+        HIPC(launch_fill<double>(D, n, k, ldk, 0.0, s));
+        HIPC(launch_axpy<double>(n, k, -1.0, G, ldk, D, ldk, s));
+      }
+      HIPC(launch_rke_quartic(R->pl, W, D, ldk, k, (const double *)R->r, P->wsum, 2 * P->L.wsum_cap,
+                              P->result, s));
+      E::count(R->pl, 4.0 + 8.0, (double)n * k * 16.0);
+      double h[5];
+      E::fetch(h, P->result, 5);
+      const double c1 = h[0] + 2.0 * lam * dot(W, D, k);
+      const double c2 = h[1] + 0.5 * h[2] + lam * dot(D, D, k);
+      const double c3 = h[3], c4 = 0.25 * h[4];
+      REQUIRE(std::isfinite(c1) && std::isfinite(c2) && std::isfinite(c3) && std::isfinite(c4),
+              BMG_ENONFINITE, "non-finite line search");
+      const double t = quartic_min(c1, c2, c3, c4);
+      if (t > 0.0) HIPC(launch_axpy<double>(n, k, t, D, ldk, W, ldk, s));
+      HIPC(launch_copy_cols<double>(n, k, G, ldk, Gp, ldk, s));
+      gp2 = g2;
+    }
+  }
+  // ||W1 W1^T - W0 W0^T||_F^2 split over ran(orth(W1)) and its complement
+  double diff2(const double *W1, int k1, const double *W0, int k0) {
+    auto three = [&](const double *A, int la, int ka, const double *B, int lb, int kb) {
+      double v = 0.0;
+      if (ka > 0) { auto g = gram(n, ka, A, la, ka, A, la); v += M::trace_prod(g, g, ka); }
+      if (kb > 0) { auto g = gram(n, kb, B, lb, kb, B, lb); v += M::trace_prod(g, g, kb); }
+      if (ka > 0 && kb > 0) {
+        auto g = gram(n, kb, B, lb, ka, A, la);
+        double c = 0.0;
+        for (double x : g) c += x * x;
+        v -= 2.0 * c;
+      }
+      return v;
+    };
+    double *Q = blk(P->L.b_B3), *T1 = blk(P->L.b_B4), *E1 = blk(P->L.b_Y), *E0 = blk(P->L.b_Y2);
+    int r = 0;
+    if (k1 > 0 && k0 > 0) {
+      HIPC(launch_copy_cols<double>(n, k1, W1, ldk, E1, qld, s));
+      r = orth(n, E1, k1, Q, T1);
+    }
+    if (r == 0) return std::max(0.0, three(W1, ldk, k1, W0, ldk, k0));
+    std::vector<double> G1 = gram(n, r, Q, qld, k1, W1, ldk), G0 = gram(n, r, Q, qld, k0, W0, ldk);
+    // (Q^T W1)(Q^T W1)^T - (Q^T W0)(Q^T W0)^T on the host (r x r)
+    double d = 0.0;
+    for (int a = 0; a < r; ++a)
+      for (int b = 0; b < r; ++b) {
+        double v = 0.0;
+        for (int c = 0; c < k1; ++c) v += G1[(size_t)a * k1 + c] * G1[(size_t)b * k1 + c];
+        for (int c = 0; c < k0; ++c) v -= G0[(size_t)a * k0 + c] * G0[(size_t)b * k0 + c];
+        d += v * v;
+      }
+    // cross term 2 ||Q^T (W1 W1^T - W0 W0^T) (I - QQ^T)||^2 = 2 ||(Q^T W0) E0^T||^2 (E1 = 0 up to rounding)
+    for (double &v : G1) v = -v;
+    for (double &v : G0) v = -v;
+    HIPC(launch_copy_cols<double>(n, k1, W1, ldk, E1, qld, s));
+    gemm(n, r, Q, qld, k1, G1, E1, qld, 1.0);
+    HIPC(launch_copy_cols<double>(n, k0, W0, ldk, E0, qld, s));
+    gemm(n, r, Q, qld, k0, G0, E0, qld, 1.0);
+    for (double &v : G1) v = -v;
+    for (double &v : G0) v = -v;
+    // Q^T X E^T blocks: (Q^T W1) (E1^T) - (Q^T W0)(E0^T): Frobenius^2 via Gram matrices
+    double cross = 0.0;
+    {
+      auto e11 = gram(n, k1, E1, qld, k1, E1, qld), e00 = gram(n, k0, E0, qld, k0, E0, qld);
+      auto e01 = gram(n, k0, E0, qld, k1, E1, qld);
+      auto g11 = std::vector<double>((size_t)k1 * k1), g00 = std::vector<double>((size_t)k0 * k0),
+           g01 = std::vector<double>((size_t)k0 * k1);
+      for (int a = 0; a < k1; ++a)
+        for (int b = 0; b < k1; ++b) {
+          double v = 0.0;
+          for (int c = 0; c < r; ++c) v += G1[(size_t)c * k1 + a] * G1[(size_t)c * k1 + b];
+          g11[(size_t)a * k1 + b] = v;
+        }
+      for (int a = 0; a < k0; ++a)
+        for (int b = 0; b < k0; ++b) {
+          double v = 0.0;
+          for (int c = 0; c < r; ++c) v += G0[(size_t)c * k0 + a] * G0[(size_t)c * k0 + b];
+          g00[(size_t)a * k0 + b] = v;
+        }
+      for (int a = 0; a < k0; ++a)
+        for (int b = 0; b < k1; ++b) {
+          double v = 0.0;
+          for (int c = 0; c < r; ++c) v += G0[(size_t)c * k0 + a] * G1[(size_t)c * k1 + b];
+          g01[(size_t)a * k1 + b] = v;
+        }
+      double c = 0.0;
+      for (size_t i = 0; i < g11.size(); ++i) c += g11[i] * e11[i];
+      for (size_t i = 0; i < g00.size(); ++i) c += g00[i] * e00[i];
+      for (size_t i = 0; i < g01.size(); ++i) c -= 2.0 * g01[i] * e01[i];
+      cross = std::max(0.0, c);
+    }
+    return d + 2.0 * cross + std::max(0.0, three(E1, qld, k1, E0, qld, k0));
+  }
+  struct Eig {
+    int k = 0, iters = 0;
+  };
+  // Prox of the PG step (Lemma PiX) from the q0 columns of U0 (block B1 or
+  // B2, ld qld): subspace iteration on M + sigma I, Rayleigh-Ritz on M, the
+  // positive Ritz pairs kept: Wn = U V_+ sqrt(theta_+), Uc = U V_+ (ld ldk).
+  Eig eig_prox(const double *W, int k, double alpha, double lam, double *U0, int q0, double tau,
+               int max_iter, double *Wn, double *Uc) {
+    Eig out;
+    double *B1 = blk(P->L.b_B1), *B2 = blk(P->L.b_B2), *B3 = blk(P->L.b_B3), *B4 = blk(P->L.b_B4);
+    double *Y = blk(P->L.b_Y), *tmp = blk(P->L.b_Y2);
+    double *U = U0 == B1 ? B2 : B1;
+    // sigma = alpha (2 max_i sum_j |r_ij| + lambda)
+    std::vector<double> ad(n);
+    HIPC(hipMemcpyAsync(ad.data(), adeg, 8 * n, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    double amax = 0.0;
+    for (double v : ad) amax = std::max(amax, v);
+    const double sigma = alpha * (2.0 * amax + lam);
+    HIPC(launch_center_cols(n, q0, U0, qld, s));
+    int q = orth(n, U0, q0, U, B4);
+    std::vector<double> prev, th, V;
+    int it = 0;
+    for (it = 1; it <= max_iter && q > 0; ++it) {
+      apply_M(W, k, alpha, lam, U, q, Y, tmp);
+      std::vector<double> T = gram(n, q, U, qld, q, Y, qld);
+      th.assign(q, 0.0);
+      V.assign((size_t)q * q, 0.0);
+      lat::sym_eig(q, T.data(), th.data(), V.data());
+      bool done = false;
+      if (!prev.empty() && prev.size() == th.size()) {
+        double dmax = 0.0;
+        for (int j = 0; j < q; ++j)
+          if (j == 0 || th[j] > 0.0) dmax = std::max(dmax, fabs(th[j] - prev[j]));
+        done = dmax <= tau * fabs(th[0]);
+      }
+      prev = th;
+      if (done || it == max_iter) break;
+      // next basis: orth(J (Y V + sigma U V))
+      std::vector<double> sV(V);
+      for (double &v : sV) v *= sigma;
+      gemm(n, q, Y, qld, q, V, B3, qld, 0.0);
+      gemm(n, q, U, qld, q, sV, B3, qld, 1.0);
+      HIPC(launch_center_cols(n, q, B3, qld, s));
+      q = orth(n, B3, q, U, B4);
+      prev.clear();
+      prev = th;
+    }
+    out.iters = std::min(it, max_iter);
+    if (q == 0 || th.empty()) return out;
+    int kp = 0;
+    while (kp < q && th[kp] > 0.0) ++kp;
+    REQUIRE(kp <= P->L.k_cap, BMG_ENOMEM, "rank of the prox output (" + std::to_string(kp) + ") exceeds k_cap");
+    std::vector<double> CW((size_t)q * std::max(kp, 1)), CU((size_t)q * std::max(kp, 1));
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < kp; ++j) {
+        CU[(size_t)i * kp + j] = V[(size_t)i * q + j];
+        CW[(size_t)i * kp + j] = V[(size_t)i * q + j] * sqrt(th[j]);
+      }
+    if (kp > 0) {
+      gemm(n, q, U, qld, kp, CW, Wn, ldk, 0.0);
+      gemm(n, q, U, qld, kp, CU, Uc, ldk, 0.0);
+    }
+    out.k = kp;
+    return out;
+  }
+
+  // Algorithm 1 on the QSDP (the readings of the oracle's rke.solve)
+  bmg_status solve(const bmg_options &o, int *k_out, bmg_result *res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    P->reset_stats();
+    std::vector<int64_t> ptr(n + 1);
+    HIPC(hipMemcpyAsync(ptr.data(), R->pl.ptr, 8 * (n + 1), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    int64_t maxdeg = 0;
+    for (int64_t i = 0; i < n; ++i) maxdeg = std::max(maxdeg, ptr[i + 1] - ptr[i]);
+    const double alpha = o.alpha / (2.0 + 2.0 * (double)maxdeg);
+    const double lam = o.lambda;
+    double *W = blk(P->L.b_W), *Wn = blk(P->L.b_Wn), *Uc = blk(P->L.b_Ucur), *Ut = blk(P->L.b_Uprev);
+    double *B1 = blk(P->L.b_B1);
+    int k = 0, kc = 0, ssi_total = 0;
+    // X_{-1} = 0: r = -d^2; the start block J times Gaussian (n x k0)
+    const int k0 = std::max(1, std::min(o.k_init, qld));
+    residual(W, 0);
+    HIPC(launch_normals<double>(o.seed, STREAM_SKETCH, n, k0, qld, B1, s));
+    Eig e0 = eig_prox(W, 0, alpha, lam, B1, k0, 1e-4, o.ssi_max_iter, Wn, Uc);
+    ssi_total += e0.iters;
+    k = kc = e0.k;
+    std::swap(W, Wn);
+    double resid = INFINITY, res_prev = 1.0, F = 0.0;
+    bool conv = false;
+    int t = 0;
+    for (t = 0; t < o.max_iter; ++t) {
+      if (k > 0 && o.bm_epochs > 0) bm_phase(W, k, lam, o.bm_epochs);
+      const double r2 = residual(W, k);
+      const double tau = std::max(o.ssi_tol_floor, std::min(1e-4, 0.1 * res_prev * res_prev));
+      // warm start [U_t, W~_t, xi_t]
+      const int q0 = std::min(qld, kc + k + 1);
+      REQUIRE(kc + k + 1 <= qld, BMG_ENOMEM, "subspace block exceeds 2 k_cap + 2 columns");
+      HIPC(launch_copy_cols<double>(n, kc, Uc, ldk, B1, qld, s));
+      HIPC(launch_copy_cols<double>(n, k, W, ldk, B1 + kc, qld, s));
+      HIPC(launch_normals<double>(o.seed, STREAM_SAFEGUARD + (uint64_t)t, n, 1, qld, B1 + kc + k, s));
+      std::swap(Uc, Ut);
+      Eig ep = eig_prox(W, k, alpha, lam, B1, q0, tau, o.ssi_max_iter, Wn, Uc);
+      ssi_total += ep.iters;
+      // relative residual ||X~ - X+|| / (1 + ||X~|| + ||grad f~(X~)||)
+      std::vector<double> dg(n);
+      HIPC(hipMemcpyAsync(dg.data(), deg, 8 * n, hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      double g2 = r2;
+      for (double v : dg) g2 += (v + lam) * (v + lam);
+      double x2 = 0.0;
+      if (k > 0) { auto g = gram(n, k, W, ldk, k, W, ldk); x2 = M::trace_prod(g, g, k); }
+      const double d2 = k > 0 ? diff2(W, k, Wn, ep.k)
+                              : (ep.k > 0 ? [&] { auto g = gram(n, ep.k, Wn, ldk, ep.k, Wn, ldk);
+                                                  return M::trace_prod(g, g, ep.k); }() : 0.0);
+      resid = sqrt(std::max(d2, 0.0)) / (1.0 + sqrt(std::max(x2, 0.0)) + sqrt(g2));
+      std::swap(W, Wn);
+      k = kc = ep.k;
+      F = 0.25 * residual(W, k) + lam * (k > 0 ? fro2(n, W, ldk, k) : 0.0);
+      REQUIRE(std::isfinite(F) && std::isfinite(resid), BMG_ENONFINITE, "non-finite objective");
+      if (o.verbose)
+        fprintf(stderr, "[bmg-rke] t=%d F=%.15g res=%.3e k=%d ssi=%d\n", t, F, resid, k, ep.iters);
+      res_prev = resid;
+      if (resid <= o.tol) {
+        conv = true;
+        ++t;
+        break;
+      }
+    }
+    HIPC(hipStreamSynchronize(s));
+    last_W = W;
+    *k_out = k;
+    if (res) {
+      memset(res, 0, sizeof(*res));
+      res->k = k;
+      res->iters = t;
+      res->ssi_iters = ssi_total;
+      res->status = conv ? BMG_OK : BMG_NOT_CONVERGED;
+      res->F = F;
+      res->residual = resid;
+      res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      res->sparse_bytes = P->bytes;
+      res->sparse_passes = P->passes;
+    }
+    return conv ? BMG_OK : BMG_NOT_CONVERGED;
+  }
+  double *last_W = nullptr;
+};
+
+static bmg_status check_rke(bmg_problem *P) {
+  if (!P) return fail(BMG_EINVAL, "null problem");
+  if (P->prec != BMG_FP64) return fail(BMG_EINVAL, "the kernel-estimation path runs in BMG_FP64");
+  if (P->m_user != P->n_user) return fail(BMG_EINVAL, "the kernel-estimation path needs a square Omega");
+  try {
+    RkeMethod M(P);
+    int *flag = (int *)P->result;
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int), P->s));
+    HIPC(launch_cmp_orient(M.R->pl.nnz, M.R->pl.idx, M.C->pl.idx, M.R->a64, M.C->a64, flag, P->s));
+    int h = 0;
+    HIPC(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, P->s));
+    HIPC(hipStreamSynchronize(P->s));
+    if (h) return fail(BMG_EINVAL, "Omega and its values must be symmetric (both (i, j) and (j, i) stored)");
+  } catch (const BmgError &e) {
+    return fail(e.st, e.msg);
+  }
+  return BMG_OK;
+}
+
+extern "C" bmg_status bmg_rke_residual(bmg_problem *P, const double *W, int k, int ld, double *r,
+                                       double *deg, double *sumsq) {
+  bmg_status st = check_rke(P);
+  if (st != BMG_OK) return st;
+  if (k < 0 || k > P->L.k_cap || ld < k || ld % 8 != 0 || (k > 0 && !W))
+    return fail(BMG_EINVAL, "bad k / ld");
+  try {
+    RkeMethod M(P);
+    double *Wi = M.blk(P->L.b_W);
+    if (k > 0) HIPC(launch_copy_cols<double>(M.n, k, W, ld, Wi, P->L.ldk, P->s));
+    const double s2 = M.residual(Wi, k);
+    if (r) HIPC(hipMemcpyAsync(r, M.R->r, 8 * M.R->pl.nnz, hipMemcpyDeviceToDevice, P->s));
+    if (deg) HIPC(hipMemcpyAsync(deg, M.deg, 8 * M.n, hipMemcpyDeviceToDevice, P->s));
+    HIPC(hipStreamSynchronize(P->s));
+    if (sumsq) *sumsq = s2;
+  } catch (const BmgError &e) {
+    return fail(e.st, e.msg);
+  }
+  return BMG_OK;
+}
+
+extern "C" bmg_status bmg_rke_solve(bmg_problem *P, double *W, int ld, const bmg_options *opt, int *k_out,
+                                    bmg_result *res) {
+  if (!opt || !W || !k_out) return fail(BMG_EINVAL, "bmg_rke_solve: null argument");
+  if (ld < 8 || ld % 8) return fail(BMG_EINVAL, "bmg_rke_solve: ld must be a positive multiple of 8");
+  if (!(opt->lambda > 0.0) || !(opt->alpha > 0.0) || opt->bm_epochs < 0 || opt->max_iter < 0 ||
+      opt->ssi_max_iter < 1 || opt->k_init < 1)
+    return fail(BMG_EINVAL, "bmg_rke_solve: bad options");
+  bmg_status st = check_rke(P);
+  if (st != BMG_OK) return st;
+  try {
+    RkeMethod M(P);
+    int k = 0;
+    st = M.solve(*opt, &k, res);
+    REQUIRE(k <= ld, BMG_ENOMEM, "rank exceeds ld");
+    if (k > 0) HIPC(launch_copy_cols<double>(M.n, k, M.last_W, P->L.ldk, W, ld, P->s));
+    HIPC(hipStreamSynchronize(P->s));
+    *k_out = k;
+  } catch (const BmgError &e) {
+    return fail(e.st, e.msg);
+  }
+  return st;
+}
+
 static bool step_rule_ok(const bmg_options *o) {
   if (o->step_rule == BMG_STEP_FIXED) return true;
   return o->step_rule == BMG_STEP_SPARSA && o->alpha_min > 0.0 && o->alpha_max >= o->alpha_min &&

@@ -189,6 +189,27 @@ template <typename T>
 hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, int jn, double t, Q4<T> *Gm,
                            Q4<T> *Gn, hipStream_t s);
 
+// Kernel-estimation QSDP pair passes (rke.hip), FP64, rows plan of a
+// symmetric Omega, factor W (n x k, ld):
+//   r_p = ||w_i - w_j||^2 - d2_p (stored), deg_i = sum r, adeg_i = sum |r|,
+//   out[0] = sum r^2; part: 2 doubles per piece; bpart: 1 double per 4 units.
+hipError_t launch_rke_res(const Plan &pl, const double *W, int ld, int k, const double *d2, double *r,
+                          double *deg, double *adeg, double *part, double *bpart, int64_t bpart_cap,
+                          double *out, hipStream_t s);
+// out[0..4] = sum of r a1, a1^2, r a2, a1 a2, a2^2 with a1 = (w_i - w_j).(d_i - d_j),
+// a2 = ||d_i - d_j||^2 (D at the same ld); bpart: 5 doubles per 4 units.
+hipError_t launch_rke_quartic(const Plan &pl, const double *W, const double *D, int ld, int k,
+                              const double *r, double *bpart, int64_t bpart_cap, double *out,
+                              hipStream_t s);
+// Out = deg U - Out (row scaling)
+hipError_t launch_rowscale_sub(int64_t n, int q, const double *deg, const double *U, int ldu, double *Out,
+                               int ldo, hipStream_t s);
+// V = J V: subtract each column's mean
+hipError_t launch_center_cols(int64_t n, int q, double *V, int ld, hipStream_t s);
+// flag[0] = 1 where the two orientations' indices or values differ
+hipError_t launch_cmp_orient(int64_t nnz, const int32_t *a, const int32_t *b, const double *va,
+                             const double *vb, int *flag, hipStream_t s);
+
 // Widest slice one launch handles for element type T.
 // (8 lanes x 16 bytes per chunk, at most 8 chunks: 128 doubles / 256 floats)
 template <typename T> constexpr int max_width() { return 128 * (16 / (int)sizeof(T)); }

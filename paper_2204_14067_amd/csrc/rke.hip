@@ -1,0 +1,233 @@
+// Pair passes of the kernel-estimation QSDP (QSDP section; BM form eq. bm2):
+// Omega is stored symmetrically (both (i, j) and (j, i), value d_ij^2) and the
+// one factor W (n x k) is gathered on both sides.  One 64-lane wave per work
+// unit of the rows plan; lanes stride over the entries and loop over the k
+// columns; reductions in a fixed order, long rows summed piece by piece in
+// piece order, so results are bitwise reproducible.  FP64 only.
+#include <hip/hip_runtime.h>
+
+#include "bmg_internal.h"
+#include "units.h"
+
+namespace bmg {
+
+namespace {
+
+constexpr int RK_WAVES = 4;  // waves per block
+
+// r_p = ||w_i - w_j||^2 - d2_p (stored); per row deg_i = sum r, adeg_i = sum |r|;
+// per block the partial sum of r^2.
+__global__ __launch_bounds__(64 * RK_WAVES) void k_rke_res(Plan pl, const double *__restrict__ W, int ld,
+                                                        int k, const double *__restrict__ d2,
+                                                        double *__restrict__ r, double *__restrict__ deg,
+                                                        double *__restrict__ adeg,
+                                                        double *__restrict__ part,
+                                                        double *__restrict__ bpart) {
+  __shared__ double sm[RK_WAVES];
+  const int64_t u = (int64_t)blockIdx.x * RK_WAVES + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  double s = 0.0, sa = 0.0, s2 = 0.0;
+  const bool live = u < pl.n_short + pl.n_pieces;
+  Unit w{};
+  if (live) {
+    w = unit_of(pl, u);
+    const double *wi = W + w.row * ld;
+    for (int64_t e = w.beg + lane; e < w.end; e += 64) {
+      const double *wj = W + (int64_t)pl.idx[e] * ld;
+      double acc = 0.0;
+      for (int c = 0; c < k; ++c) {
+        const double d = wi[c] - wj[c];
+        acc += d * d;
+      }
+      const double rr = acc - d2[e];
+      r[e] = rr;
+      s += rr;
+      sa += fabs(rr);
+      s2 += rr * rr;
+    }
+  }
+  s = wave_sum64(s);
+  sa = wave_sum64(sa);
+  s2 = wave_sum64(s2);
+  if (lane == 0) {
+    sm[wv] = s2;
+    if (live) {
+      if (w.piece) {
+        part[2 * w.p] = s;
+        part[2 * w.p + 1] = sa;
+      } else {
+        deg[w.row] = s;
+        adeg[w.row] = sa;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < RK_WAVES; ++q) t += sm[q];
+    bpart[blockIdx.x] = t;
+  }
+}
+
+__global__ void k_rke_fix(Plan pl, const double *__restrict__ part, double *__restrict__ deg,
+                          double *__restrict__ adeg) {
+  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (L >= pl.n_long) return;
+  double s = 0.0, sa = 0.0;
+  for (int p = pl.long_p0[L]; p < pl.long_p0[L + 1]; ++p) {
+    s += part[2 * p];
+    sa += part[2 * p + 1];
+  }
+  deg[pl.long_rows[L]] = s;
+  adeg[pl.long_rows[L]] = sa;
+}
+
+// Quartic coefficients along W + t D: per entry a1 = (w_i - w_j).(d_i - d_j),
+// a2 = ||d_i - d_j||^2; per block sum r a1, a1^2, r a2, a1 a2, a2^2.
+__global__ __launch_bounds__(64 * RK_WAVES) void k_rke_quartic(Plan pl, const double *__restrict__ W,
+                                                            const double *__restrict__ D, int ld, int k,
+                                                            const double *__restrict__ r,
+                                                            double *__restrict__ bpart) {
+  __shared__ double sm[RK_WAVES][5];
+  const int64_t u = (int64_t)blockIdx.x * RK_WAVES + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+  if (u < pl.n_short + pl.n_pieces) {
+    const Unit w = unit_of(pl, u);
+    const double *wi = W + w.row * ld, *di = D + w.row * ld;
+    for (int64_t e = w.beg + lane; e < w.end; e += 64) {
+      const int64_t j = pl.idx[e];
+      const double *wj = W + j * ld, *dj = D + j * ld;
+      double a1 = 0.0, a2 = 0.0;
+      for (int c = 0; c < k; ++c) {
+        const double dd = di[c] - dj[c];
+        a1 += (wi[c] - wj[c]) * dd;
+        a2 += dd * dd;
+      }
+      const double rr = r[e];
+      s0 += rr * a1;
+      s1 += a1 * a1;
+      s2 += rr * a2;
+      s3 += a1 * a2;
+      s4 += a2 * a2;
+    }
+  }
+  s0 = wave_sum64(s0);
+  s1 = wave_sum64(s1);
+  s2 = wave_sum64(s2);
+  s3 = wave_sum64(s3);
+  s4 = wave_sum64(s4);
+  if (lane == 0) {
+    sm[wv][0] = s0; sm[wv][1] = s1; sm[wv][2] = s2; sm[wv][3] = s3; sm[wv][4] = s4;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    double t = 0.0;
+    for (int q = 0; q < RK_WAVES; ++q) t += sm[q][threadIdx.x];
+    bpart[(int64_t)blockIdx.x * 5 + threadIdx.x] = t;
+  }
+}
+
+// out[c] = sum over b of parts[b * nc + c], one block, fixed order.
+__global__ __launch_bounds__(256) void k_sum_parts(const double *__restrict__ parts, int64_t nb, int nc,
+                                                   double *__restrict__ out) {
+  __shared__ double sm[4][8];
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  for (int c = 0; c < nc; ++c) {
+    double v = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) v += parts[b * nc + c];
+    v = wave_sum64(v);
+    if (lane == 0) sm[wv][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nc) out[threadIdx.x] = sm[0][threadIdx.x] + sm[1][threadIdx.x] + sm[2][threadIdx.x] +
+                                           sm[3][threadIdx.x];
+}
+
+// Out[i, c] = deg[i] U[i, c] - Out[i, c]
+__global__ void k_rowscale_sub(int64_t n, int q, const double *__restrict__ deg,
+                               const double *__restrict__ U, int ldu, double *__restrict__ Out, int ldo) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * q) return;
+  const int64_t i = t / q;
+  const int c = (int)(t % q);
+  Out[i * ldo + c] = deg[i] * U[i * ldu + c] - Out[i * ldo + c];
+}
+
+// V[:, c] -= mean(V[:, c]); one block per column, fixed-order sum.
+__global__ __launch_bounds__(256) void k_center_cols(int64_t n, double *__restrict__ V, int ld) {
+  __shared__ double sm[4];
+  __shared__ double mean;
+  const int c = blockIdx.x;
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) v += V[i * ld + c];
+  v = wave_sum64(v);
+  if (threadIdx.x % 64 == 0) sm[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) mean = (sm[0] + sm[1] + sm[2] + sm[3]) / (double)n;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += 256) V[i * ld + c] -= mean;
+}
+
+// flag = 1 when the two orientations differ (the pattern or values are not symmetric)
+__global__ void k_cmp_orient(int64_t nnz, const int32_t *__restrict__ a, const int32_t *__restrict__ b,
+                             const double *__restrict__ va, const double *__restrict__ vb,
+                             int *__restrict__ flag) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz && (a[e] != b[e] || va[e] != vb[e])) flag[0] = 1;
+}
+
+}  // namespace
+
+hipError_t launch_rke_res(const Plan &pl, const double *W, int ld, int k, const double *d2, double *r,
+                          double *deg, double *adeg, double *part, double *bpart, int64_t bpart_cap,
+                          double *out, hipStream_t s) {
+  const int64_t units = pl.n_short + pl.n_pieces;
+  const int64_t nb = (units + RK_WAVES - 1) / RK_WAVES;
+  if (nb > bpart_cap) return hipErrorInvalidValue;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_rke_res, dim3((unsigned)nb), dim3(64 * RK_WAVES), 0, s, pl, W, ld, k, d2, r, deg,
+                       adeg, part, bpart);
+  if (pl.n_long > 0)
+    hipLaunchKernelGGL(k_rke_fix, dim3((unsigned)((pl.n_long + 255) / 256)), dim3(256), 0, s, pl,
+                       (const double *)part, deg, adeg);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const double *)bpart, nb, 1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rke_quartic(const Plan &pl, const double *W, const double *D, int ld, int k,
+                              const double *r, double *bpart, int64_t bpart_cap, double *out,
+                              hipStream_t s) {
+  const int64_t units = pl.n_short + pl.n_pieces;
+  const int64_t nb = (units + RK_WAVES - 1) / RK_WAVES;
+  if (nb * 5 > bpart_cap) return hipErrorInvalidValue;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_rke_quartic, dim3((unsigned)nb), dim3(64 * RK_WAVES), 0, s, pl, W, D, ld, k, r,
+                       bpart);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const double *)bpart, nb, 5, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowscale_sub(int64_t n, int q, const double *deg, const double *U, int ldu, double *Out,
+                               int ldo, hipStream_t s) {
+  const int64_t tot = n * (int64_t)q;
+  if (tot > 0)
+    hipLaunchKernelGGL(k_rowscale_sub, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, q, deg, U,
+                       ldu, Out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_center_cols(int64_t n, int q, double *V, int ld, hipStream_t s) {
+  if (n > 0 && q > 0) hipLaunchKernelGGL(k_center_cols, dim3((unsigned)q), dim3(256), 0, s, n, V, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_cmp_orient(int64_t nnz, const int32_t *a, const int32_t *b, const double *va,
+                             const double *vb, int *flag, hipStream_t s) {
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_cmp_orient, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, a, b, va,
+                       vb, flag);
+  return hipGetLastError();
+}
+
+}  // namespace bmg

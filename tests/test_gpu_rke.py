@@ -1,0 +1,68 @@
+"""GPU parity of the kernel-estimation QSDP path (bmg_rke_*) against
+oracle/rke.py on the same seeded inputs (FP64).  Tolerances: pair residuals
+4 k u (|w_i|^2 + |w_j|^2 + d^2) elementwise; solves: objective within 1e-8
+relative, the same rank."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2204_14067_amd as bmg
+import synth
+from oracle import rke
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+U = 2.0 ** -53
+
+
+def to_dev(p, k_cap=32, precision="fp64"):
+    return bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=k_cap, precision=precision,
+                                 device=DEV)
+
+
+@pytest.mark.parametrize("n,deg,k", [(30, 8, 1), (200, 20, 5), (3000, 5000, 17)])
+def test_rke_residual_parity(n, deg, k):
+    """(3000, 5000): rows longer than one piece (split and summed in order)."""
+    p = synth.rke(n, deg, seed=n)
+    print("rke residual", n, p.nnz, k, flush=True)
+    dp = to_dev(p, k_cap=32)
+    W = np.zeros((n, 32))
+    W[:, :k] = np.random.default_rng(k).standard_normal((n, k))
+    r, dg, s2 = dp.bmg_rke_residual(torch.as_tensor(W, device=DEV), k)
+    ro = rke.pair_residual(p, W[:, :k])
+    rows = p.rows()
+    nrm = np.sum(W[:, :k] ** 2, axis=1)
+    bound = 4 * k * U * (nrm[rows] + nrm[p.col] + np.abs(p.val)) * 4
+    assert np.all(np.abs(r.cpu().numpy() - ro) <= bound + 1e-300)
+    dgo = np.bincount(rows, weights=ro, minlength=n)
+    assert np.allclose(dg.cpu().numpy(), dgo, rtol=1e-12, atol=1e-9)
+    assert math.isclose(s2, float(ro @ ro), rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("n,deg,lam", [(50, 30, 2.0), (100, 30, 1.5)])
+def test_rke_solve_parity(n, deg, lam):
+    p = synth.rke(n, deg, lam=lam, seed=3)
+    orc = rke.solve(p, lam, k0=6, tol=1e-9, seed=1, max_iter=1000)
+    dp = to_dev(p, k_cap=64)
+    W, k, r = dp.bmg_rke_solve(lam=lam, k_init=6, tol=1e-9, seed=1, max_iter=1000, bm_epochs=10)
+    print("rke solve", n, r["iters"], orc.iters, r["F"], orc.F, k, orc.k, flush=True)
+    assert r["status"] == 0 and orc.converged
+    assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
+    assert k == orc.k
+    Wg = W.cpu().numpy()[:, :k]
+    assert np.allclose(Wg.sum(axis=0), 0.0, atol=1e-8 * max(1.0, np.abs(Wg).max()))
+    assert math.isclose(rke.objective(p, Wg, lam), r["F"], rel_tol=1e-10)
+
+
+def test_rke_rejects_unsymmetric_and_reduced_precision():
+    p = synth.tiny(20, 20, 100, seed=3)            # a square but unsymmetric Omega
+    dp = to_dev(p, k_cap=8)
+    with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
+        dp.bmg_rke_solve(lam=1.0)
+    q = synth.rke(30, 8, seed=4)
+    with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
+        to_dev(q, k_cap=8, precision="fp32").bmg_rke_solve(lam=1.0)
+    with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
+        to_dev(q, k_cap=8).bmg_rke_solve(lam=-1.0)
