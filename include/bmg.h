@@ -217,8 +217,9 @@ bmg_status bmg_rke_residual(bmg_problem *p, const double *W, int k, int ld, doub
  * nonlinear conjugate-gradient steps on W with the exact (quartic) line search,
  * and one PG step with alpha = opt->alpha / (2 + 2 max degree) (a bound on
  * ||A^* A||), whose prox P_S+(J Z J) (Lemma PiX) comes from block subspace
- * iteration on the shifted operator; the positive Ritz pairs give the new W and
- * rank.  Stops when ||X~ - X+||_F / (1 + ||X~||_F + ||grad f~||_F) <= opt->tol.
+ * iteration on the shifted operator started from [W, one Gaussian column]; the
+ * positive Ritz pairs give the new W and rank (so the rank grows by at most one
+ * per step).  Stops when ||X~ - X+||_F / (1 + ||X~||_F + ||grad f~||_F) <= opt->tol.
  * Uses opt->lambda, alpha, tol, bm_epochs, max_iter, ssi_max_iter, ssi_tol_floor,
  * k_init, seed, verbose.  W (device, n x ld) output, *k_out its rank; res (host)
  * fills k, iters, ssi_iters, status, F, residual, seconds, sparse bytes/passes. */

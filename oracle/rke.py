@@ -137,8 +137,10 @@ def eig_prox(prob, W, r, alpha: float, lam: float, U0, tau: float, max_iter: int
     which is positive semidefinite (Gershgorin), so the iteration finds the
     algebraically largest eigenvalues; Rayleigh-Ritz on M with
     T = U^T M U; next U = orth(J (M + sigma I) U V).  Stop once the Ritz values
-    above 0 (and the largest) moved by at most tau * |largest|; keep the positive
-    ones: X+ = U V_+ diag(theta_+) (U V_+)^T."""
+    above 0, the largest and the first one not above 0 moved by at most
+    tau * |largest| (the last so that a positive eigenvalue still being
+    approached is not cut off); keep the positive ones:
+    X+ = U V_+ diag(theta_+) (U V_+)^T."""
     n = prob.n
     absdeg = np.bincount(prob.rows(), weights=np.abs(r), minlength=n)
     sigma = alpha * (2.0 * float(absdeg.max() if absdeg.size else 0.0) + lam)
@@ -159,6 +161,7 @@ def eig_prox(prob, W, r, alpha: float, lam: float, U0, tau: float, max_iter: int
         if prev is not None and prev.size == theta.size and theta.size:
             J = theta > 0.0
             J[0] = True
+            J[min(int(np.sum(theta > 0.0)), theta.size - 1)] = True   # the first one not kept
             done = float(np.max(np.abs(theta[J] - prev[J]))) <= tau * abs(theta[0])
         prev = theta
         if done or it == max_iter:
@@ -213,16 +216,17 @@ def solve(prob, lam: float, k0: int = 8, tol: float = 1e-6, max_iter: int = 500,
     alpha = alpha_scale / (2 + 2 max degree); the first step from X_{-1} = 0
     starts the subspace iteration from J times a Gaussian n x k0 block (stream
     STREAM_SKETCH); then per outer iteration a BM phase of bm_epochs conjugate
-    gradient steps (bm_phase), the PG step
-    warm-started from orth(J [U_t, W~_t, xi_t]) with xi_t Gaussian (stream
-    STREAM_SAFEGUARD + t), and the rank update k = number of positive Ritz
-    values.  Stop when ||X~ - X+||_F / (1 + ||X~||_F + ||grad f~(X~)||_F) <= tol
+    gradient steps (bm_phase), the PG step warm-started from orth(J [W~_t, xi_t])
+    with xi_t Gaussian (stream STREAM_SAFEGUARD + t), so the rank grows by at
+    most one per step (reading: far from the optimum nearly every eigenvalue of
+    the PG point is positive, and a block orth([U_t, W~_t]) doubles), and the
+    rank update k = number of positive Ritz values.  Stop when ||X~ - X+||_F / (1 + ||X~||_F + ||grad f~(X~)||_F) <= tol
     (the tolerance of the subspace iteration tightens with that residual)."""
     n = prob.n
     alpha = alpha_scale / lipschitz_bound(prob)
     Om = rng.normals(seed, rng.STREAM_SKETCH, n * k0).reshape(n, k0)
     e0 = eig_prox(prob, np.zeros((n, 0)), -prob.val, alpha, lam, Om, 1e-4, ssi_max_iter)
-    W, Ucur = e0.W, e0.U
+    W = e0.W
     hist: List[RkeRecord] = []
     res, res_prev, conv, t = np.inf, 1.0, False, 0
     F = objective(prob, W, lam)
@@ -232,11 +236,11 @@ def solve(prob, lam: float, k0: int = 8, tol: float = 1e-6, max_iter: int = 500,
         r = pair_residual(prob, W)
         tau = max(ssi_tol_floor, min(1e-4, 0.1 * res_prev * res_prev))
         xi = rng.normals(seed, rng.STREAM_SAFEGUARD + t, n)[:, None]
-        ep = eig_prox(prob, W, r, alpha, lam, np.column_stack([Ucur, W, xi]), tau, ssi_max_iter)
+        ep = eig_prox(prob, W, r, alpha, lam, np.column_stack([W, xi]), tau, ssi_max_iter)
         d = np.sqrt(core.diff_fro2_split(W, W, ep.W, ep.W)) if W.shape[1] else \
             np.sqrt(core.fro2_factored(ep.W, ep.W))
         res = d / (1.0 + np.sqrt(core.fro2_factored(W, W)) + grad_norm(prob, r, lam))
-        W, Ucur = ep.W, ep.U
+        W = ep.W
         F = objective(prob, W, lam)
         rec = RkeRecord(t, F, res, W.shape[1], ep.iters)
         hist.append(rec)

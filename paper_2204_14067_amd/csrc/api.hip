@@ -2301,9 +2301,13 @@ struct RkeMethod : Method<double> {
       lat::sym_eig(q, T.data(), th.data(), V.data());
       bool done = false;
       if (!prev.empty() && prev.size() == th.size()) {
+        // the Ritz values kept, the largest, and the first one not kept
+        int npos = 0;
+        while (npos < q && th[npos] > 0.0) ++npos;
         double dmax = 0.0;
         for (int j = 0; j < q; ++j)
-          if (j == 0 || th[j] > 0.0) dmax = std::max(dmax, fabs(th[j] - prev[j]));
+          if (j == 0 || th[j] > 0.0 || j == std::min(npos, q - 1))
+            dmax = std::max(dmax, fabs(th[j] - prev[j]));
         done = dmax <= tau * fabs(th[0]);
       }
       prev = th;
@@ -2348,16 +2352,16 @@ struct RkeMethod : Method<double> {
     for (int64_t i = 0; i < n; ++i) maxdeg = std::max(maxdeg, ptr[i + 1] - ptr[i]);
     const double alpha = o.alpha / (2.0 + 2.0 * (double)maxdeg);
     const double lam = o.lambda;
-    double *W = blk(P->L.b_W), *Wn = blk(P->L.b_Wn), *Uc = blk(P->L.b_Ucur), *Ut = blk(P->L.b_Uprev);
+    double *W = blk(P->L.b_W), *Wn = blk(P->L.b_Wn), *Uc = blk(P->L.b_Ucur);
     double *B1 = blk(P->L.b_B1);
-    int k = 0, kc = 0, ssi_total = 0;
+    int k = 0, ssi_total = 0;
     // X_{-1} = 0: r = -d^2; the start block J times Gaussian (n x k0)
     const int k0 = std::max(1, std::min(o.k_init, qld));
     residual(W, 0);
     HIPC(launch_normals<double>(o.seed, STREAM_SKETCH, n, k0, qld, B1, s));
     Eig e0 = eig_prox(W, 0, alpha, lam, B1, k0, 1e-4, o.ssi_max_iter, Wn, Uc);
     ssi_total += e0.iters;
-    k = kc = e0.k;
+    k = e0.k;
     std::swap(W, Wn);
     double resid = INFINITY, res_prev = 1.0, F = 0.0;
     bool conv = false;
@@ -2366,13 +2370,10 @@ struct RkeMethod : Method<double> {
       if (k > 0 && o.bm_epochs > 0) bm_phase(W, k, lam, o.bm_epochs);
       const double r2 = residual(W, k);
       const double tau = std::max(o.ssi_tol_floor, std::min(1e-4, 0.1 * res_prev * res_prev));
-      // warm start [U_t, W~_t, xi_t]
-      const int q0 = std::min(qld, kc + k + 1);
-      REQUIRE(kc + k + 1 <= qld, BMG_ENOMEM, "subspace block exceeds 2 k_cap + 2 columns");
-      HIPC(launch_copy_cols<double>(n, kc, Uc, ldk, B1, qld, s));
-      HIPC(launch_copy_cols<double>(n, k, W, ldk, B1 + kc, qld, s));
-      HIPC(launch_normals<double>(o.seed, STREAM_SAFEGUARD + (uint64_t)t, n, 1, qld, B1 + kc + k, s));
-      std::swap(Uc, Ut);
+      // warm start [W~_t, xi_t]: the rank grows by at most one per step
+      const int q0 = k + 1;
+      HIPC(launch_copy_cols<double>(n, k, W, ldk, B1, qld, s));
+      HIPC(launch_normals<double>(o.seed, STREAM_SAFEGUARD + (uint64_t)t, n, 1, qld, B1 + k, s));
       Eig ep = eig_prox(W, k, alpha, lam, B1, q0, tau, o.ssi_max_iter, Wn, Uc);
       ssi_total += ep.iters;
       // relative residual ||X~ - X+|| / (1 + ||X~|| + ||grad f~(X~)||)
@@ -2388,7 +2389,7 @@ struct RkeMethod : Method<double> {
                                                   return M::trace_prod(g, g, ep.k); }() : 0.0);
       resid = sqrt(std::max(d2, 0.0)) / (1.0 + sqrt(std::max(x2, 0.0)) + sqrt(g2));
       std::swap(W, Wn);
-      k = kc = ep.k;
+      k = ep.k;
       F = 0.25 * residual(W, k) + lam * (k > 0 ? fro2(n, W, ldk, k) : 0.0);
       REQUIRE(std::isfinite(F) && std::isfinite(resid), BMG_ENONFINITE, "non-finite objective");
       if (o.verbose)
