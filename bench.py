@@ -178,6 +178,7 @@ def main():
         if args.precision == "fp64":
             out["polymf_bm"] = polymf_bm(bmg, synth, dev, prob, p, out["time_to_tol"]["fp64"],
                                          out["time_to_tol_gpu_bound"]["lambda_100"]["fp64"])
+        out["rke_qsdp"] = rke_qsdp(bmg, synth, dev)
         out["serve"] = serving(bmg, synth, dev, args.serve_count)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -329,6 +330,32 @@ def polymf_bm(bmg, synth, dev, prob, p, fixed_small, fixed_quarter):
         log("polymf %s: median %.3fs (psd %.3fs), iters %s (psd %s)" % (
             name, rec["seconds_median"], fixed["seconds_median"], iters, fixed["iters"]))
         del pq
+    return out
+
+
+def rke_qsdp(bmg, synth, dev):
+    """BM-Global on the kernel-estimation QSDP (bmg_rke_solve, FP64) to relative
+    residual 1e-6: synthetic objects in R^3 with about 40 random partners each
+    and noisy squared distances (stored symmetrically), two sizes, two
+    algorithm seeds each."""
+    out = {}
+    for n, lam in ((20_000, 10.0), (100_000, 20.0)):
+        p = synth.rke(n, 40, lam=lam, seed=7)
+        dp = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, device=dev)
+        dp.bmg_rke_solve(lam=lam, k_init=8, tol=1e-6, seed=1, max_iter=2, bm_epochs=10)
+        secs, iters, ranks, Fs = [], [], [], []
+        for sd in (1, 2):
+            t0 = time.perf_counter()
+            W, k, r = dp.bmg_rke_solve(lam=lam, k_init=8, tol=1e-6, seed=sd, max_iter=3000, bm_epochs=10)
+            secs.append(time.perf_counter() - t0)
+            iters.append(r["iters"]); ranks.append(k); Fs.append(r["F"])
+            assert r["status"] == 0
+        out["n%d_pairs%d" % (n, p.nnz // 2)] = {"lambda": lam, "seconds": [round(x, 3) for x in secs],
+                                                 "iters": iters, "rank": ranks, "F": Fs,
+                                                 "rel_F_spread": (max(Fs) - min(Fs)) / abs(max(Fs))}
+        log("rke n=%d (%d pairs): %s s, iters %s, rank %s" % (n, p.nnz // 2, ["%.2f" % x for x in secs],
+                                                              iters, ranks))
+        del dp
     return out
 
 
