@@ -335,18 +335,18 @@ def polymf_bm(bmg, synth, dev, prob, p, fixed_small, fixed_quarter):
 
 def rke_qsdp(bmg, synth, dev):
     """BM-Global on the kernel-estimation QSDP (bmg_rke_solve, FP64) to relative
-    residual 1e-6: synthetic objects in R^3 with about 40 random partners each
-    and noisy squared distances (stored symmetrically), two sizes, two
-    algorithm seeds each."""
+    prox-gradient residual 1e-4: synthetic objects in R^3 with about 40 random
+    partners each and noisy squared distances (stored symmetrically), two
+    sizes, two algorithm seeds each."""
     out = {}
     for n, lam in ((20_000, 10.0), (100_000, 20.0)):
         p = synth.rke(n, 40, lam=lam, seed=7)
         dp = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, device=dev)
-        dp.bmg_rke_solve(lam=lam, k_init=8, tol=1e-6, seed=1, max_iter=2, bm_epochs=10)
+        dp.bmg_rke_solve(lam=lam, k_init=8, tol=1e-4, seed=1, max_iter=2, bm_epochs=10)
         secs, iters, ranks, Fs = [], [], [], []
         for sd in (1, 2):
             t0 = time.perf_counter()
-            W, k, r = dp.bmg_rke_solve(lam=lam, k_init=8, tol=1e-6, seed=sd, max_iter=3000, bm_epochs=10)
+            W, k, r = dp.bmg_rke_solve(lam=lam, k_init=8, tol=1e-4, seed=sd, max_iter=3000, bm_epochs=10)
             secs.append(time.perf_counter() - t0)
             iters.append(r["iters"]); ranks.append(k); Fs.append(r["F"])
             assert r["status"] == 0

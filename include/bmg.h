@@ -219,7 +219,7 @@ bmg_status bmg_rke_residual(bmg_problem *p, const double *W, int k, int ld, doub
  * ||A^* A||), whose prox P_S+(J Z J) (Lemma PiX) comes from block subspace
  * iteration on the shifted operator started from [W, one Gaussian column]; the
  * positive Ritz pairs give the new W and rank (so the rank grows by at most one
- * per step).  Stops when ||X~ - X+||_F / (1 + ||X~||_F + ||grad f~||_F) <= opt->tol.
+ * per step).  Stops when ||X~ - X+||_F / (alpha (1 + ||X~||_F + ||grad f~||_F)) <= opt->tol.
  * Uses opt->lambda, alpha, tol, bm_epochs, max_iter, ssi_max_iter, ssi_tol_floor,
  * k_init, seed, verbose.  W (device, n x ld) output, *k_out its rank; res (host)
  * fills k, iters, ssi_iters, status, F, residual, seconds, sparse bytes/passes. */

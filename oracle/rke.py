@@ -220,8 +220,10 @@ def solve(prob, lam: float, k0: int = 8, tol: float = 1e-6, max_iter: int = 500,
     with xi_t Gaussian (stream STREAM_SAFEGUARD + t), so the rank grows by at
     most one per step (reading: far from the optimum nearly every eigenvalue of
     the PG point is positive, and a block orth([U_t, W~_t]) doubles), and the
-    rank update k = number of positive Ritz values.  Stop when ||X~ - X+||_F / (1 + ||X~||_F + ||grad f~(X~)||_F) <= tol
-    (the tolerance of the subspace iteration tightens with that residual)."""
+    rank update k = number of positive Ritz values.  Stop when
+    ||X~ - X+||_F / (alpha (1 + ||X~||_F + ||grad f~(X~)||_F)) <= tol: the
+    prox-gradient mapping, as alpha is far below 1 here (the tolerance of the
+    subspace iteration tightens with that residual)."""
     n = prob.n
     alpha = alpha_scale / lipschitz_bound(prob)
     Om = rng.normals(seed, rng.STREAM_SKETCH, n * k0).reshape(n, k0)
@@ -239,7 +241,7 @@ def solve(prob, lam: float, k0: int = 8, tol: float = 1e-6, max_iter: int = 500,
         ep = eig_prox(prob, W, r, alpha, lam, np.column_stack([W, xi]), tau, ssi_max_iter)
         d = np.sqrt(core.diff_fro2_split(W, W, ep.W, ep.W)) if W.shape[1] else \
             np.sqrt(core.fro2_factored(ep.W, ep.W))
-        res = d / (1.0 + np.sqrt(core.fro2_factored(W, W)) + grad_norm(prob, r, lam))
+        res = d / (alpha * (1.0 + np.sqrt(core.fro2_factored(W, W)) + grad_norm(prob, r, lam)))
         W = ep.W
         F = objective(prob, W, lam)
         rec = RkeRecord(t, F, res, W.shape[1], ep.iters)

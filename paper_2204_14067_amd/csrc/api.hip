@@ -2387,7 +2387,8 @@ struct RkeMethod : Method<double> {
       const double d2 = k > 0 ? diff2(W, k, Wn, ep.k)
                               : (ep.k > 0 ? [&] { auto g = gram(n, ep.k, Wn, ldk, ep.k, Wn, ldk);
                                                   return M::trace_prod(g, g, ep.k); }() : 0.0);
-      resid = sqrt(std::max(d2, 0.0)) / (1.0 + sqrt(std::max(x2, 0.0)) + sqrt(g2));
+      // the prox-gradient mapping (divided by alpha, which is far below 1 here)
+      resid = sqrt(std::max(d2, 0.0)) / (alpha * (1.0 + sqrt(std::max(x2, 0.0)) + sqrt(g2)));
       std::swap(W, Wn);
       k = ep.k;
       F = 0.25 * residual(W, k) + lam * (k > 0 ? fro2(n, W, ldk, k) : 0.0);

@@ -44,9 +44,9 @@ def test_rke_residual_parity(n, deg, k):
 @pytest.mark.parametrize("n,deg,lam", [(50, 30, 2.0), (100, 30, 1.5)])
 def test_rke_solve_parity(n, deg, lam):
     p = synth.rke(n, deg, lam=lam, seed=3)
-    orc = rke.solve(p, lam, k0=6, tol=1e-9, seed=1, max_iter=1000)
+    orc = rke.solve(p, lam, k0=6, tol=1e-8, seed=1, max_iter=1000)
     dp = to_dev(p, k_cap=64)
-    W, k, r = dp.bmg_rke_solve(lam=lam, k_init=6, tol=1e-9, seed=1, max_iter=1000, bm_epochs=10)
+    W, k, r = dp.bmg_rke_solve(lam=lam, k_init=6, tol=1e-8, seed=1, max_iter=1000, bm_epochs=10)
     print("rke solve", n, r["iters"], orc.iters, r["F"], orc.F, k, orc.k, flush=True)
     assert r["status"] == 0 and orc.converged
     assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
