@@ -87,3 +87,32 @@ def test_serving_mixed_precisions_equal_plain_solves():
         assert info["k"] == k and info["result"]["F"] == F
         assert np.array_equal(W[:, :k], W0)
     srv.close()
+
+
+def test_serving_solver_variants_equal_plain_solves():
+    """Requests with the polyMF-SS BM solver, the SpaRSA step rule and LmSVD
+    history in one FP64 server beside default requests (lambda lowered so that
+    every solution has positive rank): every result is bit for bit the plain
+    entry point's with the same options."""
+    items = small_requests(4)
+    variants = [dict(bm_solver="polymf"), dict(step_rule="sparsa"), dict(lmsvd_p=1), {}]
+    base = dict(tol=1e-6, k_init=8, max_iter=2000, seed=13)
+    plain = []
+    for (r, p), v in zip(items, variants):
+        dp = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp64",
+                                   device=DEV)
+        W, H, k, res = dp.bmg_solve(lam=0.3 * r.lam, **base, **v)
+        plain.append((k, res["F"], res["status"], W.cpu().numpy()[:, :k].copy()))
+        print("plain", v, p.name, k, res["F"], res["iters"], flush=True)
+    srv = bmg.Server(sum(bmg.Server.footprint(p.m, p.n, p.nnz, 64, "fp64") for _, p in items) + (1 << 20),
+                     max_slots=4, device=DEV)
+    tickets = [srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp64", lam=0.3 * r.lam,
+                          **base, **v) for (r, p), v in zip(items, variants)]
+    srv.drain()
+    for (r, p), v, t, (k, F, status, W0) in zip(items, variants, tickets, plain):
+        info, W, H = srv.poll(t, p.m, p.n, 64)
+        print("served", v, p.name, info["k"], info["result"]["F"], F, flush=True)
+        assert info["state"] == 2 and info["status"] == status
+        assert info["k"] == k and info["result"]["F"] == F
+        assert np.array_equal(W[:, :k], W0)
+    srv.close()
