@@ -2124,13 +2124,26 @@ struct RkeMethod : Method<double> {
 
   // r (stored, CSR order) = ||w_i - w_j||^2 - d_ij^2, deg / adeg per row;
   // returns sum over stored entries of r^2
-  double residual(const double *W, int k) {
+  double residual(const double *W, int k, bool fetch_sum = true) {
     HIPC(launch_rke_res(R->pl, W, ldk, k, (const double *)R->a64, (double *)R->r, deg, adeg,
                         (double *)P->partial, P->wsum, 2 * P->L.wsum_cap, P->result, s));
     E::count(R->pl, 4.0 + 16.0, (double)n * k * 8.0);
+    if (!fetch_sum) return 0.0;
     double h[1];
     E::fetch(h, P->result, 1);
     return h[0];
+  }
+  // Frobenius inner products of up to four pairs of n x k blocks (ld ldk) into
+  // P->result + off (device; fetched by the caller)
+  void dots(std::initializer_list<std::pair<const double *, const double *>> pr, int k, int off) {
+    const double *A[4], *B[4];
+    int np = 0;
+    for (auto &q : pr) {
+      A[np] = q.first;
+      B[np] = q.second;
+      ++np;
+    }
+    HIPC(launch_frob_dots(n, k, ldk, A, B, np, P->wpart, P->result + off, s));
   }
   // out (ld ldo) = L_r U: the sparse x dense pass with the stored r, then deg U - (.)
   void lap(const double *U, int q, int ldu, double *out, int ldo) {
@@ -2160,22 +2173,36 @@ struct RkeMethod : Method<double> {
     return t;
   }
   // BM phase: `steps` nonlinear CG steps (Polak-Ribiere, restart at negative
-  // beta or a non-descent direction) with the exact quartic line search.
+  // beta or a non-descent direction) with the exact quartic line search.  Two
+  // host round trips per step: <G, G>, <G, G_prev>, <D_prev, G> (for beta and
+  // the descent test), then the quartic sums with <W, D>, <D, D>.
   void bm_phase(double *W, int k, double lam, int steps) {
     double *G = blk(P->L.b_G), *D = blk(P->L.b_D), *Gp = blk(P->L.b_H);
     double gp2 = 0.0;
     for (int st = 0; st < steps; ++st) {
-      residual(W, k);
+      residual(W, k, false);
       lap(W, k, ldk, G, ldk);
       HIPC(launch_axpy<double>(n, k, lam, W, ldk, G, ldk, s));
       HIPC(launch_center_cols(n, k, G, ldk, s));
-      const double g2 = dot(G, G, k);
+      double h1[3] = {0.0, 0.0, 0.0};
+      if (st == 0) {
+        dots({{G, G}}, k, 0);
+        E::fetch(h1, P->result, 1);
+      } else {
+        dots({{G, G}, {G, Gp}, {D, G}}, k, 0);
+        E::fetch(h1, P->result, 3);
+      }
+      const double g2 = h1[0];
       bool sd = st == 0;
       if (!sd) {
-        const double beta = std::max(0.0, (g2 - dot(G, Gp, k)) / gp2);
-        HIPC(launch_axpy<double>(n, k, beta - 1.0, D, ldk, D, ldk, s));   // D = beta D
-        HIPC(launch_axpy<double>(n, k, -1.0, G, ldk, D, ldk, s));          // D -= G
-        if (dot(D, G, k) >= 0.0) sd = true;
+        const double beta = std::max(0.0, (g2 - h1[1]) / gp2);
+        // <beta D_prev - G, G> >= 0: not a descent direction, restart
+        if (beta * h1[2] - g2 >= 0.0) {
+          sd = true;
+        } else {
+          HIPC(launch_axpy<double>(n, k, beta - 1.0, D, ldk, D, ldk, s));   // D = beta D
+          HIPC(launch_axpy<double>(n, k, -1.0, G, ldk, D, ldk, s));          // D -= G
+        }
       }
       if (sd) {
         HIPC(launch_fill<double>(D, n, k, ldk, 0.0, s));
@@ -2184,10 +2211,11 @@ struct RkeMethod : Method<double> {
       HIPC(launch_rke_quartic(R->pl, W, D, ldk, k, (const double *)R->r, P->wsum, 2 * P->L.wsum_cap,
                               P->result, s));
       E::count(R->pl, 4.0 + 8.0, (double)n * k * 16.0);
-      double h[5];
-      E::fetch(h, P->result, 5);
-      const double c1 = h[0] + 2.0 * lam * dot(W, D, k);
-      const double c2 = h[1] + 0.5 * h[2] + lam * dot(D, D, k);
+      dots({{W, D}, {D, D}}, k, 8);
+      double h[10];
+      E::fetch(h, P->result, 10);
+      const double c1 = h[0] + 2.0 * lam * h[8];
+      const double c2 = h[1] + 0.5 * h[2] + lam * h[9];
       const double c3 = h[3], c4 = 0.25 * h[4];
       REQUIRE(std::isfinite(c1) && std::isfinite(c2) && std::isfinite(c3) && std::isfinite(c4),
               BMG_ENONFINITE, "non-finite line search");

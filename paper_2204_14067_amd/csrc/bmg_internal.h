@@ -201,6 +201,9 @@ hipError_t launch_rke_res(const Plan &pl, const double *W, int ld, int k, const 
 hipError_t launch_rke_quartic(const Plan &pl, const double *W, const double *D, int ld, int k,
                               const double *r, double *bpart, int64_t bpart_cap, double *out,
                               hipStream_t s);
+// out[j] = <A[j], B[j]> (Frobenius) for j < np <= 4, n x k at ld; bpart: 512 doubles
+hipError_t launch_frob_dots(int64_t n, int k, int ld, const double *const *A, const double *const *B, int np,
+                            double *bpart, double *out, hipStream_t s);
 // Out = deg U - Out (row scaling)
 hipError_t launch_rowscale_sub(int64_t n, int q, const double *deg, const double *U, int ldu, double *Out,
                                int ldo, hipStream_t s);

@@ -169,6 +169,35 @@ __global__ __launch_bounds__(256) void k_center_cols(int64_t n, double *__restri
   for (int64_t i = threadIdx.x; i < n; i += 256) V[i * ld + c] -= mean;
 }
 
+// Frobenius inner products <A_j, B_j> of np pairs of n x k matrices (ld):
+// per block partial sums (block b covers rows b, b + grid, ...), fixed order.
+struct DotPairs {
+  const double *A[4];
+  const double *B[4];
+};
+__global__ __launch_bounds__(256) void k_frob_dots(int64_t n, int k, int ld, DotPairs dp, int np,
+                                                   double *__restrict__ bpart) {
+  __shared__ double sm[4][4];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t tot = n * (int64_t)k, stride = (int64_t)gridDim.x * 256;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < tot; t += stride) {
+    const int64_t i = t / k, c = t % k, o = i * ld + c;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < np) v[j] += dp.A[j][o] * dp.B[j][o];
+  }
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double t = wave_sum64(v[j]);
+    if (lane == 0) sm[wv][j] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < np)
+    bpart[(int64_t)blockIdx.x * np + threadIdx.x] =
+        sm[0][threadIdx.x] + sm[1][threadIdx.x] + sm[2][threadIdx.x] + sm[3][threadIdx.x];
+}
+
 // flag = 1 when the two orientations differ (the pattern or values are not symmetric)
 __global__ void k_cmp_orient(int64_t nnz, const int32_t *__restrict__ a, const int32_t *__restrict__ b,
                              const double *__restrict__ va, const double *__restrict__ vb,
@@ -205,6 +234,20 @@ hipError_t launch_rke_quartic(const Plan &pl, const double *W, const double *D, 
     hipLaunchKernelGGL(k_rke_quartic, dim3((unsigned)nb), dim3(64 * RK_WAVES), 0, s, pl, W, D, ld, k, r,
                        bpart);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const double *)bpart, nb, 5, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_frob_dots(int64_t n, int k, int ld, const double *const *A, const double *const *B, int np,
+                            double *bpart, double *out, hipStream_t s) {
+  constexpr int NB = 128;
+  if (np < 1 || np > 4) return hipErrorInvalidValue;
+  DotPairs dp{};
+  for (int j = 0; j < np; ++j) {
+    dp.A[j] = A[j];
+    dp.B[j] = B[j];
+  }
+  hipLaunchKernelGGL(k_frob_dots, dim3(NB), dim3(256), 0, s, n, k, ld, dp, np, bpart);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const double *)bpart, (int64_t)NB, np, out);
   return hipGetLastError();
 }
 
