@@ -2183,7 +2183,7 @@ struct RkeMethod : Method<double> {
       residual(W, k, false);
       lap(W, k, ldk, G, ldk);
       HIPC(launch_axpy<double>(n, k, lam, W, ldk, G, ldk, s));
-      HIPC(launch_center_cols(n, k, G, ldk, s));
+      HIPC(launch_center_cols(n, k, G, ldk, P->gram_part, P->L.gram_cap, s));
       double h1[3] = {0.0, 0.0, 0.0};
       if (st == 0) {
         dots({{G, G}}, k, 0);
@@ -2317,7 +2317,7 @@ struct RkeMethod : Method<double> {
     double amax = 0.0;
     for (double v : ad) amax = std::max(amax, v);
     const double sigma = alpha * (2.0 * amax + lam);
-    HIPC(launch_center_cols(n, q0, U0, qld, s));
+    HIPC(launch_center_cols(n, q0, U0, qld, P->gram_part, P->L.gram_cap, s));
     int q = orth(n, U0, q0, U, B4);
     std::vector<double> prev, th, V;
     int it = 0;
@@ -2345,7 +2345,7 @@ struct RkeMethod : Method<double> {
       for (double &v : sV) v *= sigma;
       gemm(n, q, Y, qld, q, V, B3, qld, 0.0);
       gemm(n, q, U, qld, q, sV, B3, qld, 1.0);
-      HIPC(launch_center_cols(n, q, B3, qld, s));
+      HIPC(launch_center_cols(n, q, B3, qld, P->gram_part, P->L.gram_cap, s));
       q = orth(n, B3, q, U, B4);
       prev.clear();
       prev = th;

@@ -207,8 +207,9 @@ hipError_t launch_frob_dots(int64_t n, int k, int ld, const double *const *A, co
 // Out = deg U - Out (row scaling)
 hipError_t launch_rowscale_sub(int64_t n, int q, const double *deg, const double *U, int ldu, double *Out,
                                int ldo, hipStream_t s);
-// V = J V: subtract each column's mean
-hipError_t launch_center_cols(int64_t n, int q, double *V, int ld, hipStream_t s);
+// V = J V: subtract each column's mean (part: 64 q doubles of scratch)
+hipError_t launch_center_cols(int64_t n, int q, double *V, int ld, double *part, int64_t part_cap,
+                              hipStream_t s);
 // flag[0] = 1 where the two orientations' indices or values differ
 hipError_t launch_cmp_orient(int64_t nnz, const int32_t *a, const int32_t *b, const double *va,
                              const double *vb, int *flag, hipStream_t s);

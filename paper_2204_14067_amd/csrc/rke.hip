@@ -154,19 +154,40 @@ __global__ void k_rowscale_sub(int64_t n, int q, const double *__restrict__ deg,
   Out[i * ldo + c] = deg[i] * U[i * ldu + c] - Out[i * ldo + c];
 }
 
-// V[:, c] -= mean(V[:, c]); one block per column, fixed-order sum.
-__global__ __launch_bounds__(256) void k_center_cols(int64_t n, double *__restrict__ V, int ld) {
-  __shared__ double sm[4];
-  __shared__ double mean;
-  const int c = blockIdx.x;
+// Column means in two steps, fixed order: block b sums rows [b R, (b + 1) R)
+// of every column (consecutive threads read consecutive columns), then each
+// element subtracts its column's mean, summed from the NB partials in order.
+constexpr int CC_BLOCKS = 64;
+// grid (CC_BLOCKS, ceil(q / 64)): a block covers one row chunk and up to 64
+// columns; its 256 threads split the chunk's rows nr ways per column and
+// combine the nr sums in order through LDS.
+__global__ __launch_bounds__(256) void k_colsum_part(int64_t n, int q, const double *__restrict__ V, int ld,
+                                                     double *__restrict__ part) {
+  __shared__ double sm[256];
+  const int64_t R = (n + CC_BLOCKS - 1) / CC_BLOCKS;
+  const int64_t i0 = (int64_t)blockIdx.x * R, i1 = i0 + R < n ? i0 + R : n;
+  const int c0 = blockIdx.y * 64, qt = q - c0 < 64 ? q - c0 : 64, nr = 256 / qt;
+  const int r = threadIdx.x / qt, cc = threadIdx.x % qt;
   double v = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) v += V[i * ld + c];
-  v = wave_sum64(v);
-  if (threadIdx.x % 64 == 0) sm[threadIdx.x / 64] = v;
+  if (r < nr)
+    for (int64_t i = i0 + r; i < i1; i += nr) v += V[i * ld + c0 + cc];
+  sm[threadIdx.x] = v;
   __syncthreads();
-  if (threadIdx.x == 0) mean = (sm[0] + sm[1] + sm[2] + sm[3]) / (double)n;
-  __syncthreads();
-  for (int64_t i = threadIdx.x; i < n; i += 256) V[i * ld + c] -= mean;
+  if (threadIdx.x < qt) {
+    double t = 0.0;
+    for (int rr = 0; rr < nr; ++rr) t += sm[rr * qt + threadIdx.x];
+    part[(int64_t)blockIdx.x * q + c0 + threadIdx.x] = t;
+  }
+}
+__global__ void k_colmean_sub(int64_t n, int q, double *__restrict__ V, int ld,
+                              const double *__restrict__ part) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * q) return;
+  const int64_t i = t / q;
+  const int c = (int)(t % q);
+  double sum = 0.0;
+  for (int b = 0; b < CC_BLOCKS; ++b) sum += part[(int64_t)b * q + c];
+  V[i * ld + c] -= sum / (double)n;
 }
 
 // Frobenius inner products <A_j, B_j> of np pairs of n x k matrices (ld):
@@ -260,8 +281,15 @@ hipError_t launch_rowscale_sub(int64_t n, int q, const double *deg, const double
   return hipGetLastError();
 }
 
-hipError_t launch_center_cols(int64_t n, int q, double *V, int ld, hipStream_t s) {
-  if (n > 0 && q > 0) hipLaunchKernelGGL(k_center_cols, dim3((unsigned)q), dim3(256), 0, s, n, V, ld);
+hipError_t launch_center_cols(int64_t n, int q, double *V, int ld, double *part, int64_t part_cap,
+                              hipStream_t s) {
+  if (n <= 0 || q <= 0) return hipSuccess;
+  if ((int64_t)CC_BLOCKS * q > part_cap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_colsum_part, dim3(CC_BLOCKS, (unsigned)((q + 63) / 64)), dim3(256), 0, s, n, q,
+                     (const double *)V, ld, part);
+  const int64_t tot = n * (int64_t)q;
+  hipLaunchKernelGGL(k_colmean_sub, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, q, V, ld,
+                     (const double *)part);
   return hipGetLastError();
 }
 
