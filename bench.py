@@ -407,7 +407,7 @@ def time_to_tol_gpu_bound(bmg, synth, dev, lams=(300.0, 100.0), seeds=(3, 4, 5))
     compared with the FP64 solution of the same seed."""
     import numpy as np
     p = synth.netflix_shape(scale=0.25)
-    judge = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=128, precision="fp64",
+    evaluator = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=128, precision="fp64",
                                   device=dev)
     out = {"workload": "netflix_shape x0.25: %dx%d nnz=%d, k0=16, tol 1e-4" % (p.m, p.n, p.nnz)}
     for lam in lams:
@@ -422,7 +422,7 @@ def time_to_tol_gpu_bound(bmg, synth, dev, lams=(300.0, 100.0), seeds=(3, 4, 5))
                 t0 = time.perf_counter()
                 W, H, k, r = prob.bmg_solve(lam=lam, k_init=16, tol=1e-4, seed=sd, max_iter=400)
                 secs.append(time.perf_counter() - t0)
-                F = judge.bmg_objective(W, H, k, lam)
+                F = evaluator.bmg_objective(W, H, k, lam)
                 if prec == "fp64":
                     ref[sd] = F
                 errs.append(abs(F - ref[sd]) / abs(ref[sd]))
@@ -530,7 +530,7 @@ def time_to_tol(bmg, synth, dev, seeds=(11, 12, 13, 14, 15)):
     out = {"workload": "small_uniform 1000x1500 nnz=50000 lambda=0.5 k0=8", "tol": 1e-6,
            "seeds": list(seeds)}
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", "small_uniform.json")))
-    judge = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=256, precision="fp64",
+    evaluator = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=256, precision="fp64",
                                   device=dev)
     for prec in ("fp64", "fp32", "bf16"):
         # intermediate prox outputs can reach rank ~130 on the way to the rank-91 optimum
@@ -542,7 +542,7 @@ def time_to_tol(bmg, synth, dev, seeds=(11, 12, 13, 14, 15)):
             t0 = time.perf_counter()
             W, H, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=sd, max_iter=1000)
             secs.append(time.perf_counter() - t0)
-            F64 = judge.bmg_objective(W, H, k, p.lam)
+            F64 = evaluator.bmg_objective(W, H, k, p.lam)
             errs.append((F64 - golden["F"]) / golden["F"])
             iters.append(r["iters"]); ranks.append(k); conv.append(r["status"] == 0)
         q1, med, q3 = (float(v) for v in np.percentile(secs, [25, 50, 75]))
