@@ -39,16 +39,17 @@ static inline double dot(const double *a, const double *b, int n) {
 
 void sym_eig(int n, const double *A0, double *w, double *Vout) {
   if (n <= 0) return;
-  std::vector<double> A(A0, A0 + (size_t)n * n);
-  for (int i = 0; i < n; ++i)  // symmetrise against rounding in the input
-    for (int j = i + 1; j < n; ++j) {
-      const double s = 0.5 * (at(A, n, i, j) + at(A, n, j, i));
-      at(A, n, i, j) = at(A, n, j, i) = s;
-    }
+  // Only the lower triangle is kept and updated (j <= i); it starts as the
+  // mean of A0 and A0^T against rounding asymmetry in the input.
+  std::vector<double> A((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) at(A, n, i, j) = 0.5 * (A0[(size_t)i * n + j] + A0[(size_t)j * n + i]);
   const bool vec = Vout != nullptr;
   // --- Householder tridiagonalisation.  Step k reflects rows/columns k+1..n-1
   // with H = I - tau v v^T; the trailing block gets the symmetric rank-2 update
   // A22 <- A22 - v w^T - w v^T,  w = p - (tau/2)(p^T v) v,  p = tau A22 v.
+  // p is formed from the lower triangle row by row: row i contributes its
+  // dot product with v to p_i and its entries times v_i to p_j, j < i.
   std::vector<double> vs((size_t)n * n, 0.0), taus(n, 0.0), p(n), wv(n);
   std::vector<double> d(n), e(n, 0.0);
   for (int k = 0; k + 2 < n; ++k) {
@@ -66,20 +67,27 @@ void sym_eig(int n, const double *A0, double *w, double *Vout) {
     if (vv == 0.0) continue;
     const double tau = 2.0 / vv;
     taus[k] = tau;
-    for (int i = k + 1; i < n; ++i) p[i] = tau * dot(&A[(size_t)i * n + k + 1], v + k + 1, n - k - 1);
+    for (int i = k + 1; i < n; ++i) p[i] = 0.0;
+    for (int i = k + 1; i < n; ++i) {
+      const double *row = &A[(size_t)i * n];
+      const double vi = v[i];
+      p[i] += dot(row + k + 1, v + k + 1, i - k - 1) + row[i] * vi;
+      for (int j = k + 1; j < i; ++j) p[j] += row[j] * vi;
+    }
+    for (int i = k + 1; i < n; ++i) p[i] *= tau;
     double pv = 0.0;
     for (int i = k + 1; i < n; ++i) pv += p[i] * v[i];
     for (int i = k + 1; i < n; ++i) wv[i] = p[i] - 0.5 * tau * pv * v[i];
     for (int i = k + 1; i < n; ++i) {
       double *row = &A[(size_t)i * n];
       const double vi = v[i], wi = wv[i];
-      for (int j = k + 1; j < n; ++j) row[j] -= vi * wv[j] + wi * v[j];
+      for (int j = k + 1; j <= i; ++j) row[j] -= vi * wv[j] + wi * v[j];
     }
-    at(A, n, k + 1, k) = at(A, n, k, k + 1) = alpha;
-    for (int i = k + 2; i < n; ++i) at(A, n, i, k) = at(A, n, k, i) = 0.0;
+    at(A, n, k + 1, k) = alpha;
+    for (int i = k + 2; i < n; ++i) at(A, n, i, k) = 0.0;
   }
   for (int i = 0; i < n; ++i) d[i] = at(A, n, i, i);
-  for (int i = 0; i + 1 < n; ++i) e[i] = at(A, n, i, i + 1);
+  for (int i = 0; i + 1 < n; ++i) e[i] = at(A, n, i + 1, i);
   // Z = Q^T with Q = H_0 H_1 ... H_{n-3}, accumulated backwards on rows
   std::vector<double> Z;
   if (vec) {
