@@ -2369,7 +2369,9 @@ struct RkeMethod : Method<double> {
     return out;
   }
 
-  // Algorithm 1 on the QSDP (the readings of the oracle's rke.solve)
+  // Algorithm 1 on the QSDP: BM phase, then the PG step of Lemma PiX with
+  // step alpha / (2 + 2 max degree), warm-started from [W~, xi]; the stop
+  // residual is the PG step's change divided by the step size
   bmg_status solve(const bmg_options &o, int *k_out, bmg_result *res) {
     const auto t0 = std::chrono::steady_clock::now();
     P->reset_stats();
