@@ -89,6 +89,8 @@ def main():
                     help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
     ap.add_argument("--qsdp-only", action="store_true",
                     help="only run one kernel-estimation QSDP solve (20,000 objects, tol 1e-4)")
+    ap.add_argument("--small-solve-only", action="store_true",
+                    help="only run one FP64 solve of the 1000 x 1500 workload to tol 1e-6 (seed 11)")
     ap.add_argument("--serve-count", type=int, default=256,
                     help="requests replayed by the serving measurement (256 in the full stream)")
     args = ap.parse_args()
@@ -110,6 +112,16 @@ def main():
         _, k, r = dq.bmg_rke_solve(lam=10.0, k_init=8, tol=1e-4, seed=1, max_iter=3000, bm_epochs=10)
         print(json.dumps({"qsdp_objects": q.n, "pairs": q.nnz // 2, "seconds": time.perf_counter() - t0,
                           "iters": r["iters"], "ssi_iters": r["ssi_iters"], "rank": k, "F": r["F"]}))
+        return
+    if args.small_solve_only:
+        p = synth.small_uniform()
+        prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=256, precision="fp64",
+                                     device=dev)
+        t0 = time.perf_counter()
+        _, _, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=11, max_iter=1000)
+        print(json.dumps({"workload": "small_uniform 1000x1500 nnz=50000 lambda=0.5",
+                          "seconds": time.perf_counter() - t0, "iters": r["iters"], "rank": k,
+                          "F": r["F"], "status": r["status"]}))
         return
     if args.calibrate_copy:
         x = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB

@@ -1272,9 +1272,11 @@ struct Method : Engine<T, TG> {
     int it = 0;
     for (it = 1; it <= max_iter && q > 0; ++it) {
       std::vector<double> Tm = gram(n, q, Y, qld, q, Y, qld);
+      // L(U) = Z Z^T U (Ritz rotation omitted: same range); queued before the
+      // host computes the Ritz values, so the two overlap
+      z_n(z, Y, q, V);
       std::vector<double> theta(q);
       lat::sym_eig(q, Tm.data(), theta.data(), nullptr);
-      z_n(z, Y, q, V);                 // L(U) = Z Z^T U (Ritz rotation omitted: same range)
       q = orth(m, V, q, U, tmp);       // U^{t,i+1}
       z_t(z, U, q, Y);
       if (ritz_converged(theta, prev, tau, keep_level)) break;
