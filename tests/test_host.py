@@ -107,3 +107,12 @@ def test_serving_stream_shapes():
     assert all(b > a for a, b in zip(t, t[1:]))
     assert 1.0 < t[-1] < 8.0          # ~64 / 20 per second
     assert all(500 <= r.m <= 20000 and 1000 <= r.n <= 50000 and 3 <= r.rank <= 15 for r in reqs)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
