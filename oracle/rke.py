@@ -22,6 +22,10 @@ Function -> passage -> pin (tests/test_oracle_rke.py):
                              -> Dykstra's alternating projections
   eig_prox                   the PG step's eigen-decomposition by block
                              subspace iteration (reading)   -> dense eigh
+  grad_norm, stop_residual   ||grad f~||_F and the stop residual (prox-gradient
+                             mapping)  -> finite-difference gradient of the dense
+                             objective, projection in reduced coordinates
+  lipschitz_bound            step size bound on ||A^* A|| -> dense operator norm
   solve                      Algorithm 1 on this problem    -> dense proximal
                              gradient with the exact projection
 """
@@ -209,6 +213,21 @@ def grad_norm(prob, r, lam: float) -> float:
     return float(np.sqrt(np.sum((deg + lam) ** 2) + np.dot(r, r)))
 
 
+def stop_residual(prob, W, Wn, r, alpha: float, lam: float) -> float:
+    """Stop residual of the PG step from X~ = W W^T (residual r) to X+ = Wn Wn^T:
+        ||X~ - X+||_F / (alpha (1 + ||X~||_F + ||grad f~(X~)||_F)),
+    grad f~ = L_r + lam I (grad_norm).  ||X~ - X+|| / alpha is the norm of the
+    prox-gradient mapping at step alpha (the QSDP optimality measure of Sec. 6.2
+    uses the prox at unit step; alpha is far below 1 here, so the step itself
+    would stop far too early); the difference is split over ran(W) and its
+    complement (diff_fro2_split) so that nothing cancels."""
+    if W.shape[1]:
+        d = np.sqrt(core.diff_fro2_split(W, W, Wn, Wn))
+    else:
+        d = np.sqrt(core.fro2_factored(Wn, Wn))
+    return float(d / (alpha * (1.0 + np.sqrt(core.fro2_factored(W, W)) + grad_norm(prob, r, lam))))
+
+
 def solve(prob, lam: float, k0: int = 8, tol: float = 1e-6, max_iter: int = 500, bm_epochs: int = 10,
           ssi_max_iter: int = 50, ssi_tol_floor: float = 1e-12, seed: int = 0,
           alpha_scale: float = 1.99, callback=None) -> RkeResult:
@@ -239,9 +258,7 @@ def solve(prob, lam: float, k0: int = 8, tol: float = 1e-6, max_iter: int = 500,
         tau = max(ssi_tol_floor, min(1e-4, 0.1 * res_prev * res_prev))
         xi = rng.normals(seed, rng.STREAM_SAFEGUARD + t, n)[:, None]
         ep = eig_prox(prob, W, r, alpha, lam, np.column_stack([W, xi]), tau, ssi_max_iter)
-        d = np.sqrt(core.diff_fro2_split(W, W, ep.W, ep.W)) if W.shape[1] else \
-            np.sqrt(core.fro2_factored(ep.W, ep.W))
-        res = d / (alpha * (1.0 + np.sqrt(core.fro2_factored(W, W)) + grad_norm(prob, r, lam)))
+        res = stop_residual(prob, W, ep.W, r, alpha, lam)
         W = ep.W
         F = objective(prob, W, lam)
         rec = RkeRecord(t, F, res, W.shape[1], ep.iters)
