@@ -300,6 +300,36 @@ bmg_status bmg_server_batch_stats(bmg_server *s, int64_t *launches, int64_t *pas
 /* Waits for running requests, drops queued ones, frees host state. */
 void bmg_server_destroy(bmg_server *s);
 
+/* ------------------------------------------------------------------ no allocation
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * bmg_sddmm_static computes what bmg_sddmm computes (R[p] = w_i . h_j - A_ij for
+ * every stored entry p = (i, j) in CSR order, half_sq = 1/2 sum R^2) straight
+ * from a device CSR, with no problem object and no workspace.  Its scratch (the
+ * per-wave partial sums, the reduction's stages and the CSR check's flag word)
+ * is one static device array of BMG_STATIC_SCRATCH_BYTES per GPU, held until the
+ * process ends; the call allocates nothing.  Every call on a GPU shares that
+ * GPU's array and needs nothing in it to start at zero (each call clears its
+ * flag word and writes every slot it later reads); calls that overlap on one
+ * GPU (from several host threads or streams) race on it.
+ *   csr: (host) struct of device arrays, as for bmg_problem_create, in the
+ *        caller's orientation (m > n is fine); validated on the device first
+ *        (BMG_EINVAL / BMG_ENONFINITE as bmg_problem_create reports them).
+ *   W (m x ld), H (n x ld): (device) FP64 row-major, 16-byte aligned rows,
+ *        0 <= k <= 256, ld >= k, ld a multiple of 8.
+ *   R: (device) [nnz] FP64 or NULL (then only the sum).  half_sq: (host) or NULL.
+ *   stream: a hipStream_t or NULL; the call synchronises it twice (after the
+ *        CSR check and before returning half_sq).
+ * Rows are processed in their own order, one lane team per row (long rows are
+ * not split as in a problem's plan): the entries of R are bit for bit those of
+ * bmg_sddmm; half_sq adds the same terms in another order.
+ * BMG_ENOMEM (before any device work) when m > BMG_STATIC_MAX_ROWS. */
+#define BMG_STATIC_SCRATCH_BYTES (2u << 20)
+#define BMG_STATIC_MAX_ROWS 523120
+bmg_status bmg_sddmm_static(const bmg_csr *csr, const double *W, const double *H, int k, int ld,
+                            double *R, double *half_sq, void *stream);
+
 /* Thread-local message of the last failing call on this thread. */
 const char *bmg_last_error(void);
 

@@ -195,6 +195,26 @@ class Problem:
         return W, k.value, r.as_dict()
 
 
+def bmg_sddmm_static(row_ptr, col, val, m, n, W, H, k, R=None, store=True):
+    """bmg_sddmm without a problem object or workspace (the library's static
+    device scratch; for callers that cannot allocate).  Device tensors: row_ptr
+    int64 [m+1], col int32 [nnz], val float64 [nnz], W (m x ld), H (n x ld)
+    float64.  Returns (R or None, 1/2 sum R^2)."""
+    lib = _lib.load()
+    ld = W.shape[1]
+    assert W.dtype == torch.float64 and H.dtype == torch.float64 and H.shape[1] == ld
+    assert W.is_contiguous() and H.is_contiguous()
+    nnz = int(col.numel())
+    if R is None and store:
+        R = torch.empty(max(nnz, 1), dtype=torch.float64, device=W.device)
+    csr = _lib.BmgCsr(int(m), int(n), nnz, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
+    hs = ctypes.c_double(0.0)
+    with torch.cuda.device(W.device):
+        _lib.check(lib.bmg_sddmm_static(ctypes.byref(csr), _ptr(W), _ptr(H), k, ld, _ptr(R),
+                                        ctypes.byref(hs), _stream_handle(W.device)))
+    return (R[:nnz] if R is not None else None), hs.value
+
+
 class Server:
     """Request loop over many problems on one GPU (bmg_server_*): admission by
     HBM footprint inside one torch-allocated arena, max_slots problems running

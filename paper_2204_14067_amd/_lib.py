@@ -26,7 +26,7 @@ EXPORTS = ["bmg_options_default", "bmg_workspace_size", "bmg_problem_create", "b
            "bmg_prox_step", "bmg_solve", "bmg_rke_residual", "bmg_rke_solve",
            "bmg_last_error", "bmg_server_footprint", "bmg_server_create", "bmg_server_submit",
            "bmg_server_poll", "bmg_server_drain", "bmg_server_stats", "bmg_server_batch_stats",
-           "bmg_server_destroy"]
+           "bmg_server_destroy", "bmg_sddmm_static"]
 
 
 class BmgCsr(ctypes.Structure):
@@ -115,11 +115,12 @@ def load():
     lib.bmg_server_batch_stats.argtypes = [p, P(i64), P(i64)]
     lib.bmg_server_destroy.argtypes = [p]
     lib.bmg_server_destroy.restype = None
+    lib.bmg_sddmm_static.argtypes = [P(BmgCsr), p, p, i32, i32, p, P(d), p]
     for f in ["bmg_workspace_size", "bmg_problem_create", "bmg_sddmm", "bmg_spmm", "bmg_bm_epochs",
               "bmg_polymf_epochs", "bmg_rke_residual", "bmg_rke_solve",
               "bmg_objective", "bmg_prox_step", "bmg_solve", "bmg_server_footprint",
               "bmg_server_create", "bmg_server_submit", "bmg_server_poll", "bmg_server_drain",
-              "bmg_server_stats", "bmg_server_batch_stats"]:
+              "bmg_server_stats", "bmg_server_batch_stats", "bmg_sddmm_static"]:
         getattr(lib, f).restype = ctypes.c_int
     lib.bmg_last_error.argtypes = []
     lib.bmg_last_error.restype = ctypes.c_char_p

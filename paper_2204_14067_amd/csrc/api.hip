@@ -33,6 +33,9 @@ static bmg_status fail(bmg_status s, const std::string &msg) {
   return s;
 }
 extern "C" const char *bmg_last_error(void) { return g_err.c_str(); }
+namespace bmg {
+bmg_status set_error(bmg_status s, const std::string &msg) { return fail(s, msg); }
+}  // namespace bmg
 
 struct BmgError {
   bmg_status st;

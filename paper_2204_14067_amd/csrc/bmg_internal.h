@@ -7,9 +7,14 @@
 #include <string>
 #include <vector>
 
+#include "bmg.h"
+
 namespace bmg {
 
 typedef uint16_t bf16_t;  // BF16 storage: the upper 16 bits of an FP32 (RNE)
+
+// Sets the calling thread's bmg_last_error() message and returns s.
+bmg_status set_error(bmg_status s, const std::string &msg);
 
 // One compressed orientation of Omega (rows of A for the CSR orientation,
 // rows of A^T for the column-major copy) plus its load-balancing plan:
@@ -33,7 +38,7 @@ struct Plan {
   int64_t ncols = 0;               // rows of the gathered operand (columns of Omega here)
   const int64_t *ptr = nullptr;    // [nrows+1]
   const int32_t *idx = nullptr;    // [nnz] column (or row) index of each entry
-  const int32_t *short_rows = nullptr;
+  const int32_t *short_rows = nullptr;  // (sampled residual only: null = rows 0 .. n_short-1)
   int64_t n_short = 0;
   const int32_t *piece_row = nullptr;  // [n_pieces] row of each piece (row by row)
   const int64_t *piece_beg = nullptr;  // [n_pieces] entry range [beg, end) of each piece

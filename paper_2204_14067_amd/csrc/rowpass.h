@@ -474,7 +474,8 @@ __device__ __forceinline__ void sddmm_body(const Plan &pl, int64_t blk, const T 
     const int team = lane / TL, tl = lane % TL;
     const int64_t ri = w * (64 / TL) + team;
     if (ri < pl.n_short) {
-      const int row = pl.short_rows[ri];
+      // a plan without a row list takes the rows in their own order
+      const int row = pl.short_rows ? pl.short_rows[ri] : (int)ri;
       RowT x, acc;
       x.load(X + (int64_t)row * ldx, sub, k);
       team_row<T, TG, G, C, TM_SDDMM>(pl, row, a, Y, ldy, k, x, acc, R, ss, sx, team * TL, tl);

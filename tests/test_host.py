@@ -116,3 +116,16 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_static_sddmm_rejects_oversize_before_device_work(lib):
+    """bmg_sddmm_static refuses more rows than its static scratch covers before
+    it touches the device (so this runs without a GPU)."""
+    from paper_2204_14067_amd import _lib
+    csr = _lib.BmgCsr(600_000, 10, 0, None, None, None)
+    hs = ctypes.c_double(-1.0)
+    st = lib.bmg_sddmm_static(ctypes.byref(csr), None, None, 0, 8, None, ctypes.byref(hs), None)
+    assert st == _lib.BMG_ENOMEM
+    assert b"static scratch" in lib.bmg_last_error()
+    csr = _lib.BmgCsr(10, 10, 0, None, None, None)
+    assert lib.bmg_sddmm_static(ctypes.byref(csr), None, None, 300, 304, None, None, None) == _lib.BMG_EINVAL
