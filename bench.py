@@ -136,8 +136,10 @@ def main():
     p = synth.netflix_shape(scale=args.scale)
     log("workload %s generated in %.1fs" % (p.name, time.time() - t0))
     k0, lam = 16, 20.0
+    # the workspace also holds two LmSVD history blocks (the history comparison)
     prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64,
-                                 precision=args.precision, device=dev)
+                                 precision=args.precision, device=dev,
+                                 lmsvd_p=0 if args.no_extras else 2)
     W, H = prob.zeros_factors()
     log("problem resident on %s (%.2f GB workspace)" % (dev, prob.ws.numel() / 1e9))
 
@@ -238,7 +240,7 @@ def lmsvd_history(bmg, synth, dev, prob, W, H, k0, lam, recs0, sec0, steps=3):
               1e-4, (3, 4, 5), 128, None, (0, 1))]
     for name, p, lm, kk, tol, seeds, kc, Fref, hps in cases:
         prob2 = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=kc, precision="fp64",
-                                      device=dev)
+                                      device=dev, lmsvd_p=max(hps))
         rec = {}
         for hp in hps:
             prob2.bmg_solve(lam=lm, k_init=kk, tol=tol, seed=seeds[0], max_iter=2, lmsvd_p=hp)
@@ -276,7 +278,7 @@ def sparsa_step(bmg, synth, dev, fixed_small, fixed_quarter):
               (3, 4, 5), 128, fixed_quarter)]
     for name, p, lm, kk, tol, seeds, kc, fixed in cases:
         prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=kc, precision="fp64",
-                                     device=dev)
+                                     device=dev, sparsa=True)
         prob.bmg_solve(lam=lm, k_init=kk, tol=tol, seed=seeds[0], max_iter=2, step_rule="sparsa")
         secs, iters, trials, ssi, Fs = [], [], [], [], []
         for sd in seeds:
@@ -453,11 +455,13 @@ def time_to_tol_gpu_bound(bmg, synth, dev, lams=(300.0, 100.0), seeds=(3, 4, 5))
 def serving(bmg, synth, dev, count):
     """Serving stream: requests arrive (Poisson, 20/s) with m ~ U[500, 20000],
     n ~ U[1000, 50000], density ~ U[0.5%, 2%], rank 3..15, noise variance 0.05,
-    lambda above the noise level on Omega; FP32 solves to residual 1e-5 through
-    the server (admission by footprint in an 8 GiB arena, 8 slots, sparse passes
-    of the running problems sharing launches).  Latency = completion - arrival.
-    Also the same requests all submitted at once (capacity).  Baseline: the same
-    problems one after another with the plain FP64 solver to the same residual."""
+    lambda midway between the sampling-noise level of P_Omega(A) and the
+    weakest truth direction; FP32 solves to residual 1e-5 through the server
+    (admission by footprint in an 8 GiB arena, 8 slots, sparse passes of the
+    running problems sharing launches).  Latency = completion - arrival.  Also
+    the same requests all submitted at once (capacity).  Baseline: the same
+    problems one after another with the plain FP64 solver to the same residual.
+    Per truth-rank class: how many results have the truth's rank, and p50/p99."""
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
     reqs = synth.serving_stream(count=count)
@@ -523,7 +527,22 @@ def serving(bmg, synth, dev, count):
            "capacity_vs_plain_fp64": round(burst["throughput_per_s"] * plain_total / count, 3),
            "max_rel_F_diff_vs_fp64": float(max(rel)) if rel else None,
            "F_identical_paced_vs_burst": same,
-           "ranks": sorted({i["k"] for i in infos})}
+           "ranks": sorted({i["k"] for i in infos}),
+           "rank0_results": sum(1 for i in infos if i["k"] == 0),
+           "truth_rank_recovered": sum(1 for i, r in zip(infos, reqs) if i["k"] == r.rank),
+           "truth_above_noise": sum(1 for r in reqs if r.dsig_r > r.L)}
+    classes = {}
+    for i, r in zip(infos, reqs):
+        c = classes.setdefault(r.rank, {"requests": 0, "rank_equal": 0, "ranks": [], "lat": []})
+        c["requests"] += 1
+        c["rank_equal"] += int(i["k"] == r.rank)
+        c["ranks"].append(i["k"])
+        c["lat"].append(i["total_s"])
+    out["by_truth_rank"] = {str(rk): {"requests": c["requests"], "rank_equal": c["rank_equal"],
+                                      "rank_min": min(c["ranks"]), "rank_max": max(c["ranks"]),
+                                      "p50_s": round(float(np.percentile(c["lat"], 50)), 4),
+                                      "p99_s": round(float(np.percentile(c["lat"], 99)), 4)}
+                            for rk, c in sorted(classes.items())}
     log("serving: p50 %.3fs p99 %.3fs at 20/s; all at once %.2f req/s vs plain fp64 sequential %.2f req/s" % (
         paced["p50_s"], paced["p99_s"], burst["throughput_per_s"], out["plain_fp64_sequential"]["throughput_per_s"]))
     return out

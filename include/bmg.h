@@ -14,7 +14,9 @@
  *   - Pointers marked (device) point to GPU memory, (host) to CPU memory.
  *     The caller owns every buffer it passes.  The library never allocates
  *     device memory itself: all of its internal arrays live in the workspace
- *     the caller passes to bmg_problem_create (size from bmg_workspace_size).
+ *     the caller passes to bmg_problem_create (size from bmg_workspace_size,
+ *     which also reserves what the solver variants of the given options need),
+ *     the server's in the arena the caller passes to bmg_server_create.
  *   - Dense factors are row-major FP64: W is m x ld, H is n x ld, with the
  *     first k columns in use (ld >= k, ld a multiple of 8, rows 16-byte aligned).
  *   - Omega is CSR: row_ptr[m+1] int64, col[nnz] int32 sorted and duplicate-free
@@ -138,35 +140,40 @@ typedef struct {
  * lmsvd_p 0, bm_solver BMG_BM_PSD, step_rule BMG_STEP_FIXED, alpha_min 1.99, alpha_max 1e3,
  * sparsa_beta 0.5, sparsa_delta 0.999.
  * BMG_STEP_SPARSA keeps the previous PG point (W, H and its residual) and the
- * warm start in device memory beyond the workspace (min(m,n) x (2 k_cap + 2)
- * rounded up to 16, plus (m + n) x ld_k and nnz elements of the working
- * precision), allocated on first use and kept until bmg_problem_destroy.
+ * warm start in the workspace: min(m,n) x qb, (m + n) x ld_k and 2 nnz elements
+ * of the working precision (FP64 in BMG_FP64, FP32 otherwise), qb = 2 k_cap + 2
+ * and ld_k = k_cap, each rounded up to a multiple of 16.
  * lmsvd_p = p >= 1 (Algorithm 2 with history, Suppl. A.1.2: the Ritz step runs
- * over ran(U^{t,i}, ..., U^{t,i-p}) with the basis of eqs. PUi and orth-W) needs
- * device memory beyond the workspace: (2p-1) blocks of min(m,n) x qb and 3p
- * blocks of max(m,n) x qb elements of the working precision, qb = 2 k_cap + 2
- * rounded up to a multiple of 16
- * (FP64 in BMG_FP64, FP32 otherwise).  The first solve or prox step that asks for
- * a larger p than before allocates it with hipMalloc; the problem keeps it
- * until bmg_problem_destroy.  BMG_EINVAL for p outside [0, 4]. */
+ * over ran(U^{t,i}, ..., U^{t,i-p}) with the basis of eqs. PUi and orth-W) keeps
+ * (2p-1) blocks of min(m,n) x qb and 3p blocks of max(m,n) x qb elements in the
+ * workspace.  Both regions are reserved when the workspace is sized with those
+ * options (bmg_workspace_size / bmg_problem_create); a solve or prox step that
+ * asks for more than was reserved fails with BMG_ENOMEM.  BMG_EINVAL for p
+ * outside [0, 4]. */
 void bmg_options_default(bmg_options *opt);
 
 /* Bytes of device workspace a problem of this shape needs when the rank may
  * reach k_cap (subspace blocks hold up to 2*k_cap+1 columns).  k_cap is at most
- * 256 in BMG_FP64 and 512 in BMG_FP32 / BMG_BF16 (BMG_EINVAL beyond).  (host) out. */
+ * 256 in BMG_FP64 and 512 in BMG_FP32 / BMG_BF16 (BMG_EINVAL beyond).
+ * opt: (host) the options the problem will be solved with, or NULL for the
+ * defaults; its lmsvd_p (history blocks, 0..4) and step_rule (SpaRSA state)
+ * add the regions described at bmg_options_default.  (host) out. */
 bmg_status bmg_workspace_size(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_precision prec,
-                              size_t *bytes);
+                              const bmg_options *opt, size_t *bytes);
 
 /* Validates the CSR (sorted, in range, duplicate-free, finite values), builds the
  * column-major copy of Omega used by the transposed products (a stable sort of
  * the column indices on the device), and the load-balancing plans of both
- * orientations.  ws: (device) workspace of ws_bytes; stream: a hipStream_t (or
- * NULL for the default stream).  The CSR arrays must stay alive and unchanged
- * while the problem exists.  m > n is allowed; the library then works on the
- * transpose internally (the paper assumes m <= n, Sec. 1) and the W/H arguments
- * of every call keep their user meaning. */
-bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_precision prec, void *ws,
-                              size_t ws_bytes, void *stream, bmg_problem **out);
+ * orientations.  opt: (host) as for bmg_workspace_size (NULL: defaults); it
+ * fixes the variants the workspace holds.  ws: (device) workspace of at least
+ * bmg_workspace_size(..., opt) bytes (BMG_ENOMEM otherwise); stream: a
+ * hipStream_t (or NULL for the default stream).  The CSR arrays must stay alive
+ * and unchanged while the problem exists.  m > n is allowed; the library then
+ * works on the transpose internally (the paper assumes m <= n, Sec. 1) and the
+ * W/H arguments of every call keep their user meaning. */
+bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_precision prec,
+                              const bmg_options *opt, void *ws, size_t ws_bytes, void *stream,
+                              bmg_problem **out);
 void bmg_problem_destroy(bmg_problem *p);
 
 /* Sampled residual (the sparse gradient of the MC loss, Sec. 5.1):
@@ -227,9 +234,15 @@ bmg_status bmg_rke_solve(bmg_problem *p, double *W, int ld, const bmg_options *o
                          bmg_result *res);
 
 /* Objective of (MC) at X = W H^T:  F = 1/2 ||P_Omega(X - A)||^2 + lambda ||X||_*,
- * the nuclear norm from the k x k core of thin QR factors of W and H. (host) F. */
+ * the nuclear norm from the k x k core of thin QR factors of W and H. (host) F.
+ * residual: (host) optional; the relative optimality residual at X,
+ *   ||X - prox_{alpha lambda ||.||_*}(X - alpha grad f(X))||_F / (1 + ||X||_F + ||grad f(X)||_F)
+ * (the norm of the prox-gradient mapping times alpha, the paper leaving the
+ * residual of (MC) undefined in Sec. 6.1), from one inexact PG step at the
+ * bmg_options_default step and subspace settings, warm-started from W as in
+ * bmg_prox_step; W and H are not modified.  It needs lambda > 0. */
 bmg_status bmg_objective(bmg_problem *p, const double *W, const double *H, int k, int ld,
-                         double lambda, double *F);
+                         double lambda, double *F, double *residual);
 
 /* One inexact PG step (Algorithm 1, convex-lifting phase) from X~ = W H^T with
  * step alpha, warm-started from the columns of W only (eq. rt0 with no previous
@@ -254,13 +267,14 @@ bmg_status bmg_solve(bmg_problem *p, double *W, double *H, int ld, const bmg_opt
  * A request loop over many completion problems of different shapes on one
  * GPU.  The caller gives the server one device arena; every admitted problem
  * lives in a first-fit allocation inside it (its CSR copy, W, H and its
- * workspace), so admission is by HBM footprint.  Requests are admitted in
- * arrival order, a later request may be admitted ahead of an earlier one that
- * does not fit yet (backfill).  Each of max_slots slots is a host worker with
- * its own HIP stream; admitted problems run concurrently on the device and a
- * slot and its memory are reused as soon as a problem finishes.  Every
- * problem's computation is independent of the others (own stream, own memory,
- * deterministic kernels): a result is the same alone and in the mix. */
+ * workspace, sized for the request's own options), so admission is by HBM
+ * footprint.  Requests are admitted in arrival order, a later request may be
+ * admitted ahead of an earlier one that does not fit yet (backfill).  Each of
+ * max_slots slots has its own HIP stream; a slot and its memory are reused as
+ * soon as a problem finishes.  Every problem's computation is independent of
+ * the others (own stream, own memory, deterministic kernels): a result is the
+ * same alone and in the mix.  The paper has no serving loop; this one is an
+ * addition for running many problems on one GPU. */
 typedef struct bmg_server bmg_server;
 
 typedef struct {
@@ -275,11 +289,23 @@ typedef struct {
 } bmg_request_info;
 
 /* Arena bytes one request needs (CSR copy + factors at ld = k_cap rounded to 8
- * + workspace).  (host) out. */
+ * + workspace for the options opt, NULL: defaults).  (host) out. */
 bmg_status bmg_server_footprint(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_precision prec,
-                                size_t *bytes);
-/* arena: (device) memory owned by the caller, kept alive until destroy. */
-bmg_status bmg_server_create(void *arena, size_t arena_bytes, int max_slots, bmg_server **out);
+                                const bmg_options *opt, size_t *bytes);
+/* arena: (device) memory owned by the caller, kept alive until destroy.
+ * threads = 1: each of the max_slots (1..64) slots is a host worker thread that
+ * runs its solves to the end, and the sparse passes of the running problems
+ * that are pending together share launches.  threads = 0: no threads; the
+ * caller drives the server with bmg_server_tick. */
+bmg_status bmg_server_create(void *arena, size_t arena_bytes, int max_slots, int threads,
+                             bmg_server **out);
+/* A server created with threads = 0: on the calling thread, admits queued
+ * requests into free slots (arrival order, backfill by footprint; admission
+ * copies the CSR and runs the initialisation) and advances every running solve
+ * by one outer iteration of Algorithm 1 (BM epochs + one PG step), retiring
+ * those that finish.  With worker threads it only reports.  running / queued:
+ * (host, optional) requests running and waiting after the call. */
+bmg_status bmg_server_tick(bmg_server *s, int *running, int *queued);
 /* Copies the (host) CSR and queues the request; *ticket identifies it.
  * BMG_ENOMEM if the request could never fit in the arena. */
 bmg_status bmg_server_submit(bmg_server *s, const bmg_csr *host_csr, int k_cap, bmg_precision prec,
@@ -289,7 +315,8 @@ bmg_status bmg_server_submit(bmg_server *s, const bmg_csr *host_csr, int k_cap, 
  * columns beyond k zero). */
 bmg_status bmg_server_poll(bmg_server *s, uint64_t ticket, bmg_request_info *info, double *W_host,
                            double *H_host, int ld);
-/* Blocks until every submitted request is done or failed. */
+/* Blocks until every submitted request is done or failed (with threads = 0 it
+ * calls bmg_server_tick until then). */
 bmg_status bmg_server_drain(bmg_server *s);
 /* Peak number of concurrently running problems and peak arena bytes in use. */
 bmg_status bmg_server_stats(bmg_server *s, int *peak_running, size_t *peak_bytes);

@@ -57,10 +57,11 @@ class Problem:
 
     row_ptr (int64, m+1), col (int32, nnz), val (float64, nnz) are device
     tensors that must stay alive; the workspace is a torch allocation owned by
-    this object."""
+    this object.  lmsvd_p / sparsa reserve workspace for solves with that many
+    LmSVD history blocks / with the SpaRSA step rule (bmg_workspace_size)."""
 
     def __init__(self, row_ptr, col, val, m: int, n: int, k_cap: int = 64, precision: str = "fp64",
-                 device=None):
+                 device=None, lmsvd_p: int = 0, sparsa: bool = False):
         lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("paper_2204_14067_amd needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -71,24 +72,26 @@ class Problem:
         self.m, self.n, self.nnz, self.k_cap = int(m), int(n), int(col.numel()), int(k_cap)
         self.precision = _PREC[precision]
         nbytes = ctypes.c_size_t(0)
+        self.reserve = options(lmsvd_p=lmsvd_p, step_rule="sparsa" if sparsa else "fixed")
         _lib.check(lib.bmg_workspace_size(self.m, self.n, self.nnz, self.k_cap, self.precision,
-                                          ctypes.byref(nbytes)))
+                                          ctypes.byref(self.reserve), ctypes.byref(nbytes)))
         self.ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
         csr = _lib.BmgCsr(self.m, self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
                           self.val.data_ptr())
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(lib.bmg_problem_create(ctypes.byref(csr), self.k_cap, self.precision,
-                                              _ptr(self.ws), self.ws.numel(),
+                                              ctypes.byref(self.reserve), _ptr(self.ws), self.ws.numel(),
                                               _stream_handle(self.device), ctypes.byref(h)))
         self._h = h
         self.ld = round_ld(self.k_cap)
 
     @classmethod
-    def from_host(cls, row_ptr, col, val, m, n, k_cap=64, precision="fp64", device="cuda:0"):
+    def from_host(cls, row_ptr, col, val, m, n, k_cap=64, precision="fp64", device="cuda:0",
+                  lmsvd_p=0, sparsa=False):
         t = lambda a, dt: torch.as_tensor(a).to(device=device, dtype=dt).contiguous()  # noqa: E731
         return cls(t(row_ptr, torch.int64), t(col, torch.int32), t(val, torch.float64), m, n, k_cap,
-                   precision, device)
+                   precision, device, lmsvd_p=lmsvd_p, sparsa=sparsa)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -144,11 +147,15 @@ class Problem:
                                                  ctypes.byref(F)))
         return F.value
 
-    def bmg_objective(self, W, H, k, lam):
+    def bmg_objective(self, W, H, k, lam, residual=False):
+        """F at X = W H^T; with residual=True also the relative optimality
+        residual there (one inexact PG step, the factors untouched): (F, res)."""
         ld = self._factors(W, H, k)
         F = ctypes.c_double(0.0)
-        _lib.check(_lib.load().bmg_objective(self._h, _ptr(W), _ptr(H), k, ld, lam, ctypes.byref(F)))
-        return F.value
+        res = ctypes.c_double(0.0)
+        _lib.check(_lib.load().bmg_objective(self._h, _ptr(W), _ptr(H), k, ld, lam, ctypes.byref(F),
+                                             ctypes.byref(res) if residual else None))
+        return (F.value, res.value) if residual else F.value
 
     def bmg_prox_step(self, W, H, k, **opts):
         ld = self._factors(W, H, k)
@@ -218,21 +225,26 @@ def bmg_sddmm_static(row_ptr, col, val, m, n, W, H, k, R=None, store=True):
 class Server:
     """Request loop over many problems on one GPU (bmg_server_*): admission by
     HBM footprint inside one torch-allocated arena, max_slots problems running
-    concurrently on their own streams."""
+    concurrently on their own streams.  threads=True: worker threads solve the
+    admitted problems; threads=False: the caller drives it with tick()."""
 
-    def __init__(self, arena_bytes: int, max_slots: int = 4, device="cuda:0"):
+    def __init__(self, arena_bytes: int, max_slots: int = 4, device="cuda:0", threads: bool = True):
         lib = _lib.load()
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         h = ctypes.c_void_p()
         with torch.cuda.device(torch.device(device)):
             _lib.check(lib.bmg_server_create(_ptr(self.arena), self.arena.numel(), max_slots,
-                                             ctypes.byref(h)))
+                                             1 if threads else 0, ctypes.byref(h)))
         self._h = h
 
     @staticmethod
-    def footprint(m, n, nnz, k_cap=64, precision="fp32"):
+    def footprint(m, n, nnz, k_cap=64, precision="fp32", **opts):
+        """Arena bytes of one request (opts as for submit: lmsvd_p and step_rule
+        size its workspace)."""
         b = ctypes.c_size_t(0)
-        _lib.check(_lib.load().bmg_server_footprint(m, n, nnz, k_cap, _PREC[precision], ctypes.byref(b)))
+        o = options(**opts)
+        _lib.check(_lib.load().bmg_server_footprint(m, n, nnz, k_cap, _PREC[precision], ctypes.byref(o),
+                                                    ctypes.byref(b)))
         return b.value
 
     def submit(self, row_ptr, col, val, m, n, k_cap=64, precision="fp32", **opts):
@@ -260,6 +272,12 @@ class Server:
                "run_s": info.run_s, "total_s": info.total_s, "footprint": info.footprint,
                "result": info.result.as_dict()}
         return out, W, H
+
+    def tick(self):
+        """bmg_server_tick: (running, queued) after one round."""
+        r, q = ctypes.c_int(0), ctypes.c_int(0)
+        _lib.check(_lib.load().bmg_server_tick(self._h, ctypes.byref(r), ctypes.byref(q)))
+        return r.value, q.value
 
     def drain(self):
         _lib.check(_lib.load().bmg_server_drain(self._h))

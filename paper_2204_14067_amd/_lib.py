@@ -26,7 +26,7 @@ EXPORTS = ["bmg_options_default", "bmg_workspace_size", "bmg_problem_create", "b
            "bmg_prox_step", "bmg_solve", "bmg_rke_residual", "bmg_rke_solve",
            "bmg_last_error", "bmg_server_footprint", "bmg_server_create", "bmg_server_submit",
            "bmg_server_poll", "bmg_server_drain", "bmg_server_stats", "bmg_server_batch_stats",
-           "bmg_server_destroy", "bmg_sddmm_static"]
+           "bmg_server_destroy", "bmg_server_tick", "bmg_sddmm_static"]
 
 
 class BmgCsr(ctypes.Structure):
@@ -93,8 +93,8 @@ def load():
     P = ctypes.POINTER
     lib.bmg_options_default.argtypes = [P(BmgOptions)]
     lib.bmg_options_default.restype = None
-    lib.bmg_workspace_size.argtypes = [i64, i64, i64, i32, i32, P(ctypes.c_size_t)]
-    lib.bmg_problem_create.argtypes = [P(BmgCsr), i32, i32, p, ctypes.c_size_t, p, P(p)]
+    lib.bmg_workspace_size.argtypes = [i64, i64, i64, i32, i32, P(BmgOptions), P(ctypes.c_size_t)]
+    lib.bmg_problem_create.argtypes = [P(BmgCsr), i32, i32, P(BmgOptions), p, ctypes.c_size_t, p, P(p)]
     lib.bmg_problem_destroy.argtypes = [p]
     lib.bmg_problem_destroy.restype = None
     lib.bmg_sddmm.argtypes = [p, p, p, i32, i32, p, P(d)]
@@ -103,11 +103,12 @@ def load():
     lib.bmg_polymf_epochs.argtypes = [p, p, p, i32, i32, d, i32, P(d)]
     lib.bmg_rke_residual.argtypes = [p, p, i32, i32, p, p, P(d)]
     lib.bmg_rke_solve.argtypes = [p, p, i32, P(BmgOptions), P(i32), P(BmgResult)]
-    lib.bmg_objective.argtypes = [p, p, p, i32, i32, d, P(d)]
+    lib.bmg_objective.argtypes = [p, p, p, i32, i32, d, P(d), P(d)]
     lib.bmg_prox_step.argtypes = [p, p, p, P(i32), i32, P(BmgOptions), P(d), P(d)]
     lib.bmg_solve.argtypes = [p, p, p, i32, P(BmgOptions), P(i32), P(BmgResult)]
-    lib.bmg_server_footprint.argtypes = [i64, i64, i64, i32, i32, P(ctypes.c_size_t)]
-    lib.bmg_server_create.argtypes = [p, ctypes.c_size_t, i32, P(p)]
+    lib.bmg_server_footprint.argtypes = [i64, i64, i64, i32, i32, P(BmgOptions), P(ctypes.c_size_t)]
+    lib.bmg_server_create.argtypes = [p, ctypes.c_size_t, i32, i32, P(p)]
+    lib.bmg_server_tick.argtypes = [p, P(i32), P(i32)]
     lib.bmg_server_submit.argtypes = [p, P(BmgCsr), i32, i32, P(BmgOptions), P(ctypes.c_uint64)]
     lib.bmg_server_poll.argtypes = [p, ctypes.c_uint64, P(BmgRequestInfo), p, p, i32]
     lib.bmg_server_drain.argtypes = [p]
@@ -120,7 +121,7 @@ def load():
               "bmg_polymf_epochs", "bmg_rke_residual", "bmg_rke_solve",
               "bmg_objective", "bmg_prox_step", "bmg_solve", "bmg_server_footprint",
               "bmg_server_create", "bmg_server_submit", "bmg_server_poll", "bmg_server_drain",
-              "bmg_server_stats", "bmg_server_batch_stats", "bmg_sddmm_static"]:
+              "bmg_server_stats", "bmg_server_batch_stats", "bmg_sddmm_static", "bmg_server_tick"]:
         getattr(lib, f).restype = ctypes.c_int
     lib.bmg_last_error.argtypes = []
     lib.bmg_last_error.restype = ctypes.c_char_p

@@ -115,6 +115,11 @@ struct Layout {
   size_t scratch;
   size_t s_keys_out, s_vals_in, s_rid, s_temp, s_temp_bytes;
   size_t b_W, b_H, b_G, b_D, b_Wn, b_Hn, b_Ucur, b_Uprev, b_vec, b_B1, b_B2, b_B3, b_B4, b_Y, b_Y2;
+  // variants reserved at creation: history blocks of Algorithm 2 (p_t <= hist_p)
+  // and the state of the SpaRSA step rule
+  int hist_p = 0;
+  bool sparsa = false;
+  size_t hist, hist_mb, hist_nb, sp, sp_bu, sp_bw, sp_bh, sp_br;
   size_t total;
 };
 
@@ -129,9 +134,12 @@ static size_t sort_temp_bytes(int64_t nnz) {
   return bytes + 256;
 }
 
-static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_precision prec) {
+static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_precision prec,
+                          int hist_p, bool sparsa) {
   Layout L{};
   L.m = m; L.n = n; L.nnz = nnz; L.k_cap = k_cap;
+  L.hist_p = hist_p;
+  L.sparsa = sparsa;
   // leading dimensions in multiples of 16 elements: factor rows start on 128-byte lines
   L.ldk = (int)rup(std::max(k_cap, 1), 16);
   L.qmax = 2 * k_cap + 2;
@@ -189,6 +197,22 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_prec
     L.d_W64 = take(bf ? 8 * mi0 * L.ldk : 0);
     L.d_H64 = take(bf ? 8 * ni0 * L.ldk : 0);
     L.d_R64 = take(bf ? 8 * nnz : 0);
+  }
+  {
+    // element size of the solver's blocks in this precision
+    const int64_t es = prec == BMG_FP64 ? 8 : 4;
+    const int64_t mi0 = std::min(m, n), ni0 = std::max(m, n);
+    // history: (2p - 1) short-side and 3p long-side blocks of qld columns
+    L.hist_mb = (size_t)rup(es * mi0 * L.qld, 256);
+    L.hist_nb = (size_t)rup(es * ni0 * L.qld, 256);
+    L.hist = take(hist_p > 0 ? (size_t)(2 * hist_p - 1) * L.hist_mb + (size_t)(3 * hist_p) * L.hist_nb : 0);
+    // SpaRSA: the kept warm start, the previous PG point W, H, its residual and
+    // the sampled values of X~
+    L.sp_bu = (size_t)rup(es * mi0 * L.qld, 256);
+    L.sp_bw = (size_t)rup(es * mi0 * L.ldk, 256);
+    L.sp_bh = (size_t)rup(es * ni0 * L.ldk, 256);
+    L.sp_br = (size_t)rup(es * std::max<int64_t>(nnz, 1), 256);
+    L.sp = take(sparsa ? L.sp_bu + L.sp_bw + L.sp_bh + 2 * L.sp_br : 0);
   }
   L.scratch = off;
   // setup view of the scratch region
@@ -360,12 +384,6 @@ struct bmg_problem {
   std::vector<Pend> pend;
   hipEvent_t last_a = nullptr, last_b = nullptr;
   int last_cls = 0;
-  // history blocks of Algorithm 2 with p_t >= 1 (allocated on first use)
-  char *hist = nullptr;
-  size_t hist_bytes = 0;
-  // state of the SpaRSA step rule (allocated on first use)
-  char *sp = nullptr;
-  size_t sp_bytes = 0;
   double kms[3] = {0, 0, 0}, kbytes[3] = {0, 0, 0};
   int klaunch[3] = {0, 0, 0};
   hipEvent_t get_event() {
@@ -401,8 +419,6 @@ struct bmg_problem {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (bitem.ready) (void)hipEventDestroy(bitem.ready);
     if (bitem.done) (void)hipEventDestroy(bitem.done);
-    if (hist) (void)hipFree(hist);
-    if (sp) (void)hipFree(sp);
   }
 
   template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -878,8 +894,15 @@ extern "C" void bmg_options_default(bmg_options *o) {
   o->sparsa_delta = 0.999;
 }
 
+// history length and step rule the workspace reserves for (opt may be null)
+static bool reserve_of(const bmg_options *opt, int *hist_p, bool *sparsa) {
+  *hist_p = opt ? opt->lmsvd_p : 0;
+  *sparsa = opt && opt->step_rule == BMG_STEP_SPARSA;
+  return *hist_p >= 0 && *hist_p <= LMSVD_MAX_HIST;
+}
+
 extern "C" bmg_status bmg_workspace_size(int64_t m, int64_t n, int64_t nnz, int k_cap,
-                                         bmg_precision prec, size_t *bytes) {
+                                         bmg_precision prec, const bmg_options *opt, size_t *bytes) {
   if (!bytes || m < 0 || n < 0 || nnz < 0 || k_cap < 1 || nnz > (int64_t)INT32_MAX ||
       m > (int64_t)INT32_MAX || n > (int64_t)INT32_MAX)
     return fail(BMG_EINVAL, "bmg_workspace_size: bad shape");
@@ -888,18 +911,21 @@ extern "C" bmg_status bmg_workspace_size(int64_t m, int64_t n, int64_t nnz, int 
   (void)mi;
   if (k_cap > (prec == BMG_FP64 ? max_width<double>() : max_width<float>()))
     return fail(BMG_EINVAL, "k_cap above the widest sparse-pass slice");
-  Layout L = make_layout(m, n, nnz, k_cap, prec);
+  int hp = 0;
+  bool sp = false;
+  if (!reserve_of(opt, &hp, &sp)) return fail(BMG_EINVAL, "lmsvd_p outside [0, 4]");
+  Layout L = make_layout(m, n, nnz, k_cap, prec, hp, sp);
   *bytes = L.total;
   return BMG_OK;
 }
 
 extern "C" bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_precision prec,
-                                         void *ws, size_t ws_bytes, void *stream,
-                                         bmg_problem **out) {
+                                         const bmg_options *opt, void *ws, size_t ws_bytes,
+                                         void *stream, bmg_problem **out) {
   if (!csr || !out || !ws) return fail(BMG_EINVAL, "bmg_problem_create: null argument");
   *out = nullptr;
   size_t need = 0;
-  bmg_status st = bmg_workspace_size(csr->m, csr->n, csr->nnz, k_cap, prec, &need);
+  bmg_status st = bmg_workspace_size(csr->m, csr->n, csr->nnz, k_cap, prec, opt, &need);
   if (st != BMG_OK) return st;
   if (ws_bytes < need) return fail(BMG_ENOMEM, "workspace smaller than bmg_workspace_size");
   if (csr->m == 0 || csr->n == 0) return fail(BMG_EINVAL, "empty matrix shape");
@@ -907,7 +933,10 @@ extern "C" bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_prec
     return fail(BMG_EINVAL, "null CSR array");
   bmg_problem *P = new bmg_problem();
   try {
-    P->L = make_layout(csr->m, csr->n, csr->nnz, k_cap, prec);
+    int hp = 0;
+    bool sp = false;
+    reserve_of(opt, &hp, &sp);
+    P->L = make_layout(csr->m, csr->n, csr->nnz, k_cap, prec, hp, sp);
     P->prec = prec;
     P->s = (hipStream_t)stream;
     P->ws = (char *)ws;
@@ -1330,25 +1359,13 @@ struct Method : Engine<T, TG> {
     return q;
   }
 
-  // Device memory of the history path: (2p - 1) m-side and 3p n-side blocks of
-  // qld columns, kept by the problem across calls.
+  // The history blocks ((2p - 1) m-side and 3p n-side blocks of qld columns)
+  // in the workspace region reserved at creation for p_t up to L.hist_p.
   T *hist_mem(int hp) {
-    const size_t mb = (size_t)rup((int64_t)sizeof(T) * m * qld, 256);
-    const size_t nb = (size_t)rup((int64_t)sizeof(T) * n * qld, 256);
-    const size_t need = (size_t)(2 * hp - 1) * mb + (size_t)(3 * hp) * nb;
-    if (P->hist_bytes < need) {
-      HIPC(hipStreamSynchronize(s));
-      if (P->hist) HIPC(hipFree(P->hist));
-      P->hist = nullptr;
-      P->hist_bytes = 0;
-      if (hipMalloc((void **)&P->hist, need) != hipSuccess) {
-        (void)hipGetLastError();
-        P->hist = nullptr;
-        throw BmgError{BMG_ENOMEM, "no device memory for the history blocks of the subspace iteration"};
-      }
-      P->hist_bytes = need;
-    }
-    return (T *)P->hist;
+    REQUIRE(hp <= P->L.hist_p, BMG_ENOMEM,
+            "lmsvd_p = " + std::to_string(hp) + " needs history blocks the workspace was not sized for "
+            "(it reserves p <= " + std::to_string(P->L.hist_p) + ")");
+    return (T *)P->template at<char>(P->L.hist);
   }
 
   // Algorithm 2 with p_t = hist_p >= 1.  U^{t,i} and Z^T U^{t,i} live in a ring
@@ -1367,8 +1384,7 @@ struct Method : Engine<T, TG> {
     T *B1 = blk(P->L.b_B1), *B2 = blk(P->L.b_B2);
     REQUIRE(Ubuf == B1 || Ubuf == B2, BMG_EINVAL, "subspace iteration: unexpected start block");
     char *hm = (char *)hist_mem(hp);
-    const size_t mb = (size_t)rup((int64_t)sizeof(T) * m * qld, 256);
-    const size_t nb = (size_t)rup((int64_t)sizeof(T) * n * qld, 256);
+    const size_t mb = P->L.hist_mb, nb = P->L.hist_nb;
     std::vector<T *> Ur(hp + 1), Yr(hp + 1), Pm(hp), Bm(hp), Em(hp);
     Ur[0] = Ubuf;
     Ur[1] = Ubuf == B1 ? B2 : B1;
@@ -1597,28 +1613,15 @@ struct Method : Engine<T, TG> {
   };
   // the kept warm start (m x qld), the previous PG point (W, H at ldk), its
   // row-order residual and the sampled values of this step's X~ (nnz each):
-  // device memory allocated on first use, kept by the problem
+  // the workspace region reserved at creation for the SpaRSA rule
   SpMem sparsa_mem() {
-    const size_t bu = (size_t)rup((int64_t)sizeof(T) * m * qld, 256);
-    const size_t bw = (size_t)rup((int64_t)sizeof(T) * m * ldk, 256);
-    const size_t bh = (size_t)rup((int64_t)sizeof(T) * n * ldk, 256);
-    const size_t br = (size_t)rup((int64_t)sizeof(T) * std::max<int64_t>(R->pl.nnz, 1), 256);
-    const size_t need = bu + bw + bh + 2 * br;
-    if (P->sp_bytes < need) {
-      HIPC(hipStreamSynchronize(s));
-      if (P->sp) HIPC(hipFree(P->sp));
-      P->sp = nullptr;
-      P->sp_bytes = 0;
-      if (hipMalloc((void **)&P->sp, need) != hipSuccess) {
-        (void)hipGetLastError();
-        P->sp = nullptr;
-        throw BmgError{BMG_ENOMEM, "no device memory for the SpaRSA step rule"};
-      }
-      P->sp_bytes = need;
-    }
-    char *b = P->sp;
-    return SpMem{(T *)b, (T *)(b + bu), (T *)(b + bu + bw), (T *)(b + bu + bw + bh),
-                 (T *)(b + bu + bw + bh + br)};
+    REQUIRE(P->L.sparsa, BMG_ENOMEM,
+            "the SpaRSA step rule needs state the workspace was not sized for");
+    const Layout &L = P->L;
+    char *b = P->template at<char>(L.sp);
+    return SpMem{(T *)b, (T *)(b + L.sp_bu), (T *)(b + L.sp_bu + L.sp_bw),
+                 (T *)(b + L.sp_bu + L.sp_bw + L.sp_bh),
+                 (T *)(b + L.sp_bu + L.sp_bw + L.sp_bh + L.sp_br)};
   }
   // eq. proxBB read as the BB step ||dX||^2 / <dX, d grad f> between this PG
   // point X~ = W H^T and the previous one (grad f(X) - grad f(Y) = P_Omega(X - Y)
@@ -1888,77 +1891,105 @@ struct Method : Engine<T, TG> {
     return E::loss(S.W, S.H, S.k) + lam * ssum;
   }
 
-  // Algorithm 1
-  bmg_status solve(const bmg_options &o, State &S, bmg_result *res) {
-    const auto t0 = std::chrono::steady_clock::now();
+  // Algorithm 1, one outer iteration per call of solve_step (so that a driver
+  // can interleave several solves on one host thread)
+  struct Run {
+    bmg_options o{};
+    State *S = nullptr;
+    std::chrono::steady_clock::time_point t0;
+    double F = 0.0, F_bm = 0.0, resid = INFINITY, eps = 0.0, last_refresh = INFINITY, alpha_last = 0.0;
+    int every = 1, t = 0, ssi_total = 0, trials_total = 0;
+    bool hi = false, conv = false, done = false;
+    double la = 0.0, wait = 0.0;     // host accounting of this solve
+    int syncs = 0;
+  };
+  // host accounting is per thread; a run carries its own across steps
+  struct Acct {
+    Run &r;
+    explicit Acct(Run &rr) : r(rr) { t_la_acc = r.la; t_wait_acc = r.wait; n_sync_acc = r.syncs; }
+    ~Acct() { r.la = t_la_acc; r.wait = t_wait_acc; r.syncs = n_sync_acc; }
+  };
+  void solve_begin(const bmg_options &o, State &S, Run &r) {
+    r = Run();
+    r.o = o;
+    r.S = &S;
+    r.t0 = std::chrono::steady_clock::now();
+    Acct acct(r);
     hist_p = o.lmsvd_p;
     sparsa = o.step_rule == BMG_STEP_SPARSA;
     sp_opt = o;
     sp_have_prev = false;
-    t_la_acc = t_wait_acc = 0.0;
-    n_sync_acc = 0;
+    if (hist_p > 0) hist_mem(hist_p);   // the workspace must hold them: fail early
+    if (sparsa) sparsa_mem();
     init_state(S);
     S.psi = o.psi0;
     initialize(S, o.k_init, o.lambda, o.seed);
-    double F = objective_balanced(S, o.lambda, true), F_bm = F, resid = INFINITY, eps = 0.0;
-    const int every = std::max(1, o.refresh_every);
-    bool hi = false;                    // BF16 mode switched to FP32 gathers
-    double last_refresh = INFINITY;
-    int t = 0, ssi_total = 0, trials_total = 0;
-    double alpha_last = o.alpha;
-    bool conv = false;
-    for (t = 0; t < o.max_iter; ++t) {
-      // BF16 mode: every `every`-th iteration is a refresh: no BM phase (the
-      // paper allows skipping it), R and F in FP64 and FP32 gathers in the PG
-      // step, so only its residual certifies convergence.  Once a refreshed
-      // residual is <= 1e-3 or stops falling, BF16 noise dominates the
-      // remaining error and every later iteration runs with FP32 gathers.
-      const bool refresh = !kShadow || hi || (t + 1) % every == 0;
-      this->exact_gather = kShadow && hi;
-      bool changed = false;
-      for (int e = 0; e < o.bm_epochs && S.k > 0 && !(kShadow && refresh && !hi); ++e) {
-        if (o.bm_solver == BMG_BM_POLYMF) {
-          changed |= polymf_epoch(S.W, S.H, S.k, o.lambda);
-        } else {
-          changed |= bm_half(true, S.W, S.H, S.k, o.lambda);
-          changed |= bm_half(false, S.W, S.H, S.k, o.lambda);
-        }
-      }
-      F_bm = bm_objective(S.W, S.H, S.k, o.lambda);
-      // FP32 passes cannot resolve Ritz values below ~1e-7 of the largest, and
-      // passes gathering BF16 operands (relative rounding up to 2^-9) not below
-      // ~1e-3: the subspace iteration stops at that resolution instead of
-      // running into its iteration cap (refresh steps gather FP32)
-      const bool bf16_gathers = kShadow && !refresh && !hi;
-      const double floor =
-          std::max(o.ssi_tol_floor, bf16_gathers ? 1e-3 : sizeof(T) == 4 ? 1e-6 : 0.0);
-      const double tau = std::max(floor, std::min(1e-4, 0.1 * S.res_prev * S.res_prev));
-      StepInfo st = pg_step(S, changed, o.lambda, o.alpha, tau, o.ssi_max_iter, o.seed, t, refresh);
-      ssi_total += st.iters;
-      trials_total += st.trials;
-      alpha_last = st.alpha;
-      resid = st.residual;
-      eps = st.eps;
-      F = objective_balanced(S, o.lambda, refresh);
-      REQUIRE(std::isfinite(F) && std::isfinite(resid), BMG_ENONFINITE, "non-finite objective");
-      if (o.verbose)
-        fprintf(stderr,
-                "[bmg] t=%d F=%.15g F_bm=%.15g res=%.3e k=%d q=%d ssi=%d eps=%.3e add=%d alpha=%.4g "
-                "trials=%d\n",
-                t, F, F_bm, resid, S.k, st.q, st.iters, eps, (int)st.added, st.alpha, st.trials);
-      S.res_prev = resid;
-      if (kShadow && refresh && !hi) {
-        if (resid <= 1e-3 || resid > 0.7 * last_refresh) hi = true;
-        last_refresh = resid;
-      }
-      if (resid <= o.tol && refresh) {
-        conv = true;
-        ++t;
-        break;
+    r.F = objective_balanced(S, o.lambda, true);
+    r.F_bm = r.F;
+    r.every = std::max(1, o.refresh_every);
+    r.alpha_last = o.alpha;
+    r.done = o.max_iter <= 0;
+  }
+  // returns true once the solve has converged or reached max_iter
+  bool solve_step(Run &r) {
+    if (r.done) return true;
+    Acct acct(r);
+    const bmg_options &o = r.o;
+    State &S = *r.S;
+    const int t = r.t;
+    // BF16 mode: every `every`-th iteration is a refresh: no BM phase (the
+    // paper allows skipping it), R and F in FP64 and FP32 gathers in the PG
+    // step, so only its residual certifies convergence.  Once a refreshed
+    // residual is <= 1e-3 or stops falling, BF16 noise dominates the
+    // remaining error and every later iteration runs with FP32 gathers.
+    const bool refresh = !kShadow || r.hi || (t + 1) % r.every == 0;
+    this->exact_gather = kShadow && r.hi;
+    bool changed = false;
+    for (int e = 0; e < o.bm_epochs && S.k > 0 && !(kShadow && refresh && !r.hi); ++e) {
+      if (o.bm_solver == BMG_BM_POLYMF) {
+        changed |= polymf_epoch(S.W, S.H, S.k, o.lambda);
+      } else {
+        changed |= bm_half(true, S.W, S.H, S.k, o.lambda);
+        changed |= bm_half(false, S.W, S.H, S.k, o.lambda);
       }
     }
+    r.F_bm = bm_objective(S.W, S.H, S.k, o.lambda);
+    // FP32 passes cannot resolve Ritz values below ~1e-7 of the largest, and
+    // passes gathering BF16 operands (relative rounding up to 2^-9) not below
+    // ~1e-3: the subspace iteration stops at that resolution instead of
+    // running into its iteration cap (refresh steps gather FP32)
+    const bool bf16_gathers = kShadow && !refresh && !r.hi;
+    const double floor =
+        std::max(o.ssi_tol_floor, bf16_gathers ? 1e-3 : sizeof(T) == 4 ? 1e-6 : 0.0);
+    const double tau = std::max(floor, std::min(1e-4, 0.1 * S.res_prev * S.res_prev));
+    StepInfo st = pg_step(S, changed, o.lambda, o.alpha, tau, o.ssi_max_iter, o.seed, t, refresh);
+    r.ssi_total += st.iters;
+    r.trials_total += st.trials;
+    r.alpha_last = st.alpha;
+    r.resid = st.residual;
+    r.eps = st.eps;
+    r.F = objective_balanced(S, o.lambda, refresh);
+    REQUIRE(std::isfinite(r.F) && std::isfinite(r.resid), BMG_ENONFINITE, "non-finite objective");
+    if (o.verbose)
+      fprintf(stderr,
+              "[bmg] t=%d F=%.15g F_bm=%.15g res=%.3e k=%d q=%d ssi=%d eps=%.3e add=%d alpha=%.4g "
+              "trials=%d\n",
+              t, r.F, r.F_bm, r.resid, S.k, st.q, st.iters, r.eps, (int)st.added, st.alpha, st.trials);
+    S.res_prev = r.resid;
+    if (kShadow && refresh && !r.hi) {
+      if (r.resid <= 1e-3 || r.resid > 0.7 * r.last_refresh) r.hi = true;
+      r.last_refresh = r.resid;
+    }
+    r.t = t + 1;
+    if (r.resid <= o.tol && refresh) r.conv = true;
+    r.done = r.conv || r.t >= o.max_iter;
+    return r.done;
+  }
+  bmg_status solve_end(Run &r, bmg_result *res) {
+    Acct acct(r);
+    State &S = *r.S;
     this->exact_gather = false;
-    if (kShadow) F = objective_balanced(S, o.lambda, true);
+    if (kShadow) r.F = objective_balanced(S, r.o.lambda, true);
     HIPC(hipStreamSynchronize(s));
     P->resolve_timing();
     if (res) {
@@ -1971,20 +2002,27 @@ struct Method : Engine<T, TG> {
       res->host_wait_seconds = t_wait_acc;
       res->host_syncs = n_sync_acc;
       res->k = S.k;
-      res->iters = t;
-      res->ssi_iters = ssi_total;
-      res->pg_trials = trials_total;
-      res->alpha_last = alpha_last;
-      res->status = conv ? BMG_OK : BMG_NOT_CONVERGED;
-      res->F = F;
-      res->F_bm = F_bm;
-      res->residual = resid;
-      res->eps = eps;
-      res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      res->iters = r.t;
+      res->ssi_iters = r.ssi_total;
+      res->pg_trials = r.trials_total;
+      res->alpha_last = r.alpha_last;
+      res->status = r.conv ? BMG_OK : BMG_NOT_CONVERGED;
+      res->F = r.F;
+      res->F_bm = r.F_bm;
+      res->residual = r.resid;
+      res->eps = r.eps;
+      res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - r.t0).count();
       res->sparse_bytes = P->bytes;
       res->sparse_passes = P->passes;
     }
-    return conv ? BMG_OK : BMG_NOT_CONVERGED;
+    return r.conv ? BMG_OK : BMG_NOT_CONVERGED;
+  }
+  bmg_status solve(const bmg_options &o, State &S, bmg_result *res) {
+    Run r;
+    solve_begin(o, S, r);
+    while (!solve_step(r)) {
+    }
+    return solve_end(r, res);
   }
 };
 
@@ -2073,9 +2111,10 @@ extern "C" bmg_status bmg_polymf_epochs(bmg_problem *P, double *W, double *H, in
 }
 
 extern "C" bmg_status bmg_objective(bmg_problem *P, const double *W, const double *H, int k, int ld,
-                                    double lambda, double *F) {
+                                    double lambda, double *F, double *residual) {
   bmg_status st = check_factors(P, W, H, k, ld);
   if (st != BMG_OK) return st;
+  if (residual && !(lambda > 0.0)) return fail(BMG_EINVAL, "bmg_objective: the residual needs lambda > 0");
   try {
     Method<double> M(P);
     double *Wi = M.blk(P->L.b_W), *Hi = M.blk(P->L.b_H);
@@ -2105,6 +2144,22 @@ extern "C" bmg_status bmg_objective(bmg_problem *P, const double *W, const doubl
       for (int i = 0; i < k; ++i) nuc += sqrt(std::max(w[i], 0.0));
     }
     if (F) *F = f + lambda * nuc;
+    if (residual) {
+      // one inexact PG step from X~ = W H^T at the default step and subspace
+      // settings, warm-started from W alone (as bmg_prox_step); its output stays
+      // in the workspace, the caller's factors are not touched
+      bmg_options o;
+      bmg_options_default(&o);
+      Method<double>::State S;
+      M.init_state(S);
+      S.k = k; S.kc = 0; S.kp = 0;
+      S.rank_cur = 0; S.rank_prev = 0; S.trunc_prev = 0;
+      S.has_u = false;
+      S.psi = o.psi0;
+      auto info = M.pg_step(S, true, lambda, o.alpha, o.ssi_tol_floor, o.ssi_max_iter, o.seed, 0);
+      HIPC(hipStreamSynchronize(P->s));
+      *residual = info.residual;
+    }
   } catch (const BmgError &e) {
     return fail(e.st, e.msg);
   }
@@ -2564,10 +2619,39 @@ extern "C" bmg_status bmg_prox_step(bmg_problem *P, double *W, double *H, int *k
   return BMG_OK;
 }
 
-extern "C" bmg_status bmg_solve(bmg_problem *P, double *W, double *H, int ld, const bmg_options *opt,
-                                int *k_out, bmg_result *res) {
-  if (!P || !opt || !W || !H) return fail(BMG_EINVAL, "bmg_solve: null argument");
-  if (ld < 8 || ld % 8) return fail(BMG_EINVAL, "bmg_solve: ld must be a positive multiple of 8");
+// ============================================================================ solve tasks
+struct bmg::SolveTask {
+  virtual ~SolveTask() {}
+  virtual bool step() = 0;
+  virtual bmg_status finish(double *W, double *H, int ld, int *k_out, bmg_result *res) = 0;
+  bmg_problem *P = nullptr;
+};
+
+template <typename T, typename TG>
+struct TypedTask : bmg::SolveTask {
+  Method<T, TG> M;
+  typename Method<T, TG>::State S;
+  typename Method<T, TG>::Run r;
+  TypedTask(bmg_problem *p, const bmg_options &o) : M(p) {
+    P = p;
+    M.solve_begin(o, S, r);
+  }
+  bool step() override { return M.solve_step(r); }
+  bmg_status finish(double *W, double *H, int ld, int *k_out, bmg_result *res) override {
+    const bmg_status st = M.solve_end(r, res);
+    const int k = S.k;
+    REQUIRE(k <= ld, BMG_ENOMEM, "rank exceeds ld");
+    store_factors<T>(P, S.W, S.H, k, W, H, ld);
+    HIPC(hipStreamSynchronize(P->s));
+    if (k_out) *k_out = k;
+    if (res) res->status = st;
+    return st;
+  }
+};
+
+bmg_status bmg::solve_task_create(bmg_problem *P, const bmg_options *opt, SolveTask **out) {
+  if (!P || !opt || !out) return fail(BMG_EINVAL, "bmg_solve: null argument");
+  *out = nullptr;
   if (opt->lambda <= 0.0 || opt->alpha <= 0.0 || opt->bm_epochs < 0 || opt->max_iter < 0 ||
       opt->ssi_max_iter < 1 || opt->k_init < 1 || opt->lmsvd_p < 0 ||
       opt->lmsvd_p > LMSVD_MAX_HIST || !step_rule_ok(opt) ||
@@ -2576,40 +2660,53 @@ extern "C" bmg_status bmg_solve(bmg_problem *P, double *W, double *H, int ld, co
   P->reset_stats();
   P->timing = opt->timing != 0;
   try {
-    bmg_status st;
-    int k = 0;
-    if (P->prec == BMG_FP64) {
-      Method<double> M(P);
-      Method<double>::State S;
-      st = M.solve(*opt, S, res);
-      k = S.k;
-      REQUIRE(k <= ld, BMG_ENOMEM, "rank exceeds ld");
-      store_factors<double>(P, S.W, S.H, k, W, H, ld);
-    } else if (P->prec == BMG_FP32) {
-      Method<float> M(P);
-      Method<float>::State S;
-      st = M.solve(*opt, S, res);
-      k = S.k;
-      REQUIRE(k <= ld, BMG_ENOMEM, "rank exceeds ld");
-      store_factors<float>(P, S.W, S.H, k, W, H, ld);
-    } else {
-      Method<float, bf16_t> M(P);
-      Method<float, bf16_t>::State S;
-      st = M.solve(*opt, S, res);
-      k = S.k;
-      REQUIRE(k <= ld, BMG_ENOMEM, "rank exceeds ld");
-      store_factors<float>(P, S.W, S.H, k, W, H, ld);
-    }
-    HIPC(hipStreamSynchronize(P->s));
-    P->timing = false;
-    if (k_out) *k_out = k;
-    if (res) res->status = st;
-    return st;
+    if (P->prec == BMG_FP64) *out = new TypedTask<double, double>(P, *opt);
+    else if (P->prec == BMG_FP32) *out = new TypedTask<float, float>(P, *opt);
+    else *out = new TypedTask<float, bf16_t>(P, *opt);
   } catch (const BmgError &e) {
     P->timing = false;
+    return fail(e.st, e.msg);
+  }
+  return BMG_OK;
+}
+
+bmg_status bmg::solve_task_step(SolveTask *t, int *done) {
+  try {
+    *done = t->step() ? 1 : 0;
+  } catch (const BmgError &e) {
+    t->P->timing = false;
+    return fail(e.st, e.msg);
+  }
+  return BMG_OK;
+}
+
+bmg_status bmg::solve_task_finish(SolveTask *t, double *W, double *H, int ld, int *k_out,
+                                  bmg_result *res) {
+  try {
+    const bmg_status st = t->finish(W, H, ld, k_out, res);
+    t->P->timing = false;
+    return st;
+  } catch (const BmgError &e) {
+    t->P->timing = false;
     if (res) res->status = e.st;
     return fail(e.st, e.msg);
   }
+}
+
+void bmg::solve_task_destroy(SolveTask *t) { delete t; }
+
+extern "C" bmg_status bmg_solve(bmg_problem *P, double *W, double *H, int ld, const bmg_options *opt,
+                                int *k_out, bmg_result *res) {
+  if (!P || !opt || !W || !H) return fail(BMG_EINVAL, "bmg_solve: null argument");
+  if (ld < 8 || ld % 8) return fail(BMG_EINVAL, "bmg_solve: ld must be a positive multiple of 8");
+  SolveTask *t = nullptr;
+  bmg_status st = solve_task_create(P, opt, &t);
+  int done = 0;
+  while (st == BMG_OK && !done) st = solve_task_step(t, &done);
+  if (st == BMG_OK) st = solve_task_finish(t, W, H, ld, k_out, res);
+  else if (res) res->status = st;
+  solve_task_destroy(t);
+  return st;
 }
 
 // ============================================================================ batcher API (serving)

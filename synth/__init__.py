@@ -225,22 +225,41 @@ class Request:
     rank: int
     lam: float
     seed: int
+    L: float = 0.0        # spectral level of the sampling and noise part of P_Omega(A)
+    dsig_1: float = 0.0   # d sigma_1 and d sigma_r of the truth U V^T (d = |Omega| / (m n))
+    dsig_r: float = 0.0
+
+
+def truth_levels(m: int, n: int, density: float, rank: int, seed: int, noise_var: float = 0.05):
+    """(L, d sigma_1, d sigma_r) of a serving request: L = sqrt(d (1 + noise var))
+    (sqrt(m) + sqrt(n)), the spectral norm of P_Omega(A) - d A for unit-variance
+    entries sampled with density d plus the noise, and the extreme singular
+    values of the truth U V^T (drawn exactly as request_problem draws them)
+    scaled by d, the size they have in P_Omega(A)."""
+    nnz = max(1, int(round(density * m * n)))
+    d = nnz / (m * n)
+    _, U, V = values(m, n, np.zeros(m + 1, np.int64), np.zeros(1, np.int32), rank,
+                     1.0 / math.sqrt(rank), noise_var, seed=seed + 7, keep_truth=True)
+    sig = np.sqrt(np.maximum(np.linalg.eigvalsh((U.T @ U) @ (V.T @ V)), 0.0))
+    L = math.sqrt(d * (1.0 + noise_var)) * (math.sqrt(m) + math.sqrt(n))
+    return L, d * float(sig.max()), d * float(sig.min())
 
 
 def serving_stream(count: int = 256, rate: float = 20.0, seed: int = 1005,
                    m_range=(500, 20_000), n_range=(1_000, 50_000), dens_range=(0.005, 0.02),
                    rank_range=(3, 15), lam_range=(0.1, 5.0), lam_over_noise=(1.0, 2.0),
-                   noise_var=0.05) -> list:
+                   noise_var=0.05, lam_rule: str = "levels") -> list:
     """Request descriptors of the serving workload (problems are built lazily by
     :func:`request_problem`).
 
-    lambda: with lam_over_noise set (the default), lambda = u * L with
-    u ~ U[lam_over_noise] and L = sqrt(1 + noise_var) (sqrt(n d) + sqrt(m d)),
-    the spectral norm of what sampling leaves outside the low-rank part (the
-    sampling artefact of the unit-variance truth plus the noise on Omega); a
-    lambda drawn from lam_range = [0.1, 5] sits below that level for nearly every
-    request and the solution then fits it at ranks in the hundreds.  Pass
-    lam_over_noise=None to draw from lam_range instead."""
+    lambda, by lam_rule:
+    * "levels" (the default): the midpoint of L and d sigma_r (truth_levels),
+      the level of the sampling noise in P_Omega(A) and that of the weakest
+      truth direction: where d sigma_r > L the solution has the truth's rank;
+    * "noise": lambda = u * L with u ~ U[lam_over_noise] (above the noise only:
+      a quarter of the requests then sit above d sigma_1 and end at rank 0);
+    * "uniform": lambda ~ U[lam_range], which for nearly every request lies
+      below L, so the solution fits the noise at ranks in the hundreds."""
     u = uniforms(seed, 0x77, 6 * count).reshape(count, 6)
     t = 0.0
     out = []
@@ -250,12 +269,17 @@ def serving_stream(count: int = 256, rate: float = 20.0, seed: int = 1005,
         n = int(n_range[0] + u[i, 2] * (n_range[1] - n_range[0]))
         d = dens_range[0] + u[i, 3] * (dens_range[1] - dens_range[0])
         r = int(rank_range[0] + min(rank_range[1] - rank_range[0], int(u[i, 4] * (rank_range[1] - rank_range[0] + 1))))
-        if lam_over_noise is None:
+        rs = seed * 1000 + i
+        L, ds1, dsr = truth_levels(m, n, d, r, rs, noise_var)
+        if lam_rule == "uniform":
             lam = lam_range[0] + u[i, 5] * (lam_range[1] - lam_range[0])
-        else:
-            L = math.sqrt(1.0 + noise_var) * (math.sqrt(n * d) + math.sqrt(m * d))
+        elif lam_rule == "noise":
             lam = (lam_over_noise[0] + u[i, 5] * (lam_over_noise[1] - lam_over_noise[0])) * L
-        out.append(Request(t, m, n, d, r, lam, seed * 1000 + i))
+        elif lam_rule == "levels":
+            lam = 0.5 * (L + dsr)
+        else:
+            raise ValueError("unknown lam_rule %r" % lam_rule)
+        out.append(Request(t, m, n, d, r, lam, rs, L, ds1, dsr))
     return out
 
 

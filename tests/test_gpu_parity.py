@@ -25,9 +25,10 @@ U = 2.0 ** -53
 DEV = "cuda:0"
 
 
-def to_dev(p, k_cap=32, precision="fp64"):
+def to_dev(p, k_cap=32, precision="fp64", **reserve):
+    """reserve: lmsvd_p / sparsa, the variants the workspace is sized for."""
     return bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=k_cap,
-                                 precision=precision, device=DEV)
+                                 precision=precision, device=DEV, **reserve)
 
 
 def factors(p, k, ld, seed):
@@ -167,6 +168,26 @@ def test_objective_parity(name):
 
 
 @pytest.mark.parametrize("name", ["tiny", "tall_m_gt_n", "long_rows", "powerlaw"])
+def test_objective_residual_parity(name):
+    """bmg_objective's optional residual: the relative optimality residual of
+    reading R1 at X = W H^T from one PG step at the default settings (alpha 1.99,
+    seed 0, subspace tolerance 1e-12, at most 50 iterations), against the
+    oracle's PG step from the same point; W and H are left untouched."""
+    p = case(name)
+    k, lam = 4, 0.4
+    dp = to_dev(p, k_cap=32)
+    W, H = factors(p, k, 32, seed=5)
+    Wd, Hd = t(W), t(H)
+    F, res = dp.bmg_objective(Wd, Hd, k, lam, residual=True)
+    _, _, reso = core.prox_step_standalone(p, W[:, :k], H[:, :k], lam, 1.99, seed=0, tau=1e-12,
+                                           max_iter=50)
+    print("objective residual", name, res, reso, flush=True)
+    assert math.isclose(F, core.objective(p, W[:, :k], H[:, :k], lam), rel_tol=1e-11)
+    assert math.isclose(res, reso, rel_tol=1e-5, abs_tol=1e-12)
+    assert np.array_equal(Wd.cpu().numpy(), W) and np.array_equal(Hd.cpu().numpy(), H)
+
+
+@pytest.mark.parametrize("name", ["tiny", "tall_m_gt_n", "long_rows", "powerlaw"])
 def test_prox_step_parity(name):
     p = case(name)
     lam, alpha, k = 0.4, 1.99, 4
@@ -192,7 +213,7 @@ def test_prox_step_parity_lmsvd_history(name, hp):
     oracle's LmSVD with that history length."""
     p = case(name)
     lam, alpha, k = 0.4, 1.99, 4
-    dp = to_dev(p, k_cap=32)
+    dp = to_dev(p, k_cap=32, lmsvd_p=hp)
     W, H = factors(p, k, 32, seed=5)
     Wd, Hd = t(W), t(H)
     kg, sig, res = dp.bmg_prox_step(Wd, Hd, k, lam=lam, alpha=alpha, seed=9, ssi_tol_floor=1e-13,
@@ -240,7 +261,7 @@ def test_solve_parity_fp64_lmsvd_history(shape, hp):
     recs = []
     orc = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-10, seed=3, max_iter=3000, lmsvd_p=hp),
                      callback=recs.append)
-    dp = to_dev(p, k_cap=64)
+    dp = to_dev(p, k_cap=64, lmsvd_p=hp)
     W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-10, seed=3, max_iter=3000, lmsvd_p=hp)
     print("solve history", shape, hp, r["ssi_iters"], sum(x.ssi_iters for x in recs), r["F"], orc.F,
           flush=True)
@@ -254,7 +275,7 @@ def test_solve_parity_fp64_lmsvd_history(shape, hp):
 @pytest.mark.parametrize("precision,bar", [("fp32", 1e-5), ("bf16", 1e-3)])
 def test_solve_lmsvd_history_reduced_precision(precision, bar):
     p = synth.tiny(150, 220, 5000, rank=3, lam=0.3, seed=31)
-    dp = to_dev(p, k_cap=64, precision=precision)
+    dp = to_dev(p, k_cap=64, precision=precision, lmsvd_p=1)
     W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-6 if precision == "fp32" else 1e-5, seed=3,
                               max_iter=600, lmsvd_p=1)
     Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
@@ -273,7 +294,7 @@ def test_solve_parity_fp64_sparsa(shape):
     recs = []
     orc = core.solve(p, core.Options(lam=lam, k0=4, tol=1e-10, seed=3, max_iter=3000,
                                      step_rule="sparsa"), callback=recs.append)
-    dp = to_dev(p, k_cap=128)
+    dp = to_dev(p, k_cap=128, sparsa=True)
     W, H, k, r = dp.bmg_solve(lam=lam, k_init=4, tol=1e-10, seed=3, max_iter=3000, step_rule="sparsa")
     print("sparsa", shape, r["iters"], orc.iters, r["pg_trials"], sum(x.trials for x in recs),
           r["alpha_last"], recs[-1].alpha, r["F"], orc.F, flush=True)
@@ -289,7 +310,7 @@ def test_sparsa_with_equal_bounds_is_the_fixed_step_bitwise():
     p = synth.tiny(120, 200, 4000, rank=3, lam=0.3, seed=320)
     outs = []
     for kw in ({}, {"step_rule": "sparsa", "alpha_min": 1.99, "alpha_max": 1.99}):
-        W, H, k, r = to_dev(p, k_cap=64).bmg_solve(lam=0.3, k_init=4, tol=1e-10, seed=3, **kw)
+        W, H, k, r = to_dev(p, k_cap=64, sparsa=True).bmg_solve(lam=0.3, k_init=4, tol=1e-10, seed=3, **kw)
         outs.append((W.cpu().numpy(), H.cpu().numpy(), k, r["iters"], r["pg_trials"]))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     assert outs[0][2:] == outs[1][2:] and outs[1][4] == outs[1][3]
@@ -297,7 +318,7 @@ def test_sparsa_with_equal_bounds_is_the_fixed_step_bitwise():
 
 def test_solve_sparsa_fp32_objective_error():
     p = synth.tiny(150, 220, 5000, rank=3, lam=0.3, seed=31)
-    dp = to_dev(p, k_cap=64, precision="fp32")
+    dp = to_dev(p, k_cap=64, precision="fp32", sparsa=True)
     W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-6, seed=3, max_iter=600, step_rule="sparsa")
     Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], 0.3)
     Fstar = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-11, seed=3)).F
@@ -342,7 +363,7 @@ def test_solve_parity_all_variants_together(shape):
     p = synth.tiny(m, n, nnz, rank=3, lam=0.3, seed=m + n + 1)
     orc = core.solve(p, core.Options(lam=0.3, k0=4, tol=1e-10, seed=5, max_iter=3000, bm_solver="polymf",
                                      step_rule="sparsa", lmsvd_p=1))
-    dp = to_dev(p, k_cap=64)
+    dp = to_dev(p, k_cap=64, lmsvd_p=1, sparsa=True)
     W, H, k, r = dp.bmg_solve(lam=0.3, k_init=4, tol=1e-10, seed=5, max_iter=3000, bm_solver="polymf",
                               step_rule="sparsa", lmsvd_p=1)
     print("all variants", shape, r["iters"], orc.iters, r["pg_trials"], r["F"], orc.F, flush=True)
@@ -452,6 +473,13 @@ def test_invalid_inputs_are_rejected():
                {"step_rule": "sparsa", "sparsa_delta": 0.0}):
         with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
             dp.bmg_solve(lam=0.1, **kw)
+    # variants the workspace was not sized for are refused, nothing is allocated
+    with pytest.raises(bmg.BmgError, match="BMG_ENOMEM"):
+        dp.bmg_solve(lam=0.1, lmsvd_p=1)
+    with pytest.raises(bmg.BmgError, match="BMG_ENOMEM"):
+        dp.bmg_solve(lam=0.1, step_rule="sparsa")
+    with pytest.raises(bmg.BmgError, match="BMG_ENOMEM"):
+        to_dev(p, k_cap=8, lmsvd_p=1).bmg_solve(lam=0.1, lmsvd_p=2)
 
 
 # ----------------------------------------------------------------------------- full size, sampled

@@ -1,6 +1,9 @@
 """Serving loop (bmg_server_*): continuous admission by HBM footprint, several
 problems running at once with their sparse passes sharing launches, and every
-result identical to the same problem solved alone by the plain entry point."""
+result identical to the same problem solved alone by the plain entry point and
+within the precision's bar of the oracle's solve of the same request with the
+same options (relative objective error 1e-8 in FP64, 1e-5 in FP32, 1e-3 in
+BF16)."""
 import math
 
 import numpy as np
@@ -9,9 +12,30 @@ import torch
 
 import paper_2204_14067_amd as bmg
 import synth
+from oracle import core
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
+BAR = {"fp64": 1e-8, "fp32": 1e-5, "bf16": 1e-3}
+_orc = {}
+
+
+def oracle_F(p, lam, opts):
+    """F of the oracle's solve of the request with the served options (cached)."""
+    key = (p.name, lam, tuple(sorted(opts.items())))
+    if key not in _orc:
+        o = dict(opts)
+        k0 = o.pop("k_init")
+        r = core.solve(p, core.Options(lam=lam, k0=k0, **o))
+        assert r.converged
+        _orc[key] = r.F
+    return _orc[key]
+
+
+def check_against_oracle(p, lam, F_served, precision, opts):
+    Fo = oracle_F(p, lam, opts)
+    print("oracle", p.name, lam, precision, F_served, Fo, abs(F_served - Fo) / Fo, flush=True)
+    assert abs(F_served - Fo) <= BAR[precision] * Fo
 
 
 def small_requests(count=6):
@@ -49,6 +73,7 @@ def test_serving_alone_equals_mix_and_admission_binds():
         assert info["k"] == k
         assert info["result"]["F"] == F              # bitwise: the same kernels on the same data
         assert np.all(W[:, k:] == 0)
+        check_against_oracle(p, r.lam, info["result"]["F"], "fp32", opts)
     srv.close()
 
 
@@ -86,33 +111,82 @@ def test_serving_mixed_precisions_equal_plain_solves():
         assert info["state"] == 2 and info["status"] == status
         assert info["k"] == k and info["result"]["F"] == F
         assert np.array_equal(W[:, :k], W0)
+        check_against_oracle(p, r.lam, info["result"]["F"], pr, opts)
     srv.close()
 
 
 def test_serving_solver_variants_equal_plain_solves():
     """Requests with the polyMF-SS BM solver, the SpaRSA step rule and LmSVD
-    history in one FP64 server beside default requests (lambda lowered so that
-    every solution has positive rank): every result is bit for bit the plain
-    entry point's with the same options."""
+    history in one FP64 server beside default requests: every result is bit for
+    bit the plain entry point's with the same options, and within 1e-8 of the
+    oracle's solve with those options."""
     items = small_requests(4)
-    variants = [dict(bm_solver="polymf"), dict(step_rule="sparsa"), dict(lmsvd_p=1), {}]
+    variants = [dict(bm_solver="polymf"), dict(step_rule="sparsa"), dict(lmsvd_p=2), {}]
     base = dict(tol=1e-6, k_init=8, max_iter=2000, seed=13)
     plain = []
     for (r, p), v in zip(items, variants):
         dp = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp64",
-                                   device=DEV)
-        W, H, k, res = dp.bmg_solve(lam=0.3 * r.lam, **base, **v)
+                                   device=DEV, lmsvd_p=v.get("lmsvd_p", 0),
+                                   sparsa=v.get("step_rule") == "sparsa")
+        W, H, k, res = dp.bmg_solve(lam=r.lam, **base, **v)
         plain.append((k, res["F"], res["status"], W.cpu().numpy()[:, :k].copy()))
         print("plain", v, p.name, k, res["F"], res["iters"], flush=True)
-    srv = bmg.Server(sum(bmg.Server.footprint(p.m, p.n, p.nnz, 64, "fp64") for _, p in items) + (1 << 20),
-                     max_slots=4, device=DEV)
-    tickets = [srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp64", lam=0.3 * r.lam,
+    # each request's footprint counts its variant's workspace (history blocks,
+    # SpaRSA state): nothing is allocated outside the arena
+    fps = [bmg.Server.footprint(p.m, p.n, p.nnz, 64, "fp64", **v) for (_, p), v in zip(items, variants)]
+    assert fps[2] > bmg.Server.footprint(items[2][1].m, items[2][1].n, items[2][1].nnz, 64, "fp64")
+    assert fps[1] > bmg.Server.footprint(items[1][1].m, items[1][1].n, items[1][1].nnz, 64, "fp64")
+    arena = sum(fps) + (1 << 20)
+    srv = bmg.Server(arena, max_slots=4, device=DEV)
+    tickets = [srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp64", lam=r.lam,
                           **base, **v) for (r, p), v in zip(items, variants)]
     srv.drain()
-    for (r, p), v, t, (k, F, status, W0) in zip(items, variants, tickets, plain):
+    st = srv.stats()
+    assert st["peak_bytes"] <= arena
+    for (r, p), v, t, (k, F, status, W0), fp in zip(items, variants, tickets, plain, fps):
         info, W, H = srv.poll(t, p.m, p.n, 64)
         print("served", v, p.name, info["k"], info["result"]["F"], F, flush=True)
         assert info["state"] == 2 and info["status"] == status
+        assert info["footprint"] == fp
         assert info["k"] == k and info["result"]["F"] == F
+        assert np.array_equal(W[:, :k], W0)
+        check_against_oracle(p, r.lam, info["result"]["F"], "fp64", dict(base, **v))
+    srv.close()
+
+
+def test_serving_driven_by_tick_equals_plain_solves():
+    """A server without worker threads, driven by bmg_server_tick on this thread
+    (each tick admits what fits and advances every running solve by one outer
+    iteration): admission still binds on the arena, and every result is bit
+    for bit the plain entry point's."""
+    items = small_requests(6)
+    opts = dict(tol=1e-5, k_init=8, max_iter=2000, seed=5)
+    plain = []
+    for r, p in items:
+        dp = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp32",
+                                   device=DEV)
+        W, H, k, res = dp.bmg_solve(lam=r.lam, **opts)
+        plain.append((k, res["F"], res["status"], res["iters"], W.cpu().numpy()[:, :k].copy()))
+    fps = [bmg.Server.footprint(p.m, p.n, p.nnz, 64, "fp32") for _, p in items]
+    arena = int(2.2 * max(fps))
+    srv = bmg.Server(arena, max_slots=3, device=DEV, threads=False)
+    tickets = [srv.submit(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp32", lam=r.lam,
+                          **opts) for r, p in items]
+    ticks, most = 0, 0
+    while True:
+        running, queued = srv.tick()
+        ticks += 1
+        most = max(most, running)
+        if running == 0 and queued == 0:
+            break
+        assert ticks < 20000
+    st = srv.stats()
+    print("tick stats", st, "ticks", ticks, "arena", arena, flush=True)
+    assert st["peak_bytes"] <= arena and 1 <= most <= 3 and st["shared_launches"] == 0
+    assert ticks >= max(x[3] for x in plain)
+    for (r, p), t, (k, F, status, iters, W0) in zip(items, tickets, plain):
+        info, W, H = srv.poll(t, p.m, p.n, 64)
+        assert info["state"] == 2 and info["status"] == status
+        assert info["k"] == k and info["result"]["F"] == F and info["result"]["iters"] == iters
         assert np.array_equal(W[:, :k], W0)
     srv.close()

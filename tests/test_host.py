@@ -52,18 +52,51 @@ def test_options_default(lib):
 def test_workspace_size_and_argument_checks(lib):
     from paper_2204_14067_amd import _lib
     nb = ctypes.c_size_t(0)
-    assert lib.bmg_workspace_size(1000, 1500, 50_000, 128, _lib.BMG_FP64, ctypes.byref(nb)) == 0
+    assert lib.bmg_workspace_size(1000, 1500, 50_000, 128, _lib.BMG_FP64, None, ctypes.byref(nb)) == 0
     small = nb.value
     assert small > 50_000 * 36
-    assert lib.bmg_workspace_size(1000, 1500, 500_000, 128, _lib.BMG_FP64, ctypes.byref(nb)) == 0
+    assert lib.bmg_workspace_size(1000, 1500, 500_000, 128, _lib.BMG_FP64, None, ctypes.byref(nb)) == 0
     assert nb.value > small
-    assert lib.bmg_workspace_size(-1, 5, 5, 8, 0, ctypes.byref(nb)) == _lib.BMG_EINVAL
+    assert lib.bmg_workspace_size(-1, 5, 5, 8, 0, None, ctypes.byref(nb)) == _lib.BMG_EINVAL
     assert b"bad shape" in lib.bmg_last_error()
-    assert lib.bmg_workspace_size(10, 10, 5, 0, 0, ctypes.byref(nb)) == _lib.BMG_EINVAL
-    assert lib.bmg_workspace_size(10, 10, 5, 4096, 0, ctypes.byref(nb)) == _lib.BMG_EINVAL
+    assert lib.bmg_workspace_size(10, 10, 5, 0, 0, None, ctypes.byref(nb)) == _lib.BMG_EINVAL
+    assert lib.bmg_workspace_size(10, 10, 5, 4096, 0, None, ctypes.byref(nb)) == _lib.BMG_EINVAL
     # creating with a null CSR is rejected before any device call
     h = ctypes.c_void_p()
-    assert lib.bmg_problem_create(None, 8, 0, None, 0, None, ctypes.byref(h)) == _lib.BMG_EINVAL
+    assert lib.bmg_problem_create(None, 8, 0, None, None, 0, None, ctypes.byref(h)) == _lib.BMG_EINVAL
+
+
+def test_workspace_reserves_history_and_sparsa_state(lib):
+    """The workspace grows by exactly the regions the solver variants need:
+    (2p - 1) short-side and 3p long-side blocks of qb columns for p history
+    blocks, and for SpaRSA one short-side block, (m + n) rows at ld_k and two
+    nnz-vectors (FP64 here, qb = 2 k_cap + 2 and ld_k = k_cap, both rounded up to
+    16, every region rounded up to 256 bytes)."""
+    from paper_2204_14067_amd import _lib
+    m, n, nnz, kc = 1000, 1500, 50_000, 40
+    qb, ldk = (2 * kc + 2 + 15) // 16 * 16, (kc + 15) // 16 * 16
+    r256 = lambda b: (b + 255) // 256 * 256                        # noqa: E731
+    size = {}
+    for p_, rule in ((0, 0), (1, 0), (3, 0), (0, 1)):
+        o = _lib.BmgOptions()
+        lib.bmg_options_default(ctypes.byref(o))
+        o.lmsvd_p, o.step_rule = p_, rule
+        nb = ctypes.c_size_t(0)
+        assert lib.bmg_workspace_size(m, n, nnz, kc, _lib.BMG_FP64, ctypes.byref(o), ctypes.byref(nb)) == 0
+        size[(p_, rule)] = nb.value
+    base = size[(0, 0)]
+    mb, lb = r256(8 * m * qb), r256(8 * n * qb)
+    # every region is rounded up to a multiple of 256 bytes plus one guard unit
+    for p_ in (1, 3):
+        need = (2 * p_ - 1) * mb + 3 * p_ * lb
+        assert need <= size[(p_, 0)] - base <= need + 256
+    sp = r256(8 * m * qb) + r256(8 * m * ldk) + r256(8 * n * ldk) + 2 * r256(8 * nnz)
+    assert sp <= size[(0, 1)] - base <= sp + 256
+    o = _lib.BmgOptions()
+    lib.bmg_options_default(ctypes.byref(o))
+    o.lmsvd_p = 5
+    nb = ctypes.c_size_t(0)
+    assert lib.bmg_workspace_size(m, n, nnz, kc, _lib.BMG_FP64, ctypes.byref(o), ctypes.byref(nb)) == _lib.BMG_EINVAL
 
 
 def test_no_cpu_fallback_without_gpu():
