@@ -1,20 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the BM-Global matrix-completion hot path on one MI355X.
 
-Workload: the Netflix-shaped synthetic problem (17,770 x 480,189, |Omega| = 1e8,
-capped Zipf(1.2) row and column degrees, rank-20 truth + noise, lambda = 20,
-k0 = 16), FP64.  One step = one call of bmg_solve limited to one outer
-iteration: HMT + Nystrom initialisation, 3 BM epochs, one inexact PG step
-(subspace iteration + exact SVD + soft-threshold) and the objective, every
-sparse pass in the library's HIP kernels.  Every step starts from the same
-state, so every step does identical work.
+Headline workload: the Yahoo! Music-shaped synthetic problem (624,961 x
+1,000,990, |Omega| = 2.5e8, power-law (1.1) row and column degrees, rank-30
+truth + noise variance 0.5, lambda = 50, k0 = 32), FP64: the largest of the
+benchmark configurations.  One step = one call of bmg_solve limited to one
+outer iteration: HMT + Nystrom initialisation, 3 BM epochs, one inexact PG
+step (subspace iteration + exact SVD + soft-threshold) and the objective,
+every sparse pass in the library's HIP kernels.  Every step starts from the
+same state, so every step does identical work.  --workload netflix runs the
+Netflix-shaped problem (17,770 x 480,189, |Omega| = 1e8, lambda = 20, k0 = 16)
+instead; with extras on, its step runs beside the headline anyway.
 
 value = algorithmic bytes of all sparse passes of the timed steps / wall time.
 roofline = the kernel class with the largest time, its algorithmic bytes per
 launch / its launch time, both from HIP events on the problem's stream.
 cpu_baseline = the CPU oracle's residual + product pair on the same data.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload yahoo|netflix]
 """
 import argparse
 import json
@@ -27,6 +30,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# the benchmark workloads (synth generators): the Yahoo! Music-shaped one is the
+# largest of the configurations and carries the headline line
+WORKLOADS = {
+    "yahoo": dict(gen="yahoo_shape", name="yahoo_shape", k0=32, lam=50.0, k_cap=80,
+                  desc="power-law (1.1) degrees, rank-30 truth + noise var 0.5"),
+    "netflix": dict(gen="netflix_shape", name="netflix_shape", k0=16, lam=20.0, k_cap=64,
+                    desc="capped Zipf(1.2) degrees, rank-20 truth + noise var 0.25 clipped to [1, 5]"),
+}
 KERNEL_NAMES = ["k_grad (fused sampled residual + sparse product)",
                 "k_sddmm (sampled residual / curvature)",
                 "k_spmm (sparse x dense of the subspace iteration)"]
@@ -37,10 +48,11 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def traffic_for(kernel_symbol, workload):
+def traffic_for(kernel_symbol, workload, precision="fp64"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel_symbol, workload))
+    suffix = "" if precision == "fp64" else "_" + precision
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s%s.json" % (kernel_symbol, workload, suffix))
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -50,9 +62,10 @@ def traffic_for(kernel_symbol, workload):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(p, k=16):
-    """Oracle R = P_Omega(W H^T - A) then G = R H over the whole workload, FP64,
-    on the host cores; bytes counted with the same formula as the GPU pass."""
+def cpu_baseline(p, k):
+    """Oracle R = P_Omega(W H^T - A) then G = R H over the whole workload at the
+    workload's k0, FP64, on the host cores; bytes counted with the same formula
+    as the GPU pass."""
     import numpy as np
     from oracle import core
     rng = np.random.default_rng(0)
@@ -70,8 +83,8 @@ def cpu_baseline(p, k=16):
     cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
     return {"value": round(nbytes * reps / t_tot / 1e9, 3), "unit": "GB/s", "cores": cores,
             "kind": "oracle",
-            "sample": "%d x (residual pass + row-oriented sparse product) over the full workload, "
-                      "k=16, FP64, %.1f s" % (reps, t_tot)}
+            "sample": "%d x (residual pass + row-oriented sparse product) over the full workload "
+                      "%s, k=%d, FP64, %.1f s" % (reps, p.name, k, t_tot)}
 
 
 def main():
@@ -82,6 +95,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--bm-solver", default="psd", choices=["psd", "polymf"],
                     help="BM solver of the step (psd: gradient steps, the default; polymf: polyMF-SS)")
+    ap.add_argument("--workload", default="yahoo", choices=sorted(WORKLOADS),
+                    help="yahoo: 624,961 x 1,000,990, |Omega| = 2.5e8 (the headline); netflix: 17,770 x "
+                         "480,189, |Omega| = 1e8")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -133,31 +149,82 @@ def main():
                           "copies": 3}))
         return
     t0 = time.time()
-    p = synth.netflix_shape(scale=args.scale)
+    p = getattr(synth, WORKLOADS[args.workload]["gen"])(scale=args.scale)
     log("workload %s generated in %.1fs" % (p.name, time.time() - t0))
-    k0, lam = 16, 20.0
+    wl = WORKLOADS[args.workload]
     # the workspace also holds two LmSVD history blocks (the history comparison)
-    prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64,
-                                 precision=args.precision, device=dev,
-                                 lmsvd_p=0 if args.no_extras else 2)
+    line, prob, W, H, recs, sec = step_line(bmg, p, args.workload, args.scale, args.precision, args.steps,
+                                            args.warmup, args.bm_solver, dev,
+                                            hist=0 if args.no_extras or args.workload != "netflix" else 2)
+    out = {
+        "metric": "SDDMM+SpMM GB/s (% HBM peak); time-to-tol vs plain; serve p50/p99 latency",
+        "value": line["value"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": line["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": line["dtype"], "data": "synthetic",
+        "config": line["config"], "roofline": line["roofline"], "kernels": line["kernels"],
+    }
+    if not args.no_extras:
+        if args.workload == "yahoo":
+            # the same step in FP32 on this workload, and the Netflix-shaped
+            # workload's step (FP64 and the lower precisions, and the variants)
+            out["yahoo_shape_fp32"] = step_line(bmg, p, "yahoo", args.scale, "fp32", 3, 1, "psd", dev)[0]
+            del prob, W, H
+            import torch
+            torch.cuda.empty_cache()
+            q = synth.netflix_shape(scale=args.scale)
+            nline, prob, W, H, recs, sec = step_line(bmg, q, "netflix", args.scale, "fp64", 5, 1, "psd", dev,
+                                                      hist=2)
+            out["netflix_shape_fp64"] = nline
+        else:
+            q = p
+        kq, lq = WORKLOADS["netflix"]["k0"], WORKLOADS["netflix"]["lam"]
+        out["lmsvd_history"] = lmsvd_history(bmg, synth, dev, prob, W, H, kq, lq, recs, sec)
+        out["precision_modes"] = precision_steps(bmg, q, dev, kq, lq, recs[-1]["F"])
+        out["time_to_tol"] = time_to_tol(bmg, synth, dev)
+        out["time_to_tol_gpu_bound"] = time_to_tol_gpu_bound(bmg, synth, dev)
+        out["sparsa_step"] = sparsa_step(bmg, synth, dev, out["time_to_tol"]["fp64"],
+                                         out["time_to_tol_gpu_bound"]["lambda_100"]["fp64"])
+        out["polymf_bm"] = polymf_bm(bmg, synth, dev, prob, q, out["time_to_tol"]["fp64"],
+                                     out["time_to_tol_gpu_bound"]["lambda_100"]["fp64"])
+        del prob
+        out["rke_qsdp"] = rke_qsdp(bmg, synth, dev)
+        out["serve"] = serving(bmg, synth, dev, args.serve_count)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(p, wl["k0"])
+    print(json.dumps(out), flush=True)
+
+
+def step_line(bmg, p, workload, scale, precision, steps, warmup, bm_solver, dev, hist=0):
+    """Times `steps` benchmark steps (after `warmup`) on problem p: one step is
+    bmg_solve limited to one outer iteration (initialisation, 3 BM epochs, one
+    PG step, objective), every step from the same state.  Returns the line's
+    fields, the problem, its factor buffers, the step records and seconds per
+    step."""
+    import torch
+    wl = WORKLOADS[workload]
+    k0, lam, k_cap = wl["k0"], wl["lam"], wl["k_cap"]
+    prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=k_cap, precision=precision,
+                                 device=dev, lmsvd_p=hist)
     W, H = prob.zeros_factors()
-    log("problem resident on %s (%.2f GB workspace)" % (dev, prob.ws.numel() / 1e9))
+    log("%s %s resident on %s (%.2f GB workspace)" % (p.name, precision, dev, prob.ws.numel() / 1e9))
 
     def step():
         return prob.bmg_solve(W, H, lam=lam, k_init=k0, max_iter=1, tol=0.0, seed=1003, timing=1,
-                              bm_solver=args.bm_solver)[3]
+                              bm_solver=bm_solver)[3]
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         r = step()
         log("warmup %d: k=%d F=%.6g passes=%d" % (i, r["k"], r["F"], r["sparse_passes"]))
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     recs = []
-    for i in range(args.steps):
+    for i in range(steps):
         recs.append(step())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    log("timed %d steps in %.3fs" % (args.steps, elapsed))
+    log("%s %s: timed %d steps in %.3fs" % (workload, precision, steps, elapsed))
     nbytes = sum(r["sparse_bytes"] for r in recs)
     value = nbytes / elapsed / 1e9
     kms = [sum(r["kernel_ms"][c] for r in recs) for c in range(3)]
@@ -165,18 +232,15 @@ def main():
     kla = [sum(r["kernel_launches"][c] for r in recs) for c in range(3)]
     dom = max(range(3), key=lambda c: kms[c])
     achieved = kby[dom] / (kms[dom] / 1e3) / 1e9 if kms[dom] > 0 else 0.0
-    workload = "netflix_shape" if args.scale == 1.0 else "netflix_shape_x%g" % args.scale
-    traffic = traffic_for(KERNEL_SYMBOLS[dom], workload)
-    out = {
-        "metric": "SDDMM+SpMM GB/s (% HBM peak); time-to-tol vs plain; serve p50/p99 latency",
-        "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision], "data": "synthetic",
-        "config": {"workload": "%s: %dx%d, nnz=%d, capped Zipf(1.2) degrees, rank-20 truth + "
-                               "noise var 0.25, lambda=20, k0=16" % (workload, p.m, p.n, p.nnz),
+    name = wl["name"] if scale == 1.0 else "%s_x%g" % (wl["name"], scale)
+    traffic = traffic_for(KERNEL_SYMBOLS[dom], name, precision)
+    line = {
+        "value": round(value, 3), "ms_per_step": round(elapsed / steps * 1e3, 3),
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[precision],
+        "config": {"workload": "%s: %dx%d, nnz=%d, %s, lambda=%g, k0=%d" % (
+                       name, p.m, p.n, p.nnz, wl["desc"], lam, k0),
                    "step": "init (HMT+Nystrom) + 3 BM epochs + 1 inexact PG step + objective",
-                   "precision": args.precision, "bm_solver": args.bm_solver,
+                   "precision": precision, "bm_solver": bm_solver, "k_cap": k_cap,
                    "rank_after_step": recs[-1]["k"],
                    "ssi_iters_per_step": recs[-1]["ssi_iters"],
                    "sparse_passes_per_step": recs[-1]["sparse_passes"],
@@ -190,24 +254,9 @@ def main():
         "kernels": {KERNEL_SYMBOLS[c]: {"launches": kla[c], "ms": round(kms[c], 3),
                                         "GB/s": round(kby[c] / (kms[c] / 1e3) / 1e9, 2) if kms[c] else None}
                     for c in range(3)},
+        "F_after_step": recs[-1]["F"],
     }
-    if not args.no_extras:
-        out["lmsvd_history"] = lmsvd_history(bmg, synth, dev, prob, W, H, k0, lam, recs,
-                                             elapsed / args.steps)
-        out["precision_modes"] = precision_steps(bmg, p, dev, k0, lam, recs[-1]["F"])
-        out["time_to_tol"] = time_to_tol(bmg, synth, dev)
-        out["time_to_tol_gpu_bound"] = time_to_tol_gpu_bound(bmg, synth, dev)
-        out["sparsa_step"] = sparsa_step(bmg, synth, dev, out["time_to_tol"]["fp64"],
-                                         out["time_to_tol_gpu_bound"]["lambda_100"]["fp64"])
-        if args.precision == "fp64":
-            out["polymf_bm"] = polymf_bm(bmg, synth, dev, prob, p, out["time_to_tol"]["fp64"],
-                                         out["time_to_tol_gpu_bound"]["lambda_100"]["fp64"])
-        out["rke_qsdp"] = rke_qsdp(bmg, synth, dev)
-        out["serve"] = serving(bmg, synth, dev, args.serve_count)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(p)
-    print(json.dumps(out), flush=True)
+    return line, prob, W, H, recs, elapsed / steps
 
 
 def lmsvd_history(bmg, synth, dev, prob, W, H, k0, lam, recs0, sec0, steps=3):

@@ -406,6 +406,45 @@ def test_solve_small_uniform_matches_golden(golden_dir):
     assert k == g["rank"]
 
 
+def test_netflix_quarter_solves_match_the_certified_optimum(golden_dir):
+    """Netflix-shaped generator at scale 0.25 (4,442 x 120,047, |Omega| = 6.25e6,
+    power-law degrees), lambda = 300, k0 = 16: the FP64, FP32 and BF16 solves
+    against the oracle optimum stored in tests/golden (its duality gap certifies
+    it to 2e-10 relative): objective error <= 1e-8 (FP64), 1e-5 (FP32) and 1e-3
+    (BF16, FP64 refresh every 5 iterations), same rank."""
+    g = json.load(open(os.path.join(golden_dir, "netflix_quarter_lam300.json")))
+    assert g["dual_gap"] <= 1e-9 * g["F"]
+    p = synth.netflix_shape(scale=0.25)
+    assert p.name == g["problem"]
+    evaluator = to_dev(p, k_cap=64)
+    for prec, tol, bar in (("fp64", 1e-8, 1e-8), ("fp32", 1e-6, 1e-5), ("bf16", 1e-5, 1e-3)):
+        dp = to_dev(p, k_cap=64, precision=prec)
+        W, H, k, r = dp.bmg_solve(lam=g["lam"], k_init=g["k0"], tol=tol, seed=3, max_iter=1000)
+        F64 = evaluator.bmg_objective(W, H, k, g["lam"])
+        err = abs(F64 - g["F"]) / g["F"]
+        print("netflix x0.25", prec, r["status"], r["iters"], k, r["F"], F64, err, flush=True)
+        assert r["status"] == 0 and k == g["rank"]
+        assert err <= bar
+        del dp
+
+
+def test_powerlaw_solve_three_iterations_matches_oracle():
+    """The Netflix-shaped generator at scale 0.03 (power-law rows and columns,
+    fully dense rows): three outer iterations from the same seed on both sides,
+    objective and rank after each solve's last iteration."""
+    p = case("powerlaw")
+    lam = 20.0
+    dp = to_dev(p, k_cap=64)
+    W, H, k, r = dp.bmg_solve(lam=lam, k_init=8, tol=0.0, seed=4, max_iter=3)
+    orc = core.solve(p, core.Options(lam=lam, k0=8, tol=0.0, seed=4, max_iter=3))
+    print("powerlaw 3 iterations", r["F"], orc.F, k, orc.k, r["residual"], orc.residual, flush=True)
+    assert r["iters"] == 3 and orc.iters == 3
+    assert k == orc.k
+    assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
+    Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], lam)
+    assert math.isclose(Fw, r["F"], rel_tol=1e-10)
+
+
 def test_solve_fp32_objective_error():
     p = synth.tiny(150, 220, 5000, rank=3, lam=0.3, seed=31)
     dp, W, H, k, r, orc = solve_both(p, 0.3, 4, 1e-6, precision="fp32")
