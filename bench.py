@@ -99,6 +99,8 @@ def main():
                     help="yahoo: 624,961 x 1,000,990, |Omega| = 2.5e8 (the headline); netflix: 17,770 x "
                          "480,189, |Omega| = 1e8")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
+    ap.add_argument("--dense-rows", type=float, default=0.25,
+                    help="rows of Omega at least this dense go to the dense panel (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -155,7 +157,8 @@ def main():
     # the workspace also holds two LmSVD history blocks (the history comparison)
     line, prob, W, H, recs, sec = step_line(bmg, p, args.workload, args.scale, args.precision, args.steps,
                                             args.warmup, args.bm_solver, dev,
-                                            hist=0 if args.no_extras or args.workload != "netflix" else 2)
+                                            hist=0 if args.no_extras or args.workload != "netflix" else 2,
+                                            dense_rows=args.dense_rows)
     out = {
         "metric": "SDDMM+SpMM GB/s (% HBM peak); time-to-tol vs plain; serve p50/p99 latency",
         "value": line["value"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -168,13 +171,14 @@ def main():
         if args.workload == "yahoo":
             # the same step in FP32 on this workload, and the Netflix-shaped
             # workload's step (FP64 and the lower precisions, and the variants)
-            out["yahoo_shape_fp32"] = step_line(bmg, p, "yahoo", args.scale, "fp32", 3, 1, "psd", dev)[0]
+            out["yahoo_shape_fp32"] = step_line(bmg, p, "yahoo", args.scale, "fp32", 3, 1, "psd", dev,
+                                                dense_rows=args.dense_rows)[0]
             del prob, W, H
             import torch
             torch.cuda.empty_cache()
             q = synth.netflix_shape(scale=args.scale)
             nline, prob, W, H, recs, sec = step_line(bmg, q, "netflix", args.scale, "fp64", 5, 1, "psd", dev,
-                                                      hist=2)
+                                                      hist=2, dense_rows=args.dense_rows)
             out["netflix_shape_fp64"] = nline
         else:
             q = p
@@ -196,7 +200,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def step_line(bmg, p, workload, scale, precision, steps, warmup, bm_solver, dev, hist=0):
+def step_line(bmg, p, workload, scale, precision, steps, warmup, bm_solver, dev, hist=0, dense_rows=0.0):
     """Times `steps` benchmark steps (after `warmup`) on problem p: one step is
     bmg_solve limited to one outer iteration (initialisation, 3 BM epochs, one
     PG step, objective), every step from the same state.  Returns the line's
@@ -206,7 +210,7 @@ def step_line(bmg, p, workload, scale, precision, steps, warmup, bm_solver, dev,
     wl = WORKLOADS[workload]
     k0, lam, k_cap = wl["k0"], wl["lam"], wl["k_cap"]
     prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=k_cap, precision=precision,
-                                 device=dev, lmsvd_p=hist)
+                                 device=dev, lmsvd_p=hist, dense_rows=dense_rows if bm_solver == "psd" else 0.0)
     W, H = prob.zeros_factors()
     log("%s %s resident on %s (%.2f GB workspace)" % (p.name, precision, dev, prob.ws.numel() / 1e9))
 
@@ -241,6 +245,7 @@ def step_line(bmg, p, workload, scale, precision, steps, warmup, bm_solver, dev,
                        name, p.m, p.n, p.nnz, wl["desc"], lam, k0),
                    "step": "init (HMT+Nystrom) + 3 BM epochs + 1 inexact PG step + objective",
                    "precision": precision, "bm_solver": bm_solver, "k_cap": k_cap,
+                   "dense_rows": dense_rows if bm_solver == "psd" else 0.0,
                    "rank_after_step": recs[-1]["k"],
                    "ssi_iters_per_step": recs[-1]["ssi_iters"],
                    "sparse_passes_per_step": recs[-1]["sparse_passes"],

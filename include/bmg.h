@@ -104,6 +104,9 @@ typedef struct {
   double alpha_max;
   double sparsa_beta;   /* SpaRSA: backtracking factor in (0, 1)                 */
   double sparsa_delta;  /* SpaRSA: delta of eq. back in (0, 1)                   */
+  double dense_rows;    /* rows of Omega (on the shorter side) with at least     *
+                         * dense_rows * (longer side) entries go to a dense      *
+                         * panel (0: none; see bmg_problem_create)               */
 } bmg_options;
 
 typedef struct {

@@ -58,10 +58,11 @@ class Problem:
     row_ptr (int64, m+1), col (int32, nnz), val (float64, nnz) are device
     tensors that must stay alive; the workspace is a torch allocation owned by
     this object.  lmsvd_p / sparsa reserve workspace for solves with that many
-    LmSVD history blocks / with the SpaRSA step rule (bmg_workspace_size)."""
+    LmSVD history blocks / with the SpaRSA step rule (bmg_workspace_size);
+    dense_rows > 0 moves the rows at least that dense into a dense panel."""
 
     def __init__(self, row_ptr, col, val, m: int, n: int, k_cap: int = 64, precision: str = "fp64",
-                 device=None, lmsvd_p: int = 0, sparsa: bool = False):
+                 device=None, lmsvd_p: int = 0, sparsa: bool = False, dense_rows: float = 0.0):
         lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("paper_2204_14067_amd needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -72,7 +73,8 @@ class Problem:
         self.m, self.n, self.nnz, self.k_cap = int(m), int(n), int(col.numel()), int(k_cap)
         self.precision = _PREC[precision]
         nbytes = ctypes.c_size_t(0)
-        self.reserve = options(lmsvd_p=lmsvd_p, step_rule="sparsa" if sparsa else "fixed")
+        self.reserve = options(lmsvd_p=lmsvd_p, step_rule="sparsa" if sparsa else "fixed",
+                               dense_rows=dense_rows)
         _lib.check(lib.bmg_workspace_size(self.m, self.n, self.nnz, self.k_cap, self.precision,
                                           ctypes.byref(self.reserve), ctypes.byref(nbytes)))
         self.ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
@@ -88,10 +90,10 @@ class Problem:
 
     @classmethod
     def from_host(cls, row_ptr, col, val, m, n, k_cap=64, precision="fp64", device="cuda:0",
-                  lmsvd_p=0, sparsa=False):
+                  lmsvd_p=0, sparsa=False, dense_rows=0.0):
         t = lambda a, dt: torch.as_tensor(a).to(device=device, dtype=dt).contiguous()  # noqa: E731
         return cls(t(row_ptr, torch.int64), t(col, torch.int32), t(val, torch.float64), m, n, k_cap,
-                   precision, device, lmsvd_p=lmsvd_p, sparsa=sparsa)
+                   precision, device, lmsvd_p=lmsvd_p, sparsa=sparsa, dense_rows=dense_rows)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -43,7 +43,8 @@ class BmgOptions(ctypes.Structure):
                 ("timing", ctypes.c_int), ("lmsvd_p", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("step_rule", ctypes.c_int), ("bm_solver", ctypes.c_int),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
-                ("sparsa_beta", ctypes.c_double), ("sparsa_delta", ctypes.c_double)]
+                ("sparsa_beta", ctypes.c_double), ("sparsa_delta", ctypes.c_double),
+                ("dense_rows", ctypes.c_double)]
 
 
 class BmgResult(ctypes.Structure):

@@ -19,7 +19,7 @@ SO = os.path.join(HERE, "libbmg.so")
 # and x86-64-v3, chosen at run time by linalg_dispatch.cpp)
 SOURCES = [("pass_f64.hip", "pass_f64", []), ("pass_f32.hip", "pass_f32", []),
            ("pass_bf16.hip", "pass_bf16", []), ("kernels.hip", "kernels", []),
-           ("colpass.hip", "colpass", []), ("rke.hip", "rke", []), ("noalloc.hip", "noalloc", []),
+           ("colpass.hip", "colpass", []), ("rke.hip", "rke", []), ("noalloc.hip", "noalloc", []), ("panel.hip", "panel", []),
            ("api.hip", "api", []), ("server.cpp", "server", []),
            ("linalg.cpp", "linalg_generic", ["-DLA_IMPL=la_generic"]),
            ("linalg.cpp", "linalg_v3", ["-DLA_IMPL=la_v3", "-march=x86-64-v3"]),
@@ -27,7 +27,7 @@ SOURCES = [("pass_f64.hip", "pass_f64", []), ("pass_f32.hip", "pass_f32", []),
 HOST_ONLY = ("linalg.cpp", "linalg_dispatch.cpp")
 # every source that defines device code (hashed by bench.py to match counter records)
 KERNEL_SOURCES = ["bmg_internal.h", "rowpass.h", "pass_f64.hip", "pass_f32.hip", "pass_bf16.hip",
-                  "kernels.hip", "colpass.hip", "units.h", "rke.hip", "noalloc.hip"]
+                  "kernels.hip", "colpass.hip", "units.h", "rke.hip", "noalloc.hip", "panel.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions in the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

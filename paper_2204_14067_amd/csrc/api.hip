@@ -120,26 +120,44 @@ struct Layout {
   int hist_p = 0;
   bool sparsa = false;
   size_t hist, hist_mb, hist_nb, sp, sp_bu, sp_bw, sp_bh, sp_br;
+  // dense-row panel (reserved when the options ask for one): at most pn_max
+  // rows of ldp columns, and the remainder of Omega without them in both
+  // orientations (the rows side reuses the rows arrays with a plan of its own)
+  double dense_rows = 0.0;
+  int pn_max = 0;
+  int64_t pn_ldi = 0, pn_part_cap = 0, pn_part2_cap = 0, pn_bsum_cap = 0;
+  size_t pn_rows, pn_mask, pn_A64, pn_A32, pn_R, pn_part, pn_part2, pn_bsum;
+  size_t prr_short, prr_long, prr_lp0, prr_prow, prr_pbeg, prr_pend, prr_pord;
+  size_t cr_ptr, cr_idx, cr_a64, cr_a32, cr_r;
+  size_t pcr_short, pcr_long, pcr_lp0, pcr_prow, pcr_pbeg, pcr_pend, pcr_pord;
+  size_t s_keep, s_pos;
   size_t total;
 };
 
 static size_t sort_temp_bytes(int64_t nnz) {
-  size_t bytes = 0;
+  size_t bytes = 0, scan = 0;
   if (nnz <= 0) return 256;
   if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr,
                                          (uint32_t *)nullptr, (const int32_t *)nullptr,
                                          (int32_t *)nullptr, (int)nnz, 0, 32,
                                          (hipStream_t)0) != hipSuccess)
     bytes = (size_t)nnz * 16;
-  return bytes + 256;
+  // the panel's compaction of the column-major orientation scans nnz flags
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                       (int)nnz, (hipStream_t)0) != hipSuccess)
+    scan = (size_t)nnz * 8;
+  return std::max(bytes, scan) + 256;
 }
 
+static constexpr int PANEL_MAX_ROWS = 256;   // at most this many rows go to the dense panel
+
 static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_precision prec,
-                          int hist_p, bool sparsa) {
+                          int hist_p, bool sparsa, double dense_rows) {
   Layout L{};
   L.m = m; L.n = n; L.nnz = nnz; L.k_cap = k_cap;
   L.hist_p = hist_p;
   L.sparsa = sparsa;
+  L.dense_rows = dense_rows;
   // leading dimensions in multiples of 16 elements: factor rows start on 128-byte lines
   L.ldk = (int)rup(std::max(k_cap, 1), 16);
   L.qmax = 2 * k_cap + 2;
@@ -214,6 +232,48 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_prec
     L.sp_br = (size_t)rup(es * std::max<int64_t>(nnz, 1), 256);
     L.sp = take(sparsa ? L.sp_bu + L.sp_bw + L.sp_bh + 2 * L.sp_br : 0);
   }
+  {
+    // dense-row panel: rows with at least dense_rows * n entries, so at most
+    // nnz / (dense_rows n) of them (and at most PANEL_MAX_ROWS, the densest)
+    const int64_t mi0 = std::min(m, n), ni0 = std::max(m, n);
+    int64_t pmax = 0;
+    if (dense_rows > 0.0 && dense_rows <= 1.0 && ni0 > 0)
+      pmax = std::min<int64_t>({PANEL_MAX_ROWS, mi0, (int64_t)((double)nnz / (dense_rows * (double)ni0))});
+    L.pn_max = (int)std::max<int64_t>(pmax, 0);
+    const bool pn = L.pn_max > 0;
+    L.pn_ldi = rup(std::max(L.pn_max, 1), 16);
+    const int64_t cells = pn ? L.pn_ldi * std::max<int64_t>(ni0, 1) : 0;
+    L.pn_part_cap = pn ? (int64_t)PANEL_KSPLIT * L.pn_ldi * L.qld : 0;
+    L.pn_part2_cap = pn ? (int64_t)PANEL_KGROUPS * L.pn_ldi * L.qld : 0;
+    L.pn_bsum_cap = pn ? (ni0 + 63) / 64 : 0;
+    L.pn_rows = take(pn ? 4 * L.pn_ldi : 0);
+    L.pn_mask = take(pn ? mi0 : 0);
+    L.pn_A64 = take(8 * cells);
+    L.pn_A32 = take(L.lowp ? 4 * cells : 0);
+    L.pn_R = take(8 * cells);
+    L.pn_part = take(8 * L.pn_part_cap);
+    L.pn_part2 = take(8 * L.pn_part2_cap);
+    L.pn_bsum = take(16 * L.pn_bsum_cap);
+    L.prr_short = take(pn ? 4 * mi0 : 0);
+    L.prr_long = take(pn ? 4 * L.max_long : 0);
+    L.prr_lp0 = take(pn ? 4 * (L.max_long + 1) : 0);
+    L.prr_prow = take(pn ? 4 * L.max_pieces : 0);
+    L.prr_pbeg = take(pn ? 8 * L.max_pieces : 0);
+    L.prr_pend = take(pn ? 8 * L.max_pieces : 0);
+    L.prr_pord = take(pn ? 4 * L.max_pieces : 0);
+    L.cr_ptr = take(pn ? 8 * (ni0 + 1) : 0);
+    L.cr_idx = take(pn ? 4 * nnz : 0);
+    L.cr_a64 = take(pn ? 8 * nnz : 0);
+    L.cr_a32 = take(pn && L.lowp ? 4 * nnz : 0);
+    L.cr_r = take(pn ? 8 * nnz : 0);
+    L.pcr_short = take(pn ? 4 * ni0 : 0);
+    L.pcr_long = take(pn ? 4 * L.max_long : 0);
+    L.pcr_lp0 = take(pn ? 4 * (L.max_long + 1) : 0);
+    L.pcr_prow = take(pn ? 4 * L.max_pieces : 0);
+    L.pcr_pbeg = take(pn ? 8 * L.max_pieces : 0);
+    L.pcr_pend = take(pn ? 8 * L.max_pieces : 0);
+    L.pcr_pord = take(pn ? 4 * L.max_pieces : 0);
+  }
   L.scratch = off;
   // setup view of the scratch region
   size_t so = off;
@@ -223,6 +283,8 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_prec
   L.s_rid = stake(4 * nnz);
   L.s_temp_bytes = sort_temp_bytes(nnz);
   L.s_temp = stake(L.s_temp_bytes);
+  L.s_keep = stake(4 * nnz);
+  L.s_pos = stake(4 * nnz);
   // solver view of the scratch region (element size 8 regardless of precision);
   // the solver runs on the orientation with mi = min(m, n) rows
   size_t bo = off;
@@ -364,6 +426,15 @@ struct bmg_problem {
   bool transposed;  // internal problem is the transpose (user m > n)
   Side urow, ucol;  // user CSR orientation and the built column orientation
   int32_t *perm;    // column-order position -> CSR position
+  // dense-row panel of the internal rows (P = 0: none) and Omega without its
+  // rows: prow shares the internal rows' arrays (own plan), pcol has its own
+  // column-major arrays
+  int panel_P = 0, panel_ldi = 0;
+  int32_t *panel_rows = nullptr;
+  double *panel_A64 = nullptr;
+  float *panel_A32 = nullptr;
+  void *panel_R = nullptr;
+  Side prow, pcol;
   double *result, *gram_part, *small;
   double *wsum, *wpart;
   void *partial;
@@ -442,15 +513,20 @@ struct PlanSlots {
   size_t shorts, longs, lp0, prow, pbeg, pend, pord;
 };
 
+// skip (optional, host, nrows): rows left out of the plan (the panel's rows)
 static void build_plan(bmg_problem *P, int64_t nrows, int64_t ncols, const int64_t *d_ptr,
-                       const int32_t *d_idx, const PlanSlots &o, Plan &pl) {
+                       const int32_t *d_idx, const PlanSlots &o, Plan &pl,
+                       const std::vector<uint8_t> *skip = nullptr) {
   std::vector<int64_t> ptr(nrows + 1);
   HIPC(hipMemcpyAsync(ptr.data(), d_ptr, 8 * (nrows + 1), hipMemcpyDeviceToHost, P->s));
   HIPC(hipStreamSynchronize(P->s));
   auto len = [&](int64_t r) { return ptr[r + 1] - ptr[r]; };
   std::vector<int32_t> shorts, longs;
   shorts.reserve(nrows);
+  int64_t nnz_plan = 0;
   for (int64_t i = 0; i < nrows; ++i) {
+    if (skip && (*skip)[i]) continue;
+    nnz_plan += len(i);
     if (len(i) <= LONG_ROW) shorts.push_back((int32_t)i);
     else longs.push_back((int32_t)i);
   }
@@ -534,7 +610,7 @@ static void build_plan(bmg_problem *P, int64_t nrows, int64_t ncols, const int64
   HIPC(hipStreamSynchronize(P->s));  // host vectors go out of scope
   pl.nrows = nrows;
   pl.ncols = ncols;
-  pl.nnz = ptr[nrows];
+  pl.nnz = nnz_plan;
   pl.ptr = d_ptr;
   pl.idx = d_idx;
   pl.short_rows = P->at<int32_t>(o.shorts);
@@ -547,6 +623,74 @@ static void build_plan(bmg_problem *P, int64_t nrows, int64_t ncols, const int64
   pl.piece_end = P->at<int64_t>(o.pend);
   pl.piece_ord = P->at<int32_t>(o.pord);
   pl.n_pieces = n_pieces;
+}
+
+// Dense-row panel of the internal rows: the rows with at least dense_rows * n
+// entries (the densest pn_max of them), their values as a dense panel (NaN
+// where nothing is observed), and the plans of Omega without them: the
+// internal rows' arrays with those rows skipped, and a compacted copy of the
+// column-major orientation without their entries.
+static void build_panel(bmg_problem *P) {
+  const Layout &L = P->L;
+  Side &Rw = P->rows(), &Cl = P->cols();
+  const int64_t mi = P->mi(), ni = P->ni(), nnz = P->nnz;
+  std::vector<int64_t> ptr(mi + 1);
+  HIPC(hipMemcpyAsync(ptr.data(), Rw.pl.ptr, 8 * (mi + 1), hipMemcpyDeviceToHost, P->s));
+  HIPC(hipStreamSynchronize(P->s));
+  const double thr = L.dense_rows * (double)ni;
+  std::vector<std::pair<int64_t, int32_t>> cand;
+  for (int64_t i = 0; i < mi; ++i) {
+    const int64_t len = ptr[i + 1] - ptr[i];
+    if (len > 0 && (double)len >= thr) cand.push_back({-len, (int32_t)i});
+  }
+  std::sort(cand.begin(), cand.end());
+  if ((int64_t)cand.size() > L.pn_max) cand.resize(L.pn_max);
+  std::vector<int32_t> rows;
+  for (auto &c : cand) rows.push_back(c.second);
+  std::sort(rows.begin(), rows.end());
+  if (rows.empty()) return;
+  const int Pn = (int)rows.size();
+  const int ldi = (int)rup(Pn, 16);
+  while ((int)rows.size() < ldi) rows.push_back(rows[0]);   // padding slots (unobserved)
+  P->panel_ldi = ldi;
+  P->panel_rows = P->at<int32_t>(L.pn_rows);
+  P->panel_A64 = P->at<double>(L.pn_A64);
+  P->panel_A32 = L.lowp ? P->at<float>(L.pn_A32) : nullptr;
+  P->panel_R = P->at<void>(L.pn_R);
+  std::vector<uint8_t> skip(mi, 0);
+  for (int32_t r : rows) skip[r] = 1;
+  uint8_t *mask = P->at<uint8_t>(L.pn_mask);
+  HIPC(hipMemcpyAsync(P->panel_rows, rows.data(), 4 * ldi, hipMemcpyHostToDevice, P->s));
+  HIPC(hipMemcpyAsync(mask, skip.data(), mi, hipMemcpyHostToDevice, P->s));
+  HIPC(launch_panel_fill(Pn, ni, ldi, P->panel_rows, Rw.pl.ptr, Rw.pl.idx, Rw.a64, P->panel_A64,
+                         P->panel_A32, P->s));
+  // rows of Omega without the panel's: the same arrays, a plan of their own
+  build_plan(P, mi, ni, Rw.pl.ptr, Rw.pl.idx,
+             {L.prr_short, L.prr_long, L.prr_lp0, L.prr_prow, L.prr_pbeg, L.prr_pend, L.prr_pord},
+             P->prow.pl, &skip);
+  P->prow.a64 = Rw.a64;
+  P->prow.a32 = Rw.a32;
+  P->prow.r = Rw.r;
+  // column-major orientation without the panel's entries (order kept)
+  int32_t *keep = P->at<int32_t>(L.s_keep), *pos = P->at<int32_t>(L.s_pos);
+  int64_t *cptr = P->at<int64_t>(L.cr_ptr);
+  int32_t *cidx = P->at<int32_t>(L.cr_idx);
+  double *ca = P->at<double>(L.cr_a64);
+  HIPC(launch_panel_keep(nnz, Cl.pl.idx, mask, keep, P->s));
+  size_t tb = L.s_temp_bytes;
+  HIPC(hipcub::DeviceScan::ExclusiveSum(P->at<void>(L.s_temp), tb, keep, pos, (int)nnz, P->s));
+  HIPC(launch_panel_compact(ni, nnz, Cl.pl.ptr, keep, pos, Cl.pl.idx, Cl.a64, cidx, ca, cptr, P->s));
+  HIPC(hipStreamSynchronize(P->s));
+  build_plan(P, ni, mi, cptr, cidx,
+             {L.pcr_short, L.pcr_long, L.pcr_lp0, L.pcr_prow, L.pcr_pbeg, L.pcr_pend, L.pcr_pord},
+             P->pcol.pl);
+  P->pcol.a64 = ca;
+  P->pcol.r = P->at<void>(L.cr_r);
+  if (L.lowp) {
+    P->pcol.a32 = P->at<float>(L.cr_a32);
+    HIPC((launch_convert<double, float>(P->pcol.pl.nnz, ca, P->pcol.a32, P->s)));
+  }
+  P->panel_P = Pn;
 }
 
 // ============================================================================ typed solver
@@ -562,12 +706,42 @@ struct Engine {
   int ldk, qld;
   int64_t m, n;
   Side *R, *C;
+  // dense-row panel: its rows leave the sparse passes (Rr, Cr: Omega without
+  // them) and go through the panel kernels; never with BF16 gathers or shared
+  // launches, and switched off by the solver variants that read the stored
+  // residual entry by entry (polyMF-SS, SpaRSA)
+  bool panel_on = false;
+  Side *Rr = nullptr, *Cr = nullptr;
+  PanelArg<T> pa;
 
   explicit Engine(bmg_problem *p) : P(p), s(p->s), ldk(p->L.ldk), qld(p->L.qld) {
     m = P->mi();
     n = P->ni();
     R = &P->rows();
     C = &P->cols();
+    if (P->panel_P > 0 && !kShadow && !P->batcher) {
+      panel_on = true;
+      Rr = &P->prow;
+      Cr = &P->pcol;
+      pa.P = P->panel_P;
+      pa.n = n;
+      pa.ldi = P->panel_ldi;
+      pa.rows = P->panel_rows;
+      if constexpr (sizeof(T) == 8) pa.A = (const T *)P->panel_A64;
+      else pa.A = (const T *)P->panel_A32;
+      pa.R = (T *)P->panel_R;
+    }
+  }
+  // panel residual of X_P Y^T (sums into result[4..5])
+  void panel_resid(const T *Xm, int ldx, const T *Yn, int ldy, int k, bool use_a, bool store) {
+    HIPC(launch_panel_resid<T>(pa, Xm, ldx, Yn, ldy, k, use_a, store, P->template at<double>(P->L.pn_bsum),
+                               P->L.pn_bsum_cap, P->wpart, P->result + 4, s));
+  }
+  void panel_rows(bool values, const T *Y, int ldy, int q, double coef, const T *X, int ldx, int kx,
+                  const T *M, int ldm, double lam, const T *Xl, T *Out, int ldo) {
+    HIPC(launch_panel_rows<T>(pa, values, Y, ldy, q, coef, X, ldx, kx, M, ldm, lam, Xl, ldk, Out, ldo,
+                              P->template at<double>(P->L.pn_part), P->L.pn_part_cap,
+                              P->template at<double>(P->L.pn_part2), P->L.pn_part2_cap, s));
   }
   const T *avals(Side *sd) {
     if constexpr (sizeof(T) == 8) return (const T *)sd->a64;
@@ -607,13 +781,21 @@ struct Engine {
       sc.ev0 = P->last_a = P->get_event();
       sc.ev1 = P->last_b = P->get_event();
       P->last_cls = cls;
+      if (panel_on) {
+        // the events bracket the sparse kernel and the panel kernels of the pass
+        HIPC(hipEventRecord(sc.ev0, s));
+        sc.ev0 = sc.ev1 = nullptr;
+      }
     }
     return sc;
   }
+  // algorithmic bytes of the pass over the whole of Omega (the panel's own
+  // traffic is not counted); pl is the full plan of the orientation
   void count(const Plan &pl, double per_nnz, double fixed) {
     const double b = per_nnz * (double)pl.nnz + fixed + 8.0 * (double)(pl.nrows + 1);
     P->bytes += b;
     P->passes += 1;
+    if (panel_on && P->timing && P->last_b) HIPC(hipEventRecord(P->last_b, s));
     if (P->timing && P->last_a && P->last_b) {
       P->pend.push_back({P->last_a, P->last_b, P->last_cls, b});
       P->last_a = P->last_b = nullptr;
@@ -713,6 +895,17 @@ struct Engine {
   // ---------------------------------------------------------------- sparse passes
   // BM gradient on the rows side: G = R H + lam W (+ f = 1/2 sum r^2)
   double grad_rows(const T *W, const T *H, int k, double lam, T *G) {
+    if (panel_on) {
+      // rows of Omega without the panel's, then the panel's rows: R_P stored,
+      // G_P = R_P H + lam W_P
+      pass<T>(0, Rr->pl, avals(R), W, ldk, H, ldk, k, lam, 0.0, G, ldk, 0, nullptr, 0, sx(0));
+      panel_resid(W, ldk, H, ldk, k, true, true);
+      panel_rows(false, H, ldk, k, 1.0, nullptr, 0, 0, nullptr, 0, lam, W, G, ldk);
+      count(R->pl, 4.0 + sizeof(T), (double)n * k * sizeof(TG) + 2.0 * m * k * sizeof(T));
+      double h[6];
+      fetch(h, P->result, 6);
+      return 0.5 * (h[0] + h[4]);
+    }
     with_gather(1, H, n, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
       pass<TY>(0, R->pl, avals(R), W, ldk, Yg, ldk, k, lam, 0.0, G, ldk, 0, nullptr, 0, sx(0));
@@ -723,6 +916,16 @@ struct Engine {
     return 0.5 * h[0];
   }
   double grad_cols(const T *W, const T *H, int k, double lam, T *G) {
+    if (panel_on) {
+      // columns without the panel's entries (G = R^T W + lam H), then G += R_P^T W_P
+      pass<T>(0, Cr->pl, avals(Cr), H, ldk, W, ldk, k, lam, 0.0, G, ldk, 0, nullptr, 0, sx(0));
+      panel_resid(W, ldk, H, ldk, k, true, true);
+      HIPC(launch_panel_cols<T>(pa, false, W, ldk, k, 1.0, G, ldk, s));
+      count(C->pl, 4.0 + sizeof(T), (double)m * k * sizeof(TG) + 2.0 * n * k * sizeof(T));
+      double h[6];
+      fetch(h, P->result, 6);
+      return 0.5 * (h[0] + h[4]);
+    }
     with_gather(0, W, m, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
       pass<TY>(0, C->pl, avals(C), H, ldk, Yg, ldk, k, lam, 0.0, G, ldk, 0, nullptr, 0, sx(0));
@@ -734,6 +937,18 @@ struct Engine {
   }
   // sum over Omega of (x_row . y_col)^2 on the given side
   double curvature(Side *sd, const T *X, const T *Y, int k, int64_t nx, int64_t ny) {
+    if (panel_on) {
+      const bool rows_side = sd == R;
+      pass<T>(1, rows_side ? Rr->pl : Cr->pl, (const T *)nullptr, X, ldk, Y, ldk, k, 0.0, 0.0, (T *)nullptr,
+              0, 0, nullptr, 0, sx(1));
+      // the panel's entries: (x_i . y_j)^2 with x the m-side operand
+      if (rows_side) panel_resid(X, ldk, Y, ldk, k, false, false);
+      else panel_resid(Y, ldk, X, ldk, k, false, false);
+      count(sd->pl, 4.0, (double)nx * k * sizeof(T) + (double)ny * k * sizeof(TG));
+      double h[6];
+      fetch(h, P->result, 6);
+      return h[0] + h[4];
+    }
     with_gather(sd == R ? 1 : 0, Y, ny, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
       pass<TY>(1, sd->pl, (const T *)nullptr, X, ldk, Yg, ldk, k, 0.0, 0.0, (T *)nullptr, 0, 0,
@@ -746,6 +961,25 @@ struct Engine {
   }
   // stored residual on one side; returns {sum r^2, sum r (r + a)}
   void sddmm_store(Side *sd, const T *X, const T *Y, int k, int64_t nx, int64_t ny, double out[2]) {
+    if (panel_on) {
+      if (sd == R) {
+        // rows without the panel's into the rows' residual array, the panel's into R_P
+        pass<T>(1, Rr->pl, avals(R), X, ldk, Y, ldk, k, 0.0, 0.0, (T *)R->r, 0, 0, nullptr, 0, sx(1));
+        panel_resid(X, ldk, Y, ldk, k, true, true);
+        count(R->pl, 4.0 + 2.0 * sizeof(T), (double)nx * k * sizeof(T) + (double)ny * k * sizeof(TG));
+        double h[6];
+        fetch(h, P->result, 6);
+        out[0] = h[0] + h[4];
+        out[1] = h[1] + h[5];
+      } else {
+        // the columns' copy holds the entries outside the panel only (the
+        // panel's residual is shared by both orientations): sums of those
+        pass<T>(1, Cr->pl, avals(Cr), X, ldk, Y, ldk, k, 0.0, 0.0, (T *)Cr->r, 0, 0, nullptr, 0, sx(1));
+        count(C->pl, 4.0 + 2.0 * sizeof(T), (double)nx * k * sizeof(T) + (double)ny * k * sizeof(TG));
+        fetch(out, P->result, 2);
+      }
+      return;
+    }
     with_gather(sd == R ? 1 : 0, Y, ny, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
       pass<TY>(1, sd->pl, avals(sd), X, ldk, Yg, ldk, k, 0.0, 0.0, (T *)sd->r, 0, 0, nullptr, 0,
@@ -757,6 +991,7 @@ struct Engine {
   // 1/2 sum over Omega of (w_i . h_j - v_p)^2 for values v in CSR order
   double loss_vs(const T *v, const T *W, const T *H, int k) {
     if (R->pl.nnz == 0) return 0.0;
+    REQUIRE(!panel_on, BMG_EINVAL, "entrywise sampled values are not available with a dense-row panel");
     with_gather(1, H, n, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
       pass<TY>(1, R->pl, v, W, ldk, Yg, ldk, k, 0.0, 0.0, (T *)nullptr, 0, 0, nullptr, 0, sx(1));
@@ -768,6 +1003,14 @@ struct Engine {
   }
   double loss(const T *W, const T *H, int k) {
     if (R->pl.nnz == 0) return 0.0;
+    if (panel_on) {
+      pass<T>(1, Rr->pl, avals(R), W, ldk, H, ldk, k, 0.0, 0.0, (T *)nullptr, 0, 0, nullptr, 0, sx(1));
+      panel_resid(W, ldk, H, ldk, k, true, false);
+      count(R->pl, 4.0 + sizeof(T), (double)m * k * sizeof(T) + (double)n * k * sizeof(TG));
+      double h[6];
+      fetch(h, P->result, 6);
+      return 0.5 * (h[0] + h[4]);
+    }
     with_gather(1, H, n, k, ldk, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
       pass<TY>(1, R->pl, avals(R), W, ldk, Yg, ldk, k, 0.0, 0.0, (T *)nullptr, 0, 0, nullptr, 0,
@@ -787,12 +1030,20 @@ struct Engine {
     int k;
     double alpha;
     const T *s_rows, *s_cols;
+    bool values = false;  // S is the observed values (else the stored residual)
   };
   // Y (n x q) = Z^T U = H (W^T U) - alpha S^T U
   void z_t(const ZOp &z, const T *U, int q, T *Y) {
     if (q == 0) return;
     T *dM = nullptr;
     if (z.k > 0) dM = gram_dev(m, z.k, z.W, ldk, q, U, qld, 0);
+    if (panel_on) {
+      const T *sc = z.values ? avals(Cr) : (const T *)Cr->r;
+      pass<T>(2, Cr->pl, sc, z.H, ldk, U, qld, q, 0.0, -z.alpha, Y, qld, z.k, dM, q, sx(2));
+      HIPC(launch_panel_cols<T>(pa, z.values, U, qld, q, -z.alpha, Y, qld, s));
+      count(C->pl, 4.0 + sizeof(T), (double)m * q * sizeof(TG) + (double)n * q * sizeof(T));
+      return;
+    }
     with_gather(2, U, m, q, qld, [&](auto Ug) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Ug)>>;
       pass<TY>(2, C->pl, z.s_cols, z.H, ldk, Ug, qld, q, 0.0, -z.alpha, Y, qld, z.k, dM, q, sx(2));
@@ -806,6 +1057,12 @@ struct Engine {
     const int l = ld > 0 ? ld : qld;
     T *dM = nullptr;
     if (z.k > 0) dM = gram_dev(n, z.k, z.H, ldk, q, Y, l, 1);
+    if (panel_on) {
+      pass<T>(2, Rr->pl, z.s_rows, z.W, ldk, Y, l, q, 0.0, -z.alpha, V, l, z.k, dM, q, sx(2));
+      panel_rows(z.values, Y, l, q, -z.alpha, z.W, ldk, z.k, dM, q, 0.0, nullptr, V, l);
+      count(R->pl, 4.0 + sizeof(T), (double)n * q * sizeof(TG) + (double)m * q * sizeof(T));
+      return;
+    }
     with_gather(3, Y, n, q, l, [&](auto Yg) {
       using TY = std::remove_const_t<std::remove_pointer_t<decltype(Yg)>>;
       pass<TY>(2, R->pl, z.s_rows, z.W, ldk, Yg, l, q, 0.0, -z.alpha, V, l, z.k, dM, q, sx(2));
@@ -892,13 +1149,16 @@ extern "C" void bmg_options_default(bmg_options *o) {
   o->alpha_max = 1e3;
   o->sparsa_beta = 0.5;
   o->sparsa_delta = 0.999;
+  o->dense_rows = 0.0;
 }
 
-// history length and step rule the workspace reserves for (opt may be null)
-static bool reserve_of(const bmg_options *opt, int *hist_p, bool *sparsa) {
+// history length, step rule and dense-row threshold the workspace reserves
+// for (opt may be null)
+static bool reserve_of(const bmg_options *opt, int *hist_p, bool *sparsa, double *dense_rows) {
   *hist_p = opt ? opt->lmsvd_p : 0;
   *sparsa = opt && opt->step_rule == BMG_STEP_SPARSA;
-  return *hist_p >= 0 && *hist_p <= LMSVD_MAX_HIST;
+  *dense_rows = opt ? opt->dense_rows : 0.0;
+  return *hist_p >= 0 && *hist_p <= LMSVD_MAX_HIST && *dense_rows >= 0.0 && *dense_rows <= 1.0;
 }
 
 extern "C" bmg_status bmg_workspace_size(int64_t m, int64_t n, int64_t nnz, int k_cap,
@@ -913,8 +1173,9 @@ extern "C" bmg_status bmg_workspace_size(int64_t m, int64_t n, int64_t nnz, int 
     return fail(BMG_EINVAL, "k_cap above the widest sparse-pass slice");
   int hp = 0;
   bool sp = false;
-  if (!reserve_of(opt, &hp, &sp)) return fail(BMG_EINVAL, "lmsvd_p outside [0, 4]");
-  Layout L = make_layout(m, n, nnz, k_cap, prec, hp, sp);
+  double dr = 0.0;
+  if (!reserve_of(opt, &hp, &sp, &dr)) return fail(BMG_EINVAL, "lmsvd_p outside [0, 4] or dense_rows outside [0, 1]");
+  Layout L = make_layout(m, n, nnz, k_cap, prec, hp, sp, dr);
   *bytes = L.total;
   return BMG_OK;
 }
@@ -935,8 +1196,9 @@ extern "C" bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_prec
   try {
     int hp = 0;
     bool sp = false;
-    reserve_of(opt, &hp, &sp);
-    P->L = make_layout(csr->m, csr->n, csr->nnz, k_cap, prec, hp, sp);
+    double dr = 0.0;
+    reserve_of(opt, &hp, &sp, &dr);
+    P->L = make_layout(csr->m, csr->n, csr->nnz, k_cap, prec, hp, sp, dr);
     P->prec = prec;
     P->s = (hipStream_t)stream;
     P->ws = (char *)ws;
@@ -1011,6 +1273,7 @@ extern "C" bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_prec
       HIPC((launch_convert<double, float>(nnz, csr->val, P->urow.a32, P->s)));
       HIPC((launch_convert<double, float>(nnz, ca, P->ucol.a32, P->s)));
     }
+    if (L.pn_max > 0 && nnz > 0) build_panel(P);
     HIPC(hipStreamSynchronize(P->s));
   } catch (const BmgError &e) {
     delete P;
@@ -1527,7 +1790,7 @@ struct Method : Engine<T, TG> {
   // Initialisation (Suppl. A.1.4): X_{-1} = 0, Z_{-1} = P_Omega(A), HMT range
   // finder + Nystrom for Z Z^T, then the prox tail with beta = lambda.
   void initialize(State &S, int k0, double lam, uint64_t seed) {
-    ZOp z0{nullptr, nullptr, 0, -1.0, avals(R), avals(C)};   // Z = 0 - (-1) * A
+    ZOp z0{nullptr, nullptr, 0, -1.0, avals(R), avals(C), true};   // Z = 0 - (-1) * A
     T *B1 = blk(P->L.b_B1), *B2 = blk(P->L.b_B2), *B3 = blk(P->L.b_B3), *B4 = blk(P->L.b_B4);
     T *Y = blk(P->L.b_Y);
     k0 = std::max(1, std::min(k0, qld));
@@ -1824,7 +2087,7 @@ struct Method : Engine<T, TG> {
     if (k > 0) x2 = trace_prod(gram(m, k, S.W, ldk, k, S.W, ldk), gram(n, k, S.H, ldk, k, S.H, ldk), k);
     for (info.trials = 1;; ++info.trials) {
       if (info.trials > 1 && q0 > 0) HIPC(launch_copy_cols<T>(m, q0, U0keep, qld, U0, qld, s));
-      ZOp z{S.W, S.H, k, a, (const T *)R->r, (const T *)C->r};
+      ZOp z{S.W, S.H, k, a, (const T *)R->r, (const T *)C->r, false};
       int it = 0;
       q = lmsvd(z, U0, q0, tau, ssi_max, (a * lam) * (a * lam), &Uf, &Yf, Tq, &it);
       info.iters += it;
@@ -1919,6 +2182,8 @@ struct Method : Engine<T, TG> {
     sparsa = o.step_rule == BMG_STEP_SPARSA;
     sp_opt = o;
     sp_have_prev = false;
+    // polyMF-SS and SpaRSA read the stored residual entry by entry
+    if (o.bm_solver == BMG_BM_POLYMF || sparsa) this->panel_on = false;
     if (hist_p > 0) hist_mem(hist_p);   // the workspace must hold them: fail early
     if (sparsa) sparsa_mem();
     init_state(S);
@@ -2094,6 +2359,7 @@ extern "C" bmg_status bmg_polymf_epochs(bmg_problem *P, double *W, double *H, in
   if (epochs < 0 || !(lambda > 0.0)) return fail(BMG_EINVAL, "bmg_polymf_epochs: bad arguments");
   try {
     Method<double> M(P);
+    M.panel_on = false;   // polyMF-SS reads the stored residual entry by entry
     double *Wi = M.blk(P->L.b_W), *Hi = M.blk(P->L.b_H);
     load_factors<double>(P, W, H, k, ld, Wi, Hi);
     for (int e = 0; e < epochs && k > 0; ++e) M.polymf_epoch(Wi, Hi, k, lambda);
@@ -2176,6 +2442,7 @@ struct RkeMethod : Method<double> {
   using M::P; using M::s; using M::ldk; using M::qld; using M::n; using M::R;
   using M::gram; using M::gemm; using M::orth; using M::blk; using M::fro2;
   explicit RkeMethod(bmg_problem *p) : M(p) {
+    this->panel_on = false;
     const int64_t nv = rup(n, 64);
     deg = blk(P->L.b_vec) + 2 * nv;
     adeg = blk(P->L.b_vec) + 3 * nv;
@@ -2595,6 +2862,7 @@ extern "C" bmg_status bmg_prox_step(bmg_problem *P, double *W, double *H, int *k
     M.hist_p = opt->lmsvd_p;
     M.sparsa = opt->step_rule == BMG_STEP_SPARSA;
     M.sp_opt = *opt;
+    if (M.sparsa) M.panel_on = false;
     Method<double>::State S;
     M.init_state(S);
     const int k = *k_inout;

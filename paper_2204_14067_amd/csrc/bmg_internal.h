@@ -123,6 +123,46 @@ hipError_t launch_spmm(const Plan &pl, const T *S, const TG *B, int ldb, int q, 
                        const T *X, int ldx, int kx, const T *M, int ldm, T *C, int ldc,
                        PassScratch sc, hipStream_t s);
 
+// ---------------------------------------------------------------- dense-row panel (panel.hip)
+// The rows of Omega (short side) dense enough to be kept as a dense panel over
+// all n columns, stored column by column: element (i, j) at j * ldi + i.
+template <typename T>
+struct PanelArg {
+  int P = 0;                       // panel rows
+  int64_t n = 0;                   // columns
+  int ldi = 0;                     // P rounded up to 16 (slots P..ldi-1 are padding)
+  const int32_t *rows = nullptr;   // [ldi] row of Omega of each slot (padding repeats rows[0])
+  const T *A = nullptr;            // [n x ldi] observed values, NaN where nothing is observed
+  T *R = nullptr;                  // [n x ldi] stored residual, 0 where nothing is observed
+};
+constexpr int PANEL_KSPLIT = 1024;  // column ranges of the rows product (partials added in order)
+constexpr int PANEL_KGROUPS = 16;   // first-stage groups of those partials
+// r = X_P Y^T - A (use_a) or X_P Y^T where observed, 0 elsewhere; stored in R
+// when store; out[0] = sum r^2, out[1] = sum r (X_P Y^T) (fixed order).  bsum:
+// 2 doubles per block (at most bsum_cap blocks), tmp: 512 doubles.
+template <typename T>
+hipError_t launch_panel_resid(const PanelArg<T> &pa, const T *X, int ldx, const T *Y, int ldy, int k,
+                              bool use_a, bool store, double *bsum, int64_t bsum_cap, double *tmp,
+                              double *out, hipStream_t s);
+// Out[rows[i]] = coef (S^T Y)[i] + X[rows[i]] M (kx x q, may be kx = 0) + lam Xl[rows[i]]
+// (Xl may be null) with S = A (NaN as 0) when values, else R; part, part2: partials.
+template <typename T>
+hipError_t launch_panel_rows(const PanelArg<T> &pa, bool values, const T *Y, int ldy, int q, double coef,
+                             const T *X, int ldx, int kx, const T *M, int ldm, double lam, const T *Xl,
+                             int ldl, T *Out, int ldo, double *part, int64_t part_cap, double *part2,
+                             int64_t part2_cap, hipStream_t s);
+// Out (n x q) += coef S X_P with X_P the rows rows[] of X.
+template <typename T>
+hipError_t launch_panel_cols(const PanelArg<T> &pa, bool values, const T *X, int ldx, int q, double coef,
+                             T *Out, int ldo, hipStream_t s);
+hipError_t launch_panel_fill(int P, int64_t n, int ldi, const int32_t *rows, const int64_t *ptr,
+                             const int32_t *idx, const double *val, double *A, float *A32, hipStream_t s);
+hipError_t launch_panel_keep(int64_t nnz, const int32_t *idx, const uint8_t *mask, int32_t *keep,
+                             hipStream_t s);
+hipError_t launch_panel_compact(int64_t ncols, int64_t nnz, const int64_t *ptr, const int32_t *keep,
+                                const int32_t *pos, const int32_t *idx, const double *val, int32_t *ridx,
+                                double *rval, int64_t *rptr, hipStream_t s);
+
 // Dense helpers.
 template <typename T>
 hipError_t launch_gram(int64_t N, int a, const T *X, int ldx, int b, const T *Y, int ldy,
