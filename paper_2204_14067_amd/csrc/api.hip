@@ -126,7 +126,7 @@ struct Layout {
   double dense_rows = 0.0;
   int pn_max = 0;
   int64_t pn_ldi = 0, pn_part_cap = 0, pn_part2_cap = 0, pn_bsum_cap = 0;
-  size_t pn_rows, pn_mask, pn_A64, pn_A32, pn_R, pn_part, pn_part2, pn_bsum;
+  size_t pn_rows, pn_mask, pn_A64, pn_A32, pn_R, pn_part, pn_part2, pn_bsum, pn_xt;
   size_t prr_short, prr_long, prr_lp0, prr_prow, prr_pbeg, prr_pend, prr_pord;
   size_t cr_ptr, cr_idx, cr_a64, cr_a32, cr_r;
   size_t pcr_short, pcr_long, pcr_lp0, pcr_prow, pcr_pbeg, pcr_pend, pcr_pord;
@@ -245,7 +245,7 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_prec
     const int64_t cells = pn ? L.pn_ldi * std::max<int64_t>(ni0, 1) : 0;
     L.pn_part_cap = pn ? (int64_t)PANEL_KSPLIT * L.pn_ldi * L.qld : 0;
     L.pn_part2_cap = pn ? (int64_t)PANEL_KGROUPS * L.pn_ldi * L.qld : 0;
-    L.pn_bsum_cap = pn ? (ni0 + 63) / 64 : 0;
+    L.pn_bsum_cap = pn ? (ni0 + 15) / 16 : 0;
     L.pn_rows = take(pn ? 4 * L.pn_ldi : 0);
     L.pn_mask = take(pn ? mi0 : 0);
     L.pn_A64 = take(8 * cells);
@@ -254,6 +254,7 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, int k_cap, bmg_prec
     L.pn_part = take(8 * L.pn_part_cap);
     L.pn_part2 = take(8 * L.pn_part2_cap);
     L.pn_bsum = take(16 * L.pn_bsum_cap);
+    L.pn_xt = take(pn ? 8 * L.pn_ldi * L.qld : 0);
     L.prr_short = take(pn ? 4 * mi0 : 0);
     L.prr_long = take(pn ? 4 * L.max_long : 0);
     L.prr_lp0 = take(pn ? 4 * (L.max_long + 1) : 0);
@@ -920,7 +921,7 @@ struct Engine {
       // columns without the panel's entries (G = R^T W + lam H), then G += R_P^T W_P
       pass<T>(0, Cr->pl, avals(Cr), H, ldk, W, ldk, k, lam, 0.0, G, ldk, 0, nullptr, 0, sx(0));
       panel_resid(W, ldk, H, ldk, k, true, true);
-      HIPC(launch_panel_cols<T>(pa, false, W, ldk, k, 1.0, G, ldk, s));
+      HIPC(launch_panel_cols<T>(pa, false, W, ldk, k, 1.0, G, ldk, P->template at<T>(P->L.pn_xt), s));
       count(C->pl, 4.0 + sizeof(T), (double)m * k * sizeof(TG) + 2.0 * n * k * sizeof(T));
       double h[6];
       fetch(h, P->result, 6);
@@ -1040,7 +1041,7 @@ struct Engine {
     if (panel_on) {
       const T *sc = z.values ? avals(Cr) : (const T *)Cr->r;
       pass<T>(2, Cr->pl, sc, z.H, ldk, U, qld, q, 0.0, -z.alpha, Y, qld, z.k, dM, q, sx(2));
-      HIPC(launch_panel_cols<T>(pa, z.values, U, qld, q, -z.alpha, Y, qld, s));
+      HIPC(launch_panel_cols<T>(pa, z.values, U, qld, q, -z.alpha, Y, qld, P->template at<T>(P->L.pn_xt), s));
       count(C->pl, 4.0 + sizeof(T), (double)m * q * sizeof(TG) + (double)n * q * sizeof(T));
       return;
     }

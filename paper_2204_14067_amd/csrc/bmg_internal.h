@@ -151,10 +151,10 @@ hipError_t launch_panel_rows(const PanelArg<T> &pa, bool values, const T *Y, int
                              const T *X, int ldx, int kx, const T *M, int ldm, double lam, const T *Xl,
                              int ldl, T *Out, int ldo, double *part, int64_t part_cap, double *part2,
                              int64_t part2_cap, hipStream_t s);
-// Out (n x q) += coef S X_P with X_P the rows rows[] of X.
+// Out (n x q) += coef S X_P with X_P the rows rows[] of X; Xt: q x ldi staging.
 template <typename T>
 hipError_t launch_panel_cols(const PanelArg<T> &pa, bool values, const T *X, int ldx, int q, double coef,
-                             T *Out, int ldo, hipStream_t s);
+                             T *Out, int ldo, T *Xt, hipStream_t s);
 hipError_t launch_panel_fill(int P, int64_t n, int ldi, const int32_t *rows, const int64_t *ptr,
                              const int32_t *idx, const double *val, double *A, float *A32, hipStream_t s);
 hipError_t launch_panel_keep(int64_t nnz, const int32_t *idx, const uint8_t *mask, int32_t *keep,

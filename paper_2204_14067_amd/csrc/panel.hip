@@ -15,7 +15,8 @@
 //                  optional store of r into R_P, block sums of r^2 and r D;
 //   k_panel_rows:  Out_P = coef S^T Y (+ X_P M + lam X_P) with S = R_P or A_P,
 //                  split over column ranges with partials added in order;
-//   k_panel_cols:  Out += coef S X_P (every output element owned by one lane).
+//   k_panel_cols:  Out += coef S X_P (every output element owned by one lane),
+//                  X_P first transposed into a small staging block.
 // MFMA layouts (FP64 16x16x4): lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; register v of lane l holds D[4 v + l / 16][l % 16].  The
 // contraction index is taken 16 at a time: in MFMA step s lane (kr, cl) = (l / 16,
@@ -50,9 +51,10 @@ __device__ __forceinline__ void ld4(const T *__restrict__ p, int f0, int lim, do
 }
 
 // ------------------------------------------------------------------ residual
-// Block bx: columns [64 bx, 64 bx + 64), wave w: column tile 4 bx + w and
-// every panel-row tile (at most NI).  M = columns j, N = panel rows i, K = k.
-template <typename T, int NI>
+// Block bx: column tile bx (16 columns); wave w: panel-row tiles w, w + 4,
+// w + 8, w + 12.  M = columns j, N = panel rows i, K = k (16 at a time, then
+// the last k % 16 four at a time).
+template <typename T>
 __global__ __launch_bounds__(256) void k_panel_resid(int TI, int64_t n, int k,
                                                      const int32_t *__restrict__ rows,
                                                      const T *__restrict__ X, int ldx,
@@ -62,35 +64,53 @@ __global__ __launch_bounds__(256) void k_panel_resid(int TI, int64_t n, int k,
   __shared__ double red[2][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kr = lane / 16, cl = lane % 16;
-  const int64_t j0 = (int64_t)blockIdx.x * 64 + wave * 16;
-  d4p_t acc[NI];
+  const int64_t j0 = (int64_t)blockIdx.x * 16;
+  d4p_t acc[4];
 #pragma unroll
-  for (int t = 0; t < NI; ++t) acc[t] = d4p_t{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < 4; ++t) acc[t] = d4p_t{0.0, 0.0, 0.0, 0.0};
   const int64_t ja = j0 + cl;
   const bool jv = ja < n;
   const T *yrow = Y + (jv ? ja : 0) * ldy;
-  for (int f0 = 0; f0 < k; f0 += 16) {
+  const T *xrow[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int it = wave + 4 * t;
+    xrow[t] = X + (int64_t)rows[(it < TI ? it : 0) * 16 + cl] * ldx;
+  }
+  const int k16 = k / 16 * 16;
+  for (int f0 = 0; f0 < k16; f0 += 16) {
     const int fl = f0 + 4 * kr;
     double a[4];
     ld4(yrow, fl, jv ? k : 0, a);
 #pragma unroll
-    for (int t = 0; t < NI; ++t) {
-      if (t >= TI) break;
+    for (int t = 0; t < 4; ++t) {
+      if (wave + 4 * t >= TI) break;
       double b[4];
-      ld4(X + (int64_t)rows[t * 16 + cl] * ldx, fl, k, b);
+      ld4(xrow[t], fl, k, b);
 #pragma unroll
       for (int st = 0; st < 4; ++st) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], acc[t], 0, 0, 0);
     }
   }
+  for (int f0 = k16; f0 < k; f0 += 4) {
+    const int f = f0 + kr;
+    const double a = (jv && f < k) ? (double)yrow[f] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (wave + 4 * t >= TI) break;
+      const double b = f < k ? (double)xrow[t][f] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    }
+  }
   double ss = 0.0, sx = 0.0;
 #pragma unroll
-  for (int t = 0; t < NI; ++t) {
-    if (t >= TI) break;
+  for (int t = 0; t < 4; ++t) {
+    const int it = wave + 4 * t;
+    if (it >= TI) break;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t j = j0 + 4 * v + kr;
       if (j < n) {
-        const int64_t off = j * ldi + t * 16 + cl;
+        const int64_t off = j * ldi + it * 16 + cl;
         const double av = (double)A[off];
         const double d = acc[t][v];
         const bool obs = !isnan(av);
@@ -127,21 +147,23 @@ hipError_t launch_panel_resid(const PanelArg<T> &pa, const T *X, int ldx, const 
   if (pa.P <= 0 || (ldx % 4) || (ldy % 4) || (pa.ldi % 16)) return hipErrorInvalidValue;
   const int TI = pa.ldi / 16;
   if (TI > 16) return hipErrorInvalidValue;
-  const int64_t nb = (pa.n + 63) / 64;
+  const int64_t nb = (pa.n + 15) / 16;
   if (nb > bsum_cap) return hipErrorInvalidValue;
-  T *R = store ? pa.R : (T *)nullptr;
-  if (TI <= 4)
-    hipLaunchKernelGGL((k_panel_resid<T, 4>), dim3((unsigned)nb), dim3(256), 0, s, TI, pa.n, k, pa.rows, X, ldx,
-                       Y, ldy, pa.A, pa.ldi, use_a ? 1 : 0, R, bsum);
-  else if (TI <= 8)
-    hipLaunchKernelGGL((k_panel_resid<T, 8>), dim3((unsigned)nb), dim3(256), 0, s, TI, pa.n, k, pa.rows, X, ldx,
-                       Y, ldy, pa.A, pa.ldi, use_a ? 1 : 0, R, bsum);
-  else
-    hipLaunchKernelGGL((k_panel_resid<T, 16>), dim3((unsigned)nb), dim3(256), 0, s, TI, pa.n, k, pa.rows, X,
-                       ldx, Y, ldy, pa.A, pa.ldi, use_a ? 1 : 0, R, bsum);
+  hipLaunchKernelGGL((k_panel_resid<T>), dim3((unsigned)nb), dim3(256), 0, s, TI, pa.n, k, pa.rows, X, ldx, Y,
+                     ldy, pa.A, pa.ldi, use_a ? 1 : 0, store ? pa.R : (T *)nullptr, bsum);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_reduce_wsum(bsum, nb, 2, tmp, out, s);
+}
+
+// X_P^T: Xt[c][s] = X[rows[s]][c] for the ldi panel slots s and c < q (ld ldi)
+template <typename T>
+__global__ void k_panel_xt(int ldi, int q, const int32_t *__restrict__ rows, const T *__restrict__ X, int ldx,
+                           T *__restrict__ Xt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ldi * q) return;
+  const int c = e / ldi, sl = e % ldi;
+  Xt[(int64_t)c * ldi + sl] = X[(int64_t)rows[sl] * ldx + c];
 }
 
 // ------------------------------------------------------------------ rows product
@@ -277,11 +299,11 @@ hipError_t launch_panel_rows(const PanelArg<T> &pa, bool values, const T *Y, int
 // ------------------------------------------------------------------ columns product
 // Block bx: columns [64 bx, +64), wave w: column tile 4 bx + w and every
 // output column tile (at most NQ).  M = columns j, N = output columns c,
-// K = panel rows i.
+// K = panel rows i; X_P comes transposed (Xt, ld ldi) so that a lane's four
+// values of one output column are adjacent.
 template <typename T, int NQ>
-__global__ __launch_bounds__(256) void k_panel_cols(int TI, int64_t n, int q, const int32_t *__restrict__ rows,
-                                                    const T *__restrict__ S, int ldi, int values,
-                                                    const T *__restrict__ X, int ldx, double coef,
+__global__ __launch_bounds__(256) void k_panel_cols(int TI, int64_t n, int q, const T *__restrict__ S, int ldi,
+                                                    int values, const T *__restrict__ Xt, double coef,
                                                     T *__restrict__ Out, int ldo) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kr = lane / 16, cl = lane % 16;
@@ -301,15 +323,13 @@ __global__ __launch_bounds__(256) void k_panel_cols(int TI, int64_t n, int q, co
       for (int e = 0; e < 4; ++e) a[e] = isnan(a[e]) ? 0.0 : a[e];
     }
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const T *xr = X + (int64_t)rows[ii + 4 * kr + st] * ldx;
+    for (int u = 0; u < NQ; ++u) {
+      if (u >= TQ) break;
+      const int c = u * 16 + cl;
+      double b[4];
+      ld4(Xt + (int64_t)(c < q ? c : 0) * ldi, ii + 4 * kr, c < q ? ldi : 0, b);
 #pragma unroll
-      for (int u = 0; u < NQ; ++u) {
-        if (u >= TQ) break;
-        const int c = u * 16 + cl;
-        const double b = c < q ? (double)xr[c] : 0.0;
-        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b, acc[u], 0, 0, 0);
-      }
+      for (int st = 0; st < 4; ++st) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], acc[u], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -329,21 +349,23 @@ __global__ __launch_bounds__(256) void k_panel_cols(int TI, int64_t n, int q, co
 
 template <typename T>
 hipError_t launch_panel_cols(const PanelArg<T> &pa, bool values, const T *X, int ldx, int q, double coef,
-                             T *Out, int ldo, hipStream_t s) {
+                             T *Out, int ldo, T *Xt, hipStream_t s) {
   if (pa.P <= 0 || q <= 0 || (pa.ldi % 16)) return hipErrorInvalidValue;
   const int TI = pa.ldi / 16, TQ = (q + 15) / 16;
   if (TQ > 12) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_panel_xt<T>), dim3((unsigned)((pa.ldi * q + 255) / 256)), dim3(256), 0, s, pa.ldi, q,
+                     pa.rows, X, ldx, Xt);
   const dim3 grid((unsigned)((pa.n + 63) / 64));
   const T *Sp = values ? pa.A : (const T *)pa.R;
   if (TQ <= 4)
-    hipLaunchKernelGGL((k_panel_cols<T, 4>), grid, dim3(256), 0, s, TI, pa.n, q, pa.rows, Sp, pa.ldi,
-                       values ? 1 : 0, X, ldx, coef, Out, ldo);
+    hipLaunchKernelGGL((k_panel_cols<T, 4>), grid, dim3(256), 0, s, TI, pa.n, q, Sp, pa.ldi, values ? 1 : 0,
+                       (const T *)Xt, coef, Out, ldo);
   else if (TQ <= 8)
-    hipLaunchKernelGGL((k_panel_cols<T, 8>), grid, dim3(256), 0, s, TI, pa.n, q, pa.rows, Sp, pa.ldi,
-                       values ? 1 : 0, X, ldx, coef, Out, ldo);
+    hipLaunchKernelGGL((k_panel_cols<T, 8>), grid, dim3(256), 0, s, TI, pa.n, q, Sp, pa.ldi, values ? 1 : 0,
+                       (const T *)Xt, coef, Out, ldo);
   else
-    hipLaunchKernelGGL((k_panel_cols<T, 12>), grid, dim3(256), 0, s, TI, pa.n, q, pa.rows, Sp, pa.ldi,
-                       values ? 1 : 0, X, ldx, coef, Out, ldo);
+    hipLaunchKernelGGL((k_panel_cols<T, 12>), grid, dim3(256), 0, s, TI, pa.n, q, Sp, pa.ldi, values ? 1 : 0,
+                       (const T *)Xt, coef, Out, ldo);
   return hipGetLastError();
 }
 
@@ -434,8 +456,8 @@ template hipError_t launch_panel_rows<float>(const PanelArg<float> &, bool, cons
                                              int, float *, int, double *, int64_t, double *, int64_t,
                                              hipStream_t);
 template hipError_t launch_panel_cols<double>(const PanelArg<double> &, bool, const double *, int, int, double,
-                                              double *, int, hipStream_t);
+                                              double *, int, double *, hipStream_t);
 template hipError_t launch_panel_cols<float>(const PanelArg<float> &, bool, const float *, int, int, double,
-                                             float *, int, hipStream_t);
+                                             float *, int, float *, hipStream_t);
 
 }  // namespace bmg
