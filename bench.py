@@ -109,6 +109,9 @@ def main():
                     help="only run one kernel-estimation QSDP solve (20,000 objects, tol 1e-4)")
     ap.add_argument("--small-solve-only", action="store_true",
                     help="only run one FP64 solve of the 1000 x 1500 workload to tol 1e-6 (seed 11)")
+    ap.add_argument("--only", default=None,
+                    choices=["bf16_mode", "serve", "time_to_tol", "time_to_tol_gpu_bound", "rke_qsdp"],
+                    help="run one extra measurement alone and print its JSON")
     ap.add_argument("--serve-count", type=int, default=256,
                     help="requests replayed by the serving measurement (256 in the full stream)")
     args = ap.parse_args()
@@ -140,6 +143,13 @@ def main():
         print(json.dumps({"workload": "small_uniform 1000x1500 nnz=50000 lambda=0.5",
                           "seconds": time.perf_counter() - t0, "iters": r["iters"], "rank": k,
                           "F": r["F"], "status": r["status"]}))
+        return
+    if args.only:
+        fn = {"bf16_mode": lambda: bf16_mode(bmg, synth, dev), "serve": lambda: serving(bmg, synth, dev, args.serve_count),
+              "time_to_tol": lambda: time_to_tol(bmg, synth, dev),
+              "time_to_tol_gpu_bound": lambda: time_to_tol_gpu_bound(bmg, synth, dev),
+              "rke_qsdp": lambda: rke_qsdp(bmg, synth, dev)}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
         return
     if args.calibrate_copy:
         x = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -187,6 +197,7 @@ def main():
         out["precision_modes"] = precision_steps(bmg, q, dev, kq, lq, recs[-1]["F"])
         out["time_to_tol"] = time_to_tol(bmg, synth, dev)
         out["time_to_tol_gpu_bound"] = time_to_tol_gpu_bound(bmg, synth, dev)
+        out["bf16_mode"] = bf16_mode(bmg, synth, dev)
         out["sparsa_step"] = sparsa_step(bmg, synth, dev, out["time_to_tol"]["fp64"],
                                          out["time_to_tol_gpu_bound"]["lambda_100"]["fp64"])
         out["polymf_bm"] = polymf_bm(bmg, synth, dev, prob, q, out["time_to_tol"]["fp64"],
@@ -459,11 +470,62 @@ def precision_steps(bmg, p, dev, k0, lam, F64, steps=2):
         kms = [sum(r["kernel_ms"][c] for r in recs) / steps for c in range(3)]
         out[prec] = {"ms_per_step": round(dt * 1e3, 3),
                      "GB/s": round(sum(r["sparse_bytes"] for r in recs) / steps / dt / 1e9, 2),
+                     "bf16_pass_fraction": round(recs[-1]["bf16_passes"] / max(recs[-1]["sparse_passes"], 1), 4),
                      "rank_after_step": recs[-1]["k"],
                      "rel_F_vs_fp64": abs(recs[-1]["F"] - F64) / abs(F64),
                      "kernel_ms_per_step": {KERNEL_SYMBOLS[c]: round(kms[c], 3) for c in range(3)}}
         log("step %s: %.1f ms" % (prec, dt * 1e3))
         del prob
+    return out
+
+
+def bf16_mode(bmg, synth, dev, seeds=(3, 4, 5)):
+    """The BF16 mode (BF16 gathers, FP32 accumulation and masters, FP64 refresh
+    every 5 outer iterations) on the Netflix-shaped generator at scale 0.25,
+    lambda = 300, where tests/golden holds the oracle's certified optimum F*:
+    the objective error against F* after each refresh and the fraction of
+    sparse passes that gathered BF16; then time to tolerance against the FP64
+    solver at the same tolerance (1e-3, which the BF16 phase reaches itself, and
+    1e-5), with the final objective errors, the speed-up at equal accuracy."""
+    import numpy as np
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "netflix_quarter_lam300.json")))
+    p = synth.netflix_shape(scale=0.25)
+    lam, k0, Fs = g["lam"], g["k0"], g["F"]
+    evaluator = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision="fp64",
+                                      device=dev)
+    probs = {pr: bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, precision=pr, device=dev)
+             for pr in ("fp64", "bf16")}
+    out = {"workload": "netflix_shape x0.25: %dx%d nnz=%d, lambda=%g, k0=%d; F* = %.10g (oracle, duality gap "
+                       "%.2g)" % (p.m, p.n, p.nnz, lam, k0, Fs, g["dual_gap"]),
+           "per_refresh": []}
+    for it in (5, 10, 15, 20, 25, 30):
+        W, H, k, r = probs["bf16"].bmg_solve(lam=lam, k_init=k0, tol=0.0, max_iter=it, seed=seeds[0],
+                                             refresh_every=5)
+        F = evaluator.bmg_objective(W, H, k, lam)
+        out["per_refresh"].append({"iters": it, "rel_F_err_vs_oracle": (F - Fs) / Fs, "residual": r["residual"],
+                                   "rank": k, "bf16_pass_fraction": round(r["bf16_passes"] / r["sparse_passes"], 4)})
+    for tol in (1e-3, 1e-5):
+        rec = {}
+        for pr in ("fp64", "bf16"):
+            probs[pr].bmg_solve(lam=lam, k_init=k0, tol=tol, seed=seeds[0], max_iter=2)
+            secs, errs, fr, iters = [], [], [], []
+            for sd in seeds:
+                t0 = time.perf_counter()
+                W, H, k, r = probs[pr].bmg_solve(lam=lam, k_init=k0, tol=tol, seed=sd, max_iter=400)
+                secs.append(time.perf_counter() - t0)
+                F = evaluator.bmg_objective(W, H, k, lam)
+                errs.append(abs(F - Fs) / Fs)
+                fr.append(r["bf16_passes"] / max(r["sparse_passes"], 1))
+                iters.append(r["iters"])
+            rec[pr] = {"seconds_median": round(float(np.median(secs)), 4), "iters": iters,
+                       "max_rel_F_err_vs_oracle": max(errs), "bf16_pass_fraction": round(float(np.mean(fr)), 4)}
+        rec["bf16_speedup_vs_fp64"] = round(rec["fp64"]["seconds_median"] / rec["bf16"]["seconds_median"], 3)
+        out["tol_%g" % tol] = rec
+        log("bf16 mode tol %g: fp64 %.3fs (err %.1e) bf16 %.3fs (err %.1e, %.0f%% bf16 passes)" % (
+            tol, rec["fp64"]["seconds_median"], rec["fp64"]["max_rel_F_err_vs_oracle"],
+            rec["bf16"]["seconds_median"], rec["bf16"]["max_rel_F_err_vs_oracle"],
+            100 * rec["bf16"]["bf16_pass_fraction"]))
+    del probs, evaluator
     return out
 
 
@@ -478,6 +540,7 @@ def time_to_tol_gpu_bound(bmg, synth, dev, lams=(300.0, 100.0), seeds=(3, 4, 5))
     evaluator = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=128, precision="fp64",
                                   device=dev)
     out = {"workload": "netflix_shape x0.25: %dx%d nnz=%d, k0=16, tol 1e-4" % (p.m, p.n, p.nnz)}
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "netflix_quarter_lam300.json")))
     for lam in lams:
         rec = {}
         ref = {}
@@ -485,18 +548,22 @@ def time_to_tol_gpu_bound(bmg, synth, dev, lams=(300.0, 100.0), seeds=(3, 4, 5))
             prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=128,
                                          precision=prec, device=dev)
             prob.bmg_solve(lam=lam, k_init=16, tol=1e-4, seed=seeds[0], max_iter=2)
-            secs, errs, iters, ranks = [], [], [], []
+            secs, errs, iters, ranks, Fs_all = [], [], [], [], []
             for sd in seeds:
                 t0 = time.perf_counter()
                 W, H, k, r = prob.bmg_solve(lam=lam, k_init=16, tol=1e-4, seed=sd, max_iter=400)
                 secs.append(time.perf_counter() - t0)
                 F = evaluator.bmg_objective(W, H, k, lam)
+                Fs_all.append(F)
                 if prec == "fp64":
                     ref[sd] = F
                 errs.append(abs(F - ref[sd]) / abs(ref[sd]))
                 iters.append(r["iters"]); ranks.append(k)
             rec[prec] = {"seconds_median": round(float(np.median(secs)), 4), "iters": iters,
                          "rank": ranks, "max_rel_F_vs_fp64": max(errs)}
+            if lam == golden["lam"]:
+                rec[prec]["max_rel_F_err_vs_oracle_optimum"] = max(abs(F - golden["F"]) / golden["F"]
+                                                                   for F in Fs_all)
             del prob
         for prec in ("fp32", "bf16"):
             rec[prec]["speedup_vs_fp64"] = round(rec["fp64"]["seconds_median"] / rec[prec]["seconds_median"], 3)
@@ -622,7 +689,7 @@ def time_to_tol(bmg, synth, dev, seeds=(11, 12, 13, 14, 15)):
         prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=256, precision=prec,
                                      device=dev)
         prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=seeds[0], max_iter=2)   # warm caches
-        secs, errs, iters, ranks, conv = [], [], [], [], []
+        secs, errs, iters, ranks, conv, fr = [], [], [], [], [], []
         for sd in seeds:
             t0 = time.perf_counter()
             W, H, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=sd, max_iter=1000)
@@ -630,10 +697,13 @@ def time_to_tol(bmg, synth, dev, seeds=(11, 12, 13, 14, 15)):
             F64 = evaluator.bmg_objective(W, H, k, p.lam)
             errs.append((F64 - golden["F"]) / golden["F"])
             iters.append(r["iters"]); ranks.append(k); conv.append(r["status"] == 0)
+            fr.append(r["bf16_passes"] / max(r["sparse_passes"], 1))
         q1, med, q3 = (float(v) for v in np.percentile(secs, [25, 50, 75]))
         out[prec] = {"seconds_median": round(med, 4), "seconds_iqr": [round(q1, 4), round(q3, 4)],
                      "iters": iters, "rank": ranks, "converged": all(conv),
                      "max_rel_err_vs_oracle_optimum": max(abs(x) for x in errs)}
+        if prec == "bf16":
+            out[prec]["bf16_pass_fraction"] = round(float(np.mean(fr)), 4)
         log("time-to-tol %s: median %.3fs over %d seeds, iters %s" % (prec, med, len(seeds), iters))
     for prec in ("fp32", "bf16"):
         out[prec]["speedup_vs_fp64"] = round(out["fp64"]["seconds_median"] / out[prec]["seconds_median"], 3)

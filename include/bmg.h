@@ -136,6 +136,7 @@ typedef struct {
   int host_syncs;
   int pg_trials;      /* prox computations summed over all PG steps (backtracking) */
   double alpha_last;  /* step of the last PG step                                */
+  int bf16_passes;    /* BMG_BF16: sparse passes that gathered BF16 operands      */
 } bmg_result;
 
 /* Fills the defaults: alpha 1.99, tol 1e-6, ssi_tol_floor 1e-12, psi0 0.1,

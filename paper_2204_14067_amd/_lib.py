@@ -56,7 +56,7 @@ class BmgResult(ctypes.Structure):
                 ("kernel_bytes", ctypes.c_double * 3), ("kernel_launches", ctypes.c_int * 3),
                 ("host_la_seconds", ctypes.c_double), ("host_wait_seconds", ctypes.c_double),
                 ("host_syncs", ctypes.c_int), ("pg_trials", ctypes.c_int),
-                ("alpha_last", ctypes.c_double)]
+                ("alpha_last", ctypes.c_double), ("bf16_passes", ctypes.c_int)]
 
     def as_dict(self):
         out = {}

@@ -445,6 +445,8 @@ struct bmg_problem {
   // statistics of the sparse passes since the last reset
   double bytes = 0.0;
   int passes = 0;
+  int bf16_passes = 0;     // passes that gathered BF16 copies of their operand
+  bool pass_bf16 = false;  // the pass being issued gathers BF16
   // kernel timing with HIP events (opt->timing)
   struct Pend {
     hipEvent_t a, b;
@@ -484,6 +486,7 @@ struct bmg_problem {
   void reset_stats() {
     bytes = 0.0;
     passes = 0;
+    bf16_passes = 0;
     for (int i = 0; i < 3; ++i) kms[i] = kbytes[i] = 0.0, klaunch[i] = 0;
   }
   ~bmg_problem() {
@@ -754,6 +757,7 @@ struct Engine {
   void with_gather(int slot, const T *src, int64_t rows, int cols, int ld, F &&f) {
     if constexpr (kShadow) {
       if (!exact_gather) {
+        P->pass_bf16 = true;
         f(gath(slot, src, rows, cols, ld));
         return;
       }
@@ -796,6 +800,8 @@ struct Engine {
     const double b = per_nnz * (double)pl.nnz + fixed + 8.0 * (double)(pl.nrows + 1);
     P->bytes += b;
     P->passes += 1;
+    P->bf16_passes += P->pass_bf16 ? 1 : 0;
+    P->pass_bf16 = false;
     if (panel_on && P->timing && P->last_b) HIPC(hipEventRecord(P->last_b, s));
     if (P->timing && P->last_a && P->last_b) {
       P->pend.push_back({P->last_a, P->last_b, P->last_cls, b});
@@ -2279,6 +2285,7 @@ struct Method : Engine<T, TG> {
       res->eps = r.eps;
       res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - r.t0).count();
       res->sparse_bytes = P->bytes;
+      res->bf16_passes = P->bf16_passes;
       res->sparse_passes = P->passes;
     }
     return r.conv ? BMG_OK : BMG_NOT_CONVERGED;
