@@ -142,7 +142,10 @@ def main():
         _, _, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=11, max_iter=1000)
         print(json.dumps({"workload": "small_uniform 1000x1500 nnz=50000 lambda=0.5",
                           "seconds": time.perf_counter() - t0, "iters": r["iters"], "rank": k,
-                          "F": r["F"], "status": r["status"]}))
+                          "F": r["F"], "status": r["status"], "ssi_iters": r["ssi_iters"],
+                          "host_la_seconds": r["host_la_seconds"],
+                          "host_wait_seconds": r["host_wait_seconds"], "host_syncs": r["host_syncs"],
+                          "sparse_passes": r["sparse_passes"]}))
         return
     if args.only:
         fn = {"bf16_mode": lambda: bf16_mode(bmg, synth, dev), "serve": lambda: serving(bmg, synth, dev, args.serve_count),

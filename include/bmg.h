@@ -17,6 +17,10 @@
  *     the caller passes to bmg_problem_create (size from bmg_workspace_size,
  *     which also reserves what the solver variants of the given options need),
  *     the server's in the arena the caller passes to bmg_server_create.
+ *     Host side, each problem pins one staging buffer of 24 * qb^2 bytes
+ *     (hipHostMalloc; qb the subspace block width, about 2 * k_cap) for the
+ *     small q x q transfers of the solver, released by bmg_problem_destroy;
+ *     when pinning fails the transfers use pageable memory instead.
  *   - Dense factors are row-major FP64: W is m x ld, H is n x ld, with the
  *     first k columns in use (ld >= k, ld a multiple of 8, rows 16-byte aligned).
  *   - Omega is CSR: row_ptr[m+1] int64, col[nnz] int32 sorted and duplicate-free

@@ -14,9 +14,11 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -65,6 +67,56 @@ struct HostTimer {
     acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
 };
+// One helper thread for host work that can overlap the caller's: run() hands
+// it a job, wait() returns once the job is done (started on first use).
+struct HostHelper {
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::function<void()> job;
+  bool has = false, done = true, quit = false;
+  void loop() {
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      cv.wait(lk, [&] { return has || quit; });
+      if (quit) return;
+      std::function<void()> f = std::move(job);
+      has = false;
+      lk.unlock();
+      f();
+      lk.lock();
+      done = true;
+      cv.notify_all();
+    }
+  }
+  void run(std::function<void()> f) {
+    if (!th.joinable()) th = std::thread([this] { loop(); });
+    std::lock_guard<std::mutex> g(mu);
+    job = std::move(f);
+    has = true;
+    done = false;
+    cv.notify_all();
+  }
+  void wait() {
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait(lk, [&] { return done; });
+  }
+  ~HostHelper() {
+    if (!th.joinable()) return;
+    {
+      std::lock_guard<std::mutex> g(mu);
+      quit = true;
+    }
+    cv.notify_all();
+    th.join();
+  }
+};
+// waits for the helper's job when the scope ends (also on an exception)
+struct HelperJoin {
+  HostHelper &h;
+  ~HelperJoin() { h.wait(); }
+};
+
 namespace lat {
 inline void sym_eig(int n, const double *A, double *w, double *V) {
   HostTimer t(t_la_acc);
@@ -438,6 +490,12 @@ struct bmg_problem {
   Side prow, pcol;
   double *result, *gram_part, *small;
   double *wsum, *wpart;
+  // pinned host staging of the solver's small transfers (q x q Gram matrices
+  // down, small coefficient matrices up): a fetch area of hpin_fetch doubles,
+  // then a ring of hpin_ring doubles for uploads, free again after every
+  // synchronisation of the stream.  Null when pinning failed (pageable copies).
+  double *hpin = nullptr, *hpin_dev = nullptr;  // host address, device address
+  size_t hpin_fetch = 0, hpin_ring = 0, hpin_off = 0;
   void *partial;
   // serving: sparse passes go through a shared batcher when set
   PassBatcher *batcher = nullptr;
@@ -490,6 +548,7 @@ struct bmg_problem {
     for (int i = 0; i < 3; ++i) kms[i] = kbytes[i] = 0.0, klaunch[i] = 0;
   }
   ~bmg_problem() {
+    if (hpin) (void)hipHostFree(hpin);
     for (const Pend &q : pend) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (bitem.ready) (void)hipEventDestroy(bitem.ready);
@@ -809,11 +868,14 @@ struct Engine {
     }
   }
   void fetch(double *h, const double *d, size_t cnt) {
-    HIPC(hipMemcpyAsync(h, d, 8 * cnt, hipMemcpyDeviceToHost, s));
+    const bool pin = P->hpin && cnt <= P->hpin_fetch;
+    HIPC(hipMemcpyAsync(pin ? P->hpin : h, d, 8 * cnt, hipMemcpyDeviceToHost, s));
     {
       HostTimer t(t_wait_acc);
       HIPC(hipStreamSynchronize(s));
     }
+    if (pin) memcpy(h, P->hpin, 8 * cnt);
+    P->hpin_off = 0;  // every upload queued so far has completed
     n_sync_acc += 1;
     if (!P->pend.empty()) P->resolve_timing();
   }
@@ -821,6 +883,19 @@ struct Engine {
   std::vector<double> gram(int64_t N, int a, const T *X, int ldx, int b, const T *Y, int ldy) {
     std::vector<double> h((size_t)a * b, 0.0);
     if (a == 0 || b == 0) return h;
+    if (P->hpin_dev && (size_t)a * b <= P->hpin_fetch) {
+      // the final reduction writes straight into the pinned fetch area
+      HIPC(launch_gram<T>(N, a, X, ldx, b, Y, ldy, P->gram_part, P->L.gram_cap, P->hpin_dev, s));
+      {
+        HostTimer t(t_wait_acc);
+        HIPC(hipStreamSynchronize(s));
+      }
+      memcpy(h.data(), P->hpin, 8 * h.size());
+      P->hpin_off = 0;
+      n_sync_acc += 1;
+      if (!P->pend.empty()) P->resolve_timing();
+      return h;
+    }
     HIPC(launch_gram<T>(N, a, X, ldx, b, Y, ldy, P->gram_part, P->L.gram_cap, P->small, s));
     fetch(h.data(), P->small, (size_t)a * b);
     return h;
@@ -838,12 +913,27 @@ struct Engine {
     }
     return (T *)d;
   }
+  // host source of an upload of `bytes`: a slot of the pinned ring holding a
+  // copy of src (queued copies from it run asynchronously), or src itself
+  const void *stage_up(const void *src, size_t bytes) {
+    const size_t cnt = (bytes + 255) / 256 * 32;  // doubles, 256-byte granules
+    if (!P->hpin || cnt > P->hpin_ring) return src;
+    if (P->hpin_off + cnt > P->hpin_ring) {  // ring full: wait for its copies
+      HostTimer t(t_wait_acc);
+      HIPC(hipStreamSynchronize(s));
+      P->hpin_off = 0;
+    }
+    double *dst = P->hpin + P->hpin_fetch + P->hpin_off;
+    P->hpin_off += cnt;
+    memcpy(dst, src, bytes);
+    return dst;
+  }
   // upload a small FP64 matrix into the device staging area (slot 0..7)
   double *put(const std::vector<double> &h, int slot) {
     double *d = P->small + (size_t)(slot + 1) * P->L.qld * P->L.qld;
     REQUIRE(h.size() <= (size_t)P->L.qld * P->L.qld, BMG_EINVAL, "small matrix too large");
     if (!h.empty())
-      HIPC(hipMemcpyAsync(d, h.data(), 8 * h.size(), hipMemcpyHostToDevice, s));
+      HIPC(hipMemcpyAsync(d, stage_up(h.data(), 8 * h.size()), 8 * h.size(), hipMemcpyHostToDevice, s));
     return d;
   }
   // same, converted to T (for the low-rank epilogue of the sparse products)
@@ -854,7 +944,7 @@ struct Engine {
       std::vector<float> f(h.begin(), h.end());
       T *d = (T *)(P->small + (size_t)(slot + 1) * P->L.qld * P->L.qld);
       if (!f.empty())
-        HIPC(hipMemcpyAsync(d, f.data(), 4 * f.size(), hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(d, stage_up(f.data(), 4 * f.size()), 4 * f.size(), hipMemcpyHostToDevice, s));
       return d;
     }
   }
@@ -1222,6 +1312,20 @@ extern "C" bmg_status bmg_problem_create(const bmg_csr *csr, int k_cap, bmg_prec
     P->wsum = P->at<double>(L.wsum);
     P->wpart = P->at<double>(L.wpart);
     P->partial = P->at<void>(L.partial);
+    {
+      const size_t q2 = (size_t)L.qld * L.qld;
+      if (hipHostMalloc((void **)&P->hpin, 8 * 3 * q2, hipHostMallocDefault) == hipSuccess) {
+        if (hipHostGetDevicePointer((void **)&P->hpin_dev, P->hpin, 0) != hipSuccess) {
+          P->hpin_dev = nullptr;
+          (void)hipGetLastError();
+        }
+        P->hpin_fetch = q2;
+        P->hpin_ring = 2 * q2;
+      } else {
+        P->hpin = nullptr;
+        (void)hipGetLastError();
+      }
+    }
     // --- validate the CSR (row ids first; they also feed the transpose)
     int32_t *rid = P->at<int32_t>(L.s_rid);
     int64_t nnz_dev = 0;
@@ -1565,6 +1669,7 @@ struct Method : Engine<T, TG> {
   // point at the final basis (q columns) and Z^T of it; Tq is their Gram matrix.
   // History length p_t = hist_p.
   int hist_p = 0;
+  HostHelper helper;
   int lmsvd(const ZOp &z, T *Ubuf, int q, double tau, int max_iter, double keep_level,
             T **Uout, T **Yout, std::vector<double> &Tq, int *iters) {
     if (hist_p > 0) return lmsvd_hist(z, Ubuf, q, tau, max_iter, keep_level, Uout, Yout, Tq, iters);
@@ -1574,13 +1679,23 @@ struct Method : Engine<T, TG> {
     int it = 0;
     for (it = 1; it <= max_iter && q > 0; ++it) {
       std::vector<double> Tm = gram(n, q, Y, qld, q, Y, qld);
-      // L(U) = Z Z^T U (Ritz rotation omitted: same range); queued before the
-      // host computes the Ritz values, so the two overlap
+      // L(U) = Z Z^T U (Ritz rotation omitted: same range), queued first; the
+      // Ritz values (eigenvalues of Tm, for the stopping test) are computed on
+      // the helper thread while this one orthonormalises
       z_n(z, Y, q, V);
       std::vector<double> theta(q);
-      lat::sym_eig(q, Tm.data(), theta.data(), nullptr);
-      q = orth(m, V, q, U, tmp);       // U^{t,i+1}
-      z_t(z, U, q, Y);
+      double la_s = 0.0;
+      {
+        const int qq = q;
+        helper.run([&, qq] {
+          HostTimer t(la_s);
+          la::sym_eig(qq, Tm.data(), theta.data(), nullptr);
+        });
+        HelperJoin join{helper};
+        q = orth(m, V, q, U, tmp);     // U^{t,i+1}
+        z_t(z, U, q, Y);
+      }
+      t_la_acc += la_s;
       if (ritz_converged(theta, prev, tau, keep_level)) break;
     }
     *iters = std::min(it, max_iter);

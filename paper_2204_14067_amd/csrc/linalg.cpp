@@ -69,10 +69,22 @@ void sym_eig(int n, const double *A0, double *w, double *Vout) {
     taus[k] = tau;
     for (int i = k + 1; i < n; ++i) p[i] = 0.0;
     for (int i = k + 1; i < n; ++i) {
+      // one pass over row i's part left of the diagonal: its dot product with
+      // v (eight partial sums, added in a fixed order) and its entries times v_i
       const double *row = &A[(size_t)i * n];
       const double vi = v[i];
-      p[i] += dot(row + k + 1, v + k + 1, i - k - 1) + row[i] * vi;
-      for (int j = k + 1; j < i; ++j) p[j] += row[j] * vi;
+      double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int j = k + 1;
+      for (; j + 8 <= i; j += 8)
+        for (int l = 0; l < 8; ++l) {
+          a[l] += row[j + l] * v[j + l];
+          p[j + l] += row[j + l] * vi;
+        }
+      for (int l = 0; j < i; ++j, ++l) {
+        a[l] += row[j] * v[j];
+        p[j] += row[j] * vi;
+      }
+      p[i] += (((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]))) + row[i] * vi;
     }
     for (int i = k + 1; i < n; ++i) p[i] *= tau;
     double pv = 0.0;
@@ -162,32 +174,48 @@ void sym_eig(int n, const double *A0, double *w, double *Vout) {
 }
 
 int chol_pivoted(int n, const double *G, double tol, int *perm, double *R) {
-  std::vector<double> A(G, G + (size_t)n * n);
+  // Left-looking with diagonal pivoting: dg holds the diagonal of the current
+  // Schur complement (in pivot-position order); step j picks the largest,
+  // swaps positions j and piv (perm and the columns of the rows of R already
+  // built), and forms row j of R from G and the rows above it:
+  //   R_jc = (G_{perm j, perm c} - sum_{l<j} R_lj R_lc) / R_jj,  c > j.
+  // Only the rows of R already built are read: n^3/3 flops in all.
   for (int i = 0; i < n; ++i) perm[i] = i;
   memset(R, 0, sizeof(double) * (size_t)n * n);
+  std::vector<double> dg(n), acc(n);
   double dmax0 = 0.0;
-  for (int i = 0; i < n; ++i) dmax0 = std::max(dmax0, A[(size_t)i * n + i]);
+  for (int i = 0; i < n; ++i) {
+    dg[i] = G[(size_t)i * n + i];
+    dmax0 = std::max(dmax0, dg[i]);
+  }
   if (dmax0 <= 0.0) return 0;
-  // A holds the Schur complement in the permuted order; R rows are built in order.
   int r = 0;
   for (int j = 0; j < n; ++j) {
     int piv = j;
-    double best = A[(size_t)j * n + j];
+    double best = dg[j];
     for (int i = j + 1; i < n; ++i)
-      if (A[(size_t)i * n + i] > best) { best = A[(size_t)i * n + i]; piv = i; }
+      if (dg[i] > best) { best = dg[i]; piv = i; }
     if (!(best > tol * dmax0)) break;
-    if (piv != j) {  // symmetric swap of rows/cols j and piv, and of R's columns
-      for (int i = 0; i < n; ++i) std::swap(A[(size_t)j * n + i], A[(size_t)piv * n + i]);
-      for (int i = 0; i < n; ++i) std::swap(A[(size_t)i * n + j], A[(size_t)i * n + piv]);
-      for (int i = 0; i < j; ++i) std::swap(R[(size_t)i * n + j], R[(size_t)i * n + piv]);
+    if (piv != j) {
+      std::swap(dg[j], dg[piv]);
       std::swap(perm[j], perm[piv]);
+      for (int l = 0; l < j; ++l) std::swap(R[(size_t)l * n + j], R[(size_t)l * n + piv]);
     }
-    const double rjj = sqrt(A[(size_t)j * n + j]);
-    R[(size_t)j * n + j] = rjj;
-    for (int i = j + 1; i < n; ++i) R[(size_t)j * n + i] = A[(size_t)j * n + i] / rjj;
-    for (int i = j + 1; i < n; ++i)
-      for (int l = j + 1; l < n; ++l)
-        A[(size_t)i * n + l] -= R[(size_t)j * n + i] * R[(size_t)j * n + l];
+    const double rjj = sqrt(dg[j]);
+    double *rj = &R[(size_t)j * n];
+    rj[j] = rjj;
+    const double *g = &G[(size_t)perm[j] * n];
+    for (int c = j + 1; c < n; ++c) acc[c] = g[perm[c]];
+    for (int l = 0; l < j; ++l) {
+      const double *rl = &R[(size_t)l * n];
+      const double f = rl[j];
+      for (int c = j + 1; c < n; ++c) acc[c] -= f * rl[c];
+    }
+    const double inv = 1.0 / rjj;
+    for (int c = j + 1; c < n; ++c) {
+      rj[c] = acc[c] * inv;
+      dg[c] -= rj[c] * rj[c];
+    }
     r = j + 1;
   }
   return r;
