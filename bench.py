@@ -107,6 +107,7 @@ def main():
                     help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
     ap.add_argument("--qsdp-only", action="store_true",
                     help="only run one kernel-estimation QSDP solve (20,000 objects, tol 1e-4)")
+    ap.add_argument("--verbose", action="store_true", help="per-iteration log of the solver (stderr)")
     ap.add_argument("--small-solve-only", action="store_true",
                     help="only run one FP64 solve of the 1000 x 1500 workload to tol 1e-6 (seed 11)")
     ap.add_argument("--only", default=None,
@@ -128,11 +129,15 @@ def main():
     dev = "cuda:0"
     if args.qsdp_only:
         q = synth.rke(20_000, 40, lam=10.0, seed=7)
-        dq = bmg.Problem.from_host(q.row_ptr, q.col, q.val, q.m, q.n, k_cap=64, device=dev)
+        dq = bmg.Problem.from_host(q.row_ptr, q.col, q.val, q.m, q.n, k_cap=RKE_K_CAP, device=dev,
+                                   lmsvd_p=RKE_LMSVD_P)
         t0 = time.perf_counter()
-        _, k, r = dq.bmg_rke_solve(lam=10.0, k_init=8, tol=1e-4, seed=1, max_iter=3000, bm_epochs=10)
+        _, k, r = dq.bmg_rke_solve(lam=10.0, k_init=8, tol=1e-4, seed=1, max_iter=3000, bm_epochs=10,
+                                   lmsvd_p=RKE_LMSVD_P, verbose=args.verbose)
         print(json.dumps({"qsdp_objects": q.n, "pairs": q.nnz // 2, "seconds": time.perf_counter() - t0,
-                          "iters": r["iters"], "ssi_iters": r["ssi_iters"], "rank": k, "F": r["F"]}))
+                          "iters": r["iters"], "ssi_iters": r["ssi_iters"],
+                          "ssi_per_pg_step": r["ssi_iters"] / (r["iters"] + 1), "rank": k, "F": r["F"],
+                          "status": r["status"]}))
         return
     if args.small_solve_only:
         p = synth.small_uniform()
@@ -425,6 +430,9 @@ def polymf_bm(bmg, synth, dev, prob, p, fixed_small, fixed_quarter):
     return out
 
 
+RKE_K_CAP, RKE_LMSVD_P = 160, 1   # kernel-estimation runs: rank cap and LmSVD history
+
+
 def rke_qsdp(bmg, synth, dev):
     """BM-Global on the kernel-estimation QSDP (bmg_rke_solve, FP64) to relative
     prox-gradient residual 1e-4: synthetic objects in R^3 with about 40 random
@@ -433,17 +441,22 @@ def rke_qsdp(bmg, synth, dev):
     out = {}
     for n, lam in ((20_000, 10.0), (100_000, 20.0)):
         p = synth.rke(n, 40, lam=lam, seed=7)
-        dp = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=64, device=dev)
-        dp.bmg_rke_solve(lam=lam, k_init=8, tol=1e-4, seed=1, max_iter=2, bm_epochs=10)
-        secs, iters, ranks, Fs = [], [], [], []
+        dp = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=RKE_K_CAP, device=dev,
+                                   lmsvd_p=RKE_LMSVD_P)
+        dp.bmg_rke_solve(lam=lam, k_init=8, tol=1e-4, seed=1, max_iter=2, bm_epochs=10,
+                         lmsvd_p=RKE_LMSVD_P)
+        secs, iters, ranks, Fs, ssi = [], [], [], [], []
         for sd in (1, 2):
             t0 = time.perf_counter()
-            W, k, r = dp.bmg_rke_solve(lam=lam, k_init=8, tol=1e-4, seed=sd, max_iter=3000, bm_epochs=10)
+            W, k, r = dp.bmg_rke_solve(lam=lam, k_init=8, tol=1e-4, seed=sd, max_iter=3000, bm_epochs=10,
+                                       lmsvd_p=RKE_LMSVD_P)
             secs.append(time.perf_counter() - t0)
             iters.append(r["iters"]); ranks.append(k); Fs.append(r["F"])
+            ssi.append(round(r["ssi_iters"] / (r["iters"] + 1), 2))
             assert r["status"] == 0
         out["n%d_pairs%d" % (n, p.nnz // 2)] = {"lambda": lam, "seconds": [round(x, 3) for x in secs],
                                                  "iters": iters, "rank": ranks, "F": Fs,
+                                                 "ssi_per_pg_step": ssi, "lmsvd_p": RKE_LMSVD_P,
                                                  "rel_F_spread": (max(Fs) - min(Fs)) / abs(max(Fs))}
         log("rke n=%d (%d pairs): %s s, iters %s, rank %s" % (n, p.nnz // 2, ["%.2f" % x for x in secs],
                                                               iters, ranks))

@@ -231,13 +231,18 @@ bmg_status bmg_rke_residual(bmg_problem *p, const double *W, int k, int ld, doub
  * from J times an n x k_init Gaussian block), then per outer iteration bm_epochs
  * nonlinear conjugate-gradient steps on W with the exact (quartic) line search,
  * and one PG step with alpha = opt->alpha / (2 + 2 max degree) (a bound on
- * ||A^* A||), whose prox P_S+(J Z J) (Lemma PiX) comes from block subspace
- * iteration on the shifted operator started from [W, one Gaussian column]; the
- * positive Ritz pairs give the new W and rank (so the rank grows by at most one
- * per step).  Stops when ||X~ - X+||_F / (alpha (1 + ||X~||_F + ||grad f~||_F)) <= opt->tol.
+ * ||A^* A||), whose prox P_S+(J Z J) (Lemma PiX) comes from Algorithm 2 with
+ * history opt->lmsvd_p (0 or 1; BMG_EINVAL otherwise) on the shifted operator,
+ * started from [orth(J W), the rank safeguard column of eq. rt]; the positive
+ * Ritz pairs give the new W and rank (so the rank grows by at most one per
+ * step).  With lmsvd_p = 1 the newest Ritz value of the subspace iteration's
+ * stop test is held to a tenth of the previous PG step.  Stops when
+ * ||X~ - X+||_F / (alpha (1 + ||X~||_F + ||grad f~||_F)) <= opt->tol.
  * Uses opt->lambda, alpha, tol, bm_epochs, max_iter, ssi_max_iter, ssi_tol_floor,
- * k_init, seed, verbose.  W (device, n x ld) output, *k_out its rank; res (host)
- * fills k, iters, ssi_iters, status, F, residual, seconds, sparse bytes/passes. */
+ * k_init, seed, psi0, lmsvd_p, verbose; lmsvd_p = 1 needs a problem created with
+ * lmsvd_p >= 1 reserved (BMG_ENOMEM otherwise).  W (device, n x ld) output,
+ * *k_out its rank; res (host) fills k, iters, ssi_iters, status, F, residual,
+ * seconds, sparse bytes/passes. */
 bmg_status bmg_rke_solve(bmg_problem *p, double *W, int ld, const bmg_options *opt, int *k_out,
                          bmg_result *res);
 

@@ -131,20 +131,40 @@ class EigResult:
     U: np.ndarray          # eigenvectors kept
     theta: np.ndarray      # all Ritz values of the last basis
     iters: int
+    u: object = None       # Ritz vector of the largest Ritz value not kept (None if all kept)
 
 
-def eig_prox(prob, W, r, alpha: float, lam: float, U0, tau: float, max_iter: int = 50) -> EigResult:
+def eig_prox(prob, W, r, alpha: float, lam: float, U0, tau: float, max_iter: int = 50,
+             p: int = 0, tau_new: float = 0.0) -> EigResult:
     """Prox of the PG step from X~ = W W^T (Lemma PiX):
         X+ = P_S+(M),  M = J (X~ - alpha (L_r + lam I)) J = X~ - alpha L_r - alpha lam J
-    (J X~ J = X~ as W^T e = 0, and J L_r J = L_r).  Reading: block subspace
-    iteration on M + sigma I with sigma = alpha (2 max_i sum_j |r_ij| + lam),
-    which is positive semidefinite (Gershgorin), so the iteration finds the
-    algebraically largest eigenvalues; Rayleigh-Ritz on M with
-    T = U^T M U; next U = orth(J (M + sigma I) U V).  Stop once the Ritz values
-    above 0, the largest and the first one not above 0 moved by at most
-    tau * |largest| (the last so that a positive eigenvalue still being
-    approached is not cut off); keep the positive ones:
-    X+ = U V_+ diag(theta_+) (U V_+)^T."""
+    (J X~ J = X~ as W^T e = 0, and J L_r J = L_r).  Reading: Algorithm 2 (LmSVD)
+    with history length p on the shifted operator L = M + sigma I, sigma =
+    alpha (2 max_i sum_j |r_ij| + lam), which is positive semidefinite
+    (Gershgorin), so the iteration finds the algebraically largest eigenvalues
+    of M.  With q the width of the start block U = orth(J U0) and Y = M U:
+      the block subspace is ran(U^{i}, ..., U^{i-p'}), p' = min(p, i), with the
+      orthonormal basis Q = [U, P S] of eqs. PUi and orth-W (P the history
+      blocks projected onto ker(U^T), S over the eigenvalues of P^T P above
+      core.LMSVD_EIG_TOL), and M Q = [Y, (Y_old - Y C) S] from products already
+      made (C = U^T U_old);
+      Rayleigh-Ritz on M over Q (the eigenvectors of L, values shifted by
+      sigma): theta, V = the q leading eigenpairs of Q^T M Q (eq. lmsvd-opt);
+      next U = orth(J L(Q V)) = orth(J (M Q V + sigma Q V)), Y = M U.
+    With p = 0, Q = U and this is the block subspace iteration with a
+    Rayleigh-Ritz rotation.  Stop once the Ritz values above 0, the largest and
+    the first one not above 0 moved by at most tau * |largest| (the last so that
+    a positive eigenvalue still being approached is not cut off).  Reading, with
+    history (p >= 1) and tau_new > 0: the newest of those values (the first one
+    not above 0, or the smallest above 0 when all are) is held to
+    max(tau |largest|, min(tau_new, 1e-4 |largest|)) instead, tau_new being an
+    absolute tolerance the caller ties to the size of the PG step; it sits in
+    the cluster of small eigenvalues of the complement, where the test
+    relative to the largest would wait for far more accuracy than the step's
+    own size calls for (the error this admits in X+ is of the order of tau_new,
+    the relative inexactness of eq. inexact).  The output is the last
+    Rayleigh-Ritz step's: X+ = (Q V_+) diag(theta_+) (Q V_+)^T, and u = Q
+    v_{k+1}, the Ritz vector of the largest Ritz value not kept."""
     n = prob.n
     absdeg = np.bincount(prob.rows(), weights=np.abs(r), minlength=n)
     sigma = alpha * (2.0 * float(absdeg.max() if absdeg.size else 0.0) + lam)
@@ -156,30 +176,56 @@ def eig_prox(prob, W, r, alpha: float, lam: float, U0, tau: float, max_iter: int
         return out
 
     U = core.orth(center(U0))
+    if U.shape[1] == 0:
+        return EigResult(np.zeros((n, 0)), np.zeros((n, 0)), np.zeros(0), 0)
+    Y = apply_M(U)
+    hist = []                     # (U^{j}, M U^{j}) for j = i-1, ..., i-p'
     prev = None
     it = 0
     for it in range(1, max_iter + 1):
-        Y = apply_M(U)
-        theta, V = core.eigh_desc(U.T @ Y)
+        q = U.shape[1]
+        Q, MQ = U, Y
+        if hist:
+            Uold = np.column_stack([h[0] for h in hist])
+            Yold = np.column_stack([h[1] for h in hist])
+            C = U.T @ Uold
+            Pm = Uold - U @ C                                  # eq. PUi
+            lp, Ut = core.eigh_desc(Pm.T @ Pm)
+            keep = lp > core.LMSVD_EIG_TOL
+            S = Ut[:, keep] / np.sqrt(lp[keep])
+            Q = np.column_stack([U, Pm @ S])                   # eq. orth-W
+            MQ = np.column_stack([Y, (Yold - Y @ C) @ S])
+        theta, V = core.eigh_desc(Q.T @ MQ)
+        theta, V = theta[:q], V[:, :q]                         # eq. lmsvd-opt
         done = False
         if prev is not None and prev.size == theta.size and theta.size:
             J = theta > 0.0
             J[0] = True
-            J[min(int(np.sum(theta > 0.0)), theta.size - 1)] = True   # the first one not kept
-            done = float(np.max(np.abs(theta[J] - prev[J]))) <= tau * abs(theta[0])
+            jn = min(int(np.sum(theta > 0.0)), theta.size - 1)         # the first one not kept
+            J[jn] = True
+            lim = tau * abs(theta[0])
+            if p > 0 and tau_new > 0.0 and jn > 0:
+                J[jn] = False
+                lim_new = max(lim, min(tau_new, 1e-4 * abs(theta[0])))
+                done = (float(np.max(np.abs(theta[J] - prev[J]))) <= lim
+                        and abs(theta[jn] - prev[jn]) <= lim_new)
+            else:
+                done = float(np.max(np.abs(theta[J] - prev[J]))) <= lim
         prev = theta
         if done or it == max_iter:
             break
-        U = core.orth(center(Y @ V + sigma * (U @ V)))
+        Unew = core.orth(center(MQ @ V + sigma * (Q @ V)))
+        if p > 0:
+            hist = ([(U, Y)] + hist)[:p]
+        U = Unew
         if U.shape[1] == 0:
-            break
-    if U.shape[1] == 0:
-        return EigResult(np.zeros((n, 0)), np.zeros((n, 0)), np.zeros(0), it)
-    Y = apply_M(U)
-    theta, V = core.eigh_desc(U.T @ Y)
+            return EigResult(np.zeros((n, 0)), np.zeros((n, 0)), np.zeros(0), it)
+        Y = apply_M(U)
     keep = theta > 0.0
-    Up = U @ V[:, keep]
-    return EigResult(Up * np.sqrt(theta[keep]), Up, theta, it)
+    kp = int(np.sum(keep))
+    Up = Q @ V[:, :kp]
+    u = Q @ V[:, kp] if kp < theta.size else None
+    return EigResult(Up * np.sqrt(theta[:kp]), Up, theta, it, u)
 
 
 @dataclass
@@ -213,6 +259,14 @@ def grad_norm(prob, r, lam: float) -> float:
     return float(np.sqrt(np.sum((deg + lam) ** 2) + np.dot(r, r)))
 
 
+def step_norm(W, Wn) -> float:
+    """||W W^T - Wn Wn^T||_F, split over ran(W) and its complement
+    (core.diff_fro2_split) so that nothing cancels."""
+    if W.shape[1]:
+        return float(np.sqrt(core.diff_fro2_split(W, W, Wn, Wn)))
+    return float(np.sqrt(core.fro2_factored(Wn, Wn)))
+
+
 def stop_residual(prob, W, Wn, r, alpha: float, lam: float) -> float:
     """Stop residual of the PG step from X~ = W W^T (residual r) to X+ = Wn Wn^T:
         ||X~ - X+||_F / (alpha (1 + ||X~||_F + ||grad f~(X~)||_F)),
@@ -221,44 +275,59 @@ def stop_residual(prob, W, Wn, r, alpha: float, lam: float) -> float:
     uses the prox at unit step; alpha is far below 1 here, so the step itself
     would stop far too early); the difference is split over ran(W) and its
     complement (diff_fro2_split) so that nothing cancels."""
-    if W.shape[1]:
-        d = np.sqrt(core.diff_fro2_split(W, W, Wn, Wn))
-    else:
-        d = np.sqrt(core.fro2_factored(Wn, Wn))
+    d = step_norm(W, Wn)
     return float(d / (alpha * (1.0 + np.sqrt(core.fro2_factored(W, W)) + grad_norm(prob, r, lam))))
 
 
 def solve(prob, lam: float, k0: int = 8, tol: float = 1e-6, max_iter: int = 500, bm_epochs: int = 10,
           ssi_max_iter: int = 50, ssi_tol_floor: float = 1e-12, seed: int = 0,
-          alpha_scale: float = 1.99, callback=None) -> RkeResult:
-    """Algorithm 1 on the QSDP (readings as in eig_prox and bm_step):
+          alpha_scale: float = 1.99, lmsvd_p: int = 0, psi0: float = 0.1, callback=None) -> RkeResult:
+    """Algorithm 1 on the QSDP (readings as in eig_prox and bm_phase):
     alpha = alpha_scale / (2 + 2 max degree); the first step from X_{-1} = 0
     starts the subspace iteration from J times a Gaussian n x k0 block (stream
     STREAM_SKETCH); then per outer iteration a BM phase of bm_epochs conjugate
-    gradient steps (bm_phase), the PG step warm-started from orth(J [W~_t, xi_t])
-    with xi_t Gaussian (stream STREAM_SAFEGUARD + t), so the rank grows by at
-    most one per step (reading: far from the optimum nearly every eigenvalue of
-    the PG point is positive, and a block orth([U_t, W~_t]) doubles), and the
-    rank update k = number of positive Ritz values.  Stop when
-    ||X~ - X+||_F / (alpha (1 + ||X~||_F + ||grad f~(X~)||_F)) <= tol: the
+    gradient steps (bm_phase) and the PG step (eig_prox with history lmsvd_p),
+    warm-started from [Ubase, u_t + xi_t] with Ubase = orth(J W~_t) and the
+    rank safeguard column of eq. rt (core.safeguard_column, stream
+    STREAM_SAFEGUARD + t): u is the Ritz vector of the largest Ritz value not
+    kept at the latest PG step that truncated one, xi_t a random vector of
+    norm psi_t orthogonal to [Ubase, u_t]; psi starts at psi0 and halves after
+    every PG step that truncates exactly one Ritz value (Suppl. A.1.3); the
+    newest Ritz value's tolerance tau_new of eig_prox is a tenth of the
+    previous PG step's ||X~ - X+||_F (with history only).  The
+    rank grows by at most one per step (reading: far from the optimum nearly
+    every eigenvalue of the PG point is positive, and a block orth([U_t, W~_t])
+    doubles), and the rank update k = number of positive Ritz values.  Stop
+    when ||X~ - X+||_F / (alpha (1 + ||X~||_F + ||grad f~(X~)||_F)) <= tol: the
     prox-gradient mapping, as alpha is far below 1 here (the tolerance of the
     subspace iteration tightens with that residual)."""
     n = prob.n
     alpha = alpha_scale / lipschitz_bound(prob)
     Om = rng.normals(seed, rng.STREAM_SKETCH, n * k0).reshape(n, k0)
-    e0 = eig_prox(prob, np.zeros((n, 0)), -prob.val, alpha, lam, Om, 1e-4, ssi_max_iter)
+    e0 = eig_prox(prob, np.zeros((n, 0)), -prob.val, alpha, lam, Om, 1e-4, ssi_max_iter, lmsvd_p)
     W = e0.W
+    u_keep = e0.u
+    psi = psi0
     hist: List[RkeRecord] = []
     res, res_prev, conv, t = np.inf, 1.0, False, 0
+    step_prev = 0.0
     F = objective(prob, W, lam)
     for t in range(max_iter):
         if W.shape[1] and bm_epochs > 0:
             W, _ = bm_phase(prob, W, lam, bm_epochs)
         r = pair_residual(prob, W)
         tau = max(ssi_tol_floor, min(1e-4, 0.1 * res_prev * res_prev))
-        xi = rng.normals(seed, rng.STREAM_SAFEGUARD + t, n)[:, None]
-        ep = eig_prox(prob, W, r, alpha, lam, np.column_stack([W, xi]), tau, ssi_max_iter)
+        Ubase = core.orth(center(W)) if W.shape[1] else np.zeros((n, 0))
+        col = core.safeguard_column(Ubase, u_keep, psi, seed, t)
+        ep = eig_prox(prob, W, r, alpha, lam, np.column_stack([Ubase, col]), tau, ssi_max_iter, lmsvd_p,
+                      0.1 * step_prev)
         res = stop_residual(prob, W, ep.W, r, alpha, lam)
+        step_prev = step_norm(W, ep.W)
+        # safeguard bookkeeping (eq. rt)
+        trunc = ep.theta.size - ep.W.shape[1]
+        u_keep = ep.u if trunc >= 1 else None
+        if trunc == 1:
+            psi *= 0.5
         W = ep.W
         F = objective(prob, W, lam)
         rec = RkeRecord(t, F, res, W.shape[1], ep.iters)

@@ -1668,6 +1668,42 @@ struct Method : Engine<T, TG> {
   // U0 (m x q0, orthonormal) in Ubuf (block B1 or B2).  On return *Uout / *Yout
   // point at the final basis (q columns) and Z^T of it; Tq is their Gram matrix.
   // History length p_t = hist_p.
+  // The extra column u_t + xi_t of eq. rt (Suppl. A.1.3) into col (ld qld),
+  // against the cb orthonormal columns of Ub (mm rows, ld qld): u_t is u
+  // projected onto ker(Ub^T) (when has_u), xi_t a standard normal vector
+  // (stream STREAM_SAFEGUARD + t) projected onto ker([Ub, u_t]^T) and scaled
+  // to norm psi; without u the column is that vector at norm 1.  ut and zv are
+  // mm-element scratch vectors.
+  void safeguard_col(int64_t mm, const T *Ub, int cb, const T *u, bool has_u, double psi,
+                     uint64_t seed, int t, T *col, T *ut, T *zv) {
+    HIPC(launch_normals<T>(seed, STREAM_SAFEGUARD + (uint64_t)t, mm, 1, 1, zv, s));
+    double nu = 0.0;
+    if (has_u) {
+      HIPC(launch_copy_cols<T>(mm, 1, u, 1, ut, 1, s));
+      if (cb > 0) {
+        std::vector<double> c = gram(mm, cb, Ub, qld, 1, ut, 1);
+        for (double &v : c) v = -v;
+        gemm(mm, cb, Ub, qld, 1, c, ut, 1, 1.0);
+      }
+      nu = sqrt(gram(mm, 1, ut, 1, 1, ut, 1)[0]);
+    }
+    if (cb > 0) {
+      std::vector<double> c = gram(mm, cb, Ub, qld, 1, zv, 1);
+      for (double &v : c) v = -v;
+      gemm(mm, cb, Ub, qld, 1, c, zv, 1, 1.0);
+    }
+    if (nu > 0.0) {
+      const double c = gram(mm, 1, ut, 1, 1, zv, 1)[0] / (nu * nu);
+      HIPC(launch_axpy<T>(mm, 1, -c, ut, 1, zv, 1, s));
+    }
+    const double nz = sqrt(gram(mm, 1, zv, 1, 1, zv, 1)[0]);
+    const double scale = nz > 0.0 ? 1.0 / nz : 0.0;
+    // column = u_t + psi * xi  (or the unit random vector when no u is kept)
+    HIPC(launch_fill<T>(col, mm, 1, qld, 0.0, s));
+    HIPC(launch_axpy<T>(mm, 1, (has_u ? psi : 1.0) * scale, zv, 1, col, qld, s));
+    if (has_u) HIPC(launch_axpy<T>(mm, 1, 1.0, ut, 1, col, qld, s));
+  }
+
   int hist_p = 0;
   HostHelper helper;
   int lmsvd(const ZOp &z, T *Ubuf, int q, double tau, int max_iter, double keep_level,
@@ -2144,35 +2180,8 @@ struct Method : Engine<T, TG> {
     T *U0 = B2;
     int q0 = cb;
     if (add) {
-      T *col = B2 + cb;  // column cb of the block
-      T *ut = blk(P->L.b_vec) + 2 * rup(m, 64);
-      T *zv = blk(P->L.b_vec) + 4 * rup(m, 64);
-      HIPC(launch_normals<T>(seed, STREAM_SAFEGUARD + (uint64_t)t, m, 1, 1, zv, s));
-      double nu = 0.0;
-      if (S.has_u) {
-        HIPC(launch_copy_cols<T>(m, 1, S.uvec, 1, ut, 1, s));
-        if (cb > 0) {
-          std::vector<double> c = gram(m, cb, B2, qld, 1, ut, 1);
-          for (double &v : c) v = -v;
-          gemm(m, cb, B2, qld, 1, c, ut, 1, 1.0);
-        }
-        nu = sqrt(gram(m, 1, ut, 1, 1, ut, 1)[0]);
-      }
-      if (cb > 0) {
-        std::vector<double> c = gram(m, cb, B2, qld, 1, zv, 1);
-        for (double &v : c) v = -v;
-        gemm(m, cb, B2, qld, 1, c, zv, 1, 1.0);
-      }
-      if (nu > 0.0) {
-        const double c = gram(m, 1, ut, 1, 1, zv, 1)[0] / (nu * nu);
-        HIPC(launch_axpy<T>(m, 1, -c, ut, 1, zv, 1, s));
-      }
-      const double nz = sqrt(gram(m, 1, zv, 1, 1, zv, 1)[0]);
-      const double scale = nz > 0.0 ? 1.0 / nz : 0.0;
-      // column = u_t + psi * xi  (or the unit random vector when no u is kept)
-      HIPC(launch_fill<T>(col, m, 1, qld, 0.0, s));
-      HIPC(launch_axpy<T>(m, 1, (S.has_u ? S.psi : 1.0) * scale, zv, 1, col, qld, s));
-      if (S.has_u) HIPC(launch_axpy<T>(m, 1, 1.0, ut, 1, col, qld, s));
+      safeguard_col(m, B2, cb, S.uvec, S.has_u, S.psi, seed, t, B2 + cb,
+                    blk(P->L.b_vec) + 2 * rup(m, 64), blk(P->L.b_vec) + 4 * rup(m, 64));
       q0 = orth(m, B2, cb + 1, B1, B4);
       U0 = B1;
       info.added = true;
@@ -2749,17 +2758,40 @@ struct RkeMethod : Method<double> {
     return d + 2.0 * cross + std::max(0.0, three(E1, qld, k1, E0, qld, k0));
   }
   struct Eig {
-    int k = 0, iters = 0;
+    int k = 0, iters = 0, q = 0;  // rank kept, iterations, Ritz values in the last basis
+    bool has_u = false;           // uvec holds the Ritz vector of the largest one not kept
   };
   // Prox of the PG step (Lemma PiX) from the q0 columns of U0 (block B1 or
-  // B2, ld qld): subspace iteration on M + sigma I, Rayleigh-Ritz on M, the
-  // positive Ritz pairs kept: Wn = U V_+ sqrt(theta_+), Uc = U V_+ (ld ldk).
+  // B2, ld qld): Algorithm 2 with history hp (0 or 1) on M + sigma I.  Per
+  // iteration, U (q columns) and Y = M U in the first columns of their blocks;
+  // with history, U_old / Y_old the previous ones:
+  //   C = U^T U_old, P = U_old - U C (eq. PUi), P^T P = U~ Lambda U~^T,
+  //   S = U~ Lambda^{-1/2} over the eigenvalues above LMSVD_EIG_TOL,
+  //   Q = [U, P S] (eq. orth-W; P S in U's block after its q columns),
+  //   M Q = [Y, (Y_old - Y C) S] (likewise in Y's block),
+  //   theta, V = the q leading eigenpairs of Q^T M Q (eq. lmsvd-opt),
+  //   next U = orth(J (M Q V + sigma Q V)), Y = M U.
+  // Stop once the Ritz values above 0, the largest and the first one not above
+  // 0 moved by at most tau * |largest|; with history (hp > 0) the newest of
+  // them by at most max(tau |largest|, min(tau_new, 1e-4 |largest|)) (tau_new
+  // an absolute tolerance, 0 for none).  The positive Ritz pairs of the last
+  // step are kept: Wn = Q V_+ sqrt(theta_+), Uc = Q V_+ (ld ldk); uvec =
+  // Q v_{k+1} when a Ritz value is not kept.
   Eig eig_prox(const double *W, int k, double alpha, double lam, double *U0, int q0, double tau,
-               int max_iter, double *Wn, double *Uc) {
+               double tau_new, int max_iter, int hp, double *Wn, double *Uc, double *uvec) {
     Eig out;
     double *B1 = blk(P->L.b_B1), *B2 = blk(P->L.b_B2), *B3 = blk(P->L.b_B3), *B4 = blk(P->L.b_B4);
     double *Y = blk(P->L.b_Y), *tmp = blk(P->L.b_Y2);
     double *U = U0 == B1 ? B2 : B1;
+    double *Uold = nullptr, *Yold = nullptr, *Pt = nullptr, *Et = nullptr;
+    if (hp > 0) {
+      char *hm = (char *)this->hist_mem(hp);
+      const size_t mb = P->L.hist_mb, nb = P->L.hist_nb;
+      Uold = (double *)hm;
+      Yold = (double *)(hm + mb);
+      Pt = (double *)(hm + mb + nb);
+      Et = (double *)(hm + mb + 2 * nb);
+    }
     // sigma = alpha (2 max_i sum_j |r_ij| + lambda)
     std::vector<double> ad(n);
     HIPC(hipMemcpyAsync(ad.data(), adeg, 8 * n, hipMemcpyDeviceToHost, s));
@@ -2769,62 +2801,122 @@ struct RkeMethod : Method<double> {
     const double sigma = alpha * (2.0 * amax + lam);
     HIPC(launch_center_cols(n, q0, U0, qld, P->gram_part, P->L.gram_cap, s));
     int q = orth(n, U0, q0, U, B4);
+    if (q == 0) return out;
+    apply_M(W, k, alpha, lam, U, q, Y, tmp);
     std::vector<double> prev, th, V;
+    int qo = 0, qq = q;   // history columns, columns of Q
     int it = 0;
-    for (it = 1; it <= max_iter && q > 0; ++it) {
-      apply_M(W, k, alpha, lam, U, q, Y, tmp);
-      std::vector<double> T = gram(n, q, U, qld, q, Y, qld);
-      th.assign(q, 0.0);
-      V.assign((size_t)q * q, 0.0);
-      lat::sym_eig(q, T.data(), th.data(), V.data());
+    for (it = 1; it <= max_iter; ++it) {
+      qq = q;
+      if (qo > 0) {
+        std::vector<double> Cm = gram(n, q, U, qld, qo, Uold, qld);   // q x qo
+        for (double &v : Cm) v = -v;
+        HIPC(launch_copy_cols<double>(n, qo, Uold, qld, Pt, qld, s));
+        gemm(n, q, U, qld, qo, Cm, Pt, qld, 1.0);
+        std::vector<double> G = gram(n, qo, Pt, qld, qo, Pt, qld), lp(qo), Ut((size_t)qo * qo);
+        lat::sym_eig(qo, G.data(), lp.data(), Ut.data());
+        int r2 = 0;
+        while (r2 < qo && lp[r2] > LMSVD_EIG_TOL) ++r2;
+        REQUIRE(q + r2 <= qld, BMG_ENOMEM, "subspace basis wider than the workspace blocks");
+        if (r2 > 0) {
+          std::vector<double> Sm((size_t)qo * r2);
+          for (int a = 0; a < qo; ++a)
+            for (int c = 0; c < r2; ++c) Sm[(size_t)a * r2 + c] = Ut[(size_t)a * qo + c] / sqrt(lp[c]);
+          gemm(n, qo, Pt, qld, r2, Sm, U + q, qld, 0.0);
+          HIPC(launch_copy_cols<double>(n, qo, Yold, qld, Et, qld, s));
+          gemm(n, q, Y, qld, qo, Cm, Et, qld, 1.0);
+          gemm(n, qo, Et, qld, r2, Sm, Y + q, qld, 0.0);
+          qq = q + r2;
+        }
+      }
+      std::vector<double> T = gram(n, qq, U, qld, qq, Y, qld);
+      for (int a = 0; a < qq; ++a)
+        for (int b = 0; b < a; ++b) {
+          const double v = 0.5 * (T[(size_t)a * qq + b] + T[(size_t)b * qq + a]);
+          T[(size_t)a * qq + b] = T[(size_t)b * qq + a] = v;
+        }
+      std::vector<double> thq(qq), Vq((size_t)qq * qq);
+      lat::sym_eig(qq, T.data(), thq.data(), Vq.data());
+      th.assign(thq.begin(), thq.begin() + q);
+      V.assign((size_t)qq * q, 0.0);
+      for (int a = 0; a < qq; ++a)
+        for (int c = 0; c < q; ++c) V[(size_t)a * q + c] = Vq[(size_t)a * qq + c];
       bool done = false;
       if (!prev.empty() && prev.size() == th.size()) {
         // the Ritz values kept, the largest, and the first one not kept
         int npos = 0;
         while (npos < q && th[npos] > 0.0) ++npos;
-        double dmax = 0.0;
+        // with history, the newest of them (the smallest kept when all are
+        // kept, else the first not kept) is held to tau_new instead when that
+        // is looser
+        const int jn = std::min(npos, q - 1);
+        const bool rel = hp > 0 && tau_new > 0.0 && jn > 0;
+        double dmax = 0.0, dnew = 0.0;
         for (int j = 0; j < q; ++j)
-          if (j == 0 || th[j] > 0.0 || j == std::min(npos, q - 1))
-            dmax = std::max(dmax, fabs(th[j] - prev[j]));
-        done = dmax <= tau * fabs(th[0]);
+          if (j == 0 || th[j] > 0.0 || j == jn) {
+            if (rel && j == jn) dnew = fabs(th[j] - prev[j]);
+            else dmax = std::max(dmax, fabs(th[j] - prev[j]));
+          }
+        const double lim = tau * fabs(th[0]);
+        done = dmax <= lim && dnew <= std::max(lim, std::min(tau_new, 1e-4 * fabs(th[0])));
       }
       prev = th;
       if (done || it == max_iter) break;
-      // next basis: orth(J (Y V + sigma U V))
+      // next basis: orth(J (M Q V + sigma Q V))
       std::vector<double> sV(V);
       for (double &v : sV) v *= sigma;
-      gemm(n, q, Y, qld, q, V, B3, qld, 0.0);
-      gemm(n, q, U, qld, q, sV, B3, qld, 1.0);
+      gemm(n, qq, Y, qld, q, V, B3, qld, 0.0);
+      gemm(n, qq, U, qld, q, sV, B3, qld, 1.0);
       HIPC(launch_center_cols(n, q, B3, qld, P->gram_part, P->L.gram_cap, s));
-      q = orth(n, B3, q, U, B4);
-      prev.clear();
-      prev = th;
+      if (hp > 0) {
+        HIPC(launch_copy_cols<double>(n, q, U, qld, Uold, qld, s));
+        HIPC(launch_copy_cols<double>(n, q, Y, qld, Yold, qld, s));
+        qo = q;
+      }
+      const int qn = orth(n, B3, q, U, B4);
+      if (qn == 0) {
+        out.iters = it;
+        return out;
+      }
+      q = qn;
+      apply_M(W, k, alpha, lam, U, q, Y, tmp);
     }
     out.iters = std::min(it, max_iter);
-    if (q == 0 || th.empty()) return out;
+    out.q = q;
     int kp = 0;
     while (kp < q && th[kp] > 0.0) ++kp;
     REQUIRE(kp <= P->L.k_cap, BMG_ENOMEM, "rank of the prox output (" + std::to_string(kp) + ") exceeds k_cap");
-    std::vector<double> CW((size_t)q * std::max(kp, 1)), CU((size_t)q * std::max(kp, 1));
-    for (int i = 0; i < q; ++i)
+    std::vector<double> CW((size_t)qq * std::max(kp, 1)), CU((size_t)qq * std::max(kp, 1));
+    for (int i = 0; i < qq; ++i)
       for (int j = 0; j < kp; ++j) {
         CU[(size_t)i * kp + j] = V[(size_t)i * q + j];
         CW[(size_t)i * kp + j] = V[(size_t)i * q + j] * sqrt(th[j]);
       }
     if (kp > 0) {
-      gemm(n, q, U, qld, kp, CW, Wn, ldk, 0.0);
-      gemm(n, q, U, qld, kp, CU, Uc, ldk, 0.0);
+      gemm(n, qq, U, qld, kp, CW, Wn, ldk, 0.0);
+      gemm(n, qq, U, qld, kp, CU, Uc, ldk, 0.0);
+    }
+    if (kp < q) {
+      std::vector<double> cu(qq);
+      for (int i = 0; i < qq; ++i) cu[i] = V[(size_t)i * q + kp];
+      gemm(n, qq, U, qld, 1, cu, uvec, 1, 0.0);
+      out.has_u = true;
     }
     out.k = kp;
     return out;
   }
 
   // Algorithm 1 on the QSDP: BM phase, then the PG step of Lemma PiX with
-  // step alpha / (2 + 2 max degree), warm-started from [W~, xi]; the stop
-  // residual is the PG step's change divided by the step size
+  // step alpha / (2 + 2 max degree), warm-started from [orth(J W~), u_t + xi_t]
+  // (the rank safeguard column of eq. rt, psi halving after every step that
+  // truncates exactly one Ritz value); the stop residual is the PG step's
+  // change divided by the step size
   bmg_status solve(const bmg_options &o, int *k_out, bmg_result *res) {
     const auto t0 = std::chrono::steady_clock::now();
     P->reset_stats();
+    REQUIRE(o.lmsvd_p >= 0 && o.lmsvd_p <= 1, BMG_EINVAL,
+            "the kernel-estimation path runs Algorithm 2 with lmsvd_p 0 or 1");
+    const int hp = o.lmsvd_p;
     std::vector<int64_t> ptr(n + 1);
     HIPC(hipMemcpyAsync(ptr.data(), R->pl.ptr, 8 * (n + 1), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
@@ -2833,29 +2925,43 @@ struct RkeMethod : Method<double> {
     const double alpha = o.alpha / (2.0 + 2.0 * (double)maxdeg);
     const double lam = o.lambda;
     double *W = blk(P->L.b_W), *Wn = blk(P->L.b_Wn), *Uc = blk(P->L.b_Ucur);
-    double *B1 = blk(P->L.b_B1);
+    double *B1 = blk(P->L.b_B1), *B2 = blk(P->L.b_B2), *B4 = blk(P->L.b_B4);
+    const int64_t nv = rup(n, 64);
+    double *uvec = blk(P->L.b_vec), *ut = blk(P->L.b_vec) + 4 * nv, *zv = blk(P->L.b_vec) + 5 * nv;
     int k = 0, ssi_total = 0;
     // X_{-1} = 0: r = -d^2; the start block J times Gaussian (n x k0)
     const int k0 = std::max(1, std::min(o.k_init, qld));
     residual(W, 0);
     HIPC(launch_normals<double>(o.seed, STREAM_SKETCH, n, k0, qld, B1, s));
-    Eig e0 = eig_prox(W, 0, alpha, lam, B1, k0, 1e-4, o.ssi_max_iter, Wn, Uc);
+    Eig e0 = eig_prox(W, 0, alpha, lam, B1, k0, 1e-4, 0.0, o.ssi_max_iter, hp, Wn, Uc, uvec);
     ssi_total += e0.iters;
     k = e0.k;
+    bool has_u = e0.has_u;
+    double psi = o.psi0;
     std::swap(W, Wn);
-    double resid = INFINITY, res_prev = 1.0, F = 0.0;
+    double resid = INFINITY, res_prev = 1.0, F = 0.0, step_prev = 0.0;
     bool conv = false;
     int t = 0;
     for (t = 0; t < o.max_iter; ++t) {
       if (k > 0 && o.bm_epochs > 0) bm_phase(W, k, lam, o.bm_epochs);
       const double r2 = residual(W, k);
       const double tau = std::max(o.ssi_tol_floor, std::min(1e-4, 0.1 * res_prev * res_prev));
-      // warm start [W~_t, xi_t]: the rank grows by at most one per step
-      const int q0 = k + 1;
-      HIPC(launch_copy_cols<double>(n, k, W, ldk, B1, qld, s));
-      HIPC(launch_normals<double>(o.seed, STREAM_SAFEGUARD + (uint64_t)t, n, 1, qld, B1 + k, s));
-      Eig ep = eig_prox(W, k, alpha, lam, B1, q0, tau, o.ssi_max_iter, Wn, Uc);
+      // warm start [orth(J W~_t), u_t + xi_t]: the rank grows by at most one per step
+      int cb = 0;
+      if (k > 0) {
+        HIPC(launch_copy_cols<double>(n, k, W, ldk, B1, qld, s));
+        HIPC(launch_center_cols(n, k, B1, qld, P->gram_part, P->L.gram_cap, s));
+        cb = orth(n, B1, k, B2, B4);
+      }
+      this->safeguard_col(n, B2, cb, uvec, has_u, psi, o.seed, t, B2 + cb, ut, zv);
+      // the newest Ritz value's tolerance: a tenth of the previous PG step
+      Eig ep = eig_prox(W, k, alpha, lam, B2, cb + 1, tau, 0.1 * step_prev, o.ssi_max_iter, hp, Wn, Uc,
+                        uvec);
       ssi_total += ep.iters;
+      // safeguard bookkeeping (eq. rt)
+      const int trunc = ep.q - ep.k;
+      has_u = ep.has_u && trunc >= 1;
+      if (trunc == 1) psi *= 0.5;
       // relative residual ||X~ - X+|| / (1 + ||X~|| + ||grad f~(X~)||)
       std::vector<double> dg(n);
       HIPC(hipMemcpyAsync(dg.data(), deg, 8 * n, hipMemcpyDeviceToHost, s));
@@ -2869,6 +2975,7 @@ struct RkeMethod : Method<double> {
                                                   return M::trace_prod(g, g, ep.k); }() : 0.0);
       // the prox-gradient mapping (divided by alpha, which is far below 1 here)
       resid = sqrt(std::max(d2, 0.0)) / (alpha * (1.0 + sqrt(std::max(x2, 0.0)) + sqrt(g2)));
+      step_prev = sqrt(std::max(d2, 0.0));
       std::swap(W, Wn);
       k = ep.k;
       F = 0.25 * residual(W, k) + lam * (k > 0 ? fro2(n, W, ldk, k) : 0.0);

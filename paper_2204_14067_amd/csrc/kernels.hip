@@ -244,6 +244,55 @@ __global__ __launch_bounds__(256) void k_gemm_ts(int64_t N, int a, const T *__re
   }
 }
 
+// The same product with 32 x 32 output tiles (K-chunks of 32, 2 x 2 outputs
+// per thread): four times the blocks, for products too short to fill the
+// chip with 64 x 64 tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_ts32(int64_t N, int a, const T *__restrict__ X,
+                                                   int ldx, int b, const double *__restrict__ M,
+                                                   int ldm, T *__restrict__ C, int ldc,
+                                                   double beta) {
+  __shared__ double xs[32][33];
+  __shared__ double ms[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 32;
+  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+  double acc[2][2] = {};
+  for (int k0 = 0; k0 < a; k0 += 32) {
+    for (int t = threadIdx.x; t < 32 * 32; t += 256) {
+      const int rr = t / 32, kk = t % 32;
+      const int64_t r = r0 + rr;
+      xs[rr][kk] = (r < N && k0 + kk < a) ? (double)X[r * ldx + k0 + kk] : 0.0;
+      const int mk = t / 32, mc = t % 32;
+      ms[mk][mc] = (k0 + mk < a && c0 + mc < b) ? M[(int64_t)(k0 + mk) * ldm + c0 + mc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      const double x0 = xs[tr * 2][kk], x1 = xs[tr * 2 + 1][kk];
+      const double m0 = ms[kk][tc], m1 = ms[kk][tc + 16];
+      acc[0][0] += x0 * m0;
+      acc[0][1] += x0 * m1;
+      acc[1][0] += x1 * m0;
+      acc[1][1] += x1 * m1;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int64_t r = r0 + tr * 2 + i;
+    if (r >= N) continue;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = c0 + tc + 16 * j;
+      if (c >= b) continue;
+      double v = acc[i][j];
+      if (beta != 0.0) v += beta * (double)C[r * ldc + c];
+      C[r * ldc + c] = (T)v;
+    }
+  }
+}
+
 template <typename T>
 hipError_t launch_gemm_ts(int64_t N, int a, const T *X, int ldx, int b, const double *M, int ldm,
                           T *C, int ldc, double beta, hipStream_t s) {
@@ -251,6 +300,13 @@ hipError_t launch_gemm_ts(int64_t N, int a, const T *X, int ldx, int b, const do
   if (a == 0) {  // C = beta C
     if (beta == 1.0) return hipSuccess;
     return launch_axpy<T>(N, b, beta - 1.0, C, ldc, C, ldc, s);
+  }
+  const int64_t tiles64 = ((N + 63) / 64) * ((b + 63) / 64);
+  if (tiles64 < 1024) {
+    dim3 grid((unsigned)((N + 31) / 32), (unsigned)((b + 31) / 32));
+    hipLaunchKernelGGL((k_gemm_ts32<T>), grid, dim3(256), 0, s, N, a, X, ldx, b, M, ldm, C, ldc,
+                       beta);
+    return hipGetLastError();
   }
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((b + 63) / 64));
   hipLaunchKernelGGL((k_gemm_ts<T>), grid, dim3(256), 0, s, N, a, X, ldx, b, M, ldm, C, ldc, beta);

@@ -9,7 +9,14 @@ netflix_quarter_lam300.json : the Netflix-shaped generator at scale 0.25 (4,442 
                      truth + noise variance 0.25 clipped to [1, 5]), lambda = 300,
                      k0 = 16; oracle solve to 1e-10 with its duality-gap certificate.
 
-    python tests/golden/make_golden.py [small_uniform] [netflix_quarter]
+rke_solves.json   : the kernel-estimation QSDP oracle (oracle/rke.py) on
+                     synth.rke workloads: (600 objects, 40 partners, lambda 10,
+                     seed 3; k0 6, tol 1e-5, algorithm seed 1) with lmsvd_p 0
+                     and 1, and the 20,000-object benchmark workload (lambda 10,
+                     seed 7; k0 8, tol 1e-4, algorithm seed 1, lmsvd_p 1); final
+                     F, rank, outer and subspace iterations.
+
+    python tests/golden/make_golden.py [small_uniform] [netflix_quarter] [rke_600] [rke_20000]
 """
 import json
 import os
@@ -19,7 +26,7 @@ import time
 sys.path.insert(0, os.path.abspath(os.path.join(os.path.dirname(__file__), "..", "..")))
 
 import synth  # noqa: E402
-from oracle import core, dense  # noqa: E402
+from oracle import core, dense, rke  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -48,6 +55,32 @@ def small_uniform():
 def netflix_quarter():
     p = synth.netflix_shape(scale=0.25)
     certified(p, 300.0, 16, 3, "netflix_quarter_lam300.json")
+
+
+def _rke_case(key, n, lam, seed, k0, tol, hist, alg_seed=1):
+    fname = os.path.join(HERE, "rke_solves.json")
+    p = synth.rke(n, 40, lam=lam, seed=seed)
+    t0 = time.time()
+    r = rke.solve(p, lam, k0=k0, tol=tol, seed=alg_seed, max_iter=3000, bm_epochs=10, lmsvd_p=hist,
+                  callback=lambda h: print(key, h.t, h.F, h.residual, h.k, h.ssi_iters, flush=True))
+    data = json.load(open(fname)) if os.path.exists(fname) else {}
+    data[key] = dict(problem=p.name, n=n, deg=40, lam=lam, seed=seed, k0=k0, tol=tol, lmsvd_p=hist,
+                     alg_seed=alg_seed, bm_epochs=10, F=r.F, rank=r.k, iters=r.iters,
+                     converged=r.converged, ssi_iters=sum(h.ssi_iters for h in r.history),
+                     seconds=time.time() - t0,
+                     note="written by tests/golden/make_golden.py from the CPU oracle")
+    with open(fname, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    print(key, data[key])
+
+
+def rke_600():
+    for hist in (0, 1):
+        _rke_case("n600_p%d" % hist, 600, 10.0, 3, 6, 1e-5, hist)
+
+
+def rke_20000():
+    _rke_case("n20000_p1", 20_000, 10.0, 7, 8, 1e-4, 1)
 
 
 if __name__ == "__main__":

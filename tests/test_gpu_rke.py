@@ -2,7 +2,9 @@
 oracle/rke.py on the same seeded inputs (FP64).  Tolerances: pair residuals
 4 k u (|w_i|^2 + |w_j|^2 + d^2) elementwise; solves: objective within 1e-8
 relative, the same rank."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -17,9 +19,9 @@ DEV = "cuda:0"
 U = 2.0 ** -53
 
 
-def to_dev(p, k_cap=32, precision="fp64"):
+def to_dev(p, k_cap=32, precision="fp64", lmsvd_p=0):
     return bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=k_cap, precision=precision,
-                                 device=DEV)
+                                 device=DEV, lmsvd_p=lmsvd_p)
 
 
 @pytest.mark.parametrize("n,deg,k", [(30, 8, 1), (200, 20, 5), (3000, 5000, 17)])
@@ -41,19 +43,50 @@ def test_rke_residual_parity(n, deg, k):
     assert math.isclose(s2, float(ro @ ro), rel_tol=1e-12)
 
 
+@pytest.mark.parametrize("hist", [0, 1])
 @pytest.mark.parametrize("n,deg,lam", [(50, 30, 2.0), (100, 30, 1.5)])
-def test_rke_solve_parity(n, deg, lam):
+def test_rke_solve_parity(n, deg, lam, hist):
+    """Plain subspace iteration (lmsvd_p 0) and Algorithm 2 with history 1,
+    both with the rank safeguard column of eq. rt."""
     p = synth.rke(n, deg, lam=lam, seed=3)
-    orc = rke.solve(p, lam, k0=6, tol=1e-8, seed=1, max_iter=1000)
-    dp = to_dev(p, k_cap=64)
-    W, k, r = dp.bmg_rke_solve(lam=lam, k_init=6, tol=1e-8, seed=1, max_iter=1000, bm_epochs=10)
-    print("rke solve", n, r["iters"], orc.iters, r["F"], orc.F, k, orc.k, flush=True)
+    orc = rke.solve(p, lam, k0=6, tol=1e-8, seed=1, max_iter=1000, lmsvd_p=hist)
+    dp = to_dev(p, k_cap=64, lmsvd_p=hist)
+    W, k, r = dp.bmg_rke_solve(lam=lam, k_init=6, tol=1e-8, seed=1, max_iter=1000, bm_epochs=10,
+                               lmsvd_p=hist)
+    print("rke solve", n, hist, r["iters"], orc.iters, r["F"], orc.F, k, orc.k, r["ssi_iters"],
+          sum(h.ssi_iters for h in orc.history), flush=True)
     assert r["status"] == 0 and orc.converged
     assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
     assert k == orc.k
     Wg = W.cpu().numpy()[:, :k]
     assert np.allclose(Wg.sum(axis=0), 0.0, atol=1e-8 * max(1.0, np.abs(Wg).max()))
     assert math.isclose(rke.objective(p, Wg, lam), r["F"], rel_tol=1e-10)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rke_solves.json")
+
+
+@pytest.mark.parametrize("key", ["n600_p0", "n600_p1", "n20000_p1"])
+def test_rke_solve_against_stored_oracle_solves(key):
+    """Workloads of the benchmark's shape (noisy distances, the rank growing
+    over the whole solve), too slow for the oracle at test time: its solves are
+    stored by tests/golden/make_golden.py.  The same objective to 1e-8, the same
+    rank, and the same outer and subspace iteration counts up to a few (the two
+    take the same decisions up to rounding).  n20000_p1 is the benchmark
+    workload itself (20,000 objects, lmsvd_p 1)."""
+    g = json.load(open(GOLDEN))[key]
+    p = synth.rke(g["n"], g["deg"], lam=g["lam"], seed=g["seed"])
+    dp = to_dev(p, k_cap=160, lmsvd_p=g["lmsvd_p"])
+    W, k, r = dp.bmg_rke_solve(lam=g["lam"], k_init=g["k0"], tol=g["tol"], seed=g["alg_seed"],
+                               max_iter=3000, bm_epochs=g["bm_epochs"], lmsvd_p=g["lmsvd_p"])
+    per_step = r["ssi_iters"] / (r["iters"] + 1)
+    print("rke stored", key, r["iters"], g["iters"], r["F"], g["F"], k, g["rank"], r["ssi_iters"],
+          g["ssi_iters"], "ssi per PG step %.2f" % per_step, flush=True)
+    assert r["status"] == 0 and g["converged"]
+    assert math.isclose(r["F"], g["F"], rel_tol=1e-8)
+    assert k == g["rank"]
+    assert abs(r["iters"] - g["iters"]) <= 2
+    assert abs(r["ssi_iters"] - g["ssi_iters"]) <= 0.02 * g["ssi_iters"] + 5
 
 
 def test_rke_rejects_unsymmetric_and_reduced_precision():
@@ -66,3 +99,8 @@ def test_rke_rejects_unsymmetric_and_reduced_precision():
         to_dev(q, k_cap=8, precision="fp32").bmg_rke_solve(lam=1.0)
     with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
         to_dev(q, k_cap=8).bmg_rke_solve(lam=-1.0)
+    with pytest.raises(bmg.BmgError, match="BMG_EINVAL"):
+        to_dev(q, k_cap=8, lmsvd_p=2).bmg_rke_solve(lam=1.0, lmsvd_p=2)
+    # history blocks the workspace was not sized for
+    with pytest.raises(bmg.BmgError, match="BMG_ENOMEM"):
+        to_dev(q, k_cap=8).bmg_rke_solve(lam=1.0, lmsvd_p=1)

@@ -96,7 +96,9 @@ def test_lemma_pix_against_reduced_coordinates():
         assert abs(np.sum(Pl)) < 1e-10 and np.linalg.eigvalsh(Pl).min() > -1e-10
 
 
-def test_eig_prox_is_the_projection_of_the_pg_point():
+@pytest.mark.parametrize("hist", [0, 1, 2])
+def test_eig_prox_is_the_projection_of_the_pg_point(hist):
+    """With and without the history of Algorithm 2: the same projection."""
     p = synth.rke(30, 10, seed=8)
     lam, alpha = 0.8, 1.99 / rke.lipschitz_bound(p)
     W = rke.center(rand((30, 3), 10))
@@ -104,16 +106,17 @@ def test_eig_prox_is_the_projection_of_the_pg_point():
     Z = W @ W.T - alpha * (dense_lap(p, r) + lam * np.eye(30))
     Xd = rke.project_dense(Z)
     kd = int(np.sum(np.linalg.eigvalsh(Xd) > 1e-9))
-    ep = rke.eig_prox(p, W, r, alpha, lam, rand((30, kd + 6), 11), 1e-14, max_iter=3000)
+    ep = rke.eig_prox(p, W, r, alpha, lam, rand((30, kd + 6), 11), 1e-14, max_iter=3000, p=hist)
     assert np.allclose(ep.W @ ep.W.T, Xd, atol=1e-8)
     assert ep.W.shape[1] == kd
     assert np.allclose(ep.W.sum(axis=0), 0.0, atol=1e-10)
 
 
-def test_solve_matches_dense_proximal_gradient():
+@pytest.mark.parametrize("hist", [0, 1])
+def test_solve_matches_dense_proximal_gradient(hist):
     p = synth.rke(50, 30, lam=2.0, seed=3)
     lam = 2.0
-    res = rke.solve(p, lam, k0=6, tol=1e-8, seed=1, max_iter=1000)
+    res = rke.solve(p, lam, k0=6, tol=1e-8, seed=1, max_iter=1000, lmsvd_p=hist)
     alpha = 1.99 / rke.lipschitz_bound(p)
     X = np.zeros((p.n, p.n))
     for _ in range(100000):
