@@ -108,6 +108,7 @@ def main():
     ap.add_argument("--qsdp-only", action="store_true",
                     help="only run one kernel-estimation QSDP solve (20,000 objects, tol 1e-4)")
     ap.add_argument("--verbose", action="store_true", help="per-iteration log of the solver (stderr)")
+    ap.add_argument("--qsdp-tol", type=float, default=1e-4, help="stop residual of --qsdp-only")
     ap.add_argument("--small-solve-only", action="store_true",
                     help="only run one FP64 solve of the 1000 x 1500 workload to tol 1e-6 (seed 11)")
     ap.add_argument("--only", default=None,
@@ -132,8 +133,8 @@ def main():
         dq = bmg.Problem.from_host(q.row_ptr, q.col, q.val, q.m, q.n, k_cap=RKE_K_CAP, device=dev,
                                    lmsvd_p=RKE_LMSVD_P)
         t0 = time.perf_counter()
-        _, k, r = dq.bmg_rke_solve(lam=10.0, k_init=8, tol=1e-4, seed=1, max_iter=3000, bm_epochs=10,
-                                   lmsvd_p=RKE_LMSVD_P, verbose=args.verbose)
+        _, k, r = dq.bmg_rke_solve(lam=10.0, k_init=8, tol=args.qsdp_tol, seed=1, max_iter=3000,
+                                   bm_epochs=10, lmsvd_p=RKE_LMSVD_P, verbose=args.verbose)
         print(json.dumps({"qsdp_objects": q.n, "pairs": q.nnz // 2, "seconds": time.perf_counter() - t0,
                           "iters": r["iters"], "ssi_iters": r["ssi_iters"],
                           "ssi_per_pg_step": r["ssi_iters"] / (r["iters"] + 1), "rank": k, "F": r["F"],

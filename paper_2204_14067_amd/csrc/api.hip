@@ -1668,6 +1668,32 @@ struct Method : Engine<T, TG> {
   // U0 (m x q0, orthonormal) in Ubuf (block B1 or B2).  On return *Uout / *Yout
   // point at the final basis (q columns) and Z^T of it; Tq is their Gram matrix.
   // History length p_t = hist_p.
+  // orth([Ub, c]) for the cb orthonormal columns Ub (mm rows, ld qld) and the
+  // column c right after them: c projected off ran(Ub) twice (against
+  // rounding) and scaled to unit norm in place.  Returns cb + 1, or cb when
+  // what is left of c is at most ORTH_TOL of its norm (the rank cut of orth()).
+  // The same range as orth() of the whole block, two host round trips.
+  int append_orth(int64_t mm, T *Ub, int cb) {
+    T *c = Ub + cb;
+    double n0 = 0.0, n1 = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      // [Ub, c]^T c: the projections and |c|^2 in one product
+      std::vector<double> g = gram(mm, cb + 1, Ub, qld, 1, c, qld);
+      double p2 = 0.0;
+      for (int j = 0; j < cb; ++j) p2 += g[j] * g[j];
+      if (pass == 0) n0 = sqrt(std::max(g[cb], 0.0));
+      n1 = sqrt(std::max(g[cb] - p2, 0.0));
+      if (cb > 0) {
+        std::vector<double> cf(g.begin(), g.begin() + cb);
+        for (double &v : cf) v = -v;
+        gemm(mm, cb, Ub, qld, 1, cf, c, qld, 1.0);
+      }
+    }
+    if (!(n0 > 0.0) || !(n1 > ORTH_TOL * n0)) return cb;
+    HIPC(launch_axpy<T>(mm, 1, 1.0 / n1 - 1.0, c, qld, c, qld, s));
+    return cb + 1;
+  }
+
   // The extra column u_t + xi_t of eq. rt (Suppl. A.1.3) into col (ld qld),
   // against the cb orthonormal columns of Ub (mm rows, ld qld): u_t is u
   // projected onto ker(Ub^T) (when has_u), xi_t a standard normal vector
@@ -2182,8 +2208,8 @@ struct Method : Engine<T, TG> {
     if (add) {
       safeguard_col(m, B2, cb, S.uvec, S.has_u, S.psi, seed, t, B2 + cb,
                     blk(P->L.b_vec) + 2 * rup(m, 64), blk(P->L.b_vec) + 4 * rup(m, 64));
-      q0 = orth(m, B2, cb + 1, B1, B4);
-      U0 = B1;
+      q0 = append_orth(m, B2, cb);
+      U0 = B2;
       info.added = true;
     }
     // step size: the fixed alpha, or the BB step of eq. proxBB (SpaRSA rule)

@@ -244,20 +244,49 @@ bool chol(int n, const double *G, double *R) {
 }
 
 void tri_inv_upper(int n, const double *R, double *X) {
-  // rows from the bottom: X[i, :] = (e_i - sum_{k > i} R[i, k] X[k, :]) / R[i, i];
-  // row k of X is zero left of column k, so each update is a contiguous axpy
+  // rows from the bottom, four at a time: X[i, :] = (e_i - sum_{k > i} R[i, k]
+  // X[k, :]) / R[i, i].  The rows below the block are final; each of them is
+  // loaded once for the four rows of the block (row k of X is zero left of
+  // column k, so every update is a contiguous axpy), then the block's own
+  // rows are finished bottom-up.
   memset(X, 0, sizeof(double) * (size_t)n * n);
-  for (int i = n - 1; i >= 0; --i) {
-    double *xi = &X[(size_t)i * n];
-    const double *ri = &R[(size_t)i * n];
-    for (int k = i + 1; k < n; ++k) {
-      const double f = ri[k];
+  int i1 = n;
+  while (i1 > 0) {
+    const int nb = std::min(4, i1), i0 = i1 - nb;
+    double *x0 = &X[(size_t)i0 * n];
+    for (int r = 0; r < nb; ++r) x0[(size_t)r * n + i0 + r] = 1.0;
+    for (int k = i1; k < n; ++k) {
       const double *xk = &X[(size_t)k * n];
-      for (int c = k; c < n; ++c) xi[c] -= f * xk[c];
+      double f[4] = {0, 0, 0, 0};
+      for (int r = 0; r < nb; ++r) f[r] = R[(size_t)(i0 + r) * n + k];
+      if (nb == 4) {
+        double *a = x0, *b = x0 + n, *c = x0 + 2 * (size_t)n, *d = x0 + 3 * (size_t)n;
+        for (int col = k; col < n; ++col) {
+          const double v = xk[col];
+          a[col] -= f[0] * v;
+          b[col] -= f[1] * v;
+          c[col] -= f[2] * v;
+          d[col] -= f[3] * v;
+        }
+      } else {
+        for (int r = 0; r < nb; ++r) {
+          double *xr = x0 + (size_t)r * n;
+          for (int col = k; col < n; ++col) xr[col] -= f[r] * xk[col];
+        }
+      }
     }
-    const double inv = 1.0 / ri[i];
-    xi[i] = 1.0;
-    for (int c = i; c < n; ++c) xi[c] *= inv;
+    for (int i = i1 - 1; i >= i0; --i) {
+      double *xi = &X[(size_t)i * n];
+      const double *ri = &R[(size_t)i * n];
+      for (int k = i + 1; k < i1; ++k) {
+        const double f = ri[k];
+        const double *xk = &X[(size_t)k * n];
+        for (int col = k; col < n; ++col) xi[col] -= f * xk[col];
+      }
+      const double inv = 1.0 / ri[i];
+      for (int col = i; col < n; ++col) xi[col] *= inv;
+    }
+    i1 = i0;
   }
 }
 
