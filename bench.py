@@ -93,8 +93,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--bm-solver", default="psd", choices=["psd", "polymf"],
-                    help="BM solver of the step (psd: gradient steps, the default; polymf: polyMF-SS)")
+    ap.add_argument("--bm-solver", default=None, choices=["psd", "polymf"],
+                    help="BM solver (psd: preconditioned gradient steps; polymf: polyMF-SS).  Default: psd for "
+                         "the benchmark step (whole-Omega passes, the dense-row panel), the library default "
+                         "(polymf) for --small-solve-only")
     ap.add_argument("--workload", default="yahoo", choices=sorted(WORKLOADS),
                     help="yahoo: 624,961 x 1,000,990, |Omega| = 2.5e8 (the headline); netflix: 17,770 x "
                          "480,189, |Omega| = 1e8")
@@ -145,8 +147,9 @@ def main():
         prob = bmg.Problem.from_host(p.row_ptr, p.col, p.val, p.m, p.n, k_cap=256, precision="fp64",
                                      device=dev)
         t0 = time.perf_counter()
-        _, _, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=11, max_iter=1000)
-        print(json.dumps({"workload": "small_uniform 1000x1500 nnz=50000 lambda=0.5",
+        bs = args.bm_solver or "polymf"
+        _, _, k, r = prob.bmg_solve(lam=p.lam, k_init=p.k0, tol=1e-6, seed=11, max_iter=1000, bm_solver=bs)
+        print(json.dumps({"workload": "small_uniform 1000x1500 nnz=50000 lambda=0.5", "bm_solver": bs,
                           "seconds": time.perf_counter() - t0, "iters": r["iters"], "rank": k,
                           "F": r["F"], "status": r["status"], "ssi_iters": r["ssi_iters"],
                           "host_la_seconds": r["host_la_seconds"],
@@ -175,7 +178,7 @@ def main():
     wl = WORKLOADS[args.workload]
     # the workspace also holds two LmSVD history blocks (the history comparison)
     line, prob, W, H, recs, sec = step_line(bmg, p, args.workload, args.scale, args.precision, args.steps,
-                                            args.warmup, args.bm_solver, dev,
+                                            args.warmup, args.bm_solver or "psd", dev,
                                             hist=0 if args.no_extras or args.workload != "netflix" else 2,
                                             dense_rows=args.dense_rows)
     out = {
@@ -296,7 +299,7 @@ def lmsvd_history(bmg, synth, dev, prob, W, H, k0, lam, recs0, sec0, steps=3):
                            "sparse_passes": recs0[-1]["sparse_passes"]}}}
     for hp in (1, 2):
         run = lambda: prob.bmg_solve(W, H, lam=lam, k_init=k0, max_iter=1, tol=0.0, seed=1003,  # noqa: E731
-                                     lmsvd_p=hp)[3]
+                                     lmsvd_p=hp, bm_solver="psd")[3]
         run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -377,13 +380,14 @@ def sparsa_step(bmg, synth, dev, fixed_small, fixed_quarter):
 
 
 def polymf_bm(bmg, synth, dev, prob, p, fixed_small, fixed_quarter):
-    """The polyMF-SS BM solver against the preconditioned steepest descent, FP64:
-    three epochs of each from the same factors on the benchmark workload
-    (rank 16, lambda 20; BM objective after each epoch and time per epoch), then
-    the 1000 x 1500 solve to 1e-6 (five seeds) and the quarter-scale
-    Netflix-shaped solve at lambda 100 to 1e-4 (three seeds) with polyMF-SS in
-    the BM phase.  Steepest-descent figures of the solves are those of the
-    time-to-tolerance runs above."""
+    """The polyMF-SS BM solver (the library default, as in the paper) against
+    the preconditioned steepest descent, FP64: three epochs of each from the
+    same factors on the Netflix-shaped workload (rank 16, lambda 20; BM
+    objective after each epoch and time per epoch), then the 1000 x 1500 solve
+    to 1e-6 (five seeds) and the quarter-scale Netflix-shaped solve at lambda
+    100 to 1e-4 (three seeds) with steepest descent in the BM phase.  The
+    polyMF-SS figures of the solves are those of the time-to-tolerance runs
+    above."""
     import numpy as np
     import torch
     k, lam = 16, 20.0
@@ -411,22 +415,23 @@ def polymf_bm(bmg, synth, dev, prob, p, fixed_small, fixed_quarter):
               (3, 4, 5), 128, fixed_quarter)]
     for name, q, lm, kk, tol, seeds, kc, fixed in cases:
         pq = bmg.Problem.from_host(q.row_ptr, q.col, q.val, q.m, q.n, k_cap=kc, precision="fp64", device=dev)
-        pq.bmg_solve(lam=lm, k_init=kk, tol=tol, seed=seeds[0], max_iter=2, bm_solver="polymf")
+        pq.bmg_solve(lam=lm, k_init=kk, tol=tol, seed=seeds[0], max_iter=2, bm_solver="psd")
         secs, iters, Fs = [], [], []
         for sd in seeds:
             t0 = time.perf_counter()
-            W, H, k2, r = pq.bmg_solve(lam=lm, k_init=kk, tol=tol, seed=sd, max_iter=1000, bm_solver="polymf")
+            W, H, k2, r = pq.bmg_solve(lam=lm, k_init=kk, tol=tol, seed=sd, max_iter=1000, bm_solver="psd")
             secs.append(time.perf_counter() - t0)
             iters.append(r["iters"]); Fs.append(r["F"])
-        rec = {"seconds_median": round(float(np.median(secs)), 4), "iters": iters,
-               "psd_seconds_median": fixed["seconds_median"], "psd_iters": fixed["iters"]}
+        rec = {"psd_seconds_median": round(float(np.median(secs)), 4), "psd_iters": iters,
+               "polymf_seconds_median": fixed["seconds_median"], "polymf_iters": fixed["iters"],
+               "polymf_speedup": round(float(np.median(secs)) / fixed["seconds_median"], 3)}
         if name.startswith("small"):
             rec["max_rel_err_vs_oracle_optimum"] = max(abs(F - golden["F"]) / golden["F"] for F in Fs)
         else:
             rec["F"] = Fs
         out[name] = rec
-        log("polymf %s: median %.3fs (psd %.3fs), iters %s (psd %s)" % (
-            name, rec["seconds_median"], fixed["seconds_median"], iters, fixed["iters"]))
+        log("psd BM %s: median %.3fs (polymf %.3fs), iters %s (polymf %s)" % (
+            name, rec["psd_seconds_median"], fixed["seconds_median"], iters, fixed["iters"]))
         del pq
     return out
 
@@ -503,7 +508,9 @@ def bf16_mode(bmg, synth, dev, seeds=(3, 4, 5)):
     the objective error against F* after each refresh and the fraction of
     sparse passes that gathered BF16; then time to tolerance against the FP64
     solver at the same tolerance (1e-3, which the BF16 phase reaches itself, and
-    1e-5), with the final objective errors, the speed-up at equal accuracy."""
+    1e-5), with the final objective errors, the speed-up at equal accuracy.
+    Steepest descent in the BM phase throughout: its whole-Omega passes gather
+    BF16 (polyMF-SS's column passes gather FP32)."""
     import numpy as np
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "netflix_quarter_lam300.json")))
     p = synth.netflix_shape(scale=0.25)
@@ -517,18 +524,19 @@ def bf16_mode(bmg, synth, dev, seeds=(3, 4, 5)):
            "per_refresh": []}
     for it in (5, 10, 15, 20, 25, 30):
         W, H, k, r = probs["bf16"].bmg_solve(lam=lam, k_init=k0, tol=0.0, max_iter=it, seed=seeds[0],
-                                             refresh_every=5)
+                                             refresh_every=5, bm_solver="psd")
         F = evaluator.bmg_objective(W, H, k, lam)
         out["per_refresh"].append({"iters": it, "rel_F_err_vs_oracle": (F - Fs) / Fs, "residual": r["residual"],
                                    "rank": k, "bf16_pass_fraction": round(r["bf16_passes"] / r["sparse_passes"], 4)})
     for tol in (1e-3, 1e-5):
         rec = {}
         for pr in ("fp64", "bf16"):
-            probs[pr].bmg_solve(lam=lam, k_init=k0, tol=tol, seed=seeds[0], max_iter=2)
+            probs[pr].bmg_solve(lam=lam, k_init=k0, tol=tol, seed=seeds[0], max_iter=2, bm_solver="psd")
             secs, errs, fr, iters = [], [], [], []
             for sd in seeds:
                 t0 = time.perf_counter()
-                W, H, k, r = probs[pr].bmg_solve(lam=lam, k_init=k0, tol=tol, seed=sd, max_iter=400)
+                W, H, k, r = probs[pr].bmg_solve(lam=lam, k_init=k0, tol=tol, seed=sd, max_iter=400,
+                                                 bm_solver="psd")
                 secs.append(time.perf_counter() - t0)
                 F = evaluator.bmg_objective(W, H, k, lam)
                 errs.append(abs(F - Fs) / Fs)

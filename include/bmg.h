@@ -145,7 +145,7 @@ typedef struct {
 
 /* Fills the defaults: alpha 1.99, tol 1e-6, ssi_tol_floor 1e-12, psi0 0.1,
  * bm_epochs 3, max_iter 500, ssi_max_iter 50, k_init 8, refresh_every 5,
- * lmsvd_p 0, bm_solver BMG_BM_PSD, step_rule BMG_STEP_FIXED, alpha_min 1.99, alpha_max 1e3,
+ * lmsvd_p 0, bm_solver BMG_BM_POLYMF, step_rule BMG_STEP_FIXED, alpha_min 1.99, alpha_max 1e3,
  * sparsa_beta 0.5, sparsa_delta 0.999.
  * BMG_STEP_SPARSA keeps the previous PG point (W, H and its residual) and the
  * warm start in the workspace: min(m,n) x qb, (m + n) x ld_k and 2 nnz elements

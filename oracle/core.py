@@ -577,7 +577,7 @@ class Options:
     # variant: BB step of eq. proxBB clipped to [alpha_min, alpha_max], then
     # backtracking by sparsa_beta until eq. back holds with sparsa_delta)
     step_rule: str = "fixed"
-    bm_solver: str = "psd"       # "psd": preconditioned steepest descent; "polymf": polyMF-SS
+    bm_solver: str = "polymf"    # "polymf": polyMF-SS (the paper's); "psd": preconditioned steepest descent
     alpha_min: float = 1.99      # < 2 delta / L (L = 1): eq. back holds there
     alpha_max: float = 1e3
     sparsa_beta: float = 0.5

@@ -1241,7 +1241,7 @@ extern "C" void bmg_options_default(bmg_options *o) {
   o->lmsvd_p = 0;
   o->seed = 0;
   o->step_rule = BMG_STEP_FIXED;
-  o->bm_solver = BMG_BM_PSD;
+  o->bm_solver = BMG_BM_POLYMF;
   o->alpha_min = 1.99;
   o->alpha_max = 1e3;
   o->sparsa_beta = 0.5;

@@ -1,5 +1,7 @@
 """Dense-row panel (bmg_options.dense_rows): the rows of Omega at least that
-dense leave the gather passes and go through the dense panel kernels.  The
+dense leave the gather passes and go through the dense panel kernels (solves
+with the steepest-descent BM solver: polyMF-SS, the default, and SpaRSA read
+the stored residual entry by entry and run without the panel).  The
 oracle knows nothing of panels, so every result is held to the same bars as
 without one: BM epochs, objective, prox step and solves against the oracle, and
 the panel path against the plain path of the library on the full-size
@@ -149,8 +151,8 @@ def test_panel_solve_parity_fp64(name):
     p = case(name)
     lam = 0.5
     dp = to_dev(p, k_cap=64)
-    W, H, k, r = dp.bmg_solve(lam=lam, k_init=4, tol=1e-10, seed=3, max_iter=3000)
-    orc = core.solve(p, core.Options(lam=lam, k0=4, tol=1e-10, seed=3, max_iter=3000))
+    W, H, k, r = dp.bmg_solve(lam=lam, k_init=4, tol=1e-10, seed=3, max_iter=3000, bm_solver="psd")
+    orc = core.solve(p, core.Options(lam=lam, k0=4, tol=1e-10, seed=3, max_iter=3000, bm_solver="psd"))
     print("panel solve", name, r["iters"], orc.iters, k, orc.k, r["F"], orc.F, flush=True)
     assert r["status"] == 0 and orc.converged
     assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
@@ -163,7 +165,7 @@ def test_panel_solve_fp32_objective_error():
     p = case("mixed")
     lam = 0.5
     dp = to_dev(p, k_cap=64, precision="fp32")
-    W, H, k, r = dp.bmg_solve(lam=lam, k_init=4, tol=1e-6, seed=3, max_iter=3000)
+    W, H, k, r = dp.bmg_solve(lam=lam, k_init=4, tol=1e-6, seed=3, max_iter=3000, bm_solver="psd")
     Fw = core.objective(p, W.cpu().numpy()[:, :k], H.cpu().numpy()[:, :k], lam)
     Fstar = core.solve(p, core.Options(lam=lam, k0=4, tol=1e-11, seed=3, max_iter=3000)).F
     print("panel fp32", r["status"], r["iters"], Fw, Fstar, flush=True)
@@ -176,7 +178,7 @@ def test_panel_solve_is_bitwise_deterministic_and_matches_plain_path():
     outs = []
     for dr in (0.25, 0.25, 0.0):
         dp = to_dev(p, k_cap=64, dense_rows=dr)
-        W, H, k, r = dp.bmg_solve(lam=20.0, k_init=8, tol=1e-7, max_iter=200, seed=2)
+        W, H, k, r = dp.bmg_solve(lam=20.0, k_init=8, tol=1e-7, max_iter=200, seed=2, bm_solver="psd")
         outs.append((W.cpu().numpy(), H.cpu().numpy(), r["F"], k, r["iters"]))
         print("powerlaw dense_rows", dr, k, r["F"], r["iters"], flush=True)
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][2] == outs[1][2]
@@ -207,7 +209,7 @@ def test_netflix_shape_full_size_panel_step_matches_plain_path():
     for dr in (0.25, 0.0):
         dp = to_dev(p, k_cap=64, dense_rows=dr)
         W, H = dp.zeros_factors()
-        _, _, k, r = dp.bmg_solve(W, H, lam=20.0, k_init=16, max_iter=1, tol=0.0, seed=1003)
+        _, _, k, r = dp.bmg_solve(W, H, lam=20.0, k_init=16, max_iter=1, tol=0.0, seed=1003, bm_solver="psd")
         res[dr] = (k, r["F"], r["ssi_iters"])
         print("netflix step dense_rows", dr, res[dr], flush=True)
         del dp, W, H

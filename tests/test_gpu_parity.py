@@ -231,19 +231,20 @@ def test_prox_step_parity_lmsvd_history(name, hp):
 
 # ----------------------------------------------------------------------------- solver
 
-def solve_both(p, lam, k0, tol, k_cap=64, precision="fp64", seed=3, orc=None):
+def solve_both(p, lam, k0, tol, k_cap=64, precision="fp64", seed=3, orc=None, bm_solver="polymf"):
     dp = to_dev(p, k_cap=k_cap, precision=precision)
-    W, H, k, r = dp.bmg_solve(lam=lam, k_init=k0, tol=tol, seed=seed, max_iter=3000)
+    W, H, k, r = dp.bmg_solve(lam=lam, k_init=k0, tol=tol, seed=seed, max_iter=3000, bm_solver=bm_solver)
     if orc is None:
-        orc = core.solve(p, core.Options(lam=lam, k0=k0, tol=tol, seed=seed, max_iter=3000))
+        orc = core.solve(p, core.Options(lam=lam, k0=k0, tol=tol, seed=seed, max_iter=3000, bm_solver=bm_solver))
     return dp, W, H, k, r, orc
 
 
 @pytest.mark.parametrize("shape", [(40, 60, 700), (60, 40, 700), (120, 200, 4000)])
 def test_solve_parity_fp64(shape):
+    """The steepest-descent BM solver (polyMF-SS, the default, has its own test below)."""
     m, n, nnz = shape
     p = synth.tiny(m, n, nnz, rank=3, lam=0.3, seed=m + n)
-    dp, W, H, k, r, orc = solve_both(p, 0.3, 4, 1e-10)
+    dp, W, H, k, r, orc = solve_both(p, 0.3, 4, 1e-10, bm_solver="psd")
     print("solve", shape, r, orc.F, orc.k, orc.iters, flush=True)
     assert r["status"] == 0 and orc.converged
     assert math.isclose(r["F"], orc.F, rel_tol=1e-8)
