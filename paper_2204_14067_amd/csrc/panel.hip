@@ -188,24 +188,43 @@ __global__ __launch_bounds__(256) void k_panel_rows(int TI, int64_t n, int q, in
   d4p_t acc[NQ];
 #pragma unroll
   for (int u = 0; u < NQ; ++u) acc[u] = d4p_t{0.0, 0.0, 0.0, 0.0};
-  for (int64_t jj = c0; jj < c1; jj += 16) {
+  // the operands of the next 16 columns are loaded before the products of the
+  // current ones are issued (two sets of registers)
+  double a[4], b[4][NQ];
+  auto load = [&](int64_t jj) {
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
       const int64_t j = jj + 4 * kr + st;
       const bool jv = j < c1;
       const int64_t jc = jv ? j : c0;
-      double a = (double)S[jc * ldi + i];
-      if (values) a = isnan(a) ? 0.0 : a;
-      a = jv ? a : 0.0;
+      double x = (double)S[jc * ldi + i];
+      if (values) x = isnan(x) ? 0.0 : x;
+      a[st] = jv ? x : 0.0;
       const T *yr = Y + jc * ldy;
 #pragma unroll
       for (int u = 0; u < NQ; ++u) {
-        if (u >= TQ) break;
         const int c = u * 16 + cl;
-        const double b = (jv && c < q) ? (double)yr[c] : 0.0;
-        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+        b[st][u] = (u < TQ && jv && c < q) ? (double)yr[c] : 0.0;
       }
     }
+  };
+  if (c0 < c1) load(c0);
+  for (int64_t jj = c0; jj < c1; jj += 16) {
+    double ac[4], bc[4][NQ];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      ac[st] = a[st];
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) bc[st][u] = b[st][u];
+    }
+    if (jj + 16 < c1) load(jj + 16);
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        if (u >= TQ) break;
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[st], bc[st][u], acc[u], 0, 0, 0);
+      }
   }
   double *pb = part + (int64_t)blockIdx.x * TI * 16 * Q16;
 #pragma unroll
@@ -315,9 +334,15 @@ __global__ __launch_bounds__(256) void k_panel_cols(int TI, int64_t n, int q, co
   const int64_t ja = j0 + cl;
   const bool jv = ja < n;
   const T *srow = S + (jv ? ja : 0) * ldi;
+  // the panel values of the next 16 rows are loaded before the products of
+  // the current ones are issued
+  double an[4];
+  ld4(srow, 4 * kr, jv ? ldi : 0, an);
   for (int ii = 0; ii < TI * 16; ii += 16) {
     double a[4];
-    ld4(srow, ii + 4 * kr, jv ? ldi : 0, a);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = an[e];
+    if (ii + 16 < TI * 16) ld4(srow, ii + 16 + 4 * kr, jv ? ldi : 0, an);
     if (values) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) a[e] = isnan(a[e]) ? 0.0 : a[e];
