@@ -244,6 +244,58 @@ __global__ __launch_bounds__(256) void k_gemm_ts(int64_t N, int a, const T *__re
   }
 }
 
+// The same product with 64 x (16 NC) output tiles (4 x NC outputs per
+// thread): for b in (64, 16 NC] one tile spans all of M's columns, so X is
+// read once instead of once per 64 columns.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_gemm_ts_w(int64_t N, int a, const T *__restrict__ X, int ldx,
+                                                   int b, const double *__restrict__ M, int ldm,
+                                                   T *__restrict__ C, int ldc, double beta) {
+  __shared__ double xs[64][17];
+  __shared__ double ms[16][16 * NC + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+  double acc[4][NC] = {};
+  for (int k0 = 0; k0 < a; k0 += 16) {
+    for (int t = threadIdx.x; t < 64 * 16; t += 256) {
+      const int rr = t / 16, kk = t % 16;
+      const int64_t r = r0 + rr;
+      xs[rr][kk] = (r < N && k0 + kk < a) ? (double)X[r * ldx + k0 + kk] : 0.0;
+    }
+    for (int t = threadIdx.x; t < 16 * 16 * NC; t += 256) {
+      const int mk = t / (16 * NC), mc = t % (16 * NC);
+      ms[mk][mc] = (k0 + mk < a && mc < b) ? M[(int64_t)(k0 + mk) * ldm + mc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double xv[4], mv[NC];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xv[i] = xs[tr * 4 + i][kk];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) mv[j] = ms[kk][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[i][j] += xv[i] * mv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = r0 + tr * 4 + i;
+    if (r >= N) continue;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int c = tc + 16 * j;
+      if (c >= b) continue;
+      double v = acc[i][j];
+      if (beta != 0.0) v += beta * (double)C[r * ldc + c];
+      C[r * ldc + c] = (T)v;
+    }
+  }
+}
+
 // The same product with 32 x 32 output tiles (K-chunks of 32, 2 x 2 outputs
 // per thread): four times the blocks, for products too short to fill the
 // chip with 64 x 64 tiles.
@@ -302,6 +354,14 @@ hipError_t launch_gemm_ts(int64_t N, int a, const T *X, int ldx, int b, const do
     return launch_axpy<T>(N, b, beta - 1.0, C, ldc, C, ldc, s);
   }
   const int64_t tiles64 = ((N + 63) / 64) * ((b + 63) / 64);
+  if (tiles64 >= 1024 && b > 64 && b <= 128) {
+    const dim3 grid((unsigned)((N + 63) / 64));
+    if (b <= 96)
+      hipLaunchKernelGGL((k_gemm_ts_w<T, 6>), grid, dim3(256), 0, s, N, a, X, ldx, b, M, ldm, C, ldc, beta);
+    else
+      hipLaunchKernelGGL((k_gemm_ts_w<T, 8>), grid, dim3(256), 0, s, N, a, X, ldx, b, M, ldm, C, ldc, beta);
+    return hipGetLastError();
+  }
   if (tiles64 < 1024) {
     dim3 grid((unsigned)((N + 31) / 32), (unsigned)((b + 31) / 32));
     hipLaunchKernelGGL((k_gemm_ts32<T>), grid, dim3(256), 0, s, N, a, X, ldx, b, M, ldm, C, ldc,
