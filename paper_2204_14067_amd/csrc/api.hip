@@ -1449,57 +1449,6 @@ extern "C" bmg_status bmg_spmm(bmg_problem *P, const double *S, const double *B,
 }
 
 // ============================================================================ the method (internal orientation)
-// Global minimiser over t >= 0 of psi(t) = c1 t + c2 t^2 + c3 t^3 + c4 t^4
-// (c4 >= 0): psi' is a cubic; the real roots of psi'' cut [0, B] (B a bound on
-// the roots of psi') into intervals where psi' is monotone, bisection finds
-// the root in each interval where psi' changes sign, and the best of t = 0
-// and those roots is returned.
-static double quartic_min(double c1, double c2, double c3, double c4) {
-  const double a = 4.0 * c4, b = 3.0 * c3, c = 2.0 * c2, d = c1;
-  auto dpsi = [&](double t) { return ((a * t + b) * t + c) * t + d; };
-  auto psi = [&](double t) { return (((c4 * t + c3) * t + c2) * t + c1) * t; };
-  double B;
-  if (a > 0.0) B = 1.0 + std::max(std::max(fabs(b), fabs(c)), fabs(d)) / a;
-  else if (b != 0.0) B = 1.0 + std::max(fabs(c), fabs(d)) / fabs(b);
-  else if (c != 0.0) B = 1.0 + fabs(d / c);
-  else return 0.0;
-  std::vector<double> cut{0.0};
-  // roots of psi'' = c + 2 b t + 3 a t^2
-  if (a > 0.0) {
-    const double disc = 4.0 * b * b - 12.0 * a * c;
-    if (disc > 0.0) {
-      const double sq = sqrt(disc);
-      const double q = -0.5 * (2.0 * b + (b >= 0.0 ? sq : -sq));
-      double r1 = q / (3.0 * a), r2 = q != 0.0 ? c / q : r1;
-      if (r1 > r2) std::swap(r1, r2);
-      if (r1 > 0.0 && r1 < B) cut.push_back(r1);
-      if (r2 > 0.0 && r2 < B && r2 != r1) cut.push_back(r2);
-    }
-  } else if (b != 0.0) {
-    const double r = -c / (2.0 * b);
-    if (r > 0.0 && r < B) cut.push_back(r);
-  }
-  cut.push_back(B);
-  double best = 0.0, fbest = 0.0;
-  for (size_t i = 0; i + 1 < cut.size(); ++i) {
-    double lo = cut[i], hi = cut[i + 1];
-    double flo = dpsi(lo), fhi = dpsi(hi);
-    if (flo == 0.0) { hi = lo; fhi = 0.0; }
-    else if ((flo < 0.0) == (fhi < 0.0) && fhi != 0.0) continue;
-    for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;
-      const double fm = dpsi(mid);
-      if ((fm < 0.0) == (flo < 0.0) && fm != 0.0) { lo = mid; flo = fm; }
-      else { hi = mid; fhi = fm; }
-    }
-    const double t = fabs(flo) < fabs(fhi) ? lo : hi;
-    const double ft = psi(t);
-    if (t > 0.0 && ft < fbest) { best = t; fbest = ft; }
-  }
-  return best;
-}
-
 template <typename T, typename TG = T>
 struct Method : Engine<T, TG> {
   using E = Engine<T, TG>;
@@ -1530,7 +1479,9 @@ struct Method : Engine<T, TG> {
   // Per block: the direction from one pass per orientation (each pass first
   // applies the previous block's step to that orientation's stored residual),
   // the quartic's coefficients from one pass, and its exact minimiser over
-  // t >= 0 on the host.  Returns whether any block moved.
+  // t >= 0, found on the device so that the k blocks of an epoch run without
+  // a host round trip (one fetch at the end of the epoch).  Returns whether
+  // any block moved.
   bool polymf_epoch(T *W, T *H, int k, double lam) {
     if (k == 0) return false;
     double sr[2] = {0, 0}, sc[2] = {0, 0};
@@ -1546,8 +1497,14 @@ struct Method : Engine<T, TG> {
     Q4<T> *Gm = (Q4<T> *)blk(P->L.b_G), *Gn = (Q4<T> *)blk(P->L.b_D);
     double *part = (double *)P->partial;
     HIPC(launch_col_pack0<T>(m, n, W, H, ldk, Gm, Gn, s));
-    bool changed = false, upd = false;
+    // device state of the epoch: the current block's t, the number of blocks
+    // that moved, a non-finite flag
+    double *state = P->result + 32;
+    HIPC(launch_fill<double>(state, 1, 3, 3, 0.0, s));
     for (int j = 0; j < k; ++j) {
+      // from the second block on, the passes first apply the previous block's
+      // step to the stored residual (a step of 0 leaves it unchanged)
+      const bool upd = j > 0;
       HIPC(launch_col_grad<T>(R->pl, (T *)R->r, Gm, Gn, upd, lam, part, s));
       HIPC(launch_col_grad<T>(C->pl, (T *)C->r, Gn, Gm, upd, lam, part, s));
       E::count(R->pl, 4.0 + (upd ? 2.0 : 1.0) * sizeof(T), (double)(m + n) * 4 * sizeof(T));
@@ -1555,19 +1512,13 @@ struct Method : Engine<T, TG> {
       HIPC(launch_col_quartic<T>(R->pl, (const T *)R->r, m, n, Gm, Gn, P->wsum, 2 * P->L.wsum_cap,
                                  P->wpart, P->result, s));
       E::count(R->pl, 4.0 + sizeof(T), (double)(m + n) * 4 * sizeof(T));
-      double h[9];
-      E::fetch(h, P->result, 9);
-      const double c1 = h[0] + lam * (h[5] + h[7]);
-      const double c2 = 0.5 * h[1] + h[2] + 0.5 * lam * (h[6] + h[8]);
-      const double c3 = h[3], c4 = 0.5 * h[4];
-      REQUIRE(std::isfinite(c1) && std::isfinite(c2) && std::isfinite(c3) && std::isfinite(c4),
-              BMG_ENONFINITE, "non-finite polyMF-SS line search");
-      const double t = quartic_min(c1, c2, c3, c4);
-      HIPC(launch_col_step<T>(m, n, W, H, ldk, j, j + 1 < k ? j + 1 : -1, t, Gm, Gn, s));
-      upd = t > 0.0;
-      changed |= upd;
+      HIPC(launch_col_t(P->result, lam, state, s));
+      HIPC(launch_col_step<T>(m, n, W, H, ldk, j, j + 1 < k ? j + 1 : -1, state, Gm, Gn, s));
     }
-    return changed;
+    double h[3];
+    E::fetch(h, state, 3);
+    REQUIRE(h[2] == 0.0, BMG_ENONFINITE, "non-finite polyMF-SS line search");
+    return h[1] > 0.0;
   }
 
   bool bm_half(bool rows_side, T *W, T *H, int k, double lam) {

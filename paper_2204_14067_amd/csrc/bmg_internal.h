@@ -228,11 +228,17 @@ template <typename T>
 hipError_t launch_col_quartic(const Plan &pl, const T *r, int64_t m, int64_t n, const Q4<T> *Gm,
                               const Q4<T> *Gn, double *bpart, int64_t bpart_cap, double *dpart,
                               double *out, hipStream_t s);
-// Block j moves by t along its direction: X[:, j] += t dir; the records are
-// rewritten for block jn (jn < 0: none).
+// The block's step from the nine sums h of launch_col_quartic (device, one
+// thread): the quartic c1 = h0 + lam (h5 + h7), c2 = h1 / 2 + h2 + lam (h6 +
+// h8) / 2, c3 = h3, c4 = h4 / 2 and t = quartic_min(c1..c4) into state[0];
+// state[1] counts the blocks with t > 0, state[2] is set to 1 (and t to 0)
+// when a coefficient is not finite.
+hipError_t launch_col_t(const double *h, double lam, double *state, hipStream_t s);
+// Block j moves by t = *tp (device) along its direction: X[:, j] += t dir;
+// the records are rewritten for block jn (jn < 0: none).
 template <typename T>
-hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, int jn, double t, Q4<T> *Gm,
-                           Q4<T> *Gn, hipStream_t s);
+hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, int jn, const double *tp,
+                           Q4<T> *Gm, Q4<T> *Gn, hipStream_t s);
 
 // Kernel-estimation QSDP pair passes (rke.hip), FP64, rows plan of a
 // symmetric Omega, factor W (n x k, ld):
@@ -262,6 +268,60 @@ hipError_t launch_cmp_orient(int64_t nnz, const int32_t *a, const int32_t *b, co
 // Widest slice one launch handles for element type T.
 // (8 lanes x 16 bytes per chunk, at most 8 chunks: 128 doubles / 256 floats)
 template <typename T> constexpr int max_width() { return 128 * (16 / (int)sizeof(T)); }
+
+
+// Global minimiser over t >= 0 of psi(t) = c1 t + c2 t^2 + c3 t^3 + c4 t^4
+// (c4 >= 0): psi' is a cubic; the real roots of psi'' cut [0, B] (B a bound on
+// the roots of psi') into intervals where psi' is monotone, bisection finds
+// the root in each interval where psi' changes sign, and the best of t = 0
+// and those roots is returned.  The same code runs on the host and on the
+// device (no contraction into fused multiply-adds, so both give the same t).
+__host__ __device__ inline double quartic_min(double c1, double c2, double c3, double c4) {
+#pragma clang fp contract(off)
+  const double a = 4.0 * c4, b = 3.0 * c3, c = 2.0 * c2, d = c1;
+  double B;
+  if (a > 0.0) B = 1.0 + fmax(fmax(fabs(b), fabs(c)), fabs(d)) / a;
+  else if (b != 0.0) B = 1.0 + fmax(fabs(c), fabs(d)) / fabs(b);
+  else if (c != 0.0) B = 1.0 + fabs(d / c);
+  else return 0.0;
+  double cut[4];
+  int nc = 0;
+  cut[nc++] = 0.0;
+  // roots of psi'' = c + 2 b t + 3 a t^2
+  if (a > 0.0) {
+    const double disc = 4.0 * b * b - 12.0 * a * c;
+    if (disc > 0.0) {
+      const double sq = sqrt(disc);
+      const double q = -0.5 * (2.0 * b + (b >= 0.0 ? sq : -sq));
+      double r1 = q / (3.0 * a), r2 = q != 0.0 ? c / q : r1;
+      if (r1 > r2) { const double tmp = r1; r1 = r2; r2 = tmp; }
+      if (r1 > 0.0 && r1 < B) cut[nc++] = r1;
+      if (r2 > 0.0 && r2 < B && r2 != r1) cut[nc++] = r2;
+    }
+  } else if (b != 0.0) {
+    const double r = -c / (2.0 * b);
+    if (r > 0.0 && r < B) cut[nc++] = r;
+  }
+  cut[nc++] = B;
+  double best = 0.0, fbest = 0.0;
+  for (int i = 0; i + 1 < nc; ++i) {
+    double lo = cut[i], hi = cut[i + 1];
+    double flo = ((a * lo + b) * lo + c) * lo + d, fhi = ((a * hi + b) * hi + c) * hi + d;
+    if (flo == 0.0) { hi = lo; fhi = 0.0; }
+    else if ((flo < 0.0) == (fhi < 0.0) && fhi != 0.0) continue;
+    for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      const double fm = ((a * mid + b) * mid + c) * mid + d;
+      if ((fm < 0.0) == (flo < 0.0) && fm != 0.0) { lo = mid; flo = fm; }
+      else { hi = mid; fhi = fm; }
+    }
+    const double t = fabs(flo) < fabs(fhi) ? lo : hi;
+    const double ft = (((c4 * t + c3) * t + c2) * t + c1) * t;
+    if (t > 0.0 && ft < fbest) { best = t; fbest = ft; }
+  }
+  return best;
+}
 
 }  // namespace bmg
 

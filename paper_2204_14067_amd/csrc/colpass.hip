@@ -184,7 +184,9 @@ __global__ __launch_bounds__(256) void k_col_reduce(const double *__restrict__ b
 //   G[i] = {x_i + t d_i, t d_i, X[i, jn], 0},  X[i, j] = x_i + t d_i.
 template <typename T>
 __global__ void k_col_step(int64_t m, int64_t n, T *__restrict__ W, T *__restrict__ H, int ld, int j,
-                           int jn, double t, Q4<T> *__restrict__ Gm, Q4<T> *__restrict__ Gn) {
+                           int jn, const double *__restrict__ tp, Q4<T> *__restrict__ Gm,
+                           Q4<T> *__restrict__ Gn) {
+  const double t = *tp;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
     const Q4<T> g = Gm[i];
@@ -200,6 +202,18 @@ __global__ void k_col_step(int64_t m, int64_t n, T *__restrict__ W, T *__restric
     if (t != 0.0) H[i * ld + j] = x;
     Gn[i] = Q4<T>{x, s, jn >= 0 ? H[i * ld + jn] : (T)0, (T)0};
   }
+}
+
+// The step of the block from its quartic (one thread; see launch_col_t).
+__global__ void k_col_t(const double *__restrict__ h, double lam, double *__restrict__ state) {
+  const double c1 = h[0] + lam * (h[5] + h[7]);
+  const double c2 = 0.5 * h[1] + h[2] + 0.5 * lam * (h[6] + h[8]);
+  const double c3 = h[3], c4 = 0.5 * h[4];
+  double t = 0.0;
+  if (isfinite(c1) && isfinite(c2) && isfinite(c3) && isfinite(c4)) t = quartic_min(c1, c2, c3, c4);
+  else state[2] = 1.0;
+  state[0] = t;
+  if (t > 0.0) state[1] += 1.0;
 }
 
 // Records for the first block: {0, 0, X[i, 0], 0}.
@@ -254,13 +268,18 @@ hipError_t launch_col_quartic(const Plan &pl, const T *r, int64_t m, int64_t n, 
   return hipGetLastError();
 }
 
+hipError_t launch_col_t(const double *h, double lam, double *state, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_t, dim3(1), dim3(1), 0, s, h, lam, state);
+  return hipGetLastError();
+}
+
 template <typename T>
-hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, int jn, double t, Q4<T> *Gm,
-                           Q4<T> *Gn, hipStream_t s) {
+hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, int jn, const double *tp,
+                           Q4<T> *Gm, Q4<T> *Gn, hipStream_t s) {
   const int64_t mx = m > n ? m : n;
   if (mx > 0)
     hipLaunchKernelGGL((k_col_step<T>), dim3((unsigned)((mx + 255) / 256)), dim3(256), 0, s, m, n, W, H,
-                       ld, j, jn, t, Gm, Gn);
+                       ld, j, jn, tp, Gm, Gn);
   return hipGetLastError();
 }
 
@@ -272,7 +291,7 @@ hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, int 
   template hipError_t launch_col_quartic<T>(const Plan &, const T *, int64_t, int64_t,              \
                                             const Q4<T> *, const Q4<T> *, double *, int64_t,        \
                                             double *, double *, hipStream_t);                       \
-  template hipError_t launch_col_step<T>(int64_t, int64_t, T *, T *, int, int, int, double, Q4<T> *, \
+  template hipError_t launch_col_step<T>(int64_t, int64_t, T *, T *, int, int, int, const double *, Q4<T> *, \
                                          Q4<T> *, hipStream_t);
 BMG_INST_COL(double)
 BMG_INST_COL(float)
