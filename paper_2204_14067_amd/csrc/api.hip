@@ -1510,9 +1510,8 @@ struct Method : Engine<T, TG> {
       E::count(R->pl, 4.0 + (upd ? 2.0 : 1.0) * sizeof(T), (double)(m + n) * 4 * sizeof(T));
       E::count(C->pl, 4.0 + (upd ? 2.0 : 1.0) * sizeof(T), (double)(m + n) * 4 * sizeof(T));
       HIPC(launch_col_quartic<T>(R->pl, (const T *)R->r, m, n, Gm, Gn, P->wsum, 2 * P->L.wsum_cap,
-                                 P->wpart, P->result, s));
+                                 P->wpart, P->result, lam, state, s));
       E::count(R->pl, 4.0 + sizeof(T), (double)(m + n) * 4 * sizeof(T));
-      HIPC(launch_col_t(P->result, lam, state, s));
       HIPC(launch_col_step<T>(m, n, W, H, ldk, j, j + 1 < k ? j + 1 : -1, state, Gm, Gn, s));
     }
     double h[3];

@@ -224,16 +224,15 @@ hipError_t launch_col_grad(const Plan &pl, T *r, Q4<T> *Gown, const Q4<T> *Goth,
 // out[0..4] = sum over Omega (rows orientation) of r a, a^2, r b, a b, b^2 with
 // a = dw_i h_l + w_i dh_l, b = dw_i dh_l; out[5..8] = w.dw, dw.dw, h.dh, dh.dh.
 // bpart: 5 doubles per 4 work units (bpart_cap doubles); dpart: 512 doubles.
+// With state (device, or null), also the block's step from those sums: the
+// quartic c1 = h0 + lam (h5 + h7), c2 = h1 / 2 + h2 + lam (h6 + h8) / 2,
+// c3 = h3, c4 = h4 / 2 and t = quartic_min(c1..c4) into state[0]; state[1]
+// counts the blocks with t > 0, state[2] is set to 1 (and t to 0) when a
+// coefficient is not finite.
 template <typename T>
 hipError_t launch_col_quartic(const Plan &pl, const T *r, int64_t m, int64_t n, const Q4<T> *Gm,
                               const Q4<T> *Gn, double *bpart, int64_t bpart_cap, double *dpart,
-                              double *out, hipStream_t s);
-// The block's step from the nine sums h of launch_col_quartic (device, one
-// thread): the quartic c1 = h0 + lam (h5 + h7), c2 = h1 / 2 + h2 + lam (h6 +
-// h8) / 2, c3 = h3, c4 = h4 / 2 and t = quartic_min(c1..c4) into state[0];
-// state[1] counts the blocks with t > 0, state[2] is set to 1 (and t to 0)
-// when a coefficient is not finite.
-hipError_t launch_col_t(const double *h, double lam, double *state, hipStream_t s);
+                              double *out, double lam, double *state, hipStream_t s);
 // Block j moves by t = *tp (device) along its direction: X[:, j] += t dir;
 // the records are rewritten for block jn (jn < 0: none).
 template <typename T>

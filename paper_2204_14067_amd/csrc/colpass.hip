@@ -80,11 +80,25 @@ __global__ void k_col_fix(Plan pl, const double *__restrict__ part, double lam,
 // Coefficient sums of the quartic along (w + t dw, h + t dh) on the rows
 // orientation: with a = dw_i h_l + w_i dh_l and b = dw_i dh_l per entry,
 // per block: sum r a, sum a^2, sum r b, sum a b, sum b^2.
+constexpr int DOT_BLOCKS = 128;
+
+template <typename T>
+__device__ void col_dots_block(int64_t m, int64_t n, const Q4<T> *__restrict__ Gm,
+                               const Q4<T> *__restrict__ Gn, double *__restrict__ dpart, int bid);
+
+// Blocks 0..nbq-1: the quartic sums of nbq x CP_WAVES work units; blocks
+// nbq..nbq+DOT_BLOCKS-1: the record dot products (col_dots_block).
 template <typename T>
 __global__ __launch_bounds__(64 * CP_WAVES) void k_col_quartic(Plan pl, const T *__restrict__ r,
                                                             const Q4<T> *__restrict__ Gm,
                                                             const Q4<T> *__restrict__ Gn,
-                                                            double *__restrict__ bpart) {
+                                                            double *__restrict__ bpart, int64_t nbq,
+                                                            int64_t m, int64_t n,
+                                                            double *__restrict__ dpart) {
+  if ((int64_t)blockIdx.x >= nbq) {
+    col_dots_block<T>(m, n, Gm, Gn, dpart, (int)(blockIdx.x - nbq));
+    return;
+  }
   __shared__ double sm[CP_WAVES][5];
   const int64_t u = (int64_t)blockIdx.x * CP_WAVES + threadIdx.x / 64;
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
@@ -120,23 +134,20 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_col_quartic(Plan pl, const T 
   }
 }
 
-constexpr int DOT_BLOCKS = 128;
-
-// Per block b: sum x d, sum d^2 over its slice of the m records and of the
-// n records (x = the block's current value, d = its direction).
+// Dot block b of DOT_BLOCKS: sum x d, sum d^2 over its slice of the m records
+// and of the n records (x = the block's current value, d = its direction).
 template <typename T>
-__global__ __launch_bounds__(256) void k_col_dots(int64_t m, int64_t n, const Q4<T> *__restrict__ Gm,
-                                                  const Q4<T> *__restrict__ Gn,
-                                                  double *__restrict__ dpart) {
+__device__ void col_dots_block(int64_t m, int64_t n, const Q4<T> *__restrict__ Gm,
+                               const Q4<T> *__restrict__ Gn, double *__restrict__ dpart, int bid) {
   __shared__ double sm[4][4];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += stride) {
+  const int64_t stride = (int64_t)DOT_BLOCKS * 256;
+  for (int64_t i = (int64_t)bid * 256 + threadIdx.x; i < m; i += stride) {
     const Q4<T> g = Gm[i];
     v[0] += (double)g.z * (double)g.w;
     v[1] += (double)g.w * (double)g.w;
   }
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+  for (int64_t i = (int64_t)bid * 256 + threadIdx.x; i < n; i += stride) {
     const Q4<T> g = Gn[i];
     v[2] += (double)g.z * (double)g.w;
     v[3] += (double)g.w * (double)g.w;
@@ -150,14 +161,30 @@ __global__ __launch_bounds__(256) void k_col_dots(int64_t m, int64_t n, const Q4
   __syncthreads();
   if (threadIdx.x < 4) {
     const double t = sm[0][threadIdx.x] + sm[1][threadIdx.x] + sm[2][threadIdx.x] + sm[3][threadIdx.x];
-    dpart[blockIdx.x * 4 + threadIdx.x] = t;
+    dpart[bid * 4 + threadIdx.x] = t;
   }
 }
 
-// out[0..4]: the quartic sums over nb blocks; out[5..8]: the four dot products.
+// The step of the block from its quartic's sums h (one thread): state[0] =
+// t, state[1] counts the blocks with t > 0, state[2] = 1 on a non-finite
+// coefficient (t = 0 then).
+__device__ void col_step_of(const double *h, double lam, double *__restrict__ state) {
+  const double c1 = h[0] + lam * (h[5] + h[7]);
+  const double c2 = 0.5 * h[1] + h[2] + 0.5 * lam * (h[6] + h[8]);
+  const double c3 = h[3], c4 = 0.5 * h[4];
+  double t = 0.0;
+  if (isfinite(c1) && isfinite(c2) && isfinite(c3) && isfinite(c4)) t = quartic_min(c1, c2, c3, c4);
+  else state[2] = 1.0;
+  state[0] = t;
+  if (t > 0.0) state[1] += 1.0;
+}
+
+// out[0..4]: the quartic sums over nb blocks; out[5..8]: the four dot
+// products; with state, also the block's step (col_step_of).
 __global__ __launch_bounds__(256) void k_col_reduce(const double *__restrict__ bpart, int64_t nb,
                                                     const double *__restrict__ dpart,
-                                                    double *__restrict__ out) {
+                                                    double *__restrict__ out, double lam,
+                                                    double *__restrict__ state) {
   __shared__ double sm[4][9];
   double v[9];
 #pragma unroll
@@ -177,6 +204,12 @@ __global__ __launch_bounds__(256) void k_col_reduce(const double *__restrict__ b
   __syncthreads();
   if (threadIdx.x < 9) out[threadIdx.x] = sm[0][threadIdx.x] + sm[1][threadIdx.x] + sm[2][threadIdx.x] +
                                           sm[3][threadIdx.x];
+  if (state && threadIdx.x == 0) {
+    double h[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) h[q] = sm[0][q] + sm[1][q] + sm[2][q] + sm[3][q];
+    col_step_of(h, lam, state);
+  }
 }
 
 // Block j moves by t along its direction (t = 0: no move) and the records
@@ -202,18 +235,6 @@ __global__ void k_col_step(int64_t m, int64_t n, T *__restrict__ W, T *__restric
     if (t != 0.0) H[i * ld + j] = x;
     Gn[i] = Q4<T>{x, s, jn >= 0 ? H[i * ld + jn] : (T)0, (T)0};
   }
-}
-
-// The step of the block from its quartic (one thread; see launch_col_t).
-__global__ void k_col_t(const double *__restrict__ h, double lam, double *__restrict__ state) {
-  const double c1 = h[0] + lam * (h[5] + h[7]);
-  const double c2 = 0.5 * h[1] + h[2] + 0.5 * lam * (h[6] + h[8]);
-  const double c3 = h[3], c4 = 0.5 * h[4];
-  double t = 0.0;
-  if (isfinite(c1) && isfinite(c2) && isfinite(c3) && isfinite(c4)) t = quartic_min(c1, c2, c3, c4);
-  else state[2] = 1.0;
-  state[0] = t;
-  if (t > 0.0) state[1] += 1.0;
 }
 
 // Records for the first block: {0, 0, X[i, 0], 0}.
@@ -255,21 +276,14 @@ hipError_t launch_col_grad(const Plan &pl, T *r, Q4<T> *Gown, const Q4<T> *Goth,
 template <typename T>
 hipError_t launch_col_quartic(const Plan &pl, const T *r, int64_t m, int64_t n, const Q4<T> *Gm,
                               const Q4<T> *Gn, double *bpart, int64_t bpart_cap, double *dpart,
-                              double *out, hipStream_t s) {
+                              double *out, double lam, double *state, hipStream_t s) {
   const int64_t units = pl.n_short + pl.n_pieces;
   const int64_t nb = (units + CP_WAVES - 1) / CP_WAVES;
   if (nb * 5 > bpart_cap) return hipErrorInvalidValue;
-  if (nb > 0)
-    hipLaunchKernelGGL((k_col_quartic<T>), dim3((unsigned)nb), dim3(64 * CP_WAVES), 0, s, pl, r, Gm, Gn,
-                       bpart);
-  hipLaunchKernelGGL((k_col_dots<T>), dim3(DOT_BLOCKS), dim3(256), 0, s, m, n, Gm, Gn, dpart);
+  hipLaunchKernelGGL((k_col_quartic<T>), dim3((unsigned)(nb + DOT_BLOCKS)), dim3(64 * CP_WAVES), 0, s, pl,
+                     r, Gm, Gn, bpart, nb, m, n, dpart);
   hipLaunchKernelGGL(k_col_reduce, dim3(1), dim3(256), 0, s, (const double *)bpart, nb,
-                     (const double *)dpart, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_col_t(const double *h, double lam, double *state, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_t, dim3(1), dim3(1), 0, s, h, lam, state);
+                     (const double *)dpart, out, lam, state);
   return hipGetLastError();
 }
 
@@ -290,7 +304,7 @@ hipError_t launch_col_step(int64_t m, int64_t n, T *W, T *H, int ld, int j, int 
                                          double *, hipStream_t);                                    \
   template hipError_t launch_col_quartic<T>(const Plan &, const T *, int64_t, int64_t,              \
                                             const Q4<T> *, const Q4<T> *, double *, int64_t,        \
-                                            double *, double *, hipStream_t);                       \
+                                            double *, double *, double, double *, hipStream_t);                       \
   template hipError_t launch_col_step<T>(int64_t, int64_t, T *, T *, int, int, int, const double *, Q4<T> *, \
                                          Q4<T> *, hipStream_t);
 BMG_INST_COL(double)
