@@ -177,6 +177,22 @@ def yahoo_shape(scale: float = 1.0, seed: int = 1003) -> Problem:
                     50.0, 32, seed, scale)
 
 
+def movielens_shape(which: str = "100k", seed: int = 1007) -> Problem:
+    """Rating-shaped stand-ins for the two small problems the paper times in
+    its tables (Sec. 6.1): "100k" has the MovieLens-100k shape (943 x 1,682,
+    90,570 entries, lambda 15), "toy" the toy example's (3,952 x 6,040,
+    900,189 entries, lambda 36).  Power-law degrees (exponent 1.0 on rows and
+    columns), values 3 + rank-10 Gaussian (factor variance 1/sqrt(10)) + noise
+    of variance 0.25, clipped to [1, 5]; k0 = 8.  No record of either dataset
+    is used: only their shapes and the paper's lambda."""
+    if which == "100k":
+        return powerlaw("movielens100k_shape", 943, 1_682, 90_570, 1.0, 10, 0.25, 3.0, 1.0, 5.0, 15.0, 8,
+                        seed)
+    if which == "toy":
+        return powerlaw("toy_shape", 3_952, 6_040, 900_189, 1.0, 10, 0.25, 3.0, 1.0, 5.0, 36.0, 8, seed)
+    raise ValueError("which must be '100k' or 'toy'")
+
+
 def tiny(m: int, n: int, nnz: int, rank: int = 2, var_e: float = 0.01, lam: float = 0.1,
          k0: int = 4, seed: int = 7) -> Problem:
     """Small uniform problem for brute-force checks (nnz may be 0 or m*n)."""

@@ -9,6 +9,11 @@ netflix_quarter_lam300.json : the Netflix-shaped generator at scale 0.25 (4,442 
                      truth + noise variance 0.25 clipped to [1, 5]), lambda = 300,
                      k0 = 16; oracle solve to 1e-10 with its duality-gap certificate.
 
+movielens100k_shape_lam15.json, toy_shape_lam36.json : the rating-shaped
+                     stand-ins of synth.movielens_shape ("100k": 943 x 1,682,
+                     90,570 entries, lambda 15; "toy": 3,952 x 6,040, 900,189
+                     entries, lambda 36), k0 = 8; oracle solve to relative
+                     optimality residual 1e-12 with its duality-gap certificate.
 rke_solves.json   : the kernel-estimation QSDP oracle (oracle/rke.py) on
                      synth.rke workloads: (600 objects, 40 partners, lambda 10,
                      seed 3; k0 6, tol 1e-5, algorithm seed 1) with lmsvd_p 0
@@ -16,7 +21,7 @@ rke_solves.json   : the kernel-estimation QSDP oracle (oracle/rke.py) on
                      seed 7; k0 8, tol 1e-4, algorithm seed 1, lmsvd_p 1); final
                      F, rank, outer and subspace iterations.
 
-    python tests/golden/make_golden.py [small_uniform] [netflix_quarter] [rke_600] [rke_20000]
+    python tests/golden/make_golden.py [small_uniform] [netflix_quarter] [ml100k] [toy] [rke_600] [rke_20000]
 """
 import json
 import os
@@ -31,9 +36,9 @@ from oracle import core, dense, rke  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def certified(p, lam, k0, seed, fname, first_at=1e-6):
+def certified(p, lam, k0, seed, fname, first_at=1e-6, tol=1e-10):
     t0 = time.time()
-    res = core.solve(p, core.Options(lam=lam, k0=k0, tol=1e-10, seed=seed, max_iter=3000),
+    res = core.solve(p, core.Options(lam=lam, k0=k0, tol=tol, seed=seed, max_iter=3000),
                      callback=lambda r: print(r.t, r.F, r.residual, r.k, r.q, r.ssi_iters, flush=True))
     f, R = core.loss(p, res.W, res.H)
     gap, D, g2 = dense.duality_gap(p, R, res.F, lam)
@@ -55,6 +60,16 @@ def small_uniform():
 def netflix_quarter():
     p = synth.netflix_shape(scale=0.25)
     certified(p, 300.0, 16, 3, "netflix_quarter_lam300.json")
+
+
+def ml100k():
+    p = synth.movielens_shape("100k")
+    certified(p, p.lam, p.k0, 3, "movielens100k_shape_lam15.json", tol=1e-12)
+
+
+def toy():
+    p = synth.movielens_shape("toy")
+    certified(p, p.lam, p.k0, 3, "toy_shape_lam36.json", tol=1e-12)
 
 
 def _rke_case(key, n, lam, seed, k0, tol, hist, alg_seed=1):
