@@ -271,10 +271,11 @@ template <typename T> constexpr int max_width() { return 128 * (16 / (int)sizeof
 
 // Global minimiser over t >= 0 of psi(t) = c1 t + c2 t^2 + c3 t^3 + c4 t^4
 // (c4 >= 0): psi' is a cubic; the real roots of psi'' cut [0, B] (B a bound on
-// the roots of psi') into intervals where psi' is monotone, bisection finds
-// the root in each interval where psi' changes sign, and the best of t = 0
-// and those roots is returned.  The same code runs on the host and on the
-// device (no contraction into fused multiply-adds, so both give the same t).
+// the roots of psi') into intervals where psi' is monotone, safeguarded
+// Newton (bisection every second step) finds the root in each interval where
+// psi' changes sign, and the best of t = 0 and those roots is returned.  The
+// same code runs on the host and on the device (no contraction into fused
+// multiply-adds, so both give the same t).
 __host__ __device__ inline double quartic_min(double c1, double c2, double c3, double c4) {
 #pragma clang fp contract(off)
   const double a = 4.0 * c4, b = 3.0 * c3, c = 2.0 * c2, d = c1;
@@ -308,12 +309,31 @@ __host__ __device__ inline double quartic_min(double c1, double c2, double c3, d
     double flo = ((a * lo + b) * lo + c) * lo + d, fhi = ((a * hi + b) * hi + c) * hi + d;
     if (flo == 0.0) { hi = lo; fhi = 0.0; }
     else if ((flo < 0.0) == (fhi < 0.0) && fhi != 0.0) continue;
+    // safeguarded Newton on psi' inside the bracket: a Newton step from the
+    // end with the smaller |psi'| when it lands strictly inside, else the
+    // midpoint; every second step bisects, so the bracket at least halves
+    // every two steps; stop once a Newton step moves by at most a few ulps
+    // or the bracket cannot shrink
     for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;
-      const double fm = ((a * mid + b) * mid + c) * mid + d;
-      if ((fm < 0.0) == (flo < 0.0) && fm != 0.0) { lo = mid; flo = fm; }
-      else { hi = mid; fhi = fm; }
+      double x = 0.5 * (lo + hi);
+      bool conv = false;
+      if (!(it & 1)) {
+        const bool lside = fabs(flo) < fabs(fhi);
+        const double x0 = lside ? lo : hi, f0 = lside ? flo : fhi;
+        const double d0 = (3.0 * a * x0 + 2.0 * b) * x0 + c;
+        if (d0 != 0.0) {
+          const double xn = x0 - f0 / d0;
+          if (xn > lo && xn < hi) {
+            x = xn;
+            conv = fabs(xn - x0) <= 4.0 * 2.220446049250313e-16 * fabs(x0);
+          }
+        }
+      }
+      if (x <= lo || x >= hi) break;
+      const double fm = ((a * x + b) * x + c) * x + d;
+      if ((fm < 0.0) == (flo < 0.0) && fm != 0.0) { lo = x; flo = fm; }
+      else { hi = x; fhi = fm; }
+      if (fm == 0.0 || conv) break;
     }
     const double t = fabs(flo) < fabs(fhi) ? lo : hi;
     const double ft = (((c4 * t + c3) * t + c2) * t + c1) * t;
