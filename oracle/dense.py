@@ -54,8 +54,10 @@ def proximal_gradient_dense(A, M, lam, alpha=1.0, tol=1e-12, max_iter=100000, X0
 
 def spectral_norm(prob, vals) -> float:
     """||S||_2 of the sparse matrix with values ``vals`` on Omega (ARPACK, or a
-    dense SVD for small matrices)."""
-    if min(prob.m, prob.n) <= 3000:
+    dense SVD up to 4,000 on the short side: at an optimum the top singular
+    value of the gradient is lambda with the multiplicity of the rank, a
+    cluster ARPACK may fail to converge on)."""
+    if min(prob.m, prob.n) <= 4000:
         A, M = to_dense(prob)
         S = np.zeros((prob.m, prob.n))
         S[prob.rows(), prob.col] = vals
