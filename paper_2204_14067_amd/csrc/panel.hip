@@ -26,6 +26,9 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "bmg_internal.h"
 
 namespace bmg {
@@ -167,74 +170,77 @@ __global__ void k_panel_xt(int ldi, int q, const int32_t *__restrict__ rows, con
 }
 
 // ------------------------------------------------------------------ rows product
-// Block (bx, by): columns [bx cpb, (bx + 1) cpb) (cpb a multiple of 16); wave
-// w: panel-row tile 4 by + w and every output column tile (at most NQ).
-// M = panel rows i, N = output columns c, K = columns j.
-// part[bx][i][c] (ldi x Q16 per block) gets the block's partial sums.
-template <typename T, int NQ>
+// Block (bx, by): columns [bx cpb, (bx + 1) cpb) (cpb a multiple of 16); wave w:
+// panel-row tiles 4 NT by + w + 4 t (t < NT) and every output column tile (NQ =
+// ceil(q / 16) of them).  The NT tiles of a wave share every loaded Y value, and
+// one block reads each Y row once for all the panel rows it covers; operands are
+// loaded at the start of each 16-column step (no second register set: the
+// registers go to the NT x NQ accumulators).  M = panel rows i, N = output
+// columns c, K = columns j.  part[bx][i][c] (ldi x 16 NQ per block) gets the
+// block's partial sums.
+template <typename T, int NQ, int NT>
 __global__ __launch_bounds__(256) void k_panel_rows(int TI, int64_t n, int q, int64_t cpb,
                                                     const T *__restrict__ S, int ldi, int values,
                                                     const T *__restrict__ Y, int ldy,
                                                     double *__restrict__ part) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kr = lane / 16, cl = lane % 16;
-  const int TQ = (q + 15) / 16;
-  const int Q16 = TQ * 16;
-  const int ti = blockIdx.y * 4 + wave;
-  if (ti >= TI) return;   // whole wave
+  const int Q16 = NQ * 16;
+  const int tb = blockIdx.y * 4 * NT + wave;
+  if (tb >= TI) return;   // whole wave
   const int64_t c0 = (int64_t)blockIdx.x * cpb;
   const int64_t c1 = (c0 + cpb) < n ? (c0 + cpb) : n;
-  const int i = ti * 16 + cl;
-  d4p_t acc[NQ];
+  int ir[NT];
 #pragma unroll
-  for (int u = 0; u < NQ; ++u) acc[u] = d4p_t{0.0, 0.0, 0.0, 0.0};
-  // the operands of the next 16 columns are loaded before the products of the
-  // current ones are issued (two sets of registers)
-  double a[4], b[4][NQ];
-  auto load = [&](int64_t jj) {
+  for (int t = 0; t < NT; ++t) {
+    const int ti = tb + 4 * t;
+    ir[t] = (ti < TI ? ti : tb) * 16 + cl;
+  }
+  d4p_t acc[NT][NQ];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) acc[t][u] = d4p_t{0.0, 0.0, 0.0, 0.0};
+  for (int64_t jj = c0; jj < c1; jj += 16) {
+    double a[NT][4], b[4][NQ];
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
       const int64_t j = jj + 4 * kr + st;
       const bool jv = j < c1;
       const int64_t jc = jv ? j : c0;
-      double x = (double)S[jc * ldi + i];
-      if (values) x = isnan(x) ? 0.0 : x;
-      a[st] = jv ? x : 0.0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        double x = (double)S[jc * ldi + ir[t]];
+        if (values) x = isnan(x) ? 0.0 : x;
+        a[t][st] = jv ? x : 0.0;
+      }
       const T *yr = Y + jc * ldy;
 #pragma unroll
       for (int u = 0; u < NQ; ++u) {
         const int c = u * 16 + cl;
-        b[st][u] = (u < TQ && jv && c < q) ? (double)yr[c] : 0.0;
+        b[st][u] = (jv && c < q) ? (double)yr[c] : 0.0;
       }
     }
-  };
-  if (c0 < c1) load(c0);
-  for (int64_t jj = c0; jj < c1; jj += 16) {
-    double ac[4], bc[4][NQ];
-#pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      ac[st] = a[st];
-#pragma unroll
-      for (int u = 0; u < NQ; ++u) bc[st][u] = b[st][u];
-    }
-    if (jj + 16 < c1) load(jj + 16);
 #pragma unroll
     for (int st = 0; st < 4; ++st)
 #pragma unroll
-      for (int u = 0; u < NQ; ++u) {
-        if (u >= TQ) break;
-        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[st], bc[st][u], acc[u], 0, 0, 0);
-      }
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int u = 0; u < NQ; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][st], b[st][u], acc[t][u], 0, 0, 0);
   }
   double *pb = part + (int64_t)blockIdx.x * TI * 16 * Q16;
 #pragma unroll
-  for (int u = 0; u < NQ; ++u) {
-    if (u >= TQ) break;
+  for (int t = 0; t < NT; ++t) {
+    const int ti = tb + 4 * t;
+    if (ti >= TI) break;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int ii = ti * 16 + 4 * v + kr, c = u * 16 + cl;
-      pb[(int64_t)ii * Q16 + c] = acc[u][v];
-    }
+    for (int u = 0; u < NQ; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ii = ti * 16 + 4 * v + kr, c = u * 16 + cl;
+        pb[(int64_t)ii * Q16 + c] = acc[t][u][v];
+      }
   }
 }
 
@@ -296,17 +302,37 @@ hipError_t launch_panel_rows(const PanelArg<T> &pa, bool values, const T *Y, int
   if ((int64_t)ng * per > part2_cap) return hipErrorInvalidValue;
   const int bpg = (int)((nbk + ng - 1) / ng);
   ng = (int)((nbk + bpg - 1) / bpg);
-  const dim3 grid((unsigned)nbk, (unsigned)((TI + 3) / 4));
+  // panel-row tiles per wave: as many as the accumulators allow (NT NQ <= 12)
+  const int ntc = TQ <= 3 ? 4 : (TQ == 4 ? 3 : (TQ <= 6 ? 2 : 1));
+  const int NTr = std::min((TI + 3) / 4, ntc);
+  const dim3 grid((unsigned)nbk, (unsigned)((TI + 4 * NTr - 1) / (4 * NTr)));
   const T *Sp = values ? pa.A : (const T *)pa.R;
-  if (TQ <= 4)
-    hipLaunchKernelGGL((k_panel_rows<T, 4>), grid, dim3(256), 0, s, TI, pa.n, q, cpb, Sp, pa.ldi,
-                       values ? 1 : 0, Y, ldy, part);
-  else if (TQ <= 8)
-    hipLaunchKernelGGL((k_panel_rows<T, 8>), grid, dim3(256), 0, s, TI, pa.n, q, cpb, Sp, pa.ldi,
-                       values ? 1 : 0, Y, ldy, part);
-  else
-    hipLaunchKernelGGL((k_panel_rows<T, 12>), grid, dim3(256), 0, s, TI, pa.n, q, cpb, Sp, pa.ldi,
-                       values ? 1 : 0, Y, ldy, part);
+#define BMG_PANEL_ROWS(NQv, NTv)                                                                            \
+  hipLaunchKernelGGL((k_panel_rows<T, NQv, NTv>), grid, dim3(256), 0, s, TI, pa.n, q, cpb, Sp, pa.ldi,      \
+                     values ? 1 : 0, Y, ldy, part)
+#define BMG_PANEL_ROWS_NT(NQv, NTMAX)                                                                       \
+  do {                                                                                                      \
+    if (NTr >= 4 && NTMAX >= 4) BMG_PANEL_ROWS(NQv, (NTMAX >= 4 ? 4 : 1));                                 \
+    else if (NTr == 3 && NTMAX >= 3) BMG_PANEL_ROWS(NQv, (NTMAX >= 3 ? 3 : 1));                            \
+    else if (NTr == 2 && NTMAX >= 2) BMG_PANEL_ROWS(NQv, (NTMAX >= 2 ? 2 : 1));                            \
+    else BMG_PANEL_ROWS(NQv, 1);                                                                            \
+  } while (0)
+  switch (TQ) {
+    case 1: BMG_PANEL_ROWS_NT(1, 4); break;
+    case 2: BMG_PANEL_ROWS_NT(2, 4); break;
+    case 3: BMG_PANEL_ROWS_NT(3, 4); break;
+    case 4: BMG_PANEL_ROWS_NT(4, 3); break;
+    case 5: BMG_PANEL_ROWS_NT(5, 2); break;
+    case 6: BMG_PANEL_ROWS_NT(6, 2); break;
+    case 7: BMG_PANEL_ROWS(7, 1); break;
+    case 8: BMG_PANEL_ROWS(8, 1); break;
+    case 9: BMG_PANEL_ROWS(9, 1); break;
+    case 10: BMG_PANEL_ROWS(10, 1); break;
+    case 11: BMG_PANEL_ROWS(11, 1); break;
+    default: BMG_PANEL_ROWS(12, 1); break;
+  }
+#undef BMG_PANEL_ROWS_NT
+#undef BMG_PANEL_ROWS
   hipLaunchKernelGGL(k_panel_rows_sum, dim3((unsigned)((per + 255) / 256), (unsigned)ng), dim3(256), 0, s, P16,
                      Q16, (int)nbk, bpg, (const double *)part, part2);
   const int64_t el = (int64_t)pa.P * q;
@@ -372,16 +398,169 @@ __global__ __launch_bounds__(256) void k_panel_cols(int TI, int64_t n, int q, co
   }
 }
 
+// Same product as k_panel_cols (the same MFMA sequence, so the same bits), with
+// X_P held in LDS: each block first gathers the q columns of the panel rows of
+// X there as FP64, row c of the copy at c (ldi + 2) (the two-element pad puts
+// the 16 lanes of a fragment read on distinct banks), then its waves take
+// column tiles 4 b + w, 4 (b + G) + w, ... (G blocks, as many as are resident
+// on the device at once).  Per tile the output rows are loaded at the start and
+// the panel values of four K steps one group ahead.
+template <typename T, int NQ>
+__global__ __launch_bounds__(256) void k_panel_cols_lds(int TI, int64_t n, int q, const T *__restrict__ S,
+                                                        int ldi, int values, const int32_t *__restrict__ rows,
+                                                        const T *__restrict__ X, int ldx, double coef,
+                                                        T *__restrict__ Out, int ldo) {
+  extern __shared__ double xs[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kr = lane / 16, cl = lane % 16;
+  const int ls = ldi + 2;
+  for (int e = threadIdx.x; e < q * ldi; e += 256) {
+    const int i = e / q, c = e % q;
+    xs[c * ls + i] = (double)X[(int64_t)rows[i] * ldx + c];
+  }
+  __syncthreads();
+  const int64_t tiles = (n + 15) / 16;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < tiles; t += (int64_t)gridDim.x * 4) {
+    const int64_t j0 = t * 16;
+    d4p_t acc[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) acc[u] = d4p_t{0.0, 0.0, 0.0, 0.0};
+    const int64_t ja = j0 + cl;
+    const bool jv = ja < n;
+    const T *srow = S + (jv ? ja : 0) * ldi;
+    double ov[NQ][4];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t j = j0 + 4 * v + kr;
+        const int c = u * 16 + cl;
+        ov[u][v] = (j < n && c < q) ? (double)Out[j * ldo + c] : 0.0;
+      }
+    double nx[4][4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) ld4(srow, st * 16 + 4 * kr, (jv && st < TI) ? ldi : 0, nx[st]);
+    for (int g = 0; g < TI; g += 4) {
+      double cu[4][4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cu[st][e] = nx[st][e];
+      if (g + 4 < TI) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+          ld4(srow, (g + 4 + st) * 16 + 4 * kr, (jv && g + 4 + st < TI) ? ldi : 0, nx[st]);
+      }
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        if (g + h >= TI) break;
+        const int ii = (g + h) * 16;
+        double a[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[e] = (values && isnan(cu[h][e])) ? 0.0 : cu[h][e];
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+          const int c = u * 16 + cl;
+          double b[4];
+          if (c < q) {
+            const double2 b0 = *reinterpret_cast<const double2 *>(xs + c * ls + ii + 4 * kr);
+            const double2 b1 = *reinterpret_cast<const double2 *>(xs + c * ls + ii + 4 * kr + 2);
+            b[0] = b0.x; b[1] = b0.y; b[2] = b1.x; b[3] = b1.y;
+          } else {
+            b[0] = b[1] = b[2] = b[3] = 0.0;
+          }
+#pragma unroll
+          for (int st = 0; st < 4; ++st)
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], acc[u], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NQ; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t j = j0 + 4 * v + kr;
+        const int c = u * 16 + cl;
+        if (j < n && c < q) Out[j * ldo + c] = (T)(ov[u][v] + coef * acc[u][v]);
+      }
+  }
+}
+
+// Blocks of 256 threads of kernel fn with lds bytes of dynamic LDS that are
+// resident on the current device at once (0: none fit); cached per device,
+// kernel and size.
+static int64_t resident_blocks(const void *fn, size_t lds) {
+  struct Ent {
+    int dev;
+    const void *fn;
+    size_t lds;
+    int64_t blocks;
+  };
+  static std::mutex mu;
+  static Ent cache[64];
+  static int used = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    for (int e = 0; e < used; ++e)
+      if (cache[e].dev == dev && cache[e].fn == fn && cache[e].lds == lds) return cache[e].blocks;
+  }
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    per_cu = 0;
+  }
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    cus = 0;
+  }
+  const int64_t blocks = (int64_t)std::max(per_cu, 0) * std::max(cus, 0);
+  std::lock_guard<std::mutex> g(mu);
+  if (used < 64) cache[used++] = Ent{dev, fn, lds, blocks};
+  return blocks;
+}
+
 template <typename T>
 hipError_t launch_panel_cols(const PanelArg<T> &pa, bool values, const T *X, int ldx, int q, double coef,
                              T *Out, int ldo, T *Xt, hipStream_t s) {
   if (pa.P <= 0 || q <= 0 || (pa.ldi % 16)) return hipErrorInvalidValue;
   const int TI = pa.ldi / 16, TQ = (q + 15) / 16;
   if (TQ > 12) return hipErrorInvalidValue;
+  const T *Sp = values ? pa.A : (const T *)pa.R;
+  // X_P in LDS when it fits (at most 5 output column tiles: at 6 the registers
+  // leave one wave per SIMD)
+  const size_t lds = (size_t)q * (pa.ldi + 2) * sizeof(double);
+  if (TQ <= 5 && lds <= 160 * 1024) {
+    const void *fn = nullptr;
+    switch (TQ) {
+      case 1: fn = (const void *)k_panel_cols_lds<T, 1>; break;
+      case 2: fn = (const void *)k_panel_cols_lds<T, 2>; break;
+      case 3: fn = (const void *)k_panel_cols_lds<T, 3>; break;
+      case 4: fn = (const void *)k_panel_cols_lds<T, 4>; break;
+      default: fn = (const void *)k_panel_cols_lds<T, 5>; break;
+    }
+    const int64_t tiles = (pa.n + 15) / 16;
+    int64_t nb = std::min(resident_blocks(fn, lds), (tiles + 3) / 4);
+    if (nb > 0) {
+      const dim3 g1((unsigned)nb);
+      switch (TQ) {
+#define BMG_PANEL_COLS(NQv)                                                                                   \
+  hipLaunchKernelGGL((k_panel_cols_lds<T, NQv>), g1, dim3(256), lds, s, TI, pa.n, q, Sp, pa.ldi,             \
+                     values ? 1 : 0, pa.rows, X, ldx, coef, Out, ldo)
+        case 1: BMG_PANEL_COLS(1); break;
+        case 2: BMG_PANEL_COLS(2); break;
+        case 3: BMG_PANEL_COLS(3); break;
+        case 4: BMG_PANEL_COLS(4); break;
+        default: BMG_PANEL_COLS(5); break;
+#undef BMG_PANEL_COLS
+      }
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_panel_xt<T>), dim3((unsigned)((pa.ldi * q + 255) / 256)), dim3(256), 0, s, pa.ldi, q,
                      pa.rows, X, ldx, Xt);
   const dim3 grid((unsigned)((pa.n + 63) / 64));
-  const T *Sp = values ? pa.A : (const T *)pa.R;
   if (TQ <= 4)
     hipLaunchKernelGGL((k_panel_cols<T, 4>), grid, dim3(256), 0, s, TI, pa.n, q, Sp, pa.ldi, values ? 1 : 0,
                        (const T *)Xt, coef, Out, ldo);

@@ -55,6 +55,10 @@ CASES = {
     "mixed_m_gt_n": lambda: transposed(dense_rows_problem(50, 300, (3, 20, 21, 49), 0.6, 2500, seed=6)),
     "all_dense": lambda: dense_rows_problem(12, 900, tuple(range(12)), 0.35, 0, seed=7),
     "powerlaw": lambda: synth.netflix_shape(scale=0.03),
+    # panels of 100 and 200 rows: several panel-row tiles per wave in the rows
+    # product, and large LDS copies of the gathered rows in the columns product
+    "tall_panel": lambda: dense_rows_problem(220, 700, tuple(range(0, 200, 2)), 0.4, 4000, seed=8),
+    "taller_panel": lambda: dense_rows_problem(230, 500, tuple(range(200)), 0.3, 1500, seed=9),
 }
 _cache = {}
 
@@ -110,6 +114,29 @@ def test_panel_bm_epochs_parity(name, k):
     if tp:
         Wo, Ho = Ho, Wo
     print("panel bm", name, k, Fbm, Fo, flush=True)
+    assert math.isclose(Fbm, Fo, rel_tol=1e-10)
+    scale = max(np.abs(Wo).max(), np.abs(Ho).max())
+    assert np.allclose(Wd.cpu().numpy()[:, :k], Wo, rtol=1e-8, atol=1e-9 * scale)
+    assert np.allclose(Hd.cpu().numpy()[:, :k], Ho, rtol=1e-8, atol=1e-9 * scale)
+
+
+@pytest.mark.parametrize("name", ["tall_panel", "taller_panel"])
+@pytest.mark.parametrize("k", [50, 70, 100])
+def test_panel_bm_epochs_parity_wide(name, k):
+    """Widths of 4 to 7 output tiles of 16 (the columns product falls back to
+    its register-staged form beyond 5) on panels of 100 and 200 rows."""
+    p = case(name)
+    lam = 0.7
+    dp = to_dev(p, k_cap=112)
+    ld = bmg.round_ld(112)
+    W, H = factors(p, k, ld, seed=4)
+    Wd, Hd = t(W), t(H)
+    Fbm = dp.bmg_bm_epochs(Wd, Hd, k, lam, epochs=2)
+    Wo, Ho = W[:, :k], H[:, :k]
+    for _ in range(2):
+        Wo, Ho, _ = core.bm_epoch(p, Wo, Ho, lam)
+    Fo = core.bm_objective(p, Wo, Ho, lam)
+    print("panel bm wide", name, k, Fbm, Fo, flush=True)
     assert math.isclose(Fbm, Fo, rel_tol=1e-10)
     scale = max(np.abs(Wo).max(), np.abs(Ho).max())
     assert np.allclose(Wd.cpu().numpy()[:, :k], Wo, rtol=1e-8, atol=1e-9 * scale)
