@@ -152,6 +152,72 @@ __global__ __launch_bounds__(256) void k_gram(int64_t N, int a, const T *__restr
     }
 }
 
+// X^T X for at most NT = 5 column tiles: the NT (NT + 1) / 2 tiles i <= j in one
+// pass over the rows (each row read once; the general kernel above reads it once
+// per group of four tiles and computes every tile), the result written to both
+// (i, j) and (j, i).  Same fragment layout, row stepping and wave-order sums as
+// k_gram; the values of the next 4-row step are loaded before the products of
+// the current one.
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void k_gram_sym(int64_t N, int a, const T *__restrict__ X, int ldx,
+                                                  int64_t rpb, double *__restrict__ part) {
+  __shared__ double red[4][256];
+  constexpr int NP = NT * (NT + 1) / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r1 = (r0 + rpb) < N ? (r0 + rpb) : N;
+  const int kr = lane / 16, cl = lane % 16;
+  d4_t acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = d4_t{0.0, 0.0, 0.0, 0.0};
+  auto load = [&](int64_t r, double (&v)[NT]) {
+    const int64_t row = r + kr;
+    const bool rv = row < r1;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int c = 16 * i + cl;
+      v[i] = (rv && c < a) ? (double)X[row * ldx + c] : 0.0;
+    }
+  };
+  double nx[NT];
+  int64_t r = r0 + 4 * wave;
+  if (r < r1) load(r, nx);
+  for (; r < r1; r += 16) {
+    double cu[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) cu[i] = nx[i];
+    if (r + 16 < r1) load(r + 16, nx);
+    int p = 0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int j = i; j < NT; ++j, ++p)
+        acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(cu[i], cu[j], acc[p], 0, 0, 0);
+  }
+  int p = 0;
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = i; j < NT; ++j, ++p) {
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[wave][4 * lane + v] = acc[p][v];
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double sv = ((red[0][4 * lane + v] + red[1][4 * lane + v]) + red[2][4 * lane + v]) +
+                            red[3][4 * lane + v];
+          const int oi = 16 * i + 4 * v + kr, oj = 16 * j + cl;
+          if (oi < a && oj < a) {
+            part[((int64_t)blockIdx.x * a + oi) * a + oj] = sv;
+            part[((int64_t)blockIdx.x * a + oj) * a + oi] = sv;
+          }
+        }
+      }
+    }
+}
+
 // out[e] = sum over row blocks c (in order) of part[c][e]: 64 elements per
 // block, four lanes per element take blocks c = g, g+4, ... then add in order.
 __global__ __launch_bounds__(256) void k_gram_reduce(int64_t nchunks, int64_t ab,
@@ -176,6 +242,31 @@ hipError_t launch_gram(int64_t N, int a, const T *X, int ldx, int b, const T *Y,
   const int64_t ab = (int64_t)a * b;
   if (ab == 0) return hipSuccess;
   const int TA = (a + 15) / 16, TB = (b + 15) / 16;
+  if (X == Y && a == b && ldx == ldy && TA <= 5) {
+    // X^T X: one pass, upper tiles only; one block per resident slot (two per
+    // CU at four or five tiles, whose accumulators leave two waves per SIMD)
+    int64_t nx = (N + 63) / 64;
+    const int64_t xmax = TA >= 4 ? 512 : 1024;
+    if (nx > xmax) nx = xmax;
+    if (nx * ab > part_cap) nx = part_cap / ab;
+    if (nx < 1) nx = 1;
+    if (nx * ab > part_cap) return hipErrorInvalidValue;
+    const int64_t rpb = N > 0 ? ((N + nx - 1) / nx + 3) / 4 * 4 : 4;
+    nx = N > 0 ? (N + rpb - 1) / rpb : 1;
+    switch (TA) {
+#define BMG_GRAM_SYM(NTv)                                                                                  \
+  hipLaunchKernelGGL((k_gram_sym<T, NTv>), dim3((unsigned)nx), dim3(256), 0, s, N, a, X, ldx, rpb, part)
+      case 1: BMG_GRAM_SYM(1); break;
+      case 2: BMG_GRAM_SYM(2); break;
+      case 3: BMG_GRAM_SYM(3); break;
+      case 4: BMG_GRAM_SYM(4); break;
+      default: BMG_GRAM_SYM(5); break;
+#undef BMG_GRAM_SYM
+    }
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ab + 63) / 64)), dim3(256), 0, s, nx, ab,
+                       (const double *)part, out);
+    return hipGetLastError();
+  }
   const int ny = ((TA + 3) / 4) * ((TB + 3) / 4);
   int64_t nx = (N + 63) / 64;                   // >= 64 rows per block
   const int64_t xmax = (1024 + ny - 1) / ny;    // about 1024 blocks in all
