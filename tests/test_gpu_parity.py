@@ -87,7 +87,7 @@ def test_sddmm_parity(name, k):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("q", [1, 8, 33, 130, 257])
+@pytest.mark.parametrize("q", [1, 8, 33, 34, 65, 66, 130, 257])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_spmm_parity(name, q, transpose):
     p = case(name)
