@@ -358,8 +358,11 @@ __global__ __launch_bounds__(256) void k_gemm_ts_w(int64_t N, int a, const T *__
       ms[mk][mc] = (k0 + mk < a && mc < b) ? M[(int64_t)(k0 + mk) * ldm + mc] : 0.0;
     }
     __syncthreads();
+    // the last chunk holds a % 16 terms: the rest (zeros) are skipped
+    const int kn = (a - k0) < 16 ? (a - k0) : 16;
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
+      if (kk >= kn) break;
       double xv[4], mv[NC];
 #pragma unroll
       for (int i = 0; i < 4; ++i) xv[i] = xs[tr * 4 + i][kk];
@@ -447,7 +450,9 @@ hipError_t launch_gemm_ts(int64_t N, int a, const T *X, int ldx, int b, const do
   const int64_t tiles64 = ((N + 63) / 64) * ((b + 63) / 64);
   if (tiles64 >= 1024 && b > 64 && b <= 128) {
     const dim3 grid((unsigned)((N + 63) / 64));
-    if (b <= 96)
+    if (b <= 80)
+      hipLaunchKernelGGL((k_gemm_ts_w<T, 5>), grid, dim3(256), 0, s, N, a, X, ldx, b, M, ldm, C, ldc, beta);
+    else if (b <= 96)
       hipLaunchKernelGGL((k_gemm_ts_w<T, 6>), grid, dim3(256), 0, s, N, a, X, ldx, b, M, ldm, C, ldc, beta);
     else
       hipLaunchKernelGGL((k_gemm_ts_w<T, 8>), grid, dim3(256), 0, s, N, a, X, ldx, b, M, ldm, C, ldc, beta);
