@@ -170,42 +170,65 @@ __device__ __forceinline__ int wave_work(const Plan &pl, int G, int64_t b, int64
 // ============================================================================ lane-group row access
 // A lane group of G lanes owns one row of Omega.  A dense k-vector is split in
 // C chunks of G*V consecutive columns (one 128-byte line for G = 8 in FP64);
-// lane `sub` holds columns c*G*V + sub*V .. +V-1 of chunk c.
-template <typename T, typename TG, int G, int C>
+// lane `sub` holds columns c*G*V + sub*V .. +V-1 of chunk c.  In a thin row
+// (TT) the last chunk is half as wide: lane `sub` holds V/2 columns of it, from
+// (C-1)*G*V + sub*V/2; a width just past a whole number of chunks then keeps
+// V/2 fewer registers per lane for every row in flight.
+template <typename T, typename TG, int G, int C, bool TT = false>
 struct Row {
   static constexpr int V = VT<TG>::V;
   static constexpr int CW = G * V;       // columns per chunk
   static constexpr int WB = CW * C;      // columns covered
+  // elements per lane of chunk c
+  static constexpr __host__ __device__ int vw(int c) { return (TT && c == C - 1) ? V / 2 : V; }
   T v[C][V];
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-      for (int e = 0; e < V; ++e) v[c][e] = T(0);
+      for (int e = 0; e < vw(c); ++e) v[c][e] = T(0);
   }
   template <typename TM>
   __device__ __forceinline__ void load(const TM *__restrict__ row, int sub, int lim) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) ldv<T, TM, V>(row, c * CW + sub * V, lim, v[c]);
+    for (int c = 0; c < C; ++c) {
+      if (TT && c == C - 1) {
+        T h[V / 2];
+        ldv<T, TM, V / 2>(row, c * CW + sub * (V / 2), lim, h);
+#pragma unroll
+        for (int e = 0; e < V / 2; ++e) v[c][e] = h[e];
+      } else {
+        ldv<T, TM, V>(row, c * CW + sub * V, lim, v[c]);
+      }
+    }
   }
   template <typename TM>
   __device__ __forceinline__ void store(TM *__restrict__ row, int sub, int lim) const {
 #pragma unroll
-    for (int c = 0; c < C; ++c) stv<T, TM, V>(row, c * CW + sub * V, lim, v[c]);
+    for (int c = 0; c < C; ++c) {
+      if (TT && c == C - 1) {
+        T h[V / 2];
+#pragma unroll
+        for (int e = 0; e < V / 2; ++e) h[e] = v[c][e];
+        stv<T, TM, V / 2>(row, c * CW + sub * (V / 2), lim, h);
+      } else {
+        stv<T, TM, V>(row, c * CW + sub * V, lim, v[c]);
+      }
+    }
   }
   __device__ __forceinline__ T dot(const Row &o) const {
     T s = T(0);
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-      for (int e = 0; e < V; ++e) s += v[c][e] * o.v[c][e];
+      for (int e = 0; e < vw(c); ++e) s += v[c][e] * o.v[c][e];
     return s;
   }
   __device__ __forceinline__ void axpy(T a, const Row &o) {
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-      for (int e = 0; e < V; ++e) v[c][e] += a * o.v[c][e];
+      for (int e = 0; e < vw(c); ++e) v[c][e] += a * o.v[c][e];
   }
 };
 
@@ -264,14 +287,14 @@ enum TeamMode { TM_GRAD = 0, TM_SDDMM = 1, TM_SPMM = 2 };
 // GRAD: acc += r y, ss += r^2 with r = x.y - a;  SDDMM: R = r, ss += r^2,
 // sx += r (x.y);  SPMM: acc += a y.  On return every group of the team holds
 // the row's sum in acc; ss / sx are held by the group leaders.
-template <typename T, typename TG, int G, int C, int MODE>
+template <typename T, typename TG, int G, int C, int MODE, bool TT = false>
 __device__ __forceinline__ void team_row(const Plan &pl, int row, const T *__restrict__ a,
                                          const TG *__restrict__ Y, int ldy, int width,
-                                         const Row<T, TG, G, C> &x, Row<T, TG, G, C> &acc,
+                                         const Row<T, TG, G, C, TT> &x, Row<T, TG, G, C, TT> &acc,
                                          T *__restrict__ R, double &ss, double &sx, int tbase,
                                          int tl) {
   using TM = Team<G>;
-  using RowT = Row<T, TG, G, C>;
+  using RowT = Row<T, TG, G, C, TT>;
   const int eg = tl / G, sub = tl % G;
   const bool leader = (sub == 0);
   const int64_t beg = pl.ptr[row], end = pl.ptr[row + 1];
@@ -334,7 +357,7 @@ __device__ __forceinline__ void team_row(const Plan &pl, int row, const T *__res
 #pragma unroll
       for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int e = 0; e < RowT::V; ++e) acc.v[c][e] += __shfl_xor(acc.v[c][e], o, 64);
+        for (int e = 0; e < RowT::vw(c); ++e) acc.v[c][e] += __shfl_xor(acc.v[c][e], o, 64);
   }
 }
 
@@ -508,13 +531,13 @@ __global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
 }
 
 // ============================================================================ sparse x dense
-template <typename T, typename TG, int G, int C>
+template <typename T, typename TG, int G, int C, bool TT = false>
 __device__ __forceinline__ void spmm_block(const Plan &pl, const T *__restrict__ Sv,
                                            const TG *__restrict__ B, int ldb, int wq, int sub,
-                                           Row<T, TG, G, C> &acc, int64_t p, int64_t step, int n) {
+                                           Row<T, TG, G, C, TT> &acc, int64_t p, int64_t step, int n) {
   int j[UNROLL];
   T sv[UNROLL];
-  Row<T, TG, G, C> b[UNROLL];
+  Row<T, TG, G, C, TT> b[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     const int64_t pp = p + (u < n ? u * step : 0);
@@ -530,16 +553,16 @@ __device__ __forceinline__ void spmm_block(const Plan &pl, const T *__restrict__
 }
 
 // acc <- coef * acc + x_row . M[:, slice]
-template <typename T, typename TG, int G, int C>
-__device__ __forceinline__ void lowrank_epilogue(Row<T, TG, G, C> &acc, double coef,
+template <typename T, typename TG, int G, int C, bool TT = false>
+__device__ __forceinline__ void lowrank_epilogue(Row<T, TG, G, C, TT> &acc, double coef,
                                                  const T *__restrict__ xr, int kx,
                                                  const T *__restrict__ M, int ldm, int wq,
                                                  int sub) {
-  using RowT = Row<T, TG, G, C>;
+  using RowT = Row<T, TG, G, C, TT>;
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int e = 0; e < RowT::V; ++e) acc.v[c][e] *= (T)coef;
+    for (int e = 0; e < RowT::vw(c); ++e) acc.v[c][e] *= (T)coef;
   for (int r = 0; r < kx; ++r) {
     RowT mv;
     mv.load(M + (int64_t)r * ldm, sub, wq);
@@ -547,14 +570,14 @@ __device__ __forceinline__ void lowrank_epilogue(Row<T, TG, G, C> &acc, double c
   }
 }
 
-template <typename T, typename TG, int G, int C>
+template <typename T, typename TG, int G, int C, bool TT = false>
 __device__ __forceinline__ void spmm_body(const Plan &pl, int64_t blk, const T *__restrict__ Sv,
                                               const TG *__restrict__ B, int ldb, int wq,
                                               double coef, const T *__restrict__ X, int ldx,
                                               int kx, const T *__restrict__ M, int ldm,
                                               T *__restrict__ Cm, int ldc,
                                               T *__restrict__ partial) {
-  using RowT = Row<T, TG, G, C>;
+  using RowT = Row<T, TG, G, C, TT>;
   constexpr int S = 64 / G, WB = RowT::WB;
   const int lane = threadIdx.x & 63, slot = lane / G, sub = lane % G;
   int64_t w = 0;
@@ -569,10 +592,10 @@ __device__ __forceinline__ void spmm_body(const Plan &pl, int64_t blk, const T *
       const int row = pl.short_rows[ri];
       RowT none;
       double s0 = 0.0, s1 = 0.0;
-      team_row<T, TG, G, C, TM_SPMM>(pl, row, Sv, B, ldb, wq, none, acc, (T *)nullptr, s0, s1,
+      team_row<T, TG, G, C, TM_SPMM, TT>(pl, row, Sv, B, ldb, wq, none, acc, (T *)nullptr, s0, s1,
                                      team * TL, tl);
       if (tl < G) {
-        lowrank_epilogue<T, TG, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
+        lowrank_epilogue<T, TG, G, C, TT>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
         acc.store(Cm + (int64_t)row * ldc, sub, wq);
       }
     }
@@ -582,32 +605,42 @@ __device__ __forceinline__ void spmm_body(const Plan &pl, int64_t blk, const T *
     for (int64_t p = beg + slot; p < end; p += (int64_t)S * UNROLL) {
       const int64_t rem = (end - p + S - 1) / S;
       const int n = (int)(rem < UNROLL ? rem : UNROLL);
-      spmm_block<T, TG, G, C>(pl, Sv, B, ldb, wq, sub, acc, p, S, n);
+      spmm_block<T, TG, G, C, TT>(pl, Sv, B, ldb, wq, sub, acc, p, S, n);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-      for (int e = 0; e < RowT::V; ++e) acc.v[c][e] = slot_sum<G>(acc.v[c][e]);
+      for (int e = 0; e < RowT::vw(c); ++e) acc.v[c][e] = slot_sum<G>(acc.v[c][e]);
     if (slot == 0) acc.store(partial + pc * WB, sub, WB);
   }
 }
 
-template <typename T, typename TG, int G, int C>
+template <typename T, typename TG, int G, int C, bool TT>
 __global__ __launch_bounds__(256) void k_spmm(Plan pl, const T *__restrict__ Sv,
                                               const TG *__restrict__ B, int ldb, int wq,
                                               double coef, const T *__restrict__ X, int ldx,
                                               int kx, const T *__restrict__ M, int ldm,
                                               T *__restrict__ Cm, int ldc,
                                               T *__restrict__ partial) {
-  spmm_body<T, TG, G, C>(pl, blockIdx.x, Sv, B, ldb, wq, coef, X, ldx, kx, M, ldm, Cm, ldc, partial);
+  spmm_body<T, TG, G, C, TT>(pl, blockIdx.x, Sv, B, ldb, wq, coef, X, ldx, kx, M, ldm, Cm, ldc, partial);
 }
 
+// Thin rows keep few enough registers for six waves per SIMD; the hint lets the
+// compiler fit the last few.
 template <typename T, typename TG, int G, int C>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_spmm_thin(
+    Plan pl, const T *__restrict__ Sv, const TG *__restrict__ B, int ldb, int wq, double coef,
+    const T *__restrict__ X, int ldx, int kx, const T *__restrict__ M, int ldm, T *__restrict__ Cm, int ldc,
+    T *__restrict__ partial) {
+  spmm_body<T, TG, G, C, true>(pl, blockIdx.x, Sv, B, ldb, wq, coef, X, ldx, kx, M, ldm, Cm, ldc, partial);
+}
+
+template <typename T, typename TG, int G, int C, bool TT>
 __global__ __launch_bounds__(256) void k_spmm_fix(Plan pl, const T *__restrict__ partial,
                                                   double coef, const T *__restrict__ X, int ldx,
                                                   int kx, const T *__restrict__ M, int ldm, int wq,
                                                   T *__restrict__ Cm, int ldc) {
-  using RowT = Row<T, TG, G, C>;
+  using RowT = Row<T, TG, G, C, TT>;
   const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   if (g >= pl.n_long) return;
@@ -618,7 +651,7 @@ __global__ __launch_bounds__(256) void k_spmm_fix(Plan pl, const T *__restrict__
     t.load(partial + (int64_t)pc * RowT::WB, sub, RowT::WB);
     acc.axpy(T(1), t);
   }
-  lowrank_epilogue<T, TG, G, C>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
+  lowrank_epilogue<T, TG, G, C, TT>(acc, coef, X + (int64_t)row * ldx, kx, M, ldm, wq, sub);
   acc.store(Cm + (int64_t)row * ldc, sub, wq);
 }
 
@@ -727,17 +760,38 @@ hipError_t launch_spmm(const Plan &pl, const T *Sv, const TG *B, int ldb, int q,
     const GC gc = pick_gc(wq, V);
     if (pl.n_pieces * partial_row_bytes<T, TG>(gc) > sc.partial_bytes) return hipErrorInvalidValue;
     const int64_t nb = grid_blocks(pl, gc.G);
+    // FP64 widths at most half a chunk past a whole number of chunks (q = 2k + 1
+    // of the subspace iteration, say) use thin rows: fewer registers per row in
+    // flight, so more waves per SIMD
+    // (two or three chunks: wider thin rows would still spill at six waves)
+    const bool thin = sizeof(T) == 8 && sizeof(TG) == 8 && gc.C >= 2 && gc.C <= 3 &&
+                      wq - (gc.C - 1) * gc.G * V <= gc.G * V / 2;
+#define BMG_SPMM_LAUNCH(TTv)                                                                          \
+  do {                                                                                                \
+    if (TTv)                                                                                          \
+      hipLaunchKernelGGL((k_spmm_thin<T, TG, GG, CC>), dim3((unsigned)nb), dim3(256), 0, s, pl, Sv,   \
+                         B + c0, ldb, wq, coef, X, ldx, kx, M ? M + c0 : M, ldm, Cm + c0, ldc,       \
+                         (T *)sc.partial);                                                           \
+    else                                                                                              \
+      hipLaunchKernelGGL((k_spmm<T, TG, GG, CC, false>), dim3((unsigned)nb), dim3(256), 0, s, pl, Sv, \
+                         B + c0, ldb, wq, coef, X, ldx, kx, M ? M + c0 : M, ldm, Cm + c0, ldc,       \
+                         (T *)sc.partial);                                                           \
+    if (pl.n_long > 0) {                                                                              \
+      const int64_t thr = pl.n_long * GG;                                                             \
+      hipLaunchKernelGGL((k_spmm_fix<T, TG, GG, CC, TTv>), dim3((unsigned)((thr + 255) / 256)),      \
+                         dim3(256), 0, s, pl, (const T *)sc.partial, coef, X, ldx, kx,               \
+                         M ? M + c0 : M, ldm, wq, Cm + c0, ldc);                                     \
+    }                                                                                                 \
+  } while (0)
     BMG_DISPATCH_GC(gc, {
-      hipLaunchKernelGGL((k_spmm<T, TG, GG, CC>), dim3((unsigned)nb), dim3(256), 0, s, pl, Sv,
-                         B + c0, ldb, wq, coef, X, ldx, kx, M ? M + c0 : M, ldm, Cm + c0, ldc,
-                         (T *)sc.partial);
-      if (pl.n_long > 0) {
-        const int64_t thr = pl.n_long * GG;
-        hipLaunchKernelGGL((k_spmm_fix<T, TG, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
-                           dim3(256), 0, s, pl, (const T *)sc.partial, coef, X, ldx, kx,
-                           M ? M + c0 : M, ldm, wq, Cm + c0, ldc);
+      if constexpr (CC >= 2 && CC <= 3 && sizeof(T) == 8 && sizeof(TG) == 8) {
+        if (thin) BMG_SPMM_LAUNCH(true);
+        else BMG_SPMM_LAUNCH(false);
+      } else {
+        BMG_SPMM_LAUNCH(false);
       }
     });
+#undef BMG_SPMM_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -856,7 +910,7 @@ hipError_t launch_batch(const PassArg<T, TG> *d, int nd, int mode, hipStream_t s
                            dim3(256), 0, s, D.pl, (const T *)D.partial, D.X, D.ldx, D.width, D.lam,
                            D.out, D.ldo);
       else
-        hipLaunchKernelGGL((k_spmm_fix<T, TG, GG, CC>), dim3((unsigned)((thr + 255) / 256)),
+        hipLaunchKernelGGL((k_spmm_fix<T, TG, GG, CC, false>), dim3((unsigned)((thr + 255) / 256)),
                            dim3(256), 0, s, D.pl, (const T *)D.partial, D.coef, D.X, D.ldx, D.kx,
                            D.M, D.ldm, D.width, D.out, D.ldo);
     }
