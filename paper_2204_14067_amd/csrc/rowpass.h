@@ -69,6 +69,10 @@ __device__ __forceinline__ void ldv(const TM *__restrict__ row, int f0, int lim,
         x[4 * h] = (T)v.x; x[4 * h + 1] = (T)v.y; x[4 * h + 2] = (T)v.z; x[4 * h + 3] = (T)v.w;
       }
       return;
+    } else if constexpr (sizeof(TM) == 4 && V == 2) {
+      const float2 v = *reinterpret_cast<const float2 *>(row + f0);
+      x[0] = (T)v.x; x[1] = (T)v.y;
+      return;
     } else if constexpr (sizeof(TM) == 2 && V == 8) {
       const uint4 v = *reinterpret_cast<const uint4 *>(row + f0);
       const uint32_t w[4] = {v.x, v.y, v.z, v.w};
@@ -95,6 +99,9 @@ __device__ __forceinline__ void stv(TM *__restrict__ row, int f0, int lim, const
       for (int h = 0; h < V / 4; ++h)
         *reinterpret_cast<float4 *>(row + f0 + 4 * h) =
             make_float4(x[4 * h], x[4 * h + 1], x[4 * h + 2], x[4 * h + 3]);
+      return;
+    } else if constexpr (sizeof(TM) == 4 && sizeof(T) == 4 && V == 2) {
+      *reinterpret_cast<float2 *>(row + f0) = make_float2(x[0], x[1]);
       return;
     }
   }
@@ -760,12 +767,12 @@ hipError_t launch_spmm(const Plan &pl, const T *Sv, const TG *B, int ldb, int q,
     const GC gc = pick_gc(wq, V);
     if (pl.n_pieces * partial_row_bytes<T, TG>(gc) > sc.partial_bytes) return hipErrorInvalidValue;
     const int64_t nb = grid_blocks(pl, gc.G);
-    // FP64 widths at most half a chunk past a whole number of chunks (q = 2k + 1
-    // of the subspace iteration, say) use thin rows: fewer registers per row in
-    // flight, so more waves per SIMD
-    // (two or three chunks: wider thin rows would still spill at six waves)
-    const bool thin = sizeof(T) == 8 && sizeof(TG) == 8 && gc.C >= 2 && gc.C <= 3 &&
-                      wq - (gc.C - 1) * gc.G * V <= gc.G * V / 2;
+    // FP64 and FP32 widths at most half a chunk past a whole number of chunks
+    // (q = 2k + 1 of the subspace iteration, say) use thin rows: fewer registers
+    // per row in flight, so more waves per SIMD (two or three chunks: wider thin
+    // rows would still spill at six waves)
+    constexpr bool same = sizeof(T) == sizeof(TG);
+    const bool thin = same && gc.C >= 2 && gc.C <= 3 && wq - (gc.C - 1) * gc.G * V <= gc.G * V / 2;
 #define BMG_SPMM_LAUNCH(TTv)                                                                          \
   do {                                                                                                \
     if (TTv)                                                                                          \
@@ -784,7 +791,7 @@ hipError_t launch_spmm(const Plan &pl, const T *Sv, const TG *B, int ldb, int q,
     }                                                                                                 \
   } while (0)
     BMG_DISPATCH_GC(gc, {
-      if constexpr (CC >= 2 && CC <= 3 && sizeof(T) == 8 && sizeof(TG) == 8) {
+      if constexpr (CC >= 2 && CC <= 3 && same) {
         if (thin) BMG_SPMM_LAUNCH(true);
         else BMG_SPMM_LAUNCH(false);
       } else {
