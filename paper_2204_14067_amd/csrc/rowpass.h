@@ -135,6 +135,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 #endif
 constexpr int UNROLL = BMG_UNROLL;  // entries in flight per lane group
 constexpr int WAVES_PER_BLOCK = 4;
+// Waves per SIMD the compiler is asked to fit for a row kernel (1: its own
+// choice).  The FP64 width-32 passes of the BM phase sit just above a wave
+// boundary (98 and 83 VGPRs); asked for one wave more, they fit without spills.
+template <typename T, int G, int C> constexpr int grad_waves() { return (sizeof(T) == 8 && G == 8 && C == 2) ? 5 : 1; }
+template <typename T, int G, int C> constexpr int sddmm_waves() { return (sizeof(T) == 8 && G == 8 && C == 2) ? 6 : 1; }
 
 // Short rows: a team of max(8, G) lanes per row, 64 / team rows per wave.
 __host__ __device__ inline int64_t short_waves(const Plan &pl, int G) {
@@ -422,7 +427,7 @@ __device__ __forceinline__ void grad_body(const Plan &pl, int64_t blk, const T *
   if (lane == 0) wsum[gw] = ss;
 }
 template <typename T, typename TG, int G, int C>
-__global__ __launch_bounds__(256) void k_grad(Plan pl, const T *__restrict__ a,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grad_waves<T, G, C>()))) void k_grad(Plan pl, const T *__restrict__ a,
                                               const T *__restrict__ X, int ldx,
                                               const TG *__restrict__ Y, int ldy, int k, double lam,
                                               T *__restrict__ Out, int ldo,
@@ -530,7 +535,7 @@ __device__ __forceinline__ void sddmm_body(const Plan &pl, int64_t blk, const T 
   }
 }
 template <typename T, typename TG, int G, int C>
-__global__ __launch_bounds__(256) void k_sddmm(Plan pl, const T *__restrict__ a,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sddmm_waves<T, G, C>()))) void k_sddmm(Plan pl, const T *__restrict__ a,
                                                const T *__restrict__ X, int ldx,
                                                const TG *__restrict__ Y, int ldy, int k,
                                                T *__restrict__ R, double *__restrict__ wsum) {
