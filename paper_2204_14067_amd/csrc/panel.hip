@@ -179,7 +179,7 @@ __global__ void k_panel_xt(int ldi, int q, const int32_t *__restrict__ rows, con
 // columns c, K = columns j.  part[bx][i][c] (ldi x 16 NQ per block) gets the
 // block's partial sums.
 template <typename T, int NQ, int NT>
-__global__ __launch_bounds__(256) void k_panel_rows(int TI, int64_t n, int q, int64_t cpb,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NQ * NT >= 9 ? 3 : 1))) void k_panel_rows(int TI, int64_t n, int q, int64_t cpb,
                                                     const T *__restrict__ S, int ldi, int values,
                                                     const T *__restrict__ Y, int ldy,
                                                     double *__restrict__ part) {
